@@ -1,0 +1,183 @@
+"""Benchmark: half-space spectral Ewald summation on one MI355X.
+
+One step = one full evaluation of the half-space stokeslet sum (binning,
+real-space sum, spreading, zero-padded 3D transforms with the fused scaling,
+inverse transforms, quadrature and FP64 combination) for N = 100,000 sources
+= targets uniform in [0,1)^2 x (0,1], forces N(0,1), FP64 at tol 1e-10, with
+xi and r_c chosen for about 30 neighbours per point.  Inputs are resident in
+device memory before the timed region; the truncated-kernel precompute is done
+during warm-up (it depends only on the grid size and is excluded, as in the
+paper's timings).
+
+Prints one JSON line.  Extra fields: the FP32 path on the same workload at
+tol 1e-5, the relative RMS error of both against the FP64 oracle on a sample
+of targets, per-stage times, the roofline of the dominant kernel and the
+oracle's own throughput on the host cores (cpu_baseline).
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def _stage_bytes(rep, ncin, esz):
+    """Algorithmic HBM bytes of each transform pass (inputs read once, outputs written once)."""
+    Mt = rep.Mt
+    c = 2 * esz
+    real = Mt * Mt * 2 * Mt * esz
+    a = (Mt + 1) * 2 * Mt * Mt * c
+    z = (Mt + 1) * 4 * Mt * Mt * c
+    oct_bytes = (Mt + 1) * (Mt + 1) * (2 * Mt + 1) * 8 * (1 if rep.family == 2 else 2)
+    return {
+        "fwd_x": ncin * (real + a),
+        "fwd_y": ncin * (a + z),
+        "z_scale": ncin * z + 6 * z + oct_bytes,
+        "inv_y": 6 * (z + a),
+        "inv_x": 6 * (a + real),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=100_000)
+    ap.add_argument("--neighbours", type=float, default=30.0)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target duration of the oracle sample")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp32", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path (use --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1802_07844_amd as ehs
+    from paper_1802_07844_amd import workloads
+
+    n = args.n
+    seed = workloads.SEED_BASE + 1
+    y, f = workloads.uniform_stokeslet(n, seed)
+    dev = torch.device("cuda:0")
+    yd = torch.from_numpy(y).to(dev)
+    fd = torch.from_numpy(f).to(dev)
+    out = torch.empty((n, 3), dtype=torch.float64, device=dev)
+    # r_c for ~30 neighbours in the unit box, xi from the real-space estimate
+    rc = (args.neighbours * 3.0 / (4.0 * math.pi * n)) ** (1.0 / 3.0)
+    tol = 1e-10
+    xi = ehs.xi_for_cutoff("stokeslet", rc, tol)
+
+    ctx = ehs.Context(0)
+    ctx.set_option(ehs.OPT_PRECISION, 1)
+    ctx.set_option(ehs.OPT_TIMING, 1)
+
+    def step(o, t):
+        return ctx.stokeslet(yd, fd, yd, xi, rc, t, out=o, report=True)[1]
+
+    for _ in range(args.warmup):
+        step(out, tol)
+    torch.cuda.synchronize()
+    stage_sum = np.zeros(ehs.NSTAGES)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        rep = step(out, tol)
+        stage_sum += np.array(list(rep.ms_stage))
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ms_per_step = dt / args.steps * 1e3
+    value = n * args.steps / dt
+    stage_ms = dict(zip(ehs.STAGES, (stage_sum / args.steps).tolist()))
+    u64 = out.cpu().numpy()
+
+    # dominant transform kernel and its roofline (algorithmic bytes / launch time)
+    esz = 8
+    sb = _stage_bytes(rep, 7, esz)
+    dom = max(sb.keys(), key=lambda k: stage_ms[k])
+    achieved = sb[dom] / (stage_ms[dom] * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": None, "bytes_per_launch": sb[dom]}
+
+    result = {
+        "metric": "points/sec at rel-RMS 1e-10 (FP64)",
+        "value": value,
+        "unit": "points/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"half-space stokeslet, N={n} sources=targets uniform in [0,1)^2x(0,1], "
+                               f"forces N(0,1), FP64 tol 1e-10, ~{args.neighbours:g} neighbours",
+                   "N": n, "xi": xi, "r_c": rc, "tol": tol, "M": rep.M, "P": rep.P, "Mt": rep.Mt,
+                   "eta": rep.eta, "seed": seed},
+        "stage_ms": stage_ms,
+        "roofline": roofline,
+    }
+
+    # FP32 path on the same workload at tol 1e-5
+    u32 = None
+    if not args.no_fp32:
+        tol32 = 1e-5
+        ctx.set_option(ehs.OPT_PRECISION, 2)
+        xi32 = ehs.xi_for_cutoff("stokeslet", rc, tol32)
+        out32 = torch.empty_like(out)
+
+        def step32():
+            return ctx.stokeslet(yd, fd, yd, xi32, rc, tol32, out=out32, report=True)[1]
+
+        for _ in range(args.warmup):
+            step32()
+        torch.cuda.synchronize()
+        st32 = np.zeros(ehs.NSTAGES)
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            r32 = step32()
+            st32 += np.array(list(r32.ms_stage))
+        torch.cuda.synchronize()
+        dt32 = time.perf_counter() - t0
+        u32 = out32.cpu().numpy()
+        result["fp32"] = {"value": n * args.steps / dt32, "unit": "points/s", "ms_per_step": dt32 / args.steps * 1e3,
+                          "tol": tol32, "xi": xi32, "M": r32.M, "P": r32.P, "Mt": r32.Mt,
+                          "stage_ms": dict(zip(ehs.STAGES, (st32 / args.steps).tolist()))}
+
+    # oracle on the host cores: a bounded sample of targets against all sources
+    if not args.no_cpu_baseline:
+        import oracle
+
+        cores = oracle.max_threads()
+        # size the sample from a short probe
+        probe = 64
+        t0 = time.perf_counter()
+        oracle.halfspace("stokeslet", y, f, y[:probe])
+        tp = time.perf_counter() - t0
+        S = int(max(probe, min(n, probe * args.cpu_seconds / max(tp, 1e-6))))
+        g = workloads.rng(seed + 1000)
+        idx = np.sort(g.choice(n, size=S, replace=False))
+        t0 = time.perf_counter()
+        ref = oracle.halfspace("stokeslet", y, f, y[idx])
+        tc = time.perf_counter() - t0
+        result["cpu_baseline"] = {"value": S / tc, "unit": "points/s", "cores": cores, "kind": "oracle",
+                                  "sample": f"{S} of {n} targets against all {n} sources, FP64 direct sum, "
+                                            f"{tc:.1f} s"}
+        result["rel_rms_fp64"] = oracle.rel_rms(ref, u64[idx])
+        if u32 is not None:
+            result["fp32"]["rel_rms"] = oracle.rel_rms(ref, u32[idx])
+    print(json.dumps(result))
+
+
+if __name__ == "__main__":
+    main()

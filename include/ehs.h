@@ -1,0 +1,178 @@
+/*
+ * ehs.h -- C ABI of the MI355X half-space spectral Ewald library.
+ *
+ * Fast summation of the half-space Green's functions of Stokes flow
+ * (stokeslet, stresslet, rotlet with their wall images and harmonic
+ * corrections), after Srinivasan & Tornberg, "Fast Ewald summation for
+ * Green's functions of Stokes flow in a half-space":
+ *
+ *   u(x_t) = sum_m K(x_t - y_m) s_m - K(x_t - y_m^I) s_m^I
+ *                  - x_t3 grad phi_m(x_t) + e_3 phi_m(x_t)
+ *
+ * (Sec. 3, eq. (v_sum_halfspace) with the potentials of eq. (phi)), split by
+ * Ewald's method into a real-space sum over neighbours within r_c (Sec. 5.1)
+ * and a Fourier-space part evaluated with Gaussian spreading, zero-padded
+ * FFTs, scaling by the truncated-kernel multipliers, inverse FFTs and Gaussian
+ * quadrature (Sec. 5.2, Algorithm 1).
+ *
+ * Normalisation: the kernels are S f = f/r + r(r.f)/r^3, T[g,q] =
+ * -6 r (r.g)(r.q)/r^5 and the rotlet 2 W v = 2 (v x r)/r^3 (the paper's
+ * 8 pi S, 8 pi T and 4 pi W of Sec. 2 without the constants); the wall is the
+ * plane x3 = 0 and all points lie in x3 >= 0.
+ *
+ * Conventions for every entry point below:
+ *  - all array pointers are DEVICE pointers (HIP memory of the context's
+ *    device), row-major float64, owned by the caller; the library keeps no
+ *    pointer after the call returns;
+ *  - `stream` is a hipStream_t passed as void* (NULL: the default stream).
+ *    The call returns after enqueueing; results are valid once the stream has
+ *    synchronised.  One blocking device-to-host read (64 bytes, the bounding
+ *    box) happens inside every call; a cache miss of the truncated-kernel
+ *    precompute adds one more synchronisation;
+ *  - outputs are overwritten, never accumulated;
+ *  - a context is not thread safe and calls on one context must not overlap
+ *    (they share the context's workspace);
+ *  - return value: 0 on success or a negative EHS_E* code (ehs_strerror).
+ */
+#ifndef EHS_H
+#define EHS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define EHS_OK 0
+#define EHS_EINVAL (-1)  /* null pointer, bad size or parameter */
+#define EHS_EDOMAIN (-2) /* a source with y3 <= 0, a target with x3 < 0, or a non-finite input */
+#define EHS_ERANGE (-3)  /* no admissible grid for the request (too fine, or eta >= 1) */
+#define EHS_ENOMEM (-4)  /* device allocation failed or the memory cap is too small */
+#define EHS_EHIP (-5)    /* a HIP runtime error */
+
+/* kernel families */
+#define EHS_STOKESLET 0
+#define EHS_STRESSLET 1
+#define EHS_ROTLET 2
+
+/* options (ehs_set_option) */
+#define EHS_OPT_PRECISION 0 /* 0: auto (FP32 when tol >= 1e-5, else FP64), 1: FP64, 2: FP32 */
+#define EHS_OPT_TIMING 1    /* 1: record per-stage times into the report (adds a synchronisation) */
+#define EHS_OPT_FORCE_M 2   /* > 0: use this M (grid intervals over the box) instead of the estimate */
+#define EHS_OPT_FORCE_P 3   /* > 0: use this Gaussian support P (even) */
+#define EHS_OPT_FORCE_MT 4  /* > 0: use this total grid size M~ (>= M + P, 7-smooth, even) */
+#define EHS_OPT_MEM_CAP 5   /* > 0: refuse a workspace larger than this many bytes (EHS_ENOMEM) */
+
+/* stage indices of ehs_report.ms_stage */
+#define EHS_ST_BBOX 0       /* bounding box + validation reduction and its readback */
+#define EHS_ST_PRECOMP 1    /* truncated-kernel precompute (cache miss only) */
+#define EHS_ST_BIN 2        /* cell keys, radix sorts, offsets, sorted copies */
+#define EHS_ST_REAL 3       /* real-space sum */
+#define EHS_ST_SPREAD 4     /* point keys, sort, records, spreading */
+#define EHS_ST_FWDX 5       /* forward x1 pass (real to half spectrum) */
+#define EHS_ST_FWDY 6       /* forward x2 pass */
+#define EHS_ST_ZSCALE 7     /* fused x3 transform, scaling, inverse x3 transform */
+#define EHS_ST_INVY 8       /* inverse x2 pass */
+#define EHS_ST_INVX 9       /* inverse x1 pass */
+#define EHS_ST_GATHER 10    /* quadrature at the targets + FP64 combination */
+#define EHS_ST_TOTAL 11
+#define EHS_NSTAGES 12
+
+typedef struct ehs_ctx ehs_ctx;
+
+typedef struct ehs_report {
+    int32_t M, P, Mt;       /* grid intervals over the box, Gaussian support, total grid size M~ */
+    int32_t precision;      /* 1: FP64, 2: FP32 */
+    int32_t Q;              /* phases of the fused x3 pass */
+    int32_t nf, nf3;        /* oversampled precompute grid (in-plane, x3) */
+    int32_t warnings;       /* bit 0: real-space estimate above tol/2 (r_c too small for xi);
+                               bit 1: the precompute ran in this call */
+    int32_t ncell[3];       /* real-space cells per axis */
+    int32_t family;
+    double L, h, Lt, eta;   /* box, grid spacing, extended box M~ h, Gaussian shape */
+    double xi, r_c, tol;
+    double est_real, est_fourier; /* relative truncation estimates (Sec. 6, Tables 1-2) */
+    double origin[3];       /* grid origin (the wall is at x3 = 0) */
+    double ms_stage[EHS_NSTAGES]; /* stage times when EHS_OPT_TIMING is on, else 0 */
+    double workspace_bytes;
+} ehs_report;
+
+/* Create a context on HIP device `hip_device`.  `arena_bytes` is reserved
+   for future use and may be 0.  Returns EHS_OK or an error; *out is NULL on
+   error. */
+int ehs_create(ehs_ctx** out, int hip_device, size_t arena_bytes);
+/* Release the context and all its device memory (NULL is allowed). */
+void ehs_destroy(ehs_ctx* ctx);
+/* Set an EHS_OPT_* option; returns EHS_EINVAL for an unknown option. */
+int ehs_set_option(ehs_ctx* ctx, int option, double value);
+
+/*
+ * Half-space stokeslet sum (Sec. 3 eq. (v_sum_halfspace) a).
+ *   sources: N x 3 positions y_m (y_m3 > 0);  f: N x 3 forces;
+ *   targets: T x 3 positions x_t (x_t3 >= 0), may alias `sources`;
+ *   xi: Ewald parameter (> 0); r_c: real-space cutoff (> 0);
+ *   tol: target relative RMS error in [1e-14, 1e-2];
+ *   u_out: T x 3 velocities.
+ * A target that coincides exactly with a source omits that source's direct
+ * term (p != m of Sec. 2); its image and correction terms are kept.
+ */
+int ewald_halfspace_stokeslet(ehs_ctx* ctx, const double* sources, const double* f, int64_t N,
+                              const double* targets, int64_t T, double xi, double r_c, double tol,
+                              double* u_out, void* stream, ehs_report* rep);
+
+/* Half-space stresslet sum (eq. (v_sum_halfspace) b); strengths N x 6 rows
+   (g1, g2, g3, q1, q2, q3): strength g then orientation q.  Other arguments
+   as for the stokeslet. */
+int ewald_halfspace_stresslet(ehs_ctx* ctx, const double* sources, const double* gq, int64_t N,
+                              const double* targets, int64_t T, double xi, double r_c, double tol,
+                              double* u_out, void* stream, ehs_report* rep);
+
+/* Half-space rotlet sum (eq. (v_sum_halfspace) c); strengths N x 3 torques
+   v = g x q (the sum depends on g and q only through g x q). */
+int ewald_halfspace_rotlet(ehs_ctx* ctx, const double* sources, const double* v, int64_t N,
+                           const double* targets, int64_t T, double xi, double r_c, double tol,
+                           double* u_out, void* stream, ehs_report* rep);
+
+/* Message for an EHS_* code (static storage). */
+const char* ehs_strerror(int code);
+
+/*
+ * Ewald parameter xi for which the real-space truncation estimate of the
+ * half-space sum (Sec. 6, Table 2 with sources and images counted) equals
+ * tol/2 relative to sqrt(Q)/L, for cutoff r_c and box size L.  Host-only
+ * arithmetic; returns a value > 0, or -1 for bad arguments.
+ */
+double ehs_xi_for_cutoff(int family, double r_c, double tol, double L);
+
+/*
+ * Parameter selection only (host arithmetic, no device work): the plan that
+ * an evaluation would use for N sources, T targets in the bounding box
+ * [lo, hi] (x3 of the box measured from the wall), strength measure Q (sum of
+ * squared strength norms: |f|^2, |g|^2 |q|^2 or |v|^2), xi, r_c and tol.
+ * precision: 0 auto, 1 FP64, 2 FP32.  Fills rep (workspace_bytes = bytes of
+ * the workspace the evaluation would allocate).
+ */
+int ehs_plan_query(int family, int64_t N, int64_t T, const double* lo, const double* hi, double Q, double xi,
+                   double r_c, double tol, int precision, ehs_report* rep);
+
+/*
+ * Truncated Green's function transforms of Sec. 5.2 evaluated on the host:
+ * kind 0: H^R(k) = 8 pi sin^2(R k / 2) / k^2; kind 1: B^R(k) =
+ * 4 pi [(2 - R^2 k^2) cos Rk + 2 Rk sin Rk - 2] / k^4 (series near k = 0).
+ */
+double ehs_truncated_kernel_hat(int kind, double k, double R);
+
+/*
+ * Unit-test entry: `nl` independent in-place-style FFTs of length n on the
+ * context's device (in, out: device arrays of nl * n interleaved complex
+ * values, float64 when fp32 == 0 else float32).  Unnormalised; inverse != 0
+ * uses exp(+2 pi i k t / n).  n must factor into 2, 3, 5, 7.
+ */
+int ehs_debug_line_fft(ehs_ctx* ctx, int n, int nl, const void* in, void* out, int inverse, int fp32,
+                       void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* EHS_H */

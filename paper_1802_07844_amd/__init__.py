@@ -1,0 +1,258 @@
+"""MI355X half-space spectral Ewald summation of Stokes Green's functions.
+
+Thin ctypes binding of the C ABI in ``include/ehs.h`` (library ``libehs.so``
+in this directory).  Argument marshalling only: every step of the summation
+runs in the HIP kernels of the library.  PyTorch provides device memory and
+the current stream.
+
+    import torch, paper_1802_07844_amd as ehs
+    u = ehs.stokeslet(y, f, y, xi, r_c, tol)        # y, f: (N, 3) float64 on cuda
+
+The library must be built (``python -m paper_1802_07844_amd.build``); a
+missing library raises ``RuntimeError`` -- there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libehs.so")
+
+STOKESLET, STRESSLET, ROTLET = 0, 1, 2
+FAMILIES = {"stokeslet": STOKESLET, "stresslet": STRESSLET, "rotlet": ROTLET}
+OPT_PRECISION, OPT_TIMING, OPT_FORCE_M, OPT_FORCE_P, OPT_FORCE_MT, OPT_MEM_CAP = range(6)
+STAGES = ["bbox", "precompute", "binning", "realspace", "spread", "fwd_x", "fwd_y", "z_scale", "inv_y", "inv_x",
+          "gather", "total"]
+NSTAGES = len(STAGES)
+
+EHS_OK, EHS_EINVAL, EHS_EDOMAIN, EHS_ERANGE, EHS_ENOMEM, EHS_EHIP = 0, -1, -2, -3, -4, -5
+
+
+class Report(ctypes.Structure):
+    _fields_ = [
+        ("M", ctypes.c_int32), ("P", ctypes.c_int32), ("Mt", ctypes.c_int32), ("precision", ctypes.c_int32),
+        ("Q", ctypes.c_int32), ("nf", ctypes.c_int32), ("nf3", ctypes.c_int32), ("warnings", ctypes.c_int32),
+        ("ncell", ctypes.c_int32 * 3), ("family", ctypes.c_int32),
+        ("L", ctypes.c_double), ("h", ctypes.c_double), ("Lt", ctypes.c_double), ("eta", ctypes.c_double),
+        ("xi", ctypes.c_double), ("r_c", ctypes.c_double), ("tol", ctypes.c_double),
+        ("est_real", ctypes.c_double), ("est_fourier", ctypes.c_double),
+        ("origin", ctypes.c_double * 3),
+        ("ms_stage", ctypes.c_double * NSTAGES),
+        ("workspace_bytes", ctypes.c_double),
+    ]
+
+    def as_dict(self) -> dict:
+        d = {k: getattr(self, k) for k, _ in self._fields_}
+        d["ncell"] = list(self.ncell)
+        d["origin"] = list(self.origin)
+        d["ms_stage"] = dict(zip(STAGES, list(self.ms_stage)))
+        return d
+
+
+class EhsError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"ehs error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+_lock = threading.Lock()
+
+
+def lib():
+    """Load libehs.so (raises RuntimeError if it has not been built)."""
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(LIB_PATH):
+                raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_1802_07844_amd.build`")
+            L = ctypes.CDLL(LIB_PATH)
+            vp, dp, i64 = ctypes.c_void_p, ctypes.c_double, ctypes.c_int64
+            L.ehs_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int, ctypes.c_size_t]
+            L.ehs_create.restype = ctypes.c_int
+            L.ehs_destroy.argtypes = [vp]
+            L.ehs_destroy.restype = None
+            L.ehs_set_option.argtypes = [vp, ctypes.c_int, dp]
+            L.ehs_set_option.restype = ctypes.c_int
+            for name in ("ewald_halfspace_stokeslet", "ewald_halfspace_stresslet", "ewald_halfspace_rotlet"):
+                fn = getattr(L, name)
+                fn.argtypes = [vp, vp, vp, i64, vp, i64, dp, dp, dp, vp, vp, ctypes.POINTER(Report)]
+                fn.restype = ctypes.c_int
+            L.ehs_strerror.argtypes = [ctypes.c_int]
+            L.ehs_strerror.restype = ctypes.c_char_p
+            L.ehs_xi_for_cutoff.argtypes = [ctypes.c_int, dp, dp, dp]
+            L.ehs_xi_for_cutoff.restype = dp
+            L.ehs_truncated_kernel_hat.argtypes = [ctypes.c_int, dp, dp]
+            L.ehs_truncated_kernel_hat.restype = dp
+            L.ehs_plan_query.argtypes = [ctypes.c_int, i64, i64, ctypes.POINTER(dp), ctypes.POINTER(dp), dp, dp, dp,
+                                         dp, ctypes.c_int, ctypes.POINTER(Report)]
+            L.ehs_plan_query.restype = ctypes.c_int
+            L.ehs_debug_line_fft.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp, vp, ctypes.c_int, ctypes.c_int, vp]
+            L.ehs_debug_line_fft.restype = ctypes.c_int
+            _bind_serving(L)
+            _lib = L
+    return _lib
+
+
+def _bind_serving(L):
+    if not hasattr(L, "ehs_server_create"):
+        return
+    vp, dp, i64 = ctypes.c_void_p, ctypes.c_double, ctypes.c_int64
+    L.ehs_server_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int, ctypes.c_size_t, ctypes.c_int]
+    L.ehs_server_create.restype = ctypes.c_int
+    L.ehs_server_destroy.argtypes = [vp]
+    L.ehs_server_destroy.restype = None
+    L.ehs_server_submit.argtypes = [vp, ctypes.c_int, vp, vp, i64, vp, i64, dp, dp, dp, vp,
+                                    ctypes.POINTER(ctypes.c_uint64)]
+    L.ehs_server_submit.restype = ctypes.c_int
+    L.ehs_server_wait.argtypes = [vp, ctypes.c_uint64, dp, ctypes.POINTER(ServeStats)]
+    L.ehs_server_wait.restype = ctypes.c_int
+
+
+class ServeStats(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("slot", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("Mt", ctypes.c_int32), ("t_submit", ctypes.c_double), ("t_admit", ctypes.c_double),
+                ("t_start", ctypes.c_double), ("t_done", ctypes.c_double), ("bytes", ctypes.c_double)]
+
+
+def strerror(code: int) -> str:
+    return lib().ehs_strerror(int(code)).decode()
+
+
+def check(code: int) -> None:
+    if code != EHS_OK:
+        raise EhsError(code, strerror(code))
+
+
+def xi_for_cutoff(family, r_c: float, tol: float, L: float = 1.0) -> float:
+    """xi for which the real-space truncation estimate equals tol/2 (host arithmetic in the library)."""
+    fam = FAMILIES[family] if isinstance(family, str) else int(family)
+    return float(lib().ehs_xi_for_cutoff(fam, float(r_c), float(tol), float(L)))
+
+
+def plan_query(family, N, T, lo, hi, Q, xi, r_c, tol, precision=0) -> Report:
+    """The plan an evaluation would use (host arithmetic only; no GPU needed)."""
+    fam = FAMILIES[family] if isinstance(family, str) else int(family)
+    lo3 = (ctypes.c_double * 3)(*[float(v) for v in lo])
+    hi3 = (ctypes.c_double * 3)(*[float(v) for v in hi])
+    rep = Report()
+    check(lib().ehs_plan_query(fam, int(N), int(T), lo3, hi3, float(Q), float(xi), float(r_c), float(tol),
+                               int(precision), ctypes.byref(rep)))
+    return rep
+
+
+def truncated_kernel_hat(kind: int, k: float, R: float) -> float:
+    return float(lib().ehs_truncated_kernel_hat(int(kind), float(k), float(R)))
+
+
+def _stream_handle(stream=None):
+    import torch
+
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(int(s.cuda_stream))
+
+
+def _dev_ptr(t, name, cols):
+    import torch
+
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != torch.float64:
+        raise TypeError(f"{name} must be float64")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if t.dim() != 2 or t.shape[1] != cols:
+        raise ValueError(f"{name} must have shape (n, {cols})")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Context:
+    """An ehs_ctx on one HIP device (owns workspace and the kernel cache)."""
+
+    def __init__(self, device: int = 0):
+        self._h = ctypes.c_void_p()
+        check(lib().ehs_create(ctypes.byref(self._h), int(device), 0))
+        self.device = int(device)
+
+    def close(self):
+        if self._h:
+            lib().ehs_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_option(self, option: int, value: float) -> None:
+        check(lib().ehs_set_option(self._h, int(option), float(value)))
+
+    def evaluate(self, family, sources, strengths, targets, xi, r_c, tol, out=None, stream=None, report=False):
+        import torch
+
+        fam = FAMILIES[family] if isinstance(family, str) else int(family)
+        ncol = 6 if fam == STRESSLET else 3
+        ys = _dev_ptr(sources, "sources", 3)
+        ss = _dev_ptr(strengths, "strengths", ncol)
+        if strengths.shape[0] != sources.shape[0]:
+            raise ValueError("strengths and sources differ in length")
+        xs = _dev_ptr(targets, "targets", 3)
+        T = targets.shape[0]
+        if out is None:
+            out = torch.empty((T, 3), dtype=torch.float64, device=targets.device)
+        uo = _dev_ptr(out, "out", 3)
+        rep = Report()
+        fn = {STOKESLET: lib().ewald_halfspace_stokeslet, STRESSLET: lib().ewald_halfspace_stresslet,
+              ROTLET: lib().ewald_halfspace_rotlet}[fam]
+        rc = fn(self._h, ys, ss, int(sources.shape[0]), xs, int(T), float(xi), float(r_c), float(tol), uo,
+                _stream_handle(stream), ctypes.byref(rep))
+        check(rc)
+        return (out, rep) if report else out
+
+    def stokeslet(self, y, f, x, xi, r_c, tol, **kw):
+        return self.evaluate(STOKESLET, y, f, x, xi, r_c, tol, **kw)
+
+    def stresslet(self, y, gq, x, xi, r_c, tol, **kw):
+        return self.evaluate(STRESSLET, y, gq, x, xi, r_c, tol, **kw)
+
+    def rotlet(self, y, v, x, xi, r_c, tol, **kw):
+        return self.evaluate(ROTLET, y, v, x, xi, r_c, tol, **kw)
+
+    def debug_line_fft(self, x, inverse=False, stream=None):
+        """Unnormalised FFT along the last axis of a complex CUDA tensor (unit tests)."""
+        import torch
+
+        if not x.is_cuda or x.dtype not in (torch.complex128, torch.complex64):
+            raise TypeError("complex CUDA tensor expected")
+        x = x.contiguous()
+        n = x.shape[-1]
+        nl = x.numel() // n
+        out = torch.empty_like(x)
+        fp32 = 1 if x.dtype == torch.complex64 else 0
+        check(lib().ehs_debug_line_fft(self._h, n, nl, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                       1 if inverse else 0, fp32, _stream_handle(stream)))
+        return out
+
+
+_ctx = {}
+
+
+def default_context(device: int = 0) -> Context:
+    if device not in _ctx:
+        _ctx[device] = Context(device)
+    return _ctx[device]
+
+
+def stokeslet(y, f, x, xi, r_c, tol, **kw):
+    return default_context(y.device.index or 0).stokeslet(y, f, x, xi, r_c, tol, **kw)
+
+
+def stresslet(y, gq, x, xi, r_c, tol, **kw):
+    return default_context(y.device.index or 0).stresslet(y, gq, x, xi, r_c, tol, **kw)
+
+
+def rotlet(y, v, x, xi, r_c, tol, **kw):
+    return default_context(y.device.index or 0).rotlet(y, v, x, xi, r_c, tol, **kw)

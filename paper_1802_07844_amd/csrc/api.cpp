@@ -1,0 +1,724 @@
+// Host side of the C ABI: validation, parameter selection (plan), workspace,
+// the truncated-kernel cache and the stage-by-stage orchestration of one
+// half-space Ewald evaluation on a HIP stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <new>
+#include <utility>
+#include <vector>
+
+#include "../../include/ehs.h"
+#include "kernels.h"
+#include "plan.h"
+
+using namespace ehs;
+
+namespace {
+
+constexpr size_t ALIGN = 256;
+inline size_t al(size_t n) { return (n + ALIGN - 1) / ALIGN * ALIGN; }
+
+struct Octants {
+    double* B64 = nullptr;
+    double* H64 = nullptr;
+    float* B32 = nullptr;
+    float* H32 = nullptr;
+    int nf = 0, nf3 = 0;
+};
+
+}  // namespace
+
+struct ehs_ctx {
+    int device = 0;
+    void* ws = nullptr;
+    size_t ws_bytes = 0;
+    std::map<int, Octants> cache;                 // by M~
+    std::map<std::pair<int, int>, void*> tables;  // (n, 8 or 4 bytes) -> twiddle table
+    double* host_bbox = nullptr;                  // pinned, 16 doubles
+    hipEvent_t ev[EHS_NSTAGES + 1] = {};
+    bool ev_ok = false;
+    int opt_prec = 0, opt_timing = 0, force_M = 0, force_P = 0, force_Mt = 0;
+    double mem_cap = 0.0;
+};
+
+namespace {
+
+#define HIPCHK(x)                              \
+    do {                                       \
+        hipError_t e_ = (x);                   \
+        if (e_ != hipSuccess) return EHS_EHIP; \
+    } while (0)
+
+int tw_table(ehs_ctx* c, int n, int esz, void** out)
+{
+    auto key = std::make_pair(n, esz);
+    auto it = c->tables.find(key);
+    if (it != c->tables.end()) {
+        *out = it->second;
+        return EHS_OK;
+    }
+    std::vector<double> h(2 * (size_t)n);
+    const double tp = 6.283185307179586476925286766559;
+    for (int t = 0; t < n; ++t) {
+        // exp(-2 pi i t / n), reduced to the first half period for accuracy
+        double a = tp * (double)t / (double)n;
+        h[2 * t] = std::cos(a);
+        h[2 * t + 1] = -std::sin(a);
+    }
+    void* d = nullptr;
+    size_t bytes = (size_t)n * 2 * esz;
+    if (hipMalloc(&d, bytes) != hipSuccess) return EHS_ENOMEM;
+    if (esz == 8) {
+        if (hipMemcpy(d, h.data(), bytes, hipMemcpyHostToDevice) != hipSuccess) return EHS_EHIP;
+    } else {
+        std::vector<float> f(h.begin(), h.end());
+        if (hipMemcpy(d, f.data(), bytes, hipMemcpyHostToDevice) != hipSuccess) return EHS_EHIP;
+    }
+    c->tables[key] = d;
+    *out = d;
+    return EHS_OK;
+}
+
+int fft_plan(ehs_ctx* c, int n, int esz, FftPlanDev* p)
+{
+    std::vector<int> r;
+    if (!factor_radices(n, r) || (int)r.size() > FFT_MAX_STAGES) return EHS_ERANGE;
+    std::memset(p, 0, sizeof(*p));
+    p->n = n;
+    p->nst = (int)r.size();
+    for (size_t i = 0; i < r.size(); ++i) p->rad[i] = r[i];
+    void* t = nullptr;
+    int rc = tw_table(c, n, esz, &t);
+    if (rc) return rc;
+    p->tw = t;
+    return EHS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// truncated-kernel precompute (Sec. 5.2, the three precompute steps), in
+// units of L~ = 1, h = 1 / M~:
+//   sample K^R(|k|) on the oversampled grid (nf x nf x nf3, R = sqrt 6),
+//   inverse transform, keep the window |j1|, |j2| <= M~, |j3| <= 2 M~,
+//   forward transform on the 2M~ x 2M~ x 4M~ grid, keep the octant.
+// Every transform is a real even one done axis by axis on octant data.
+// ---------------------------------------------------------------------------
+int precompute_kind(ehs_ctx* c, int Mt, int nf, int nf3, int kind, double* scratch, double* oct, hipStream_t st)
+{
+    const long long h1 = nf / 2 + 1, m1 = Mt + 1, z1 = 2 * Mt + 1;
+    double* out1 = scratch;                // h1 x h1 x z1
+    double* out2 = scratch + h1 * h1 * z1; // h1 x m1 x z1
+    double* out3 = out1;                   // m1 x m1 x z1
+    double* out4 = out2;
+    double* out5 = out1;
+    FftPlanDev pf3, pf, p4, p2;
+    int rc;
+    if ((rc = fft_plan(c, nf3, 8, &pf3)) || (rc = fft_plan(c, nf, 8, &pf)) || (rc = fft_plan(c, 4 * Mt, 8, &p4)) ||
+        (rc = fft_plan(c, 2 * Mt, 8, &p2)))
+        return rc;
+    const double tp = 6.283185307179586476925286766559;
+    EvenArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.R = std::sqrt(6.0);
+    a.kind = kind;
+    a.dkg1 = tp * Mt / nf;
+    a.dkg3 = tp * Mt / nf3;
+    // P1: along n3, analytic input, lines (n1, n2)
+    a.n1 = (int)h1; a.n2 = (int)h1; a.f = pf3; a.generate = 1;
+    a.so1 = h1 * z1; a.so2 = z1; a.sk = 1; a.nkeep = (int)z1; a.scale = 1.0;
+    HIPCHK(launch_even_line(nullptr, out1, a, st));
+    // P2: along n2, lines (n1, j3)
+    a.generate = 0; a.f = pf; a.n1 = (int)h1; a.n2 = (int)z1;
+    a.si1 = h1 * z1; a.si2 = 1; a.st = z1;
+    a.so1 = m1 * z1; a.so2 = 1; a.sk = z1; a.nkeep = (int)m1;
+    HIPCHK(launch_even_line(out1, out2, a, st));
+    // P3: along n1, lines (j2, j3); normalisation of the inverse transform
+    a.n1 = (int)m1; a.n2 = (int)z1;
+    a.si1 = z1; a.si2 = 1; a.st = m1 * z1;
+    a.so1 = z1; a.so2 = 1; a.sk = m1 * z1; a.nkeep = (int)m1;
+    a.scale = 1.0 / ((double)nf * (double)nf * (double)nf3);
+    HIPCHK(launch_even_line(out2, out3, a, st));
+    // Q1: along j3 (period 4 M~), lines (j1, j2)
+    a.scale = 1.0; a.f = p4; a.n1 = (int)m1; a.n2 = (int)m1;
+    a.si1 = m1 * z1; a.si2 = z1; a.st = 1;
+    a.so1 = m1 * z1; a.so2 = z1; a.sk = 1; a.nkeep = (int)z1;
+    HIPCHK(launch_even_line(out3, out4, a, st));
+    // Q2: along j2 (period 2 M~), lines (j1, k3)
+    a.f = p2; a.n1 = (int)m1; a.n2 = (int)z1;
+    a.si1 = m1 * z1; a.si2 = 1; a.st = z1;
+    a.so1 = m1 * z1; a.so2 = 1; a.sk = z1; a.nkeep = (int)m1;
+    HIPCHK(launch_even_line(out4, out5, a, st));
+    // Q3: along j1, lines (k2, k3) -> octant [k1][k2][k3]
+    a.n1 = (int)m1; a.n2 = (int)z1;
+    a.si1 = z1; a.si2 = 1; a.st = m1 * z1;
+    a.so1 = z1; a.so2 = 1; a.sk = m1 * z1; a.nkeep = (int)m1;
+    HIPCHK(launch_even_line(out5, oct, a, st));
+    return EHS_OK;
+}
+
+int ensure_octants(ehs_ctx* c, const Plan& p, hipStream_t st, bool* ran, Octants** out)
+{
+    Octants& o = c->cache[p.Mt];
+    bool needB = p.family != EHS_ROTLET;
+    bool needH = true;
+    bool need32 = p.prec == 2;
+    const long long n = (long long)(p.Mt + 1) * (p.Mt + 1) * (2 * p.Mt + 1);
+    o.nf = p.nf;
+    o.nf3 = p.nf3;
+    *ran = false;
+    double* scratch = static_cast<double*>(c->ws);
+    for (int kind = 0; kind < 2; ++kind) {
+        bool need = kind == 0 ? needH : needB;
+        if (!need) continue;
+        double*& d64 = kind == 0 ? o.H64 : o.B64;
+        float*& d32 = kind == 0 ? o.H32 : o.B32;
+        if (!d64) {
+            if (hipMalloc((void**)&d64, n * sizeof(double)) != hipSuccess) {
+                d64 = nullptr;
+                return EHS_ENOMEM;
+            }
+            int rc = precompute_kind(c, p.Mt, p.nf, p.nf3, kind, scratch, d64, st);
+            if (rc) return rc;
+            *ran = true;
+        }
+        if (need32 && !d32) {
+            if (hipMalloc((void**)&d32, n * sizeof(float)) != hipSuccess) {
+                d32 = nullptr;
+                return EHS_ENOMEM;
+            }
+            HIPCHK(launch_oct_to_f32(d64, d32, n, st));
+            *ran = true;
+        }
+    }
+    if (*ran) HIPCHK(hipStreamSynchronize(st));
+    *out = &o;
+    return EHS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// workspace layout
+// ---------------------------------------------------------------------------
+struct Layout {
+    size_t X, Y, Zo, rec, keys, sortsc, toff, soff, tgoff, chunks, ys, ss, xs, upart, bb, total;
+};
+
+// Host-side audit: the largest extent every pass writes or reads must fit the
+// region it is given.  Returns 0 or EHS_ERANGE (never launches an
+// out-of-bounds kernel).
+int check_extents(const Plan& p, const Layout& L, size_t esz)
+{
+    const size_t Mt = p.Mt;
+    const size_t c = 2 * esz;
+    const size_t real = Mt * Mt * 2 * Mt * esz;
+    const size_t a = (Mt + 1) * 2 * Mt * Mt * c;
+    const size_t z = (Mt + 1) * 2 * Mt * 2 * Mt * c;
+    const size_t nin = (size_t)p.ncin;
+    const size_t xreg = L.Y - L.X, yreg = L.Zo - L.Y, zreg = L.rec - L.Zo;
+    auto fits = [](size_t need, size_t have) { return need <= have; };
+    bool ok = fits(nin * real, xreg)                  // spread -> X
+              && fits(nin * a, yreg)                  // forward x1 -> Y
+              && fits(nin * z, xreg)                  // forward x2 -> X
+              && fits(6 * z, p.resident ? xreg : zreg)  // fused x3 outputs
+              && fits(6 * a, yreg)                    // inverse x2 -> Y
+              && fits(6 * real, xreg)                 // inverse x1 -> X (read by the gather)
+              && fits((size_t)2 * p.N * record_stride(p.family, p.P, esz) * esz, L.keys - L.rec)
+              && fits((size_t)(4 * p.N + 4 * p.T + 8 * p.N) * 4, L.sortsc - L.keys)
+              && fits((size_t)(p.ntiles + 1) * 4, L.soff - L.toff)
+              && fits((size_t)(p.ncell + 1) * 4, L.tgoff - L.soff)
+              && fits((size_t)(p.ncell + 1) * 4, L.chunks - L.tgoff)
+              && fits((size_t)(2 * p.ncell + 2 * p.max_chunks + 1) * 4, L.ys - L.chunks)
+              && fits((size_t)3 * p.N * 8, L.ss - L.ys) && fits((size_t)6 * p.N * 8, L.xs - L.ss)
+              && fits((size_t)3 * p.T * 8, L.upart - L.xs) && fits((size_t)3 * p.T * 8, L.bb - L.upart);
+    // precompute scratch in X
+    size_t h1 = p.nf / 2 + 1;
+    ok = ok && fits((h1 * h1 * (2 * Mt + 1) + h1 * (Mt + 1) * (2 * Mt + 1)) * 8, xreg);
+    // the fused x3 pass holds lines of length 4Mt/Q for max(ncin, 6) components
+    int nq = 4 * p.Mt / p.Qz;
+    ok = ok && (4 * p.Mt) % p.Qz == 0 && z_lds_bytes(p.family, p.Mt, p.Qz, esz) <= 160 * 1024 &&
+         std::max(p.ncin, 6) * nq <= lds_fft_cap(nq, 512);
+    // x / y passes: B lines of Mt in LDS and in the 16-element register budget
+    ok = ok && p.Bx * p.Mt <= lds_fft_cap(p.Mt, 512) && p.By * p.Mt <= lds_fft_cap(p.Mt, 512) &&
+         p.Bx * p.Mt <= 16 * 512 && p.By * p.Mt <= 16 * 512 && (p.Bx % 2) == 0;
+    // gather weights table (3P <= 96) and spread support within the grid
+    ok = ok && 3 * p.P <= 96 && p.P <= p.Mt;
+    return ok ? EHS_OK : EHS_ERANGE;
+}
+
+Layout layout(const Plan& p, size_t esz)
+{
+    Layout L;
+    const long long Mt = p.Mt;
+    const int ncin = p.ncin;
+    const int nl = std::max(ncin, 6);
+    size_t cz = (size_t)(Mt + 1) * 2 * Mt * 2 * Mt * 2 * esz;  // one Z component (complex)
+    size_t cy = (size_t)(Mt + 1) * 2 * Mt * Mt * 2 * esz;      // one A / D component
+    size_t x_bytes = std::max((size_t)nl * cz, (size_t)ncin * (size_t)(Mt * Mt * 2 * Mt) * esz);
+    // the precompute scratch also lives in X
+    long long h1 = p.nf / 2 + 1;
+    size_t pre = (size_t)(h1 * h1 * (2 * Mt + 1) + h1 * (Mt + 1) * (2 * Mt + 1)) * sizeof(double);
+    x_bytes = std::max(x_bytes, pre);
+    size_t off = 0;
+    L.X = off; off += al(x_bytes);
+    L.Y = off; off += al((size_t)nl * cy);  // forward passes use ncin components, inverse passes 6
+    L.Zo = off; off += p.resident ? 0 : al((size_t)6 * cz);
+    long long N = p.N, T = p.T;
+    L.rec = off; off += al((size_t)2 * N * record_stride(p.family, p.P, esz) * esz);
+    // keys / values: sources (4 N), targets (4 T), points (4 * 2N)
+    L.keys = off; off += al((size_t)(4 * N + 4 * T + 8 * N) * sizeof(uint32_t));
+    L.sortsc = off; off += al(radix_sort_scratch_bytes(std::max(2 * N, T)) + scan_scratch_bytes(p.ncell + 1) + 1024);
+    L.toff = off; off += al((size_t)(p.ntiles + 1) * sizeof(uint32_t));
+    L.soff = off; off += al((size_t)(p.ncell + 1) * sizeof(uint32_t));
+    L.tgoff = off; off += al((size_t)(p.ncell + 1) * sizeof(uint32_t));
+    // chunk work list: counts, offsets (ncell each), cell + first (max_chunks each), count
+    L.chunks = off; off += al((size_t)(2 * p.ncell + 2 * p.max_chunks + 4) * sizeof(uint32_t));
+    L.ys = off; off += al((size_t)3 * N * sizeof(double));
+    L.ss = off; off += al((size_t)6 * N * sizeof(double));
+    L.xs = off; off += al((size_t)3 * T * sizeof(double));
+    L.upart = off; off += al((size_t)3 * T * sizeof(double));
+    L.bb = off; off += al((size_t)(1024 * 10 + 16) * sizeof(double));
+    L.total = off;
+    return L;
+}
+
+int ensure_ws(ehs_ctx* c, size_t bytes, hipStream_t st)
+{
+    if (c->mem_cap > 0 && (double)bytes > c->mem_cap) return EHS_ENOMEM;
+    if (bytes <= c->ws_bytes) return EHS_OK;
+    HIPCHK(hipStreamSynchronize(st));
+    if (c->ws) hipFree(c->ws);
+    c->ws = nullptr;
+    c->ws_bytes = 0;
+    if (hipMalloc(&c->ws, bytes) != hipSuccess) {
+        c->ws = nullptr;
+        hipGetLastError();
+        return EHS_ENOMEM;
+    }
+    c->ws_bytes = bytes;
+    return EHS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// one evaluation
+// ---------------------------------------------------------------------------
+template <typename T>
+int run(ehs_ctx* c, Plan& p, const double* y, const double* s, const double* x, double* u, hipStream_t st,
+        ehs_report* rep, bool alias)
+{
+    const size_t esz = sizeof(T);
+    Layout Lo = layout(p, esz);
+    int rc = check_extents(p, Lo, esz);
+    if (rc) return rc;
+    rc = ensure_ws(c, Lo.total, st);
+    if (rc) return rc;
+    char* base = static_cast<char*>(c->ws);
+    auto rec_ev = [&](int i) {
+        if (c->opt_timing && c->ev_ok) hipEventRecord(c->ev[i], st);
+    };
+    rec_ev(EHS_ST_PRECOMP);
+    bool ran = false;
+    Octants* oct = nullptr;
+    rc = ensure_octants(c, p, st, &ran, &oct);
+    if (rc) return rc;
+    if (ran) p.warnings |= 2;
+    rec_ev(EHS_ST_BIN);
+
+    const long long N = p.N, TT = p.T;
+    uint32_t* kbase = reinterpret_cast<uint32_t*>(base + Lo.keys);
+    uint32_t *ks = kbase, *vs = ks + N, *ks2 = vs + N, *vs2 = ks2 + N;
+    uint32_t *kt = vs2 + N, *vt = kt + TT, *kt2 = vt + TT, *vt2 = kt2 + TT;
+    uint32_t *kp = vt2 + TT, *vp = kp + 2 * N, *kp2 = vp + 2 * N, *vp2 = kp2 + 2 * N;
+    void* sortsc = base + Lo.sortsc;
+    uint32_t* toff = reinterpret_cast<uint32_t*>(base + Lo.toff);
+    uint32_t* soff = reinterpret_cast<uint32_t*>(base + Lo.soff);
+    uint32_t* tgoff = reinterpret_cast<uint32_t*>(base + Lo.tgoff);
+    uint32_t* ch = reinterpret_cast<uint32_t*>(base + Lo.chunks);
+    uint32_t *ch_counts = ch, *ch_offs = ch + p.ncell, *ch_cell = ch_offs + p.ncell,
+             *ch_first = ch_cell + p.max_chunks, *ch_n = ch_first + p.max_chunks;
+    double* ys = reinterpret_cast<double*>(base + Lo.ys);
+    double* ss = reinterpret_cast<double*>(base + Lo.ss);
+    double* xs = reinterpret_cast<double*>(base + Lo.xs);
+    double* upart = reinterpret_cast<double*>(base + Lo.upart);
+
+    // -- real-space binning: sort sources (and targets) by cell
+    int cbits = bits_for(p.ncell);
+    uint32_t *sk, *sperm;
+    HIPCHK(launch_cell_keys(y, N, p.cg, ks, vs, st));
+    HIPCHK(radix_sort(ks, vs, ks2, vs2, N, cbits, sortsc, st, &sk, &sperm));
+    HIPCHK(launch_cell_ranges(sk, N, soff, nullptr, p.ncell, st));
+    HIPCHK(launch_gather_sources(p.family, y, s, sperm, N, ys, ss, st));
+    uint32_t *tk, *tperm;
+    if (alias) {
+        tk = sk;
+        tperm = sperm;
+        HIPCHK(hipMemcpyAsync(tgoff, soff, (p.ncell + 1) * sizeof(uint32_t), hipMemcpyDeviceToDevice, st));
+    } else {
+        HIPCHK(launch_cell_keys(x, TT, p.cg, kt, vt, st));
+        HIPCHK(radix_sort(kt, vt, kt2, vt2, TT, cbits, sortsc, st, &tk, &tperm));
+        HIPCHK(launch_cell_ranges(tk, TT, tgoff, nullptr, p.ncell, st));
+    }
+    HIPCHK(launch_gather_points(x, tperm, TT, xs, st));
+    HIPCHK(launch_chunks(tgoff, nullptr, p.ncell, ch_counts, ch_offs, sortsc, ch_cell, ch_first, ch_n, st));
+    rec_ev(EHS_ST_REAL);
+
+    // -- real-space sum
+    RealArgs ra;
+    ra.cg = p.cg;
+    ra.N = N;
+    ra.T = TT;
+    ra.xi = p.xi;
+    ra.rc2 = p.rc * p.rc;
+    ra.src_off = soff;
+    ra.tgt_off = tgoff;
+    ra.chunk_cell = ch_cell;
+    ra.chunk_first = ch_first;
+    ra.nchunks = ch_n;
+    ra.tgt_perm = tperm;
+    HIPCHK(launch_realspace<T>(p.family, ra, ys, ss, xs, upart, p.max_chunks, st));
+    rec_ev(EHS_ST_SPREAD);
+
+    // -- spreading
+    T* X = reinterpret_cast<T*>(base + Lo.X);
+    cplx<T>* Xc = reinterpret_cast<cplx<T>*>(base + Lo.X);
+    cplx<T>* Yc = reinterpret_cast<cplx<T>*>(base + Lo.Y);
+    cplx<T>* Zo = p.resident ? Xc : reinterpret_cast<cplx<T>*>(base + Lo.Zo);
+    T* rec = reinterpret_cast<T*>(base + Lo.rec);
+    uint32_t *pk, *pperm;
+    HIPCHK(launch_point_keys(y, N, p.g, kp, vp, st));
+    HIPCHK(radix_sort(kp, vp, kp2, vp2, 2 * N, bits_for(p.ntiles), sortsc, st, &pk, &pperm));
+    HIPCHK(launch_cell_ranges(pk, 2 * N, toff, nullptr, p.ntiles, st));
+    HIPCHK(launch_records<T>(p.family, y, s, pperm, N, p.g, rec, st));
+    const long long Mt = p.Mt;
+    const long long csR = Mt * Mt * 2 * Mt;          // real grid component
+    const long long csA = (Mt + 1) * 2 * Mt * Mt;    // A / D component (complex)
+    const long long csZ = (Mt + 1) * 2 * Mt * 2 * Mt;  // Z component (complex)
+    HIPCHK(launch_spread<T>(p.family, p.g, rec, toff, X, csR, st));
+    rec_ev(EHS_ST_FWDX);
+
+    // -- forward transforms
+    PassArgs pa;
+    std::memset(&pa, 0, sizeof(pa));
+    pa.Mt = p.Mt;
+    void* tw2 = nullptr;
+    if ((rc = tw_table(c, 2 * p.Mt, (int)esz, &tw2))) return rc;
+    pa.tw2 = tw2;
+    if ((rc = fft_plan(c, p.Mt, (int)esz, &pa.fM))) return rc;
+    pa.B = p.Bx;
+    pa.cs_in = csR;
+    pa.cs_out = csA;
+    HIPCHK(launch_fwd_x<T>(X, Yc, pa, p.ncin, st));
+    rec_ev(EHS_ST_FWDY);
+    pa.B = p.By;
+    pa.cs_in = csA;
+    pa.cs_out = csZ;
+    HIPCHK(launch_fwd_y<T>(Yc, Xc, pa, p.ncin, st));
+    rec_ev(EHS_ST_ZSCALE);
+
+    // -- fused x3 transform + scaling + inverse x3 transform
+    ZArgs za;
+    std::memset(&za, 0, sizeof(za));
+    za.Mt = p.Mt;
+    za.Q = p.Qz;
+    za.cs = csZ;
+    za.cs_out = csZ;
+    void* tw4 = nullptr;
+    if ((rc = tw_table(c, 4 * p.Mt, (int)esz, &tw4))) return rc;
+    za.tw4 = tw4;
+    if ((rc = fft_plan(c, 4 * p.Mt / p.Qz, (int)esz, &za.fq))) return rc;
+    const double pi = 3.14159265358979323846;
+    za.dk12 = pi / p.Lt;
+    za.dk3 = pi / (2.0 * p.Lt);
+    za.c_exp = (1.0 - p.eta) / (4.0 * p.xi * p.xi);
+    za.c_has = 1.0 / (4.0 * p.xi * p.xi);
+    double npad = 16.0 * (double)Mt * (double)Mt * (double)Mt;
+    za.cB = std::pow(p.Lt, 4) / npad;
+    za.cH = p.Lt * p.Lt / npad;
+    za.octB64 = oct->B64;
+    za.octH64 = oct->H64;
+    za.octB32 = oct->B32;
+    za.octH32 = oct->H32;
+    za.near0 = 2;
+    HIPCHK(launch_z<T>(p.family, Xc, Zo, za, p.resident, st));
+    rec_ev(EHS_ST_INVY);
+
+    // -- inverse transforms
+    pa.B = p.By;
+    pa.cs_in = csZ;
+    pa.cs_out = csA;
+    HIPCHK(launch_inv_y<T>(Zo, Yc, pa, 6, st));
+    rec_ev(EHS_ST_INVX);
+    pa.B = p.Bx;
+    pa.cs_in = csA;
+    pa.cs_out = csR;
+    HIPCHK(launch_inv_x<T>(Yc, X, pa, 6, st));
+    rec_ev(EHS_ST_GATHER);
+
+    // -- quadrature at the targets and FP64 combination with the real part
+    HIPCHK(launch_gather<T>(p.g, X, csR, xs, tperm, TT, upart, u, st));
+    rec_ev(EHS_ST_TOTAL);
+    (void)rep;
+    return EHS_OK;
+}
+
+int validate_and_plan(ehs_ctx* c, int family, const double* y, const double* s, int64_t N, const double* x, int64_t T,
+                      double xi, double rc, double tol, hipStream_t st, Plan* p)
+{
+    if (!y || !s || N < 1 || T < 0 || (T > 0 && !x)) return EHS_EINVAL;
+    if (!(xi > 0) || !(rc > 0) || !std::isfinite(xi) || !std::isfinite(rc)) return EHS_EINVAL;
+    if (!(tol >= 1e-14 && tol <= 1e-2)) return EHS_EINVAL;
+    if (N >= (1LL << 30) || T >= (1LL << 31)) return EHS_EINVAL;
+    // bounding box, validation and Q (one readback)
+    char* base = static_cast<char*>(c->ws);
+    size_t need = al((size_t)(1024 * 10 + 16) * sizeof(double));
+    int rc0 = ensure_ws(c, std::max(need, c->ws_bytes), st);
+    if (rc0) return rc0;
+    base = static_cast<char*>(c->ws);
+    double* partial = reinterpret_cast<double*>(base);
+    double* out16 = partial + 1024 * 10;
+    int nb = bbox_blocks(N + T);
+    HIPCHK(launch_bbox(family, y, s, N, x, T, partial, nb, out16, st));
+    HIPCHK(hipMemcpyAsync(c->host_bbox, out16, 16 * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    const double* b = c->host_bbox;
+    if (b[8] > 0) return EHS_EDOMAIN;
+    if (!(b[6] > 0)) return EHS_EDOMAIN;
+    if (T > 0 && !(b[7] >= 0)) return EHS_EDOMAIN;
+    PlanInput in;
+    in.family = family;
+    in.N = N;
+    in.T = T;
+    in.xi = xi;
+    in.rc = rc;
+    in.tol = tol;
+    for (int a = 0; a < 3; ++a) {
+        in.lo[a] = b[a];
+        in.hi[a] = b[3 + a];
+    }
+    in.Q = b[9];
+    in.prec = c->opt_prec;
+    in.force_M = c->force_M;
+    in.force_P = c->force_P;
+    in.force_Mt = c->force_Mt;
+    return make_plan(in, p);
+}
+
+void fill_report(const Plan& p, ehs_report* r)
+{
+    std::memset(r, 0, sizeof(*r));
+    r->M = p.M;
+    r->P = p.P;
+    r->Mt = p.Mt;
+    r->precision = p.prec;
+    r->Q = p.Qz;
+    r->nf = p.nf;
+    r->nf3 = p.nf3;
+    r->warnings = p.warnings;
+    for (int a = 0; a < 3; ++a) {
+        r->ncell[a] = p.cg.nc[a];
+        r->origin[a] = p.g.o[a];
+    }
+    r->family = p.family;
+    r->L = p.L;
+    r->h = p.h;
+    r->Lt = p.Lt;
+    r->eta = p.eta;
+    r->xi = p.xi;
+    r->r_c = p.rc;
+    r->tol = p.tol;
+    r->est_real = p.est_r;
+    r->est_fourier = p.est_f;
+}
+
+int evaluate(ehs_ctx* c, int family, const double* y, const double* s, int64_t N, const double* x, int64_t T,
+             double xi, double rc, double tol, double* u, void* stream, ehs_report* rep)
+{
+    if (!c) return EHS_EINVAL;
+    if (T > 0 && !u) return EHS_EINVAL;
+    if (hipSetDevice(c->device) != hipSuccess) return EHS_EHIP;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (c->opt_timing && !c->ev_ok) {
+        bool ok = true;
+        for (int i = 0; i <= EHS_NSTAGES; ++i) ok = ok && hipEventCreate(&c->ev[i]) == hipSuccess;
+        c->ev_ok = ok;
+    }
+    if (c->opt_timing && c->ev_ok) hipEventRecord(c->ev[EHS_ST_BBOX], st);
+    Plan p;
+    int rc0 = validate_and_plan(c, family, y, s, N, x, T, xi, rc, tol, st, &p);
+    if (rc0) return rc0;
+    if (T == 0) {
+        if (rep) fill_report(p, rep);
+        return EHS_OK;
+    }
+    bool alias = (x == y) && (T == N);
+    int r = (p.prec == 1) ? run<double>(c, p, y, s, x, u, st, rep, alias) : run<float>(c, p, y, s, x, u, st, rep, alias);
+    if (r) return r;
+    if (rep) {
+        fill_report(p, rep);
+        rep->workspace_bytes = (double)c->ws_bytes;
+        if (c->opt_timing && c->ev_ok) {
+            if (hipEventSynchronize(c->ev[EHS_ST_TOTAL]) != hipSuccess) return EHS_EHIP;
+            for (int i = 0; i < EHS_ST_TOTAL; ++i) {
+                float ms = 0.f;
+                hipEventElapsedTime(&ms, c->ev[i], c->ev[i + 1]);
+                rep->ms_stage[i] = ms;
+            }
+            float tot = 0.f;
+            hipEventElapsedTime(&tot, c->ev[EHS_ST_BBOX], c->ev[EHS_ST_TOTAL]);
+            rep->ms_stage[EHS_ST_TOTAL] = tot;
+        }
+    }
+    return EHS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ehs_create(ehs_ctx** out, int hip_device, size_t arena_bytes)
+{
+    (void)arena_bytes;
+    if (!out) return EHS_EINVAL;
+    *out = nullptr;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || hip_device < 0 || hip_device >= n) return EHS_EINVAL;
+    if (hipSetDevice(hip_device) != hipSuccess) return EHS_EHIP;
+    ehs_ctx* c = new (std::nothrow) ehs_ctx();
+    if (!c) return EHS_ENOMEM;
+    c->device = hip_device;
+    if (hipHostMalloc((void**)&c->host_bbox, 16 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+        delete c;
+        return EHS_ENOMEM;
+    }
+    *out = c;
+    return EHS_OK;
+}
+
+void ehs_destroy(ehs_ctx* c)
+{
+    if (!c) return;
+    hipSetDevice(c->device);
+    hipDeviceSynchronize();
+    if (c->ws) hipFree(c->ws);
+    for (auto& kv : c->cache) {
+        if (kv.second.B64) hipFree(kv.second.B64);
+        if (kv.second.H64) hipFree(kv.second.H64);
+        if (kv.second.B32) hipFree(kv.second.B32);
+        if (kv.second.H32) hipFree(kv.second.H32);
+    }
+    for (auto& kv : c->tables) hipFree(kv.second);
+    if (c->ev_ok)
+        for (int i = 0; i <= EHS_NSTAGES; ++i) hipEventDestroy(c->ev[i]);
+    if (c->host_bbox) hipHostFree(c->host_bbox);
+    delete c;
+}
+
+int ehs_set_option(ehs_ctx* c, int option, double value)
+{
+    if (!c) return EHS_EINVAL;
+    switch (option) {
+        case EHS_OPT_PRECISION:
+            if (value != 0 && value != 1 && value != 2) return EHS_EINVAL;
+            c->opt_prec = (int)value;
+            return EHS_OK;
+        case EHS_OPT_TIMING: c->opt_timing = value != 0; return EHS_OK;
+        case EHS_OPT_FORCE_M: c->force_M = (int)value; return EHS_OK;
+        case EHS_OPT_FORCE_P: c->force_P = (int)value; return EHS_OK;
+        case EHS_OPT_FORCE_MT: c->force_Mt = (int)value; return EHS_OK;
+        case EHS_OPT_MEM_CAP: c->mem_cap = value; return EHS_OK;
+        default: return EHS_EINVAL;
+    }
+}
+
+int ewald_halfspace_stokeslet(ehs_ctx* c, const double* sources, const double* f, int64_t N, const double* targets,
+                              int64_t T, double xi, double r_c, double tol, double* u_out, void* stream,
+                              ehs_report* rep)
+{
+    return evaluate(c, EHS_STOKESLET, sources, f, N, targets, T, xi, r_c, tol, u_out, stream, rep);
+}
+
+int ewald_halfspace_stresslet(ehs_ctx* c, const double* sources, const double* gq, int64_t N, const double* targets,
+                              int64_t T, double xi, double r_c, double tol, double* u_out, void* stream,
+                              ehs_report* rep)
+{
+    return evaluate(c, EHS_STRESSLET, sources, gq, N, targets, T, xi, r_c, tol, u_out, stream, rep);
+}
+
+int ewald_halfspace_rotlet(ehs_ctx* c, const double* sources, const double* v, int64_t N, const double* targets,
+                           int64_t T, double xi, double r_c, double tol, double* u_out, void* stream, ehs_report* rep)
+{
+    return evaluate(c, EHS_ROTLET, sources, v, N, targets, T, xi, r_c, tol, u_out, stream, rep);
+}
+
+const char* ehs_strerror(int code)
+{
+    switch (code) {
+        case EHS_OK: return "success";
+        case EHS_EINVAL: return "invalid argument (null pointer, size or parameter out of range)";
+        case EHS_EDOMAIN: return "point outside the half space (source y3 <= 0, target x3 < 0) or non-finite input";
+        case EHS_ERANGE: return "no admissible grid for the requested accuracy";
+        case EHS_ENOMEM: return "device memory exhausted or above the memory cap";
+        case EHS_EHIP: return "HIP runtime error";
+        default: return "unknown error";
+    }
+}
+
+double ehs_xi_for_cutoff(int family, double r_c, double tol, double L) { return xi_for_cutoff(family, r_c, tol, L); }
+
+int ehs_plan_query(int family, int64_t N, int64_t T, const double* lo, const double* hi, double Q, double xi,
+                   double r_c, double tol, int precision, ehs_report* rep)
+{
+    if (!lo || !hi || !rep || family < 0 || family > 2 || N < 1 || T < 0) return EHS_EINVAL;
+    if (!(xi > 0) || !(r_c > 0) || !(tol >= 1e-14 && tol <= 1e-2)) return EHS_EINVAL;
+    PlanInput in;
+    std::memset(&in, 0, sizeof(in));
+    in.family = family;
+    in.N = N;
+    in.T = T;
+    in.xi = xi;
+    in.rc = r_c;
+    in.tol = tol;
+    for (int a = 0; a < 3; ++a) {
+        in.lo[a] = lo[a];
+        in.hi[a] = hi[a];
+    }
+    in.Q = Q;
+    in.prec = precision;
+    Plan p;
+    int rc = make_plan(in, &p);
+    if (rc) return rc;
+    fill_report(p, rep);
+    Layout Lo = layout(p, p.prec == 1 ? 8 : 4);
+    rc = check_extents(p, Lo, p.prec == 1 ? 8 : 4);
+    if (rc) return rc;
+    rep->workspace_bytes = (double)Lo.total;
+    return EHS_OK;
+}
+
+double ehs_truncated_kernel_hat(int kind, double k, double R) { return khat_truncated(kind, k, R); }
+
+int ehs_debug_line_fft(ehs_ctx* c, int n, int nl, const void* in, void* out, int inverse, int fp32, void* stream)
+{
+    if (!c || !in || !out || n < 1 || nl < 1) return EHS_EINVAL;
+    if (hipSetDevice(c->device) != hipSuccess) return EHS_EHIP;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    FftPlanDev p;
+    int esz = fp32 ? 4 : 8;
+    int rc = fft_plan(c, n, esz, &p);
+    if (rc) return rc;
+    int cap = lds_fft_cap(n, 512);
+    int per = std::max(1, std::min(cap / n, 16));
+    if (n > cap) return EHS_ERANGE;
+    if ((size_t)per * (n + 1) * 2 * esz > 160 * 1024) per = std::max(1, (int)(160 * 1024 / ((n + 1) * 2 * esz)));
+    if (fp32)
+        HIPCHK(launch_line_fft<float>(static_cast<const cplx<float>*>(in), static_cast<cplx<float>*>(out), nl, per, p,
+                                      inverse != 0, st));
+    else
+        HIPCHK(launch_line_fft<double>(static_cast<const cplx<double>*>(in), static_cast<cplx<double>*>(out), nl, per,
+                                       p, inverse != 0, st));
+    return EHS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,308 @@
+// Shared device-side helpers of the MI355X half-space spectral Ewald library:
+// complex arithmetic, the kernel-family traits and the LDS-resident mixed-radix
+// Stockham FFT used by every transform pass.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ehs {
+
+// ---------------------------------------------------------------------------
+// complex numbers (interleaved re, im)
+// ---------------------------------------------------------------------------
+template <typename T>
+struct alignas(2 * sizeof(T)) cplx {
+    T x, y;
+};
+
+template <typename T>
+__host__ __device__ __forceinline__ cplx<T> cmk(T a, T b)
+{
+    cplx<T> r;
+    r.x = a;
+    r.y = b;
+    return r;
+}
+template <typename T>
+__host__ __device__ __forceinline__ cplx<T> cadd(cplx<T> a, cplx<T> b) { return cmk<T>(a.x + b.x, a.y + b.y); }
+template <typename T>
+__host__ __device__ __forceinline__ cplx<T> csub(cplx<T> a, cplx<T> b) { return cmk<T>(a.x - b.x, a.y - b.y); }
+template <typename T>
+__host__ __device__ __forceinline__ cplx<T> cmul(cplx<T> a, cplx<T> b)
+{
+    return cmk<T>(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+template <typename T>
+__host__ __device__ __forceinline__ cplx<T> cconj(cplx<T> a) { return cmk<T>(a.x, -a.y); }
+template <typename T>
+__host__ __device__ __forceinline__ cplx<T> cscale(cplx<T> a, T s) { return cmk<T>(a.x * s, a.y * s); }
+// multiply by -i
+template <typename T>
+__host__ __device__ __forceinline__ cplx<T> cmul_mi(cplx<T> a) { return cmk<T>(a.y, -a.x); }
+// multiply by +i
+template <typename T>
+__host__ __device__ __forceinline__ cplx<T> cmul_pi(cplx<T> a) { return cmk<T>(-a.y, a.x); }
+
+// ---------------------------------------------------------------------------
+// kernel families and their grid-component counts
+//   A-grids: the 2N consolidated sources (sources and their wall images);
+//   B-grids: the correction sources, centred at the images only.
+// ---------------------------------------------------------------------------
+enum Family { STOKESLET = 0, STRESSLET = 1, ROTLET = 2 };
+
+template <int K>
+struct Traits;
+template <>
+struct Traits<STOKESLET> {
+    static constexpr int nstr = 3;  // f
+    static constexpr int ncA = 3;   // f at y, -f^I at y^I
+    static constexpr int ncB = 4;   // f3 and y3 f^I at y^I
+};
+template <>
+struct Traits<STRESSLET> {
+    static constexpr int nstr = 6;  // (g, q)
+    static constexpr int ncA = 6;   // sym(g q) at y, -R sym(g q) R at y^I
+    static constexpr int ncB = 7;   // g.q and y3 R sym(g q) R at y^I
+};
+template <>
+struct Traits<ROTLET> {
+    static constexpr int nstr = 3;  // torque v = g x q
+    static constexpr int ncA = 3;   // v at y, v^I at y^I
+    static constexpr int ncB = 2;   // w = 2(-v2, v1) at y^I
+};
+constexpr int NCOUT = 6;  // Y1 (3) and Y2 (3)
+
+// ---------------------------------------------------------------------------
+// FFT plan for one line length: radices (each 2,3,4,5,7 or 8) and the
+// twiddle table tw[t] = exp(-2 pi i t / n), t < n, in device memory.
+// ---------------------------------------------------------------------------
+constexpr int FFT_MAX_STAGES = 24;
+struct FftPlanDev {
+    int n;
+    int nst;
+    int rad[FFT_MAX_STAGES];
+    const void* tw;  // cplx<T>*
+};
+
+// radix-R DFT in registers, forward sign exp(-2 pi i k q / R)
+template <typename T, int R>
+struct Dft;
+
+template <typename T>
+struct Dft<T, 2> {
+    __device__ __forceinline__ static void run(cplx<T>* v)
+    {
+        cplx<T> a = v[0], b = v[1];
+        v[0] = cadd(a, b);
+        v[1] = csub(a, b);
+    }
+};
+template <typename T>
+struct Dft<T, 4> {
+    __device__ __forceinline__ static void run(cplx<T>* v)
+    {
+        cplx<T> a0 = cadd(v[0], v[2]), a1 = csub(v[0], v[2]);
+        cplx<T> b0 = cadd(v[1], v[3]), b1 = cmul_mi(csub(v[1], v[3]));
+        v[0] = cadd(a0, b0);
+        v[2] = csub(a0, b0);
+        v[1] = cadd(a1, b1);
+        v[3] = csub(a1, b1);
+    }
+};
+template <typename T>
+struct Dft<T, 8> {
+    __device__ __forceinline__ static void run(cplx<T>* v)
+    {
+        const T s = (T)0.70710678118654752440;
+        // two radix-4 on even/odd, then combine
+        cplx<T> e[4] = {v[0], v[2], v[4], v[6]};
+        cplx<T> o[4] = {v[1], v[3], v[5], v[7]};
+        Dft<T, 4>::run(e);
+        Dft<T, 4>::run(o);
+        // twiddles exp(-2 pi i k / 8), k = 0..3
+        cplx<T> t1 = cmk<T>(s * (o[1].x + o[1].y), s * (o[1].y - o[1].x));
+        cplx<T> t2 = cmul_mi(o[2]);
+        cplx<T> t3 = cmk<T>(s * (o[3].y - o[3].x), -s * (o[3].x + o[3].y));
+        v[0] = cadd(e[0], o[0]);
+        v[4] = csub(e[0], o[0]);
+        v[1] = cadd(e[1], t1);
+        v[5] = csub(e[1], t1);
+        v[2] = cadd(e[2], t2);
+        v[6] = csub(e[2], t2);
+        v[3] = cadd(e[3], t3);
+        v[7] = csub(e[3], t3);
+    }
+};
+template <typename T>
+struct Dft<T, 3> {
+    __device__ __forceinline__ static void run(cplx<T>* v)
+    {
+        const T c1 = (T)-0.5;
+        const T s1 = (T)0.86602540378443864676;  // sin(2 pi / 3)
+        cplx<T> a = cadd(v[1], v[2]), d = csub(v[1], v[2]);
+        cplx<T> m = cmk<T>(v[0].x + c1 * a.x, v[0].y + c1 * a.y);
+        cplx<T> t = cmk<T>(s1 * d.y, -s1 * d.x);  // -i s1 d
+        v[0] = cadd(v[0], a);
+        v[1] = cadd(m, t);
+        v[2] = csub(m, t);
+    }
+};
+template <typename T>
+struct Dft<T, 5> {
+    __device__ __forceinline__ static void run(cplx<T>* v)
+    {
+        const T c1 = (T)0.30901699437494742410;   // cos(2 pi / 5)
+        const T c2 = (T)-0.80901699437494742410;  // cos(4 pi / 5)
+        const T s1 = (T)0.95105651629515357212;   // sin(2 pi / 5)
+        const T s2 = (T)0.58778525229247312917;   // sin(4 pi / 5)
+        cplx<T> a1 = cadd(v[1], v[4]), d1 = csub(v[1], v[4]);
+        cplx<T> a2 = cadd(v[2], v[3]), d2 = csub(v[2], v[3]);
+        cplx<T> m1 = cmk<T>(v[0].x + c1 * a1.x + c2 * a2.x, v[0].y + c1 * a1.y + c2 * a2.y);
+        cplx<T> m2 = cmk<T>(v[0].x + c2 * a1.x + c1 * a2.x, v[0].y + c2 * a1.y + c1 * a2.y);
+        // -i (s1 d1 + s2 d2) and -i (s2 d1 - s1 d2)
+        cplx<T> t1 = cmk<T>(s1 * d1.y + s2 * d2.y, -(s1 * d1.x + s2 * d2.x));
+        cplx<T> t2 = cmk<T>(s2 * d1.y - s1 * d2.y, -(s2 * d1.x - s1 * d2.x));
+        v[0] = cadd(v[0], cadd(a1, a2));
+        v[1] = cadd(m1, t1);
+        v[4] = csub(m1, t1);
+        v[2] = cadd(m2, t2);
+        v[3] = csub(m2, t2);
+    }
+};
+template <typename T>
+struct Dft<T, 7> {
+    __device__ __forceinline__ static void run(cplx<T>* v)
+    {
+        const T c1 = (T)0.62348980185873353053;   // cos(2 pi / 7)
+        const T c2 = (T)-0.22252093395631440429;  // cos(4 pi / 7)
+        const T c3 = (T)-0.90096886790241912624;  // cos(6 pi / 7)
+        const T s1 = (T)0.78183148246802980871;   // sin(2 pi / 7)
+        const T s2 = (T)0.97492791218182360702;   // sin(4 pi / 7)
+        const T s3 = (T)0.43388373911755812048;   // sin(6 pi / 7)
+        cplx<T> a1 = cadd(v[1], v[6]), d1 = csub(v[1], v[6]);
+        cplx<T> a2 = cadd(v[2], v[5]), d2 = csub(v[2], v[5]);
+        cplx<T> a3 = cadd(v[3], v[4]), d3 = csub(v[3], v[4]);
+        cplx<T> m1 = cmk<T>(v[0].x + c1 * a1.x + c2 * a2.x + c3 * a3.x, v[0].y + c1 * a1.y + c2 * a2.y + c3 * a3.y);
+        cplx<T> m2 = cmk<T>(v[0].x + c2 * a1.x + c3 * a2.x + c1 * a3.x, v[0].y + c2 * a1.y + c3 * a2.y + c1 * a3.y);
+        cplx<T> m3 = cmk<T>(v[0].x + c3 * a1.x + c1 * a2.x + c2 * a3.x, v[0].y + c3 * a1.y + c1 * a2.y + c2 * a3.y);
+        // sin(2 pi k q / 7) for (k,q): row k=1: s1 s2 s3; k=2: s2 -s3 -s1; k=3: s3 -s1 s2
+        cplx<T> p1 = cmk<T>(s1 * d1.x + s2 * d2.x + s3 * d3.x, s1 * d1.y + s2 * d2.y + s3 * d3.y);
+        cplx<T> p2 = cmk<T>(s2 * d1.x - s3 * d2.x - s1 * d3.x, s2 * d1.y - s3 * d2.y - s1 * d3.y);
+        cplx<T> p3 = cmk<T>(s3 * d1.x - s1 * d2.x + s2 * d3.x, s3 * d1.y - s1 * d2.y + s2 * d3.y);
+        v[0] = cadd(v[0], cadd(a1, cadd(a2, a3)));
+        v[1] = cadd(m1, cmul_mi(p1));
+        v[6] = csub(m1, cmul_mi(p1));
+        v[2] = cadd(m2, cmul_mi(p2));
+        v[5] = csub(m2, cmul_mi(p2));
+        v[3] = cadd(m3, cmul_mi(p3));
+        v[4] = csub(m3, cmul_mi(p3));
+    }
+};
+
+// One Stockham stage of radix R on `nl` lines of length n held in LDS
+// (line q at buf + q * ld).  Every thread of the block calls it; each thread
+// handles up to E/R butterflies held in registers between the two barriers.
+template <typename T, int NT, int E, int R, bool INV>
+__device__ __forceinline__ void fft_stage(cplx<T>* buf, int ld, int nl, int n, int Ns, const cplx<T>* tw)
+{
+    constexpr int MB = (E / R) > 0 ? (E / R) : 1;
+    const int nb = n / R;
+    const int total = nl * nb;
+    const int tstride = n / (Ns * R);
+    cplx<T> v[MB][R];
+    int base[MB];
+#pragma unroll
+    for (int i = 0; i < MB; ++i) {
+        int b = threadIdx.x + i * NT;
+        base[i] = -1;
+        if (b < total) {
+            int line = b / nb;
+            int j = b - line * nb;
+            const cplx<T>* src = buf + line * ld + j;
+#pragma unroll
+            for (int q = 0; q < R; ++q) {
+                cplx<T> a = src[q * nb];
+                v[i][q] = INV ? cconj(a) : a;
+            }
+            int k = j % Ns;
+            if (k != 0) {
+                cplx<T> w1 = tw[k * tstride];
+                cplx<T> w = w1;
+#pragma unroll
+                for (int q = 1; q < R; ++q) {
+                    v[i][q] = cmul(v[i][q], w);
+                    if (q + 1 < R) w = cmul(w, w1);
+                }
+            }
+            Dft<T, R>::run(v[i]);
+            base[i] = line * ld + (j / Ns) * Ns * R + k;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < MB; ++i) {
+        if (base[i] >= 0) {
+            cplx<T>* dst = buf + base[i];
+#pragma unroll
+            for (int q = 0; q < R; ++q) dst[q * Ns] = INV ? cconj(v[i][q]) : v[i][q];
+        }
+    }
+    __syncthreads();
+}
+
+// Full in-place FFT (unnormalised) of nl lines of length p.n in LDS.
+// Requires nl * p.n <= E * NT (checked by the host planner).  Caller must
+// __syncthreads() before (data written) -- this routine ends with a barrier.
+template <typename T, int NT, int E, bool INV>
+__device__ void lds_fft(cplx<T>* buf, int ld, int nl, const FftPlanDev& p)
+{
+    const cplx<T>* tw = static_cast<const cplx<T>*>(p.tw);
+    int Ns = 1;
+    for (int s = 0; s < p.nst; ++s) {
+        int r = p.rad[s];
+        switch (r) {
+            case 2: fft_stage<T, NT, E, 2, INV>(buf, ld, nl, p.n, Ns, tw); break;
+            case 3: fft_stage<T, NT, E, 3, INV>(buf, ld, nl, p.n, Ns, tw); break;
+            case 4: fft_stage<T, NT, E, 4, INV>(buf, ld, nl, p.n, Ns, tw); break;
+            case 5: fft_stage<T, NT, E, 5, INV>(buf, ld, nl, p.n, Ns, tw); break;
+            case 7: fft_stage<T, NT, E, 7, INV>(buf, ld, nl, p.n, Ns, tw); break;
+            default: fft_stage<T, NT, E, 8, INV>(buf, ld, nl, p.n, Ns, tw); break;
+        }
+        Ns *= r;
+    }
+}
+
+// Truncated Green's function transforms (paper Sec. 5.2): the free-space
+// harmonic (kind 0) and biharmonic (kind 1) kernels cut off at radius R.
+//   H^R(k) = 8 pi sin^2(R k / 2) / k^2
+//   B^R(k) = 4 pi [(2 - R^2 k^2) cos Rk + 2 Rk sin Rk - 2] / k^4
+// B^R cancels catastrophically near k = 0 and is summed from its series
+// 4 pi R^4 sum_n (-1)^n (Rk)^{2n} / ((2n+1)! (2n+4)) there.
+__host__ __device__ inline double khat_truncated(int kind, double k, double R)
+{
+    // kind 0: H^R(k) = 8 pi sin^2(R k / 2) / k^2
+    // kind 1: B^R(k) = 4 pi [(2 - R^2 k^2) cos Rk + 2 Rk sin Rk - 2] / k^4, series for small Rk
+    const double pi = 3.14159265358979323846;
+    double x = R * k;
+    if (kind == 0) {
+        if (x < 1e-4) return 2.0 * pi * R * R * (1.0 - x * x / 12.0);
+        double s = sin(0.5 * x) / k;
+        return 8.0 * pi * s * s;
+    }
+    if (x < 0.5) {
+        // 4 pi R^4 sum_n (-1)^n x^{2n} / ((2n+1)! (2n+4))
+        double x2 = x * x, term = 1.0, acc = 0.0;
+        double fact = 1.0;  // (2n+1)!
+        for (int n = 0; n < 14; ++n) {
+            if (n > 0) fact *= (double)(2 * n) * (double)(2 * n + 1);
+            acc += term / (fact * (double)(2 * n + 4));
+            term *= -x2;
+        }
+        return 4.0 * pi * R * R * R * R * acc;
+    }
+    double k2 = k * k;
+    return 4.0 * pi * ((2.0 - x * x) * cos(x) + 2.0 * x * sin(x) - 2.0) / (k2 * k2);
+}
+
+
+}  // namespace ehs

@@ -1,0 +1,641 @@
+// Zero-padded 3D transforms of the Fourier-space pipeline and the truncated
+// Green's-function precompute.
+//
+// Grid conventions (one component shown; components are stacked):
+//   real grid   R[l][j][i]      i,j < Mt (x1, x2), l < 2 Mt (x3)
+//   after X     A[k1][l][j]     k1 <= Mt (half spectrum of the 2Mt padded x1 axis)
+//   after Y     Z[k1][k2][l]    k2 < 2Mt (padded x2 axis), l < 2Mt (unpadded x3)
+// The x3 transform (padded to 4 Mt), the k-space scaling and the inverse x3
+// transform are fused into one pass over Z, so the 2Mt x 2Mt x 4Mt spectrum is
+// never written to memory.  The inverse passes mirror the forward ones and keep
+// only the unpadded M~ x M~ x 2M~ block.
+//
+// Zero padding by 2 along an axis is done without touching the zeros: for a
+// line x_t, t < n, padded to 2n, the even outputs X[2m] are DFT_n(x)[m] and the
+// odd outputs X[2m+1] are DFT_n(x_t e^{-i pi t/n})[m].  Along x3 the same
+// identity is used with Q "phases" k3 = Q m + s.
+#include "common.h"
+#include "kernels.h"
+
+namespace ehs {
+
+constexpr int PASS_NT = 512;  // threads of the x / y passes
+constexpr int PASS_E = 16;    // complex elements per thread in the LDS FFT
+constexpr int Z_NT = 512;
+constexpr int Z_E = 16;
+
+// ---------------------------------------------------------------------------
+// forward x pass: real lines of Mt values, zero-padded to 2Mt, half spectrum
+// k1 = 0..Mt.  Two real lines are packed into one complex line.
+// grid: (ceil(Mt / B), 2Mt, ncomp); B even.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(PASS_NT) k_fwd_x(const T* __restrict__ in, cplx<T>* __restrict__ out, PassArgs a)
+{
+    extern __shared__ unsigned char smem_raw[];
+    cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
+    const int Mt = a.Mt, B = a.B, ld = Mt + 1;
+    const int j0 = blockIdx.x * B, l = blockIdx.y, c = blockIdx.z;
+    const int nb = min(B, Mt - j0);
+    const cplx<T>* tw2 = static_cast<const cplx<T>*>(a.tw2);
+    const T* src = in + (long long)c * a.cs_in + ((long long)l * Mt + j0) * Mt;
+    const int np = B / 2;
+    for (int f = threadIdx.x; f < np * Mt; f += PASS_NT) {
+        int p = f / Mt, i = f - p * Mt;
+        T va = (2 * p < nb) ? src[(2 * p) * Mt + i] : (T)0;
+        T vb = (2 * p + 1 < nb) ? src[(2 * p + 1) * Mt + i] : (T)0;
+        cplx<T> z = cmk<T>(va, vb);
+        buf[(2 * p) * ld + i] = z;
+        buf[(2 * p + 1) * ld + i] = cmul(z, tw2[i]);
+    }
+    __syncthreads();
+    lds_fft<T, PASS_NT, PASS_E, false>(buf, ld, B, a.fM);
+    // unpack the two real spectra: A = (Z[k] + conj Z[-k]) / 2, B = (Z[k] - conj Z[-k]) / 2i
+    cplx<T>* dst = out + (long long)c * a.cs_out;
+    const long long rowk = (long long)2 * Mt * Mt;  // stride of k1
+    for (int f = threadIdx.x; f < (Mt + 1) * B; f += PASS_NT) {
+        int k = f / B, b = f - k * B;
+        if (b >= nb) continue;
+        int p = b >> 1, s = k & 1, m = k >> 1;
+        int mm = Mt - m - s;
+        if (mm >= Mt) mm -= Mt;
+        cplx<T> zk = buf[(2 * p + s) * ld + m];
+        cplx<T> zn = cconj(buf[(2 * p + s) * ld + mm]);
+        cplx<T> r;
+        if ((b & 1) == 0)
+            r = cmk<T>((T)0.5 * (zk.x + zn.x), (T)0.5 * (zk.y + zn.y));
+        else
+            r = cmk<T>((T)0.5 * (zk.y - zn.y), (T)-0.5 * (zk.x - zn.x));
+        dst[k * rowk + (long long)l * Mt + j0 + b] = r;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// forward y pass: complex lines along j (Mt values, contiguous), padded to
+// 2Mt; output Z[k1][k2][l] (l fastest).  grid: (ceil(2Mt / B), Mt + 1, ncomp)
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(PASS_NT) k_fwd_y(const cplx<T>* __restrict__ in, cplx<T>* __restrict__ out, PassArgs a)
+{
+    extern __shared__ unsigned char smem_raw[];
+    cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
+    const int Mt = a.Mt, B = a.B, ld = Mt + 1;
+    const int l0 = blockIdx.x * B, k1 = blockIdx.y, c = blockIdx.z;
+    const int nl = 2 * Mt;
+    const int nb = min(B, nl - l0);
+    const cplx<T>* tw2 = static_cast<const cplx<T>*>(a.tw2);
+    const cplx<T>* src = in + (long long)c * a.cs_in + ((long long)k1 * nl + l0) * Mt;
+    constexpr int MAXR = PASS_E;
+    cplx<T> x[MAXR];
+#pragma unroll
+    for (int i = 0; i < MAXR; ++i) {
+        int f = threadIdx.x + i * PASS_NT;
+        x[i] = cmk<T>(0, 0);
+        if (f < B * Mt) {
+            int b = f / Mt;
+            if (b < nb) x[i] = src[f];
+        }
+    }
+    cplx<T>* dst = out + (long long)c * a.cs_out + (long long)k1 * nl * nl + l0;
+    for (int s = 0; s < 2; ++s) {
+#pragma unroll
+        for (int i = 0; i < MAXR; ++i) {
+            int f = threadIdx.x + i * PASS_NT;
+            if (f < B * Mt) {
+                int b = f / Mt, j = f - b * Mt;
+                buf[b * ld + j] = s ? cmul(x[i], tw2[j]) : x[i];
+            }
+        }
+        __syncthreads();
+        lds_fft<T, PASS_NT, PASS_E, false>(buf, ld, B, a.fM);
+        for (int f = threadIdx.x; f < Mt * B; f += PASS_NT) {
+            int m = f / B, b = f - m * B;
+            if (b < nb) dst[(long long)(2 * m + s) * nl + b] = buf[b * ld + m];
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// inverse y pass: lines along k2 (2Mt values, stride 2Mt), keep j < Mt.
+// output D[k1][l][j].  grid: (ceil(2Mt / B), Mt + 1, ncomp)
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(PASS_NT) k_inv_y(const cplx<T>* __restrict__ in, cplx<T>* __restrict__ out, PassArgs a)
+{
+    extern __shared__ unsigned char smem_raw[];
+    cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
+    const int Mt = a.Mt, B = a.B, ld = Mt + 1;
+    const int l0 = blockIdx.x * B, k1 = blockIdx.y, c = blockIdx.z;
+    const int nl = 2 * Mt;
+    const int nb = min(B, nl - l0);
+    const cplx<T>* tw2 = static_cast<const cplx<T>*>(a.tw2);
+    const cplx<T>* src = in + (long long)c * a.cs_in + (long long)k1 * nl * nl + l0;
+    constexpr int MAXR = PASS_E;
+    cplx<T> acc[MAXR];
+    for (int s = 0; s < 2; ++s) {
+        for (int f = threadIdx.x; f < Mt * B; f += PASS_NT) {
+            int m = f / B, b = f - m * B;
+            buf[b * ld + m] = (b < nb) ? src[(long long)(2 * m + s) * nl + b] : cmk<T>(0, 0);
+        }
+        __syncthreads();
+        lds_fft<T, PASS_NT, PASS_E, true>(buf, ld, B, a.fM);
+#pragma unroll
+        for (int i = 0; i < MAXR; ++i) {
+            int f = threadIdx.x + i * PASS_NT;
+            if (f < B * Mt) {
+                int b = f / Mt, t = f - b * Mt;
+                cplx<T> v = buf[b * ld + t];
+                if (s == 0)
+                    acc[i] = v;
+                else
+                    acc[i] = cadd(acc[i], cmul(v, cconj(tw2[t])));
+            }
+        }
+        __syncthreads();
+    }
+    cplx<T>* dst = out + (long long)c * a.cs_out + ((long long)k1 * nl + l0) * Mt;
+#pragma unroll
+    for (int i = 0; i < MAXR; ++i) {
+        int f = threadIdx.x + i * PASS_NT;
+        if (f < B * Mt) {
+            int b = f / Mt;
+            if (b < nb) dst[f] = acc[i];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// inverse x pass (complex-to-real): lines along k1 (Mt + 1 values of the half
+// spectrum), keep i < Mt.  Two real output lines share one complex line.
+// output R[l][j][i].  grid: (ceil(Mt / B), 2Mt, ncomp); B even.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(PASS_NT) k_inv_x(const cplx<T>* __restrict__ in, T* __restrict__ out, PassArgs a)
+{
+    extern __shared__ unsigned char smem_raw[];
+    cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
+    const int Mt = a.Mt, B = a.B, ld = Mt + 1;
+    const int j0 = blockIdx.x * B, l = blockIdx.y, c = blockIdx.z;
+    const int nb = min(B, Mt - j0);
+    const cplx<T>* tw2 = static_cast<const cplx<T>*>(a.tw2);
+    const cplx<T>* src = in + (long long)c * a.cs_in + (long long)l * Mt + j0;
+    const long long rowk = (long long)2 * Mt * Mt;
+    // Z_p[k] = Ya[k] + i Yb[k] over the full padded range k < 2Mt; the
+    // position k = 2m + s is stored at buf[(2p + s) * ld + m].
+    for (int part = 0; part < 2; ++part) {
+        for (int f = threadIdx.x; f < (Mt + 1) * (B / 2); f += PASS_NT) {
+            int k = f / (B / 2), p = f - k * (B / 2);
+            int b = 2 * p + part;
+            cplx<T> v = (b < nb) ? src[k * rowk + b] : cmk<T>(0, 0);
+            if (k == 0 || k == Mt) v.y = 0;  // self-conjugate bins are real
+            cplx<T> w1 = part ? cmul_pi(v) : v;
+            int s = k & 1, m = k >> 1;
+            cplx<T>* d1 = &buf[(2 * p + s) * ld + m];
+            *d1 = part ? cadd(*d1, w1) : w1;
+            if (k > 0 && k < Mt) {
+                int k2 = 2 * Mt - k;
+                cplx<T> v2 = cconj(v);
+                cplx<T> w2 = part ? cmul_pi(v2) : v2;
+                cplx<T>* d2 = &buf[(2 * p + (k2 & 1)) * ld + (k2 >> 1)];
+                *d2 = part ? cadd(*d2, w2) : w2;
+            }
+        }
+        __syncthreads();
+    }
+    lds_fft<T, PASS_NT, PASS_E, true>(buf, ld, B, a.fM);
+    T* dst = out + (long long)c * a.cs_out + ((long long)l * Mt + j0) * Mt;
+    for (int f = threadIdx.x; f < nb * Mt; f += PASS_NT) {
+        int b = f / Mt, t = f - b * Mt;
+        int p = b >> 1;
+        cplx<T> r0 = buf[(2 * p) * ld + t];
+        cplx<T> r1 = buf[(2 * p + 1) * ld + t];
+        cplx<T> y = cadd(r0, cmul(r1, cconj(tw2[t])));
+        dst[f] = (b & 1) ? y.y : y.x;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// k-space multipliers (the scaling step).  X: the ncin transformed grids at
+// one wave vector; Y: the six outputs Y1 = t1 + e3 phi, Y2 = i k phi.
+//   gB = (1 + k^2/4xi^2) e^{-(1-eta) k^2/4xi^2} B^R(k) / Npad
+//   gH =                e^{-(1-eta) k^2/4xi^2} H^R(k) / Npad
+// ---------------------------------------------------------------------------
+template <typename U>
+__device__ __forceinline__ void mult_stokeslet(const cplx<U>* X, cplx<U>* Y, U kx, U ky, U kz, U gB, U gH)
+{
+    U k2 = kx * kx + ky * ky + kz * kz;
+    // t1 = -(k^2 I - k k) C1 * gB   (the A^S(k) of the stokeslet)
+    cplx<U> kc = cmk<U>(kx * X[0].x + ky * X[1].x + kz * X[2].x, kx * X[0].y + ky * X[1].y + kz * X[2].y);
+    U kv[3] = {kx, ky, kz};
+    // phi = gH (-2 C2 - 2 i k.C3)
+    cplx<U> kc3 = cmk<U>(kx * X[4].x + ky * X[5].x + kz * X[6].x, kx * X[4].y + ky * X[5].y + kz * X[6].y);
+    cplx<U> phi = cmk<U>(gH * (-2 * X[3].x + 2 * kc3.y), gH * (-2 * X[3].y - 2 * kc3.x));
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        Y[q] = cmk<U>(-gB * (k2 * X[q].x - kv[q] * kc.x), -gB * (k2 * X[q].y - kv[q] * kc.y));
+        Y[3 + q] = cmk<U>(-kv[q] * phi.y, kv[q] * phi.x);  // i k phi
+    }
+    Y[2] = cadd(Y[2], phi);
+}
+
+template <typename U>
+__device__ __forceinline__ void mult_stresslet(const cplx<U>* X, cplx<U>* Y, U kx, U ky, U kz, U gB, U gH)
+{
+    U k2 = kx * kx + ky * ky + kz * kz;
+    // C1 symmetric: xx xy xz yy yz zz
+    cplx<U> ck[3];
+    ck[0] = cmk<U>(X[0].x * kx + X[1].x * ky + X[2].x * kz, X[0].y * kx + X[1].y * ky + X[2].y * kz);
+    ck[1] = cmk<U>(X[1].x * kx + X[3].x * ky + X[4].x * kz, X[1].y * kx + X[3].y * ky + X[4].y * kz);
+    ck[2] = cmk<U>(X[2].x * kx + X[4].x * ky + X[5].x * kz, X[2].y * kx + X[4].y * ky + X[5].y * kz);
+    cplx<U> tr = cmk<U>(X[0].x + X[3].x + X[5].x, X[0].y + X[3].y + X[5].y);
+    cplx<U> kck = cmk<U>(kx * ck[0].x + ky * ck[1].x + kz * ck[2].x, kx * ck[0].y + ky * ck[1].y + kz * ck[2].y);
+    U kv[3] = {kx, ky, kz};
+    // C3 symmetric (indices 7..12), phi = gH (4 i kz C2 + 4 k.C3.k)
+    const cplx<U>* B3 = X + 7;
+    U kbk_x = kx * kx * B3[0].x + ky * ky * B3[3].x + kz * kz * B3[5].x +
+              2 * (kx * ky * B3[1].x + kx * kz * B3[2].x + ky * kz * B3[4].x);
+    U kbk_y = kx * kx * B3[0].y + ky * ky * B3[3].y + kz * kz * B3[5].y +
+              2 * (kx * ky * B3[1].y + kx * kz * B3[2].y + ky * kz * B3[4].y);
+    cplx<U> phi = cmk<U>(gH * (-4 * kz * X[6].y + 4 * kbk_x), gH * (4 * kz * X[6].x + 4 * kbk_y));
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        // t1 = -i gB [k^2 (2 C k + k trC) - 2 k (k.C k)]
+        cplx<U> s = cmk<U>(k2 * (2 * ck[q].x + kv[q] * tr.x) - 2 * kv[q] * kck.x,
+                           k2 * (2 * ck[q].y + kv[q] * tr.y) - 2 * kv[q] * kck.y);
+        Y[q] = cmk<U>(gB * s.y, -gB * s.x);
+        Y[3 + q] = cmk<U>(-kv[q] * phi.y, kv[q] * phi.x);
+    }
+    Y[2] = cadd(Y[2], phi);
+}
+
+template <typename U>
+__device__ __forceinline__ void mult_rotlet(const cplx<U>* X, cplx<U>* Y, U kx, U ky, U kz, U gH)
+{
+    // t1 = -2 i gH (C1 x k)
+    cplx<U> cx[3];
+    cx[0] = cmk<U>(X[1].x * kz - X[2].x * ky, X[1].y * kz - X[2].y * ky);
+    cx[1] = cmk<U>(X[2].x * kx - X[0].x * kz, X[2].y * kx - X[0].y * kz);
+    cx[2] = cmk<U>(X[0].x * ky - X[1].x * kx, X[0].y * ky - X[1].y * kx);
+    // phi = gH 2 i (kx w1 + ky w2)
+    cplx<U> kw = cmk<U>(kx * X[3].x + ky * X[4].x, kx * X[3].y + ky * X[4].y);
+    cplx<U> phi = cmk<U>(-2 * gH * kw.y, 2 * gH * kw.x);
+    U kv[3] = {kx, ky, kz};
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        Y[q] = cmk<U>(2 * gH * cx[q].y, -2 * gH * cx[q].x);
+        Y[3 + q] = cmk<U>(-kv[q] * phi.y, kv[q] * phi.x);
+    }
+    Y[2] = cadd(Y[2], phi);
+}
+
+template <typename U, int K>
+__device__ __forceinline__ void apply_mult(const cplx<U>* X, cplx<U>* Y, U kx, U ky, U kz, U gB, U gH)
+{
+    if (K == STOKESLET)
+        mult_stokeslet<U>(X, Y, kx, ky, kz, gB, gH);
+    else if (K == STRESSLET)
+        mult_stresslet<U>(X, Y, kx, ky, kz, gB, gH);
+    else
+        mult_rotlet<U>(X, Y, kx, ky, kz, gH);
+}
+
+// ---------------------------------------------------------------------------
+// fused x3 pass: forward padded transform of the ncin grids along x3, scaling
+// by the multipliers, inverse transform, truncation to l < 2Mt.  In place on
+// Z[k1][k2][l]; the six outputs overwrite components 0..5.
+// grid: (2Mt, Mt + 1).  RES: inputs and outputs held in registers (else the
+// inputs are re-read and outputs accumulated in memory phase by phase).
+// ---------------------------------------------------------------------------
+template <typename T, int K, bool RES>
+__global__ void __launch_bounds__(Z_NT) k_z_scale(cplx<T>* zb, cplx<T>* zout, ZArgs a)
+{
+    constexpr int ncin = Traits<K>::ncA + Traits<K>::ncB;
+    constexpr int nlines = ncin > NCOUT ? ncin : NCOUT;
+    constexpr int NZMAX = ZResident<K>::nz_max;
+    constexpr int MAXI = RES ? (ncin * NZMAX + Z_NT - 1) / Z_NT : 1;
+    constexpr int MAXO = RES ? (NCOUT * NZMAX + Z_NT - 1) / Z_NT : 1;
+    extern __shared__ unsigned char smem_raw[];
+    cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
+    const int Mt = a.Mt, Q = a.Q;
+    const int nz = 2 * Mt, n4 = 4 * Mt, nq = n4 / Q, ld = nq + 1;
+    const int k2 = blockIdx.x, k1 = blockIdx.y;
+    const long long cs = a.cs;
+    const long long base = ((long long)k1 * nz + k2) * nz;
+    const cplx<T>* tw4 = static_cast<const cplx<T>*>(a.tw4);
+
+    cplx<T> xin[MAXI];
+    cplx<T> yout[MAXO];
+    if (RES) {
+#pragma unroll
+        for (int i = 0; i < MAXI; ++i) {
+            int f = threadIdx.x + i * Z_NT;
+            if (f < ncin * nz) {
+                int c = f / nz, l = f - c * nz;
+                xin[i] = zb[c * cs + base + l];
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < MAXO; ++i) yout[i] = cmk<T>(0, 0);
+    }
+
+    // signed wave numbers of this line
+    const int k2s = (k2 < Mt) ? k2 : k2 - nz;
+    const int ak2 = k2s < 0 ? -k2s : k2s;
+    const bool nyq12 = (k1 == Mt) || (k2 == Mt);
+    const double kxd = a.dk12 * k1, kyd = a.dk12 * k2s;
+    const long long oct_line = ((long long)k1 * (Mt + 1) + ak2) * (2 * Mt + 1);
+
+    for (int s = 0; s < Q; ++s) {
+        // fold and twist the inputs into LDS: line c holds
+        //   sum_h x_c[l' + h nq] exp(-2 pi i s (l' + h nq) / 4Mt),  l' < nq
+        const int nh = (nz + nq - 1) / nq;
+        for (int h = 0; h < nh; ++h) {
+            if (RES) {
+#pragma unroll
+                for (int i = 0; i < MAXI; ++i) {
+                    int f = threadIdx.x + i * Z_NT;
+                    if (f < ncin * nz) {
+                        int c = f / nz, l = f - c * nz;
+                        if (l / nq == h) {
+                            int lp = l - h * nq;
+                            cplx<T> v = cmul(xin[i], tw4[(long long)s * l % n4]);
+                            buf[c * ld + lp] = h ? cadd(buf[c * ld + lp], v) : v;
+                        }
+                    }
+                }
+            } else {
+                for (int f = threadIdx.x; f < ncin * nq; f += Z_NT) {
+                    int c = f / nq, lp = f - c * nq;
+                    int l = lp + h * nq;
+                    cplx<T> v = cmk<T>(0, 0);
+                    if (l < nz) v = cmul(zb[c * cs + base + l], tw4[(long long)s * l % n4]);
+                    buf[c * ld + lp] = h ? cadd(buf[c * ld + lp], v) : v;
+                }
+            }
+            __syncthreads();
+        }
+        lds_fft<T, Z_NT, Z_E, false>(buf, ld, ncin, a.fq);
+
+        // scaling at k3 = Q m + s
+        for (int m = threadIdx.x; m < nq; m += Z_NT) {
+            int k3 = Q * m + s;
+            int k3s = (k3 < nz) ? k3 : k3 - n4;
+            int ak3 = k3s < 0 ? -k3s : k3s;
+            cplx<T> X[ncin];
+#pragma unroll
+            for (int c = 0; c < ncin; ++c) X[c] = buf[c * ld + m];
+            cplx<T> Y[NCOUT];
+            if (nyq12 || k3 == nz) {
+#pragma unroll
+                for (int c = 0; c < NCOUT; ++c) Y[c] = cmk<T>(0, 0);
+            } else {
+                double kzd = a.dk3 * k3s;
+                long long oi = oct_line + ak3;
+                bool near0 = (k1 <= a.near0) && (ak2 <= a.near0) && (ak3 <= 2 * a.near0);
+                if (sizeof(T) == 8 || near0) {
+                    double k2v = kxd * kxd + kyd * kyd + kzd * kzd;
+                    double ep = exp(-a.c_exp * k2v);
+                    double gB = 0.0, gH = ep * a.cH * a.octH64[oi];
+                    if (K != ROTLET) gB = (1.0 + a.c_has * k2v) * ep * a.cB * a.octB64[oi];
+                    cplx<double> Xd[ncin], Yd[NCOUT];
+#pragma unroll
+                    for (int c = 0; c < ncin; ++c) Xd[c] = cmk<double>((double)X[c].x, (double)X[c].y);
+                    apply_mult<double, K>(Xd, Yd, kxd, kyd, kzd, gB, gH);
+#pragma unroll
+                    for (int c = 0; c < NCOUT; ++c) Y[c] = cmk<T>((T)Yd[c].x, (T)Yd[c].y);
+                } else {
+                    float kx = (float)kxd, ky = (float)kyd, kz = (float)kzd;
+                    float k2v = kx * kx + ky * ky + kz * kz;
+                    float ep = expf(-(float)a.c_exp * k2v);
+                    float gH = ep * (float)a.cH * a.octH32[oi];
+                    float gB = 0.f;
+                    if (K != ROTLET) gB = (1.f + (float)a.c_has * k2v) * ep * (float)a.cB * a.octB32[oi];
+                    cplx<float> Xf[ncin], Yf[NCOUT];
+#pragma unroll
+                    for (int c = 0; c < ncin; ++c) Xf[c] = cmk<float>((float)X[c].x, (float)X[c].y);
+                    apply_mult<float, K>(Xf, Yf, kx, ky, kz, gB, gH);
+#pragma unroll
+                    for (int c = 0; c < NCOUT; ++c) Y[c] = cmk<T>((T)Yf[c].x, (T)Yf[c].y);
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < NCOUT; ++c) buf[c * ld + m] = Y[c];
+        }
+        __syncthreads();
+        lds_fft<T, Z_NT, Z_E, true>(buf, ld, NCOUT, a.fq);
+
+        // unfold: out_c[l] += buf_c[l mod nq] exp(+2 pi i s l / 4Mt), l < 2Mt
+        if (RES) {
+#pragma unroll
+            for (int i = 0; i < MAXO; ++i) {
+                int f = threadIdx.x + i * Z_NT;
+                if (f < NCOUT * nz) {
+                    int c = f / nz, l = f - c * nz;
+                    int lp = l % nq;
+                    yout[i] = cadd(yout[i], cmul(buf[c * ld + lp], cconj(tw4[(long long)s * l % n4])));
+                }
+            }
+        } else {
+            // outputs accumulate phase by phase in the separate output grids
+            for (int f = threadIdx.x; f < NCOUT * nz; f += Z_NT) {
+                int c = f / nz, l = f - c * nz;
+                int lp = l % nq;
+                cplx<T> v = cmul(buf[c * ld + lp], cconj(tw4[(long long)s * l % n4]));
+                cplx<T>* o = zout + c * a.cs_out + base + l;
+                *o = (s == 0) ? v : cadd(*o, v);
+            }
+        }
+        __syncthreads();
+    }
+    if (RES) {
+#pragma unroll
+        for (int i = 0; i < MAXO; ++i) {
+            int f = threadIdx.x + i * Z_NT;
+            if (f < NCOUT * nz) {
+                int c = f / nz, l = f - c * nz;
+                zout[c * a.cs_out + base + l] = yout[i];
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// precompute: one real, even line transform per block.
+//   v[t] = in[min(t, n - t)] (even extension of the stored half line), t < n
+//   out[k] = scale * Re sum_t v[t] exp(-2 pi i k t / n),  k < nkeep
+// In generate mode the input is the analytic kernel K^R(|k|) sampled on the
+// oversampled grid, for the octant indices (o1, o2) of the block.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_even_line(const double* __restrict__ in, double* __restrict__ out,
+                                                    EvenArgs a)
+{
+    extern __shared__ unsigned char smem_raw[];
+    cplx<double>* buf = reinterpret_cast<cplx<double>*>(smem_raw);
+    long long g = blockIdx.x + (long long)gridDim.x * blockIdx.y;
+    if (g >= (long long)a.n1 * a.n2) return;
+    int o1 = (int)(g / a.n2), o2 = (int)(g - (long long)o1 * a.n2);
+    const int n = a.f.n;
+    for (int t = threadIdx.x; t < n; t += 256) {
+        int tt = (t <= n - t) ? t : n - t;
+        double v;
+        if (a.generate) {
+            // octant indices (o1, o2) along the two oversampled in-plane axes and
+            // tt along the current axis
+            double k1 = a.dkg1 * o1, k2 = a.dkg1 * o2, k3 = a.dkg3 * tt;
+            v = khat_truncated(a.kind, sqrt(k1 * k1 + k2 * k2 + k3 * k3), a.R);
+        } else {
+            v = in[(long long)o1 * a.si1 + (long long)o2 * a.si2 + (long long)tt * a.st];
+        }
+        buf[t] = cmk<double>(v, 0.0);
+    }
+    __syncthreads();
+    lds_fft<double, 256, 16, false>(buf, n, 1, a.f);
+    for (int k = threadIdx.x; k < a.nkeep; k += 256)
+        out[(long long)o1 * a.so1 + (long long)o2 * a.so2 + (long long)k * a.sk] = a.scale * buf[k].x;
+}
+
+__global__ void k_oct_to_f32(const double* __restrict__ in, float* __restrict__ out, long long n)
+{
+    long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (i < n) out[i] = (float)in[i];
+}
+
+// debug / unit-test entry: nl independent FFTs of length p.n, each line
+// contiguous, one block handling `per` lines.
+template <typename T, bool INV>
+__global__ void __launch_bounds__(PASS_NT) k_line_fft(const cplx<T>* __restrict__ in, cplx<T>* __restrict__ out, int nl,
+                                                       int per, FftPlanDev p)
+{
+    extern __shared__ unsigned char smem_raw[];
+    cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
+    const int n = p.n, ld = n + 1;
+    int l0 = blockIdx.x * per;
+    int nb = min(per, nl - l0);
+    for (int f = threadIdx.x; f < per * n; f += PASS_NT) {
+        int b = f / n, t = f - b * n;
+        buf[b * ld + t] = (b < nb) ? in[(long long)(l0 + b) * n + t] : cmk<T>(0, 0);
+    }
+    __syncthreads();
+    lds_fft<T, PASS_NT, PASS_E, INV>(buf, ld, per, p);
+    for (int f = threadIdx.x; f < nb * n; f += PASS_NT) {
+        int b = f / n, t = f - b * n;
+        out[(long long)(l0 + b) * n + t] = buf[b * ld + t];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// host launchers
+// ---------------------------------------------------------------------------
+static size_t pass_lds(int Mt, int B, size_t esz) { return (size_t)B * (Mt + 1) * 2 * esz; }
+
+template <typename T>
+hipError_t launch_fwd_x(const T* in, cplx<T>* out, const PassArgs& a, int ncomp, hipStream_t st)
+{
+    dim3 grid((a.Mt + a.B - 1) / a.B, 2 * a.Mt, ncomp);
+    hipLaunchKernelGGL(k_fwd_x<T>, grid, dim3(PASS_NT), pass_lds(a.Mt, a.B, sizeof(T)), st, in, out, a);
+    return hipGetLastError();
+}
+template <typename T>
+hipError_t launch_fwd_y(const cplx<T>* in, cplx<T>* out, const PassArgs& a, int ncomp, hipStream_t st)
+{
+    dim3 grid((2 * a.Mt + a.B - 1) / a.B, a.Mt + 1, ncomp);
+    hipLaunchKernelGGL(k_fwd_y<T>, grid, dim3(PASS_NT), pass_lds(a.Mt, a.B, sizeof(T)), st, in, out, a);
+    return hipGetLastError();
+}
+template <typename T>
+hipError_t launch_inv_y(const cplx<T>* in, cplx<T>* out, const PassArgs& a, int ncomp, hipStream_t st)
+{
+    dim3 grid((2 * a.Mt + a.B - 1) / a.B, a.Mt + 1, ncomp);
+    hipLaunchKernelGGL(k_inv_y<T>, grid, dim3(PASS_NT), pass_lds(a.Mt, a.B, sizeof(T)), st, in, out, a);
+    return hipGetLastError();
+}
+template <typename T>
+hipError_t launch_inv_x(const cplx<T>* in, T* out, const PassArgs& a, int ncomp, hipStream_t st)
+{
+    dim3 grid((a.Mt + a.B - 1) / a.B, 2 * a.Mt, ncomp);
+    hipLaunchKernelGGL(k_inv_x<T>, grid, dim3(PASS_NT), pass_lds(a.Mt, a.B, sizeof(T)), st, in, out, a);
+    return hipGetLastError();
+}
+
+size_t z_lds_bytes(int family, int Mt, int Q, size_t esz)
+{
+    int ncin = family == STOKESLET ? 7 : family == STRESSLET ? 13 : 5;
+    int nl = ncin > NCOUT ? ncin : NCOUT;
+    return (size_t)nl * (4 * Mt / Q + 1) * 2 * esz;
+}
+
+bool z_resident_ok(int family, int Mt)
+{
+    int nzmax = family == STRESSLET ? ZResident<STRESSLET>::nz_max
+                                    : (family == STOKESLET ? ZResident<STOKESLET>::nz_max : ZResident<ROTLET>::nz_max);
+    return 2 * Mt <= nzmax;
+}
+
+template <typename T, int K>
+static hipError_t launch_z_t(cplx<T>* zb, cplx<T>* zout, const ZArgs& a, bool res, hipStream_t st)
+{
+    dim3 grid(2 * a.Mt, a.Mt + 1);
+    size_t lds = z_lds_bytes(K, a.Mt, a.Q, sizeof(T));
+    if (res)
+        hipLaunchKernelGGL((k_z_scale<T, K, true>), grid, dim3(Z_NT), lds, st, zb, zout, a);
+    else
+        hipLaunchKernelGGL((k_z_scale<T, K, false>), grid, dim3(Z_NT), lds, st, zb, zout, a);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_z(int family, cplx<T>* zb, cplx<T>* zout, const ZArgs& a, bool res, hipStream_t st)
+{
+    switch (family) {
+        case STOKESLET: return launch_z_t<T, STOKESLET>(zb, zout, a, res, st);
+        case STRESSLET: return launch_z_t<T, STRESSLET>(zb, zout, a, res, st);
+        default: return launch_z_t<T, ROTLET>(zb, zout, a, res, st);
+    }
+}
+
+hipError_t launch_even_line(const double* in, double* out, const EvenArgs& a, hipStream_t st)
+{
+    long long nlines = (long long)a.n1 * a.n2;
+    unsigned gx = (unsigned)(nlines < 65535 ? nlines : 65535);
+    unsigned gy = (unsigned)((nlines + gx - 1) / gx);
+    size_t lds = (size_t)a.f.n * sizeof(cplx<double>);
+    hipLaunchKernelGGL(k_even_line, dim3(gx, gy), dim3(256), lds, st, in, out, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_oct_to_f32(const double* in, float* out, long long n, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_oct_to_f32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, in, out, n);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_line_fft(const cplx<T>* in, cplx<T>* out, int nl, int per, const FftPlanDev& p, bool inv,
+                           hipStream_t st)
+{
+    dim3 grid((nl + per - 1) / per);
+    size_t lds = (size_t)per * (p.n + 1) * sizeof(cplx<T>);
+    if (inv)
+        hipLaunchKernelGGL((k_line_fft<T, true>), grid, dim3(PASS_NT), lds, st, in, out, nl, per, p);
+    else
+        hipLaunchKernelGGL((k_line_fft<T, false>), grid, dim3(PASS_NT), lds, st, in, out, nl, per, p);
+    return hipGetLastError();
+}
+
+template hipError_t launch_fwd_x<double>(const double*, cplx<double>*, const PassArgs&, int, hipStream_t);
+template hipError_t launch_fwd_x<float>(const float*, cplx<float>*, const PassArgs&, int, hipStream_t);
+template hipError_t launch_fwd_y<double>(const cplx<double>*, cplx<double>*, const PassArgs&, int, hipStream_t);
+template hipError_t launch_fwd_y<float>(const cplx<float>*, cplx<float>*, const PassArgs&, int, hipStream_t);
+template hipError_t launch_inv_y<double>(const cplx<double>*, cplx<double>*, const PassArgs&, int, hipStream_t);
+template hipError_t launch_inv_y<float>(const cplx<float>*, cplx<float>*, const PassArgs&, int, hipStream_t);
+template hipError_t launch_inv_x<double>(const cplx<double>*, double*, const PassArgs&, int, hipStream_t);
+template hipError_t launch_inv_x<float>(const cplx<float>*, float*, const PassArgs&, int, hipStream_t);
+template hipError_t launch_z<double>(int, cplx<double>*, cplx<double>*, const ZArgs&, bool, hipStream_t);
+template hipError_t launch_z<float>(int, cplx<float>*, cplx<float>*, const ZArgs&, bool, hipStream_t);
+template hipError_t launch_line_fft<double>(const cplx<double>*, cplx<double>*, int, int, const FftPlanDev&, bool,
+                                            hipStream_t);
+template hipError_t launch_line_fft<float>(const cplx<float>*, cplx<float>*, int, int, const FftPlanDev&, bool,
+                                           hipStream_t);
+
+}  // namespace ehs

@@ -1,0 +1,344 @@
+// Gaussian spreading onto the grid and Gaussian gathering (quadrature) at the
+// targets -- steps 5 and 10 of the paper's Algorithm 1, with the window
+// W(d) = (2 xi^2 / (pi eta))^{3/2} exp(-2 xi^2 |d|^2 / eta) truncated to P^3
+// nodes.
+//
+// Spreading is atomic-free: the 2N points (sources and their wall images)
+// are sorted by the grid tile that holds the first node of their support;
+// every output tile is owned by one wavefront, which walks the records of the
+// neighbouring tiles in sorted order and accumulates its own nodes in
+// registers.  The result is deterministic and every grid node is written
+// exactly once (zeros included).
+#include <math.h>
+
+#include "common.h"
+#include "kernels.h"
+
+namespace ehs {
+
+template <int K>
+struct RecLayout {
+    static constexpr int ncA = Traits<K>::ncA;
+    static constexpr int ncB = Traits<K>::ncB;
+};
+
+// header of 4 int32 (base x, y, z, image flag) stored in the first 16 bytes
+size_t record_stride(int family, int P, size_t esz)
+{
+    int nc = family == STOKESLET ? 7 : family == STRESSLET ? 13 : 5;
+    return 16 / esz + 3 * (size_t)P + nc;
+}
+
+__device__ __forceinline__ int support_base(double z, double o, double h, int P, int n)
+{
+    int b = (int)floor((z - o) / h) - P / 2 + 1;
+    if (b < 0) b = 0;
+    if (b > n - P) b = n - P;
+    return b;
+}
+
+__global__ void k_point_keys(const double* __restrict__ y, long long N, GridArgs g, uint32_t* __restrict__ keys,
+                             uint32_t* __restrict__ idx)
+{
+    long long p = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (p >= 2 * N) return;
+    long long m = p < N ? p : p - N;
+    double z[3] = {y[3 * m], y[3 * m + 1], p < N ? y[3 * m + 2] : -y[3 * m + 2]};
+    int dims[3] = {g.Mt, g.Mt, 2 * g.Mt};
+    int t[3];
+    for (int a = 0; a < 3; ++a) t[a] = support_base(z[a], g.o[a], g.h, g.P, dims[a]) / g.tile[a];
+    keys[p] = (uint32_t)(((long long)t[2] * g.nt[1] + t[1]) * g.nt[0] + t[0]);
+    idx[p] = (uint32_t)p;
+}
+
+hipError_t launch_point_keys(const double* y, long long N, GridArgs g, uint32_t* keys, uint32_t* idx, hipStream_t st)
+{
+    if (N <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_point_keys, dim3((unsigned)((2 * N + 255) / 256)), dim3(256), 0, st, y, N, g, keys, idx);
+    return hipGetLastError();
+}
+
+// strengths of the consolidated sources (A-grids) and of the correction
+// sources (B-grids) for point p (p >= N: image of source p - N)
+template <int K>
+__device__ __forceinline__ void point_strengths(const double* s, const double* y, long long p, long long N, double* cA,
+                                                double* cB)
+{
+    bool img = p >= N;
+    long long m = img ? p - N : p;
+    if (K == STOKESLET) {
+        const double* f = s + 3 * m;
+        if (!img) {
+            cA[0] = f[0];
+            cA[1] = f[1];
+            cA[2] = f[2];
+        } else {
+            // -f^I at y^I;  correction sources f3 and y3 f^I
+            cA[0] = -f[0];
+            cA[1] = -f[1];
+            cA[2] = f[2];
+            double y3 = y[3 * m + 2];
+            cB[0] = f[2];
+            cB[1] = y3 * f[0];
+            cB[2] = y3 * f[1];
+            cB[3] = -y3 * f[2];
+        }
+    } else if (K == STRESSLET) {
+        const double* g = s + 6 * m;
+        const double* q = s + 6 * m + 3;
+        double S[6] = {g[0] * q[0], 0.5 * (g[0] * q[1] + g[1] * q[0]), 0.5 * (g[0] * q[2] + g[2] * q[0]),
+                       g[1] * q[1], 0.5 * (g[1] * q[2] + g[2] * q[1]), g[2] * q[2]};
+        if (!img) {
+            for (int c = 0; c < 6; ++c) cA[c] = S[c];
+        } else {
+            // R S R flips xz and yz
+            double SI[6] = {S[0], S[1], -S[2], S[3], -S[4], S[5]};
+            for (int c = 0; c < 6; ++c) cA[c] = -SI[c];
+            double y3 = y[3 * m + 2];
+            cB[0] = S[0] + S[3] + S[5];
+            for (int c = 0; c < 6; ++c) cB[1 + c] = y3 * SI[c];
+        }
+    } else {
+        const double* v = s + 3 * m;
+        if (!img) {
+            cA[0] = v[0];
+            cA[1] = v[1];
+            cA[2] = v[2];
+        } else {
+            cA[0] = v[0];
+            cA[1] = v[1];
+            cA[2] = -v[2];
+            cB[0] = -2.0 * v[1];
+            cB[1] = 2.0 * v[0];
+        }
+    }
+}
+
+template <typename T, int K>
+__global__ void k_records(const double* __restrict__ y, const double* __restrict__ s, const uint32_t* __restrict__ perm,
+                          long long N, GridArgs g, T* __restrict__ rec)
+{
+    constexpr int ncA = RecLayout<K>::ncA, ncB = RecLayout<K>::ncB;
+    long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (q >= 2 * N) return;
+    const int P = g.P;
+    const long long stride = 16 / sizeof(T) + 3 * P + ncA + ncB;
+    long long p = perm[q];
+    long long m = p < N ? p : p - N;
+    bool img = p >= N;
+    double z[3] = {y[3 * m], y[3 * m + 1], img ? -y[3 * m + 2] : y[3 * m + 2]};
+    int dims[3] = {g.Mt, g.Mt, 2 * g.Mt};
+    T* r = rec + q * stride;
+    int* hdr = reinterpret_cast<int*>(r);
+    int base[3];
+    for (int a = 0; a < 3; ++a) {
+        base[a] = support_base(z[a], g.o[a], g.h, P, dims[a]);
+        hdr[a] = base[a];
+    }
+    hdr[3] = img ? 1 : 0;
+    T* w = r + 16 / sizeof(T);
+    for (int a = 0; a < 3; ++a) {
+        for (int t = 0; t < P; ++t) {
+            double d = g.o[a] + (base[a] + t) * g.h - z[a];
+            double v = exp(-g.a2 * d * d);
+            if (a == 0) v *= g.pref;
+            w[a * P + t] = (T)v;
+        }
+    }
+    double cA[ncA], cB[ncB];
+    for (int c = 0; c < ncB; ++c) cB[c] = 0.0;
+    point_strengths<K>(s, y, p, N, cA, cB);
+    T* cs = w + 3 * P;
+    for (int c = 0; c < ncA; ++c) cs[c] = (T)cA[c];
+    for (int c = 0; c < ncB; ++c) cs[ncA + c] = (T)cB[c];
+}
+
+template <typename T>
+hipError_t launch_records(int family, const double* y, const double* s, const uint32_t* perm, long long N, GridArgs g,
+                          T* rec, hipStream_t st)
+{
+    if (N <= 0) return hipSuccess;
+    dim3 grid((unsigned)((2 * N + 255) / 256));
+    switch (family) {
+        case STOKESLET: hipLaunchKernelGGL((k_records<T, STOKESLET>), grid, dim3(256), 0, st, y, s, perm, N, g, rec); break;
+        case STRESSLET: hipLaunchKernelGGL((k_records<T, STRESSLET>), grid, dim3(256), 0, st, y, s, perm, N, g, rec); break;
+        default: hipLaunchKernelGGL((k_records<T, ROTLET>), grid, dim3(256), 0, st, y, s, perm, N, g, rec); break;
+    }
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// spreading: one wavefront (block of 64) per output tile of 8 x 8 x TZ nodes;
+// lane (i, j) owns the column of TZ nodes along x3.
+// ---------------------------------------------------------------------------
+constexpr int SP_CHUNK = 32;
+
+template <typename T, int K, int TZ>
+__global__ void __launch_bounds__(64) k_spread(GridArgs g, const T* __restrict__ rec,
+                                               const uint32_t* __restrict__ toff, T* __restrict__ grids, long long cs)
+{
+    constexpr int ncA = RecLayout<K>::ncA, ncB = RecLayout<K>::ncB, nc = ncA + ncB;
+    extern __shared__ unsigned char smem_raw[];
+    T* sh = reinterpret_cast<T*>(smem_raw);
+    const int P = g.P;
+    const int stride = 16 / sizeof(T) + 3 * P + nc;
+    const int lane = threadIdx.x;
+    const int tx = blockIdx.x, ty = blockIdx.y, tz = blockIdx.z;
+    const int i = tx * 8 + (lane & 7), j = ty * 8 + (lane >> 3);
+    const int l0 = tz * TZ;
+    T acc[TZ][nc];
+#pragma unroll
+    for (int z = 0; z < TZ; ++z)
+#pragma unroll
+        for (int c = 0; c < nc; ++c) acc[z][c] = (T)0;
+
+    const int x_lo = tx - g.K[0] < 0 ? 0 : tx - g.K[0];
+    for (int sz = tz - g.K[2]; sz <= tz; ++sz) {
+        if (sz < 0) continue;
+        for (int sy = ty - g.K[1]; sy <= ty; ++sy) {
+            if (sy < 0) continue;
+            long long row = ((long long)sz * g.nt[1] + sy) * g.nt[0];
+            uint32_t r0 = toff[row + x_lo], r1 = toff[row + tx + 1];
+            for (uint32_t c0 = r0; c0 < r1; c0 += SP_CHUNK) {
+                int nr = (int)min((uint32_t)SP_CHUNK, r1 - c0);
+                // stage the records of this chunk
+                const T* src = rec + (long long)c0 * stride;
+                for (int f = lane; f < nr * stride; f += 64) sh[f] = src[f];
+                __syncthreads();
+                for (int q = 0; q < nr; ++q) {
+                    const T* r = sh + q * stride;
+                    const int* hdr = reinterpret_cast<const int*>(r);
+                    int dx = i - hdr[0], dy = j - hdr[1];
+                    if ((unsigned)dx < (unsigned)P && (unsigned)dy < (unsigned)P) {
+                        const T* w = r + 16 / sizeof(T);
+                        T wxy = w[dx] * w[P + dy];
+                        const T* cv = w + 3 * P;
+                        const bool img = hdr[3] != 0;
+#pragma unroll
+                        for (int z = 0; z < TZ; ++z) {
+                            int dz = l0 + z - hdr[2];
+                            if ((unsigned)dz < (unsigned)P) {
+                                T wv = wxy * w[2 * P + dz];
+#pragma unroll
+                                for (int c = 0; c < ncA; ++c) acc[z][c] += wv * cv[c];
+                                if (img) {
+#pragma unroll
+                                    for (int c = 0; c < ncB; ++c) acc[z][ncA + c] += wv * cv[ncA + c];
+                                }
+                            }
+                        }
+                    }
+                }
+                __syncthreads();
+            }
+        }
+    }
+    const int Mt = g.Mt;
+    if (i < Mt && j < Mt) {
+#pragma unroll
+        for (int z = 0; z < TZ; ++z) {
+            int l = l0 + z;
+            if (l < 2 * Mt) {
+                long long node = ((long long)l * Mt + j) * Mt + i;
+#pragma unroll
+                for (int c = 0; c < nc; ++c) grids[c * cs + node] = acc[z][c];
+            }
+        }
+    }
+}
+
+template <typename T>
+hipError_t launch_spread(int family, GridArgs g, const T* rec, const uint32_t* toff, T* grids, long long cs,
+                         hipStream_t st)
+{
+    dim3 grid(g.nt[0], g.nt[1], g.nt[2]);
+    int nc = family == STOKESLET ? 7 : family == STRESSLET ? 13 : 5;
+    size_t lds = (size_t)SP_CHUNK * (16 / sizeof(T) + 3 * g.P + nc) * sizeof(T);
+    switch (family) {
+        case STOKESLET: hipLaunchKernelGGL((k_spread<T, STOKESLET, 8>), grid, dim3(64), lds, st, g, rec, toff, grids, cs); break;
+        case STRESSLET: hipLaunchKernelGGL((k_spread<T, STRESSLET, 4>), grid, dim3(64), lds, st, g, rec, toff, grids, cs); break;
+        default: hipLaunchKernelGGL((k_spread<T, ROTLET, 8>), grid, dim3(64), lds, st, g, rec, toff, grids, cs); break;
+    }
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// gather (quadrature) and the FP64 combination u = u_R + self + u_F:
+//   u_F(x) = h^3 sum_nodes W(x - x_g) [T1(x_g) - x3 T2(x_g)]
+// one wavefront per target; lanes cover P consecutive x1 nodes of
+// floor(64 / P) rows at a time.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(256) k_gather(GridArgs g, const T* __restrict__ grids, long long cs,
+                                                const double* __restrict__ xs, const uint32_t* __restrict__ tperm,
+                                                long long TT, const double* __restrict__ upart,
+                                                double* __restrict__ uout)
+{
+    __shared__ T wsh[4][3 * 32];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const long long t_raw = blockIdx.x * 4LL + wv;
+    const bool valid = t_raw < TT;  // no early exit: every wave reaches the barrier
+    const long long t = valid ? t_raw : TT - 1;
+    const int P = g.P, Mt = g.Mt;
+    const double x[3] = {xs[t], xs[TT + t], xs[2 * TT + t]};
+    int dims[3] = {Mt, Mt, 2 * Mt};
+    int base[3];
+    for (int a = 0; a < 3; ++a) base[a] = support_base(x[a], g.o[a], g.h, P, dims[a]);
+    for (int f = lane; f < 3 * P; f += 64) {
+        int a = f / P, q = f - a * P;
+        double d = g.o[a] + (base[a] + q) * g.h - x[a];
+        double v = exp(-g.a2 * d * d);
+        if (a == 0) v *= g.pref;
+        wsh[wv][f] = (T)v;
+    }
+    __syncthreads();
+    const int rows = 64 / P;
+    const int xi = lane % P, row = lane / P;
+    T acc[6] = {0, 0, 0, 0, 0, 0};
+    if (row < rows) {
+        const T wx = wsh[wv][xi];
+        for (int rr = row; rr < P * P; rr += rows) {
+            int dz = rr / P, dy = rr - dz * P;
+            T w = wx * wsh[wv][P + dy] * wsh[wv][2 * P + dz];
+            long long node = ((long long)(base[2] + dz) * Mt + base[1] + dy) * Mt + base[0] + xi;
+#pragma unroll
+            for (int c = 0; c < 6; ++c) acc[c] += w * grids[c * cs + node];
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+        T v = acc[c];
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+        acc[c] = v;
+    }
+    if (lane == 0 && valid) {
+        long long o = tperm[t];
+        double h3 = g.h * g.h * g.h;
+        for (int a = 0; a < 3; ++a)
+            uout[3 * o + a] = upart[3 * o + a] + h3 * ((double)acc[a] - x[2] * (double)acc[3 + a]);
+    }
+}
+
+template <typename T>
+hipError_t launch_gather(GridArgs g, const T* grids, long long cs, const double* xs, const uint32_t* tperm,
+                         long long T_, const double* upart, double* uout, hipStream_t st)
+{
+    if (T_ <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_gather<T>, dim3((unsigned)((T_ + 3) / 4)), dim3(256), 0, st, g, grids, cs, xs, tperm, T_,
+                       upart, uout);
+    return hipGetLastError();
+}
+
+template hipError_t launch_records<double>(int, const double*, const double*, const uint32_t*, long long, GridArgs,
+                                           double*, hipStream_t);
+template hipError_t launch_records<float>(int, const double*, const double*, const uint32_t*, long long, GridArgs,
+                                          float*, hipStream_t);
+template hipError_t launch_spread<double>(int, GridArgs, const double*, const uint32_t*, double*, long long,
+                                          hipStream_t);
+template hipError_t launch_spread<float>(int, GridArgs, const float*, const uint32_t*, float*, long long, hipStream_t);
+template hipError_t launch_gather<double>(GridArgs, const double*, long long, const double*, const uint32_t*,
+                                          long long, const double*, double*, hipStream_t);
+template hipError_t launch_gather<float>(GridArgs, const float*, long long, const double*, const uint32_t*, long long,
+                                         const double*, double*, hipStream_t);
+
+}  // namespace ehs

@@ -1,0 +1,172 @@
+// Kernel argument blocks and host-side launchers of the device kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "common.h"
+
+namespace ehs {
+
+// x / y transform passes
+struct PassArgs {
+    int Mt;              // grid nodes along x1 and x2 (2 Mt along x3)
+    int B;               // lines per block
+    long long cs_in;     // elements between components of the input
+    long long cs_out;    // elements between components of the output
+    const void* tw2;     // exp(-2 pi i t / 2Mt), t < 2Mt
+    FftPlanDev fM;       // FFT of length Mt
+};
+
+// largest 2 Mt for which the fused x3 pass keeps its lines in registers
+template <int K>
+struct ZResident;
+template <>
+struct ZResident<STOKESLET> {
+    static constexpr int nz_max = 1280;
+};
+template <>
+struct ZResident<STRESSLET> {
+    static constexpr int nz_max = 1024;
+};
+template <>
+struct ZResident<ROTLET> {
+    static constexpr int nz_max = 1280;
+};
+
+// fused x3 transform + scaling
+struct ZArgs {
+    int Mt;
+    int Q;                 // phases of the 4Mt padded axis; line length 4Mt / Q
+    long long cs;          // elements between input components
+    long long cs_out;      // elements between output components
+    const void* tw4;       // exp(-2 pi i t / 4Mt), t < 4Mt
+    FftPlanDev fq;         // FFT of length 4Mt / Q
+    double dk12, dk3;      // wave-number steps: pi / L~ (x1, x2) and pi / (2 L~) (x3)
+    double c_exp;          // (1 - eta) / (4 xi^2)
+    double c_has;          // 1 / (4 xi^2)
+    double cB, cH;         // L~^4 / Npad and L~^2 / Npad
+    const double* octB64;  // truncated biharmonic kernel, octant (Mt+1) x (Mt+1) x (2Mt+1)
+    const double* octH64;  // truncated harmonic kernel, same layout
+    const float* octB32;
+    const float* octH32;
+    int near0;             // index radius of the k ~ 0 region computed in FP64
+};
+
+// one even real line transform per block (precompute)
+struct EvenArgs {
+    int n1, n2;          // outer index ranges (one line per pair)
+    FftPlanDev f;        // FFT of the period n
+    int generate;        // 1: analytic input (K^R sampled on the oversampled grid)
+    int kind;            // 0: H^R, 1: B^R
+    double R;            // truncation radius (units of L~)
+    double dkg1, dkg3;   // oversampled wave-number steps (in-plane, x3)
+    long long si1, si2, st;  // input strides (outer 1, outer 2, along the line)
+    long long so1, so2, sk;  // output strides
+    int nkeep;           // outputs kept (k < nkeep)
+    double scale;
+};
+
+size_t z_lds_bytes(int family, int Mt, int Q, size_t esz);
+bool z_resident_ok(int family, int Mt);
+
+template <typename T>
+hipError_t launch_fwd_x(const T* in, cplx<T>* out, const PassArgs& a, int ncomp, hipStream_t st);
+template <typename T>
+hipError_t launch_fwd_y(const cplx<T>* in, cplx<T>* out, const PassArgs& a, int ncomp, hipStream_t st);
+template <typename T>
+hipError_t launch_inv_y(const cplx<T>* in, cplx<T>* out, const PassArgs& a, int ncomp, hipStream_t st);
+template <typename T>
+hipError_t launch_inv_x(const cplx<T>* in, T* out, const PassArgs& a, int ncomp, hipStream_t st);
+template <typename T>
+hipError_t launch_z(int family, cplx<T>* zb, cplx<T>* zout, const ZArgs& a, bool res, hipStream_t st);
+hipError_t launch_even_line(const double* in, double* out, const EvenArgs& a, hipStream_t st);
+hipError_t launch_oct_to_f32(const double* in, float* out, long long n, hipStream_t st);
+template <typename T>
+hipError_t launch_line_fft(const cplx<T>* in, cplx<T>* out, int nl, int per, const FftPlanDev& p, bool inv,
+                           hipStream_t st);
+
+// ---------------------------------------------------------------------------
+// binning: bounding box, keys, radix sort, scans, cell ranges
+// ---------------------------------------------------------------------------
+// bbox / validation reduction over sources and targets; 16 doubles out:
+// [0..2] min over all points, [3..5] max, [6] min source x3, [7] min target x3,
+// [8] non-finite count, [9] Q (sum of squared strength norms)
+hipError_t launch_bbox(int family, const double* y, const double* s, long long N, const double* x, long long T,
+                       double* partial, int nblocks, double* out16, hipStream_t st);
+int bbox_blocks(long long n);
+
+// stable LSD radix sort of (key, value) pairs on `bits` low key bits
+size_t radix_sort_scratch_bytes(long long n);
+hipError_t radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_tmp, uint32_t* vals_tmp, long long n, int bits,
+                      void* scratch, hipStream_t st, uint32_t** keys_out, uint32_t** vals_out);
+// exclusive scan of n uint32 values (in place allowed); scratch from scan_scratch_bytes
+size_t scan_scratch_bytes(long long n);
+hipError_t exclusive_scan(const uint32_t* in, uint32_t* out, long long n, void* scratch, hipStream_t st);
+hipError_t fill_u32(uint32_t* p, uint32_t v, long long n, hipStream_t st);
+// off[c] (c <= ncell) = first sorted position with key >= c, written to `start`
+hipError_t launch_cell_ranges(const uint32_t* skeys, long long n, uint32_t* start, uint32_t* end, long long ncell,
+                              hipStream_t st);
+
+// ---------------------------------------------------------------------------
+// real-space sum
+// ---------------------------------------------------------------------------
+struct CellGeom {
+    int nc[3];        // cells per axis
+    double lo[3];     // origin of the cell grid (x3 origin is the wall)
+    double inv[3];    // 1 / cell side
+};
+
+struct RealArgs {
+    CellGeom cg;
+    long long N, T;
+    double xi, rc2;
+    const uint32_t* src_off;      // ncell + 1 offsets into the sorted sources
+    const uint32_t* tgt_off;      // ncell + 1 offsets into the sorted targets
+    const uint32_t* chunk_cell;   // work list: cell of each 64-target chunk
+    const uint32_t* chunk_first;  // first sorted target of each chunk
+    const uint32_t* nchunks;      // device count of chunks
+    const uint32_t* tgt_perm;     // sorted target -> original target
+};
+
+hipError_t launch_cell_keys(const double* p, long long n, CellGeom cg, uint32_t* keys, uint32_t* idx, hipStream_t st);
+hipError_t launch_chunks(const uint32_t* tstart, const uint32_t* tend, long long ncell, uint32_t* counts,
+                         uint32_t* offs, void* scan_scratch, uint32_t* chunk_cell, uint32_t* chunk_first,
+                         uint32_t* nchunks, hipStream_t st);
+hipError_t launch_gather_points(const double* x, const uint32_t* perm, long long T, double* xs, hipStream_t st);
+// gathers sorted source data: positions (SoA, 3 x N) and strengths (nstr x N), FP64
+hipError_t launch_gather_sources(int family, const double* y, const double* s, const uint32_t* perm, long long N,
+                                 double* ys, double* ss, hipStream_t st);
+template <typename T>
+hipError_t launch_realspace(int family, const RealArgs& a, const double* ys, const double* ss, const double* xt,
+                            double* upart, long long max_chunks, hipStream_t st);
+
+// ---------------------------------------------------------------------------
+// spreading and gathering
+// ---------------------------------------------------------------------------
+struct GridArgs {
+    int Mt, P;
+    double o[3];        // grid origin
+    double h;
+    double a2;          // 2 xi^2 / eta (Gaussian exponent factor)
+    double pref;        // (2 xi^2 / (pi eta))^{3/2}
+    int tile[3];        // spread tile edge per axis (nodes)
+    int nt[3];          // tiles per axis
+    int K[3];           // neighbour tiles per axis: ceil((P - 1) / tile)
+};
+
+// 2N points (sources then images): support base tile keys
+hipError_t launch_point_keys(const double* y, long long N, GridArgs g, uint32_t* keys, uint32_t* idx,
+                             hipStream_t st);
+// records of the sorted points (base, 1D weights, strengths) in precision T
+size_t record_stride(int family, int P, size_t esz);
+template <typename T>
+hipError_t launch_records(int family, const double* y, const double* s, const uint32_t* perm, long long N, GridArgs g,
+                          T* rec, hipStream_t st);
+template <typename T>
+hipError_t launch_spread(int family, GridArgs g, const T* rec, const uint32_t* toff, T* grids, long long cs,
+                         hipStream_t st);
+template <typename T>
+hipError_t launch_gather(GridArgs g, const T* grids, long long cs, const double* x, const uint32_t* tperm,
+                         long long T_, const double* upart, double* uout, hipStream_t st);
+
+}  // namespace ehs

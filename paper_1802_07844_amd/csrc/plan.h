@@ -1,0 +1,286 @@
+// Parameter selection for one evaluation (host-only arithmetic).
+//
+// Given xi and r_c from the caller and the target relative RMS error tol:
+//  * M (grid intervals over the box L) from the Fourier truncation estimate
+//    of the paper's Table 1 with k_inf = pi / h = pi M / L, sources and images
+//    counted (Q -> 2Q), budget tol/4 relative to sqrt(Q)/L;
+//  * P (Gaussian support, even) from exp(-pi P c^2 / 2) <= tol/4, c = 0.95,
+//    eta = P xi^2 h^2 / (c^2 pi) (Algorithm 1 step 4), M raised until eta < 0.95;
+//  * the box is extended by max(P, m / (sqrt2 xi h)) nodes with
+//    m = sqrt(2 ln(1/tol)): the Gaussian support of Algorithm 1 step 3 plus a
+//    margin for the k-space screening exp(-(1-eta) k^2/4xi^2), which is
+//    applied to the window-truncated kernel and must not reach the window's
+//    edge; M~ is then rounded up to an even 7-smooth size (FFT radices 2..8);
+//  * the real-space estimate of Table 2 (Q -> 2Q) is reported and flagged
+//    when above tol/2.
+#pragma once
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "kernels.h"
+
+namespace ehs {
+
+constexpr double C_SHAPE = 0.95;
+
+inline bool smooth7(long long n)
+{
+    if (n < 1) return false;
+    for (int p : {2, 3, 5, 7})
+        while (n % p == 0) n /= p;
+    return n == 1;
+}
+
+inline int next_smooth_even(double x)
+{
+    long long n = (long long)std::ceil(x);
+    if (n < 2) n = 2;
+    while (!(n % 2 == 0 && smooth7(n))) ++n;
+    return (int)n;
+}
+
+// radices 8, 4, 2, then 7, 5, 3
+inline bool factor_radices(int n, std::vector<int>& r)
+{
+    r.clear();
+    if (n < 1) return false;
+    if (n == 1) {
+        r.push_back(2);  // never used: callers require n >= 2
+        return false;
+    }
+    int m = n;
+    while (m % 8 == 0) {
+        r.push_back(8);
+        m /= 8;
+    }
+    if (m % 4 == 0) {
+        r.push_back(4);
+        m /= 4;
+    }
+    if (m % 2 == 0) {
+        r.push_back(2);
+        m /= 2;
+    }
+    for (int p : {7, 5, 3})
+        while (m % p == 0) {
+            r.push_back(p);
+            m /= p;
+        }
+    return m == 1;
+}
+
+// elements a block of `nt` threads can transform in LDS (16 per thread,
+// rounded down to whole butterflies of every radix used)
+inline int lds_fft_cap(int n, int nt)
+{
+    std::vector<int> r;
+    if (!factor_radices(n, r)) return 0;
+    int per = 16;
+    for (int x : r) per = std::min(per, (16 / x) * x);
+    return per * nt;
+}
+
+inline int bits_for(long long nkeys)
+{
+    int b = 4;
+    while ((1LL << b) < nkeys) b += 4;
+    return b;
+}
+
+inline int ncomp_in(int family) { return family == 0 ? 7 : family == 1 ? 13 : 5; }
+
+// relative truncation estimates (paper Tables 1 and 2), sources and images
+// counted, normalised by sqrt(Q)/L; R in Table 1 taken as sqrt(6) L
+inline double est_fourier_rel(int family, double k, double xi, double L)
+{
+    const double pi = 3.14159265358979323846;
+    double e = std::exp(-k * k / (4 * xi * xi));
+    double R = std::sqrt(6.0) * L;
+    if (family == 0) return std::sqrt(2.0) * R * k * k * k / (xi * xi * pi) * e;
+    if (family == 1) return std::sqrt(7.0 / 3.0) * R * k * k * k * k / (xi * xi * pi) * e;
+    return std::sqrt(16.0 * xi * xi / (3.0 * pi * L * k)) * e;
+}
+
+inline double est_real_rel(int family, double rc, double xi, double L)
+{
+    double e = std::exp(-xi * xi * rc * rc);
+    if (family == 0) return std::sqrt(8.0 * rc / L) * e;
+    if (family == 1) return std::sqrt(224.0 * xi * xi * xi * xi * rc * rc * rc / (9.0 * L)) * e;
+    return std::sqrt(16.0 / (3.0 * L * rc)) * e;
+}
+
+inline double xi_for_cutoff(int family, double rc, double tol, double L)
+{
+    if (!(rc > 0) || !(tol > 0) || !(L > 0) || family < 0 || family > 2) return -1.0;
+    // bisection on xi in (0, 100 / rc]: the estimate decreases for xi rc > ~1
+    double lo = 0.5 / rc, hi = 100.0 / rc;
+    for (int it = 0; it < 200; ++it) {
+        double mid = 0.5 * (lo + hi);
+        if (est_real_rel(family, rc, mid, L) > 0.5 * tol)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    return hi;
+}
+
+struct PlanInput {
+    int family;
+    long long N, T;
+    double xi, rc, tol;
+    double lo[3], hi[3];
+    double Q;
+    int prec;  // 0 auto, 1 fp64, 2 fp32
+    int force_M, force_P, force_Mt;
+};
+
+struct Plan {
+    int family, prec;
+    long long N, T;
+    double xi, rc, tol;
+    double L, h, Lt, eta, Q;
+    int M, P, Mt, Qz, nf, nf3, ncin;
+    bool resident;
+    double est_r, est_f;
+    CellGeom cg;
+    long long ncell;
+    GridArgs g;
+    long long ntiles;
+    int Bx, By;
+    long long max_chunks;
+    int warnings;
+};
+
+constexpr int EHS_MT_MAX = 2048;
+
+inline int choose_lines(int Mt, size_t esz, bool even)
+{
+    int cap = lds_fft_cap(Mt, 512);
+    int B = std::min(cap / Mt, 32);
+    if (even) B &= ~1;
+    while (B > (even ? 2 : 1) && (size_t)B * (Mt + 1) * 2 * esz > 96 * 1024) B -= even ? 2 : 1;
+    return B;
+}
+
+inline int make_plan(const PlanInput& in, Plan* out)
+{
+    Plan p;
+    std::memset(&p, 0, sizeof(p));
+    p.family = in.family;
+    p.N = in.N;
+    p.T = in.T;
+    p.xi = in.xi;
+    p.rc = in.rc;
+    p.tol = in.tol;
+    p.Q = in.Q;
+    p.ncin = ncomp_in(in.family);
+    p.prec = in.prec == 0 ? (in.tol >= 1e-5 ? 2 : 1) : in.prec;
+    const double pi = 3.14159265358979323846;
+    double ext1 = in.hi[0] - in.lo[0], ext2 = in.hi[1] - in.lo[1], ext3 = in.hi[2];
+    double L = std::max(std::max(ext1, ext2), ext3);
+    if (!(L > 0)) return -3;
+    L *= 1.0 + 1e-12;
+    p.L = L;
+    const double xi = in.xi, tol = in.tol;
+
+    // Gaussian support
+    int P = in.force_P;
+    if (P <= 0) {
+        P = 4;
+        while (std::exp(-pi * P * C_SHAPE * C_SHAPE / 2) > tol / 4) P += 2;
+    }
+    if (P < 2 || P > 30 || (P & 1)) return -1;
+    // grid intervals over the box
+    int M = in.force_M;
+    if (M <= 0) {
+        M = 4;
+        while (est_fourier_rel(in.family, pi * M / L, xi, L) > tol / 4) {
+            if (++M > EHS_MT_MAX) return -3;
+        }
+        while (P * xi * xi * (L / M) * (L / M) / (C_SHAPE * C_SHAPE * pi) >= 0.95) {
+            if (++M > EHS_MT_MAX) return -3;
+        }
+    }
+    double h = L / M;
+    double eta = P * xi * xi * h * h / (C_SHAPE * C_SHAPE * pi);
+    if (!(eta < 1.0)) return -3;
+    double m = std::sqrt(2.0 * std::log(1.0 / tol));
+    int ext = std::max(P, (int)std::ceil(m / (std::sqrt(2.0) * xi * h)));
+    int Mt = in.force_Mt > 0 ? in.force_Mt : next_smooth_even(M + ext);
+    if (Mt < M + P || (Mt & 1) || !smooth7(Mt) || Mt > EHS_MT_MAX) return -3;
+    p.M = M;
+    p.P = P;
+    p.Mt = Mt;
+    p.h = h;
+    p.Lt = Mt * h;
+    p.eta = eta;
+    p.nf = next_smooth_even((1.0 + std::sqrt(6.0)) * Mt);
+    p.nf3 = next_smooth_even((2.0 + std::sqrt(6.0)) * Mt);
+    // the precompute transforms one line of each length per 256-thread block
+    for (int n : {p.nf, p.nf3, 2 * Mt, 4 * Mt})
+        if (n > lds_fft_cap(n, 256)) return -3;
+    p.est_f = est_fourier_rel(in.family, pi / h, xi, L);
+    p.est_r = est_real_rel(in.family, in.rc, xi, L);
+    if (p.est_r > tol / 2) p.warnings |= 1;
+
+    // fused x3 pass: smallest number of phases that fits registers and LDS
+    const size_t esz = p.prec == 1 ? 8 : 4;
+    const int nl = std::max(p.ncin, 6);
+    p.Qz = 0;
+    for (int Q : {2, 4, 8}) {
+        if ((4 * Mt) % Q) continue;
+        int nq = 4 * Mt / Q;
+        if (!smooth7(nq)) continue;
+        if (nl * nq > lds_fft_cap(nq, 512)) continue;
+        if (z_lds_bytes(in.family, Mt, Q, esz) > 150 * 1024) continue;
+        p.Qz = Q;
+        break;
+    }
+    if (!p.Qz) return -3;
+    p.resident = z_resident_ok(in.family, Mt);
+    p.Bx = choose_lines(Mt, esz, true);
+    p.By = choose_lines(Mt, esz, false);
+    if (p.Bx < 2 || p.By < 1) return -3;
+
+    // real-space cells (side >= r_c; x3 measured from the wall)
+    double extent[3] = {ext1, ext2, ext3};
+    long long ncell = 1;
+    for (int a = 0; a < 3; ++a) {
+        int nc = (int)std::floor(extent[a] / in.rc);
+        nc = std::max(1, std::min(nc, 256));
+        p.cg.nc[a] = nc;
+        p.cg.lo[a] = a < 2 ? in.lo[a] : 0.0;
+        double side = extent[a] > 0 ? extent[a] / nc : 1.0;
+        p.cg.inv[a] = 1.0 / side;
+        ncell *= nc;
+    }
+    p.ncell = ncell;
+    p.max_chunks = (in.T + 63) / 64 + std::min(ncell, in.T);
+
+    // spreading tiles
+    GridArgs& g = p.g;
+    g.Mt = Mt;
+    g.P = P;
+    g.o[0] = in.lo[0] - P * h / 2;
+    g.o[1] = in.lo[1] - P * h / 2;
+    g.o[2] = -p.Lt;
+    g.h = h;
+    g.a2 = 2 * xi * xi / eta;
+    g.pref = std::pow(2 * xi * xi / (pi * eta), 1.5);
+    int tz = in.family == 1 ? 4 : 8;
+    int dims[3] = {Mt, Mt, 2 * Mt};
+    int tl[3] = {8, 8, tz};
+    p.ntiles = 1;
+    for (int a = 0; a < 3; ++a) {
+        g.tile[a] = tl[a];
+        g.nt[a] = (dims[a] + tl[a] - 1) / tl[a];
+        g.K[a] = (P - 1 + tl[a] - 1) / tl[a];
+        p.ntiles *= g.nt[a];
+    }
+    *out = p;
+    return 0;
+}
+
+}  // namespace ehs

@@ -1,0 +1,256 @@
+// Real-space (short-range) part of the half-space Ewald sum.
+//
+// One wavefront per chunk of <= 64 targets of one cell (cells have side
+// >= r_c).  All lanes walk the same neighbour-cell source ranges, so source
+// loads are wave-uniform; each lane accumulates its own target.  Direct terms
+// use the Ewald real-space kernels S_R, T_R, W_R (paper Sec. 4 and Appendix);
+// image and correction terms use the same kernels at r~ = x - y^I together
+// with the real-space parts of G, grad G, grad grad G and grad grad grad G
+// (paper eq. (G_R), written with erfc instead of 1 - erf).  Only targets in
+// the bottom cell layer can be within r_c of an image.
+#include <math.h>
+
+#include "common.h"
+#include "kernels.h"
+
+namespace ehs {
+
+template <typename T>
+__device__ __forceinline__ T t_erfc(T x);
+template <>
+__device__ __forceinline__ double t_erfc<double>(double x) { return erfc(x); }
+template <>
+__device__ __forceinline__ float t_erfc<float>(float x) { return erfcf(x); }
+template <typename T>
+__device__ __forceinline__ T t_exp(T x);
+template <>
+__device__ __forceinline__ double t_exp<double>(double x) { return exp(x); }
+template <>
+__device__ __forceinline__ float t_exp<float>(float x) { return expf(x); }
+template <typename T>
+__device__ __forceinline__ T t_sqrt(T x);
+template <>
+__device__ __forceinline__ double t_sqrt<double>(double x) { return sqrt(x); }
+template <>
+__device__ __forceinline__ float t_sqrt<float>(float x) { return sqrtf(x); }
+
+// direct term K_R(r) s, r != 0
+template <typename T, int K>
+__device__ __forceinline__ void direct_term(T rx, T ry, T rz, T r2, const T* s, T xi, T c2, T* acc)
+{
+    T r = t_sqrt<T>(r2);
+    T ir = (T)1 / r;
+    T E = t_exp<T>(-xi * xi * r2);
+    T C = t_erfc<T>(xi * r);
+    if (K == STOKESLET) {
+        // S_R f = (a - 2 c2 E) f + a (r.f) r / r^2,  a = c2 E + C / r
+        T a = c2 * E + C * ir;
+        T rf = rx * s[0] + ry * s[1] + rz * s[2];
+        T b = a * rf * ir * ir;
+        T d = a - (T)2 * c2 * E;
+        acc[0] += d * s[0] + b * rx;
+        acc[1] += d * s[1] + b * ry;
+        acc[2] += d * s[2] + b * rz;
+    } else if (K == STRESSLET) {
+        // T_R[S] = A (r.S r) r + Bc (2 S r + r tr S)
+        T ir2 = ir * ir;
+        T A = (T)-2 * ir2 * ir2 * ((T)3 * C * ir + c2 * ((T)3 + (T)2 * xi * xi * r2) * E);
+        T Bc = (T)2 * xi * xi * c2 * E;
+        T sr0 = s[0] * rx + s[1] * ry + s[2] * rz;
+        T sr1 = s[1] * rx + s[3] * ry + s[4] * rz;
+        T sr2 = s[2] * rx + s[4] * ry + s[5] * rz;
+        T rsr = rx * sr0 + ry * sr1 + rz * sr2;
+        T tr = s[0] + s[3] + s[5];
+        T g = A * rsr;
+        acc[0] += g * rx + Bc * ((T)2 * sr0 + rx * tr);
+        acc[1] += g * ry + Bc * ((T)2 * sr1 + ry * tr);
+        acc[2] += g * rz + Bc * ((T)2 * sr2 + rz * tr);
+    } else {
+        // W_R v = 2 alpha (v x r), alpha = C / r^3 + c2 E / r^2
+        T al = (T)2 * (C * ir * ir * ir + c2 * E * ir * ir);
+        acc[0] += al * (s[1] * rz - s[2] * ry);
+        acc[1] += al * (s[2] * rx - s[0] * rz);
+        acc[2] += al * (s[0] * ry - s[1] * rx);
+    }
+}
+
+// image kernel term plus the harmonic corrections -x3 grad phi_R + e3 phi_R
+// of one source (strength s, height y3) at r~ = x - y^I
+template <typename T, int K>
+__device__ __forceinline__ void image_term(T rx, T ry, T rz, T r2, const T* s, T y3, T x3, T xi, T c2, T* acc)
+{
+    T r = t_sqrt<T>(r2);
+    T ir = (T)1 / r;
+    T ir2 = ir * ir;
+    T E = t_exp<T>(-xi * xi * r2);
+    T C = t_erfc<T>(xi * r);
+    T xi2 = xi * xi;
+    // grad G_R = -alpha r, grad grad G_R = -alpha I + beta r r,
+    // grad grad grad G_R = beta (d r)_sym + gamma r r r
+    T al = C * ir2 * ir + c2 * E * ir2;
+    T be = (T)3 * C * ir2 * ir2 * ir + c2 * E * ((T)3 * ir2 * ir2 + (T)2 * xi2 * ir2);
+    T phi, g0, g1, g2;
+    if (K == STOKESLET) {
+        T f0 = s[0], f1 = s[1], f2 = -s[2];  // f^I
+        T a = c2 * E + C * ir;
+        T rf = rx * f0 + ry * f1 + rz * f2;
+        T b = a * rf * ir2;
+        T d = a - (T)2 * c2 * E;
+        acc[0] -= d * f0 + b * rx;
+        acc[1] -= d * f1 + b * ry;
+        acc[2] -= d * f2 + b * rz;
+        // phi = -2 f3 G_R - 2 y3 f^I . grad G_R
+        T f3 = s[2];
+        phi = (T)-2 * f3 * C * ir + (T)2 * y3 * al * rf;
+        T u = (T)2 * f3 * al - (T)2 * y3 * be * rf;
+        T v = (T)2 * y3 * al;
+        g0 = u * rx + v * f0;
+        g1 = u * ry + v * f1;
+        g2 = u * rz + v * f2;
+    } else if (K == STRESSLET) {
+        // S^I = R S R: flip the xz, yz entries
+        T s0 = s[0], s1 = s[1], s2 = -s[2], s3 = s[3], s4 = -s[4], s5 = s[5];
+        T A = (T)-2 * ir2 * ir2 * ((T)3 * C * ir + c2 * ((T)3 + (T)2 * xi2 * r2) * E);
+        T Bc = (T)2 * xi2 * c2 * E;
+        T sr0 = s0 * rx + s1 * ry + s2 * rz;
+        T sr1 = s1 * rx + s3 * ry + s4 * rz;
+        T sr2 = s2 * rx + s4 * ry + s5 * rz;
+        T rsr = rx * sr0 + ry * sr1 + rz * sr2;
+        T tr = s0 + s3 + s5;
+        T gk = A * rsr;
+        acc[0] -= gk * rx + Bc * ((T)2 * sr0 + rx * tr);
+        acc[1] -= gk * ry + Bc * ((T)2 * sr1 + ry * tr);
+        acc[2] -= gk * rz + Bc * ((T)2 * sr2 + rz * tr);
+        T ga = (T)-15 * C * ir2 * ir2 * ir2 * ir -
+               c2 * E * ((T)15 * ir2 * ir2 * ir2 + (T)10 * xi2 * ir2 * ir2 + (T)4 * xi2 * xi2 * ir2);
+        // phi = 4 tr dG_R/dx3 - 4 y3 grad grad G_R : S^I
+        phi = (T)-4 * al * rz * tr + (T)4 * y3 * al * tr - (T)4 * y3 * be * rsr;
+        // grad phi = 4 tr (-alpha e3 + beta r3 r) - 4 y3 [beta (tr r + 2 S^I r) + gamma (r.S^I r) r]
+        T u = (T)4 * tr * be * rz - (T)4 * y3 * (be * tr + ga * rsr);
+        T v = (T)-8 * y3 * be;
+        g0 = u * rx + v * sr0;
+        g1 = u * ry + v * sr1;
+        g2 = u * rz + v * sr2 - (T)4 * tr * al;
+    } else {
+        // + W_R(r~) v^I
+        T v0 = s[0], v1 = s[1], v2 = -s[2];
+        T a2 = (T)2 * al;
+        acc[0] += a2 * (v1 * rz - v2 * ry);
+        acc[1] += a2 * (v2 * rx - v0 * rz);
+        acc[2] += a2 * (v0 * ry - v1 * rx);
+        // w = 2 (-v2, v1, 0); phi = 2 w . grad G_R; grad phi = 2 grad grad G_R w
+        T w0 = (T)-2 * s[1], w1 = (T)2 * s[0];
+        T rw = rx * w0 + ry * w1;
+        phi = (T)-2 * al * rw;
+        T u = (T)2 * be * rw;
+        g0 = u * rx - (T)2 * al * w0;
+        g1 = u * ry - (T)2 * al * w1;
+        g2 = u * rz;
+    }
+    acc[0] -= x3 * g0;
+    acc[1] -= x3 * g1;
+    acc[2] += phi - x3 * g2;
+}
+
+template <typename T, int K>
+__global__ void __launch_bounds__(256) k_realspace(RealArgs a, const double* __restrict__ ys,
+                                                   const double* __restrict__ ss, const double* __restrict__ xt,
+                                                   double* __restrict__ upart)
+{
+    constexpr int NS = (K == STRESSLET) ? 6 : 3;
+    const int lane = threadIdx.x & 63;
+    const long long w = blockIdx.x * 4LL + (threadIdx.x >> 6);
+    if (w >= (long long)(*a.nchunks)) return;
+    const uint32_t cell = a.chunk_cell[w];
+    const uint32_t first = a.chunk_first[w];
+    const int cnt = (int)min(64u, a.tgt_off[cell + 1] - first);
+    const bool act = lane < cnt;
+    const long long t = first + (act ? lane : 0);
+    const long long N = a.N, TT = a.T;
+    const double xd0 = xt[t], xd1 = xt[TT + t], xd2 = xt[2 * TT + t];
+    const int n0 = a.cg.nc[0], n1 = a.cg.nc[1], n2 = a.cg.nc[2];
+    const int c1 = (int)(cell % (uint32_t)n0);
+    const int c2i = (int)((cell / (uint32_t)n0) % (uint32_t)n1);
+    const int c3 = (int)(cell / ((uint32_t)n0 * (uint32_t)n1));
+    const T xi = (T)a.xi;
+    const T c2 = (T)(2.0 * a.xi / 1.7724538509055160273);
+    const double rc2 = a.rc2;
+    T acc[3] = {0, 0, 0};
+    double self[3] = {0.0, 0.0, 0.0};
+    const int lo1 = c1 > 0 ? c1 - 1 : 0, hi1 = c1 < n0 - 1 ? c1 + 1 : n0 - 1;
+    for (int d3 = -1; d3 <= 1; ++d3) {
+        int cc3 = c3 + d3;
+        if (cc3 < 0 || cc3 >= n2) continue;
+        for (int d2 = -1; d2 <= 1; ++d2) {
+            int cc2 = c2i + d2;
+            if (cc2 < 0 || cc2 >= n1) continue;
+            long long row = ((long long)cc3 * n1 + cc2) * n0;
+            uint32_t s0 = a.src_off[row + lo1], s1 = a.src_off[row + hi1 + 1];
+            for (uint32_t m = s0; m < s1; ++m) {
+                double dx = xd0 - ys[m], dy = xd1 - ys[N + m], dz = xd2 - ys[2 * N + m];
+                double r2 = dx * dx + dy * dy + dz * dz;
+                if (r2 < rc2) {
+                    if (r2 > 0.0) {
+                        T sv[NS];
+#pragma unroll
+                        for (int c = 0; c < NS; ++c) sv[c] = (T)ss[c * N + m];
+                        direct_term<T, K>((T)dx, (T)dy, (T)dz, (T)r2, sv, xi, c2, acc);
+                    } else if (K == STOKESLET) {
+                        // self interaction: limit of S_R - S at r = 0 is -(4 xi / sqrt(pi)) I
+                        double cs = 4.0 * a.xi / 1.7724538509055160273;
+                        self[0] -= cs * ss[m];
+                        self[1] -= cs * ss[N + m];
+                        self[2] -= cs * ss[2 * N + m];
+                    }
+                }
+            }
+        }
+    }
+    if (c3 == 0) {
+        const T x3 = (T)xd2;
+        for (int d2 = -1; d2 <= 1; ++d2) {
+            int cc2 = c2i + d2;
+            if (cc2 < 0 || cc2 >= n1) continue;
+            long long row = (long long)cc2 * n0;
+            uint32_t s0 = a.src_off[row + lo1], s1 = a.src_off[row + hi1 + 1];
+            for (uint32_t m = s0; m < s1; ++m) {
+                double y3 = ys[2 * N + m];
+                double dx = xd0 - ys[m], dy = xd1 - ys[N + m], dz = xd2 + y3;
+                double r2 = dx * dx + dy * dy + dz * dz;
+                if (r2 < rc2) {
+                    T sv[NS];
+#pragma unroll
+                    for (int c = 0; c < NS; ++c) sv[c] = (T)ss[c * N + m];
+                    image_term<T, K>((T)dx, (T)dy, (T)dz, (T)r2, sv, (T)y3, x3, xi, c2, acc);
+                }
+            }
+        }
+    }
+    if (act) {
+        long long o = a.tgt_perm[t];
+        upart[3 * o + 0] = (double)acc[0] + self[0];
+        upart[3 * o + 1] = (double)acc[1] + self[1];
+        upart[3 * o + 2] = (double)acc[2] + self[2];
+    }
+}
+
+template <typename T>
+hipError_t launch_realspace(int family, const RealArgs& a, const double* ys, const double* ss, const double* xt,
+                            double* upart, long long max_chunks, hipStream_t st)
+{
+    if (max_chunks <= 0) return hipSuccess;
+    dim3 grid((unsigned)((max_chunks + 3) / 4));
+    switch (family) {
+        case STOKESLET: hipLaunchKernelGGL((k_realspace<T, STOKESLET>), grid, dim3(256), 0, st, a, ys, ss, xt, upart); break;
+        case STRESSLET: hipLaunchKernelGGL((k_realspace<T, STRESSLET>), grid, dim3(256), 0, st, a, ys, ss, xt, upart); break;
+        default: hipLaunchKernelGGL((k_realspace<T, ROTLET>), grid, dim3(256), 0, st, a, ys, ss, xt, upart); break;
+    }
+    return hipGetLastError();
+}
+
+template hipError_t launch_realspace<double>(int, const RealArgs&, const double*, const double*, const double*,
+                                             double*, long long, hipStream_t);
+template hipError_t launch_realspace<float>(int, const RealArgs&, const double*, const double*, const double*, double*,
+                                            long long, hipStream_t);
+
+}  // namespace ehs

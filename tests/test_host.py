@@ -1,0 +1,165 @@
+"""Host-side checks of the library (no GPU needed).
+
+* the C ABI loads and exports every entry point that include/ehs.h declares;
+* the truncated Green's function transforms (paper Sec. 5.2) against 1D
+  radial quadrature and their k -> 0 limits;
+* parameter selection (plan) invariants and argument errors.
+"""
+import ctypes
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+from scipy import integrate
+
+import paper_1802_07844_amd as ehs
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_symbols():
+    text = open(os.path.join(ROOT, "include", "ehs.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b((?:ehs|ewald)_\w+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ehs.lib()
+    syms = _declared_symbols()
+    assert "ewald_halfspace_stokeslet" in syms and "ehs_create" in syms
+    for s in syms:
+        assert hasattr(lib, s), f"{s} declared in ehs.h but not exported"
+
+
+def test_strerror_codes():
+    for code in (0, -1, -2, -3, -4, -5):
+        assert len(ehs.strerror(code)) > 4
+    assert "unknown" in ehs.strerror(-99)
+
+
+def _quad_H(k, R):
+    # FT of 1/r restricted to r < R: (4 pi / k) int_0^R sin(k r) dr
+    v, _ = integrate.quad(lambda r: math.sin(k * r), 0.0, R, limit=400)
+    return 4 * math.pi / k * v
+
+
+def _quad_B(k, R):
+    # FT of r restricted to r < R: (4 pi / k) int_0^R r^2 sin(k r) dr
+    v, _ = integrate.quad(lambda r: r * r * math.sin(k * r), 0.0, R, limit=400)
+    return 4 * math.pi / k * v
+
+
+@pytest.mark.parametrize("R", [0.7, 2.449, 5.0])
+@pytest.mark.parametrize("k", [1e-3, 0.05, 0.3, 1.0, 3.7, 12.0, 41.0])
+def test_truncated_kernels_match_radial_quadrature(R, k):
+    for kind, q in ((0, _quad_H), (1, _quad_B)):
+        ref = q(k, R)
+        got = ehs.truncated_kernel_hat(kind, k, R)
+        scale = 2 * math.pi * R * R if kind == 0 else math.pi * R**4
+        assert abs(got - ref) <= 1e-10 * scale, (kind, k, R, got, ref)
+
+
+@pytest.mark.parametrize("R", [0.5, 2.449])
+def test_truncated_kernels_limits_at_zero(R):
+    assert ehs.truncated_kernel_hat(0, 0.0, R) == pytest.approx(2 * math.pi * R * R, rel=1e-15)
+    assert ehs.truncated_kernel_hat(1, 0.0, R) == pytest.approx(math.pi * R**4, rel=1e-15)
+    # continuity across the switch between series and closed form (R k = 0.5)
+    for kind in (0, 1):
+        a = ehs.truncated_kernel_hat(kind, (0.5 - 1e-13) / R, R)
+        b = ehs.truncated_kernel_hat(kind, (0.5 + 1e-13) / R, R)
+        assert abs(a - b) <= 1e-12 * abs(a)
+
+
+def test_xi_for_cutoff_monotone():
+    xa = ehs.xi_for_cutoff("stokeslet", 0.1, 1e-10)
+    xb = ehs.xi_for_cutoff("stokeslet", 0.1, 1e-5)
+    xc = ehs.xi_for_cutoff("stokeslet", 0.2, 1e-10)
+    assert xa > xb > 0 and xa > xc > 0
+    # xi r_c of about 4.8 for 1e-10 (exp(-(xi r_c)^2) ~ 1e-10)
+    assert 4.0 < xa * 0.1 < 5.5
+    assert ehs.xi_for_cutoff("rotlet", -1.0, 1e-10) < 0
+
+
+def _plan(family="stokeslet", tol=1e-10, xi=12.0, rc=0.4, n=1000, prec=0, lo=(0, 0, 0), hi=(1, 1, 1)):
+    return ehs.plan_query(family, n, n, lo, hi, 3.0 * n, xi, rc, tol, prec)
+
+
+def _smooth7(n):
+    for p in (2, 3, 5, 7):
+        while n % p == 0:
+            n //= p
+    return n == 1
+
+
+@pytest.mark.parametrize("family", ["stokeslet", "stresslet", "rotlet"])
+@pytest.mark.parametrize("tol", [1e-10, 1e-5])
+def test_plan_invariants(family, tol):
+    r = _plan(family, tol)
+    # Gaussian support from exp(-pi P c^2 / 2) <= tol / 4 with c = 0.95
+    assert r.P == (18 if tol == 1e-10 else 10)
+    assert r.Mt % 2 == 0 and _smooth7(r.Mt) and r.Mt >= r.M + r.P
+    assert 0.0 < r.eta < 1.0
+    assert r.precision == (1 if tol < 1e-5 else 2)
+    assert r.h == pytest.approx(r.L / r.M)
+    assert r.Lt == pytest.approx(r.Mt * r.h)
+    assert r.est_fourier <= tol / 4
+    # the wall is a grid node: origin x3 = -M~ h
+    assert r.origin[2] == pytest.approx(-r.Lt)
+    assert r.nf >= (1 + math.sqrt(6)) * r.Mt and r.nf3 >= (2 + math.sqrt(6)) * r.Mt
+    assert r.workspace_bytes > 0
+
+
+def test_plan_errors():
+    with pytest.raises(ehs.EhsError) as e:
+        _plan(tol=1e-1)
+    assert e.value.code == ehs.EHS_EINVAL
+    with pytest.raises(ehs.EhsError) as e:
+        _plan(xi=-1.0)
+    assert e.value.code == ehs.EHS_EINVAL
+    # a grid far beyond the supported size
+    with pytest.raises(ehs.EhsError) as e:
+        _plan(xi=4000.0, rc=0.001)
+    assert e.value.code == ehs.EHS_ERANGE
+
+
+def test_plan_box_covers_points_and_margin():
+    r = _plan(lo=(0.25, -0.5, 0), hi=(0.9, 0.2, 0.8))
+    L = max(0.65, 0.7, 0.8)
+    assert r.L == pytest.approx(L, rel=1e-9)
+    # in-plane origin half a support below the lowest point
+    assert r.origin[0] == pytest.approx(0.25 - r.P * r.h / 2)
+    assert r.origin[1] == pytest.approx(-0.5 - r.P * r.h / 2)
+    # the screening margin: (M~ - M) h >= sqrt(2 ln(1/tol)) / (sqrt2 xi)
+    assert (r.Mt - r.M) * r.h >= math.sqrt(2 * math.log(1e10)) / (math.sqrt(2) * 12.0) - 1e-12
+
+
+def test_create_without_device_fails_cleanly():
+    """On a host without a GPU, context creation returns an error code."""
+    import torch
+
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    h = ctypes.c_void_p()
+    rc = ehs.lib().ehs_create(ctypes.byref(h), 0, 0)
+    assert rc != 0 and not h.value
+
+
+@pytest.mark.parametrize("family", ["stokeslet", "stresslet", "rotlet"])
+@pytest.mark.parametrize("prec", [1, 2])
+def test_plan_sweep_passes_extent_audit(family, prec):
+    """Every plan over a sweep of sizes passes the library's buffer-extent audit."""
+    tol = 1e-10 if prec == 1 else 1e-5
+    for n, t in ((1, 1), (2, 5), (300, 300), (1000, 77), (100_000, 100_000), (1_000_000, 1_000_000)):
+        for nb in (30, 300, 2000):
+            rc = (nb * 3.0 / (4.0 * math.pi * n)) ** (1.0 / 3.0)
+            xi = ehs.xi_for_cutoff(family, rc, tol)
+            try:
+                r = ehs.plan_query(family, n, t, (0, 0, 0), (1, 1, 1), 3.0 * n, xi, rc, tol, prec)
+            except ehs.EhsError as e:
+                # only "grid too large" is acceptable, never an internal inconsistency
+                assert e.code == ehs.EHS_ERANGE
+                assert (math.pi / (1.0 / 2048)) < 7 * xi or nb == 30
+                continue
+            assert r.workspace_bytes > 0 and r.Mt >= r.M + r.P
