@@ -3,8 +3,11 @@
 // Given xi and r_c from the caller and the target relative RMS error tol:
 //  * M (grid intervals over the box L) from the Fourier truncation estimate
 //    of the paper's Table 1 with k_inf = pi / h = pi M / L, sources and images
-//    counted (Q -> 2Q), budget tol/4 relative to sqrt(Q)/L;
-//  * P (Gaussian support, even) from exp(-pi P c^2 / 2) <= tol/4, c = 0.95,
+//    counted (Q -> 2Q), budget tol/4 relative to sqrt(Q)/L (tol/40 for the
+//    rotlet, whose correction terms are of the same order as the kernel and
+//    are not covered by the free-space estimate -- paper Sec. 6);
+//  * P (Gaussian support, even) from exp(-pi P c^2 / 2) <= tol/40 (tol/4 when
+//    tol >= 1e-6, where the FP32 rounding dominates), c = 0.95,
 //    eta = P xi^2 h^2 / (c^2 pi) (Algorithm 1 step 4), M raised until eta < 0.95;
 //  * the box is extended by max(P, m / (sqrt2 xi h)) nodes with
 //    m = sqrt(2 ln(1/tol)): the Gaussian support of Algorithm 1 step 3 plus a
@@ -189,14 +192,16 @@ inline int make_plan(const PlanInput& in, Plan* out)
     int P = in.force_P;
     if (P <= 0) {
         P = 4;
-        while (std::exp(-pi * P * C_SHAPE * C_SHAPE / 2) > tol / 4) P += 2;
+        const double pbudget = tol < 1e-6 ? tol / 40 : tol / 4;
+        while (std::exp(-pi * P * C_SHAPE * C_SHAPE / 2) > pbudget) P += 2;
     }
     if (P < 2 || P > 30 || (P & 1)) return -1;
     // grid intervals over the box
     int M = in.force_M;
     if (M <= 0) {
         M = 4;
-        while (est_fourier_rel(in.family, pi * M / L, xi, L) > tol / 4) {
+        const double budget = in.family == 2 ? tol / 40 : tol / 4;
+        while (est_fourier_rel(in.family, pi * M / L, xi, L) > budget) {
             if (++M > EHS_MT_MAX) return -3;
         }
         while (P * xi * xi * (L / M) * (L / M) / (C_SHAPE * C_SHAPE * pi) >= 0.95) {

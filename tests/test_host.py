@@ -97,14 +97,14 @@ def _smooth7(n):
 @pytest.mark.parametrize("tol", [1e-10, 1e-5])
 def test_plan_invariants(family, tol):
     r = _plan(family, tol)
-    # Gaussian support from exp(-pi P c^2 / 2) <= tol / 4 with c = 0.95
-    assert r.P == (18 if tol == 1e-10 else 10)
+    # Gaussian support from exp(-pi P c^2 / 2) <= tol / 40 (tol / 4 for tol >= 1e-6), c = 0.95
+    assert r.P == (20 if tol == 1e-10 else 10)
     assert r.Mt % 2 == 0 and _smooth7(r.Mt) and r.Mt >= r.M + r.P
     assert 0.0 < r.eta < 1.0
     assert r.precision == (1 if tol < 1e-5 else 2)
     assert r.h == pytest.approx(r.L / r.M)
     assert r.Lt == pytest.approx(r.Mt * r.h)
-    assert r.est_fourier <= tol / 4
+    assert r.est_fourier <= (tol / 40 if family == "rotlet" else tol / 4)
     # the wall is a grid node: origin x3 = -M~ h
     assert r.origin[2] == pytest.approx(-r.Lt)
     assert r.nf >= (1 + math.sqrt(6)) * r.Mt and r.nf3 >= (2 + math.sqrt(6)) * r.Mt
