@@ -75,7 +75,8 @@ def main():
     # r_c for ~30 neighbours in the unit box, xi from the real-space estimate
     rc = (args.neighbours * 3.0 / (4.0 * math.pi * n)) ** (1.0 / 3.0)
     tol = 1e-10
-    xi = ehs.xi_for_cutoff("stokeslet", rc, tol)
+    # the real-space estimate takes a quarter of the budget (xi_for_cutoff gives estimate = tol'/2)
+    xi = ehs.xi_for_cutoff("stokeslet", rc, tol / 2)
 
     ctx = ehs.Context(0)
     ctx.set_option(ehs.OPT_PRECISION, 1)
@@ -133,7 +134,7 @@ def main():
     if not args.no_fp32:
         tol32 = 1e-5
         ctx.set_option(ehs.OPT_PRECISION, 2)
-        xi32 = ehs.xi_for_cutoff("stokeslet", rc, tol32)
+        xi32 = ehs.xi_for_cutoff("stokeslet", rc, tol32 / 2)
         out32 = torch.empty_like(out)
 
         def step32():
