@@ -158,8 +158,11 @@ int ehs_plan_query(int family, int64_t N, int64_t T, const double* lo, const dou
 
 /*
  * Truncated Green's function transforms of Sec. 5.2 evaluated on the host:
- * kind 0: H^R(k) = 8 pi sin^2(R k / 2) / k^2; kind 1: B^R(k) =
- * 4 pi [(2 - R^2 k^2) cos Rk + 2 Rk sin Rk - 2] / k^4 (series near k = 0).
+ * kind 0: H^R(k) = 8 pi sin^2(R k / 2) / k^2, the transform of (1/r) 1[r < R];
+ * kind 1: the transform of the biharmonic kernel shifted by a constant,
+ * (r - R) 1[r < R]: 4 pi [2 cos Rk + Rk sin Rk - 2] / k^4 (series near
+ * k = 0).  The shift is invisible to the second and third derivatives
+ * through which the biharmonic kernel enters.
  */
 double ehs_truncated_kernel_hat(int kind, double k, double R);
 

@@ -91,7 +91,16 @@ int fft_plan(ehs_ctx* c, int n, int esz, FftPlanDev* p)
     std::memset(p, 0, sizeof(*p));
     p->n = n;
     p->nst = (int)r.size();
-    for (size_t i = 0; i < r.size(); ++i) p->rad[i] = r[i];
+    int ns = 1;
+    for (size_t i = 0; i < r.size(); ++i) {
+        p->rad[i] = r[i];
+        p->ns[i] = ns;
+        p->mns[i] = magic_of((unsigned)ns);
+        p->nb[i] = n / r[i];
+        p->mnb[i] = magic_of((unsigned)(n / r[i]));
+        p->tstr[i] = n / (ns * r[i]);
+        ns *= r[i];
+    }
     void* t = nullptr;
     int rc = tw_table(c, n, esz, &t);
     if (rc) return rc;
@@ -241,8 +250,12 @@ int check_extents(const Plan& p, const Layout& L, size_t esz)
     ok = ok && (4 * p.Mt) % p.Qz == 0 && z_lds_bytes(p.family, p.Mt, p.Qz, esz) <= 160 * 1024 &&
          std::max(p.ncin, 6) * nq <= lds_fft_cap(nq, 512);
     // x / y passes: B lines of Mt in LDS and in the 16-element register budget
-    ok = ok && p.Bx * p.Mt <= lds_fft_cap(p.Mt, 512) && p.By * p.Mt <= lds_fft_cap(p.Mt, 512) &&
-         p.Bx * p.Mt <= 16 * 512 && p.By * p.Mt <= 16 * 512 && (p.Bx % 2) == 0;
+    ok = ok && p.Bx * p.Mt <= lds_fft_cap(p.Mt, 512) && 2 * p.By * p.Mt <= lds_fft_cap(p.Mt, 512) &&
+         (p.Bx % 2) == 0 && p.By >= 1 && (size_t)2 * p.By * (p.Mt + 1) * c <= 160 * 1024 &&
+         (size_t)p.Bx * (p.Mt + 1) * c <= 160 * 1024;
+    // magic-number division is exact for numerator * divisor < 2^32
+    ok = ok && (long long)(p.Mt + 1) * std::max(p.Bx, 2 * p.By) * std::max(p.Mt, 2 * p.By) < (1LL << 31) &&
+         (long long)std::max(p.ncin, 6) * 2 * p.Mt * 2 * p.Mt < (1LL << 31);
     // gather weights table (3P <= 96) and spread support within the grid
     ok = ok && 3 * p.P <= 96 && p.P <= p.Mt;
     return ok ? EHS_OK : EHS_ERANGE;
@@ -406,12 +419,18 @@ int run(ehs_ctx* c, Plan& p, const double* y, const double* s, const double* x, 
     if ((rc = tw_table(c, 2 * p.Mt, (int)esz, &tw2))) return rc;
     pa.tw2 = tw2;
     if ((rc = fft_plan(c, p.Mt, (int)esz, &pa.fM))) return rc;
-    pa.B = p.Bx;
+    pa.mMt = magic_of((unsigned)p.Mt);
+    auto set_b = [&](int B) {
+        pa.B = B;
+        pa.mB = magic_of((unsigned)B);
+        pa.mB2 = magic_of((unsigned)(B / 2));
+    };
+    set_b(p.Bx);
     pa.cs_in = csR;
     pa.cs_out = csA;
     HIPCHK(launch_fwd_x<T>(X, Yc, pa, p.ncin, st));
     rec_ev(EHS_ST_FWDY);
-    pa.B = p.By;
+    set_b(p.By);
     pa.cs_in = csA;
     pa.cs_out = csZ;
     HIPCHK(launch_fwd_y<T>(Yc, Xc, pa, p.ncin, st));
@@ -422,6 +441,9 @@ int run(ehs_ctx* c, Plan& p, const double* y, const double* s, const double* x, 
     std::memset(&za, 0, sizeof(za));
     za.Mt = p.Mt;
     za.Q = p.Qz;
+    za.mnz = magic_of((unsigned)(2 * p.Mt));
+    za.mnq = magic_of((unsigned)(4 * p.Mt / p.Qz));
+    za.mn4 = magic_of((unsigned)(4 * p.Mt));
     za.cs = csZ;
     za.cs_out = csZ;
     void* tw4 = nullptr;
@@ -445,12 +467,12 @@ int run(ehs_ctx* c, Plan& p, const double* y, const double* s, const double* x, 
     rec_ev(EHS_ST_INVY);
 
     // -- inverse transforms
-    pa.B = p.By;
+    set_b(p.By);
     pa.cs_in = csZ;
     pa.cs_out = csA;
     HIPCHK(launch_inv_y<T>(Zo, Yc, pa, 6, st));
     rec_ev(EHS_ST_INVX);
-    pa.B = p.Bx;
+    set_b(p.Bx);
     pa.cs_in = csA;
     pa.cs_out = csR;
     HIPCHK(launch_inv_x<T>(Yc, X, pa, 6, st));

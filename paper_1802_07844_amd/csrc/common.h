@@ -73,16 +73,27 @@ struct Traits<ROTLET> {
 constexpr int NCOUT = 6;  // Y1 (3) and Y2 (3)
 
 // ---------------------------------------------------------------------------
-// FFT plan for one line length: radices (each 2,3,4,5,7 or 8) and the
-// twiddle table tw[t] = exp(-2 pi i t / n), t < n, in device memory.
+// FFT plan for one line length: radices (each 2,3,4,5,7 or 8), the twiddle
+// table tw[t] = exp(-2 pi i t / n), t < n, in device memory, and for every
+// stage the index divisors with their multiply-high reciprocals (exact for
+// numerators and divisors below 2^16), so that no kernel divides at run time.
 // ---------------------------------------------------------------------------
-constexpr int FFT_MAX_STAGES = 24;
+constexpr int FFT_MAX_STAGES = 16;
 struct FftPlanDev {
     int n;
     int nst;
     int rad[FFT_MAX_STAGES];
-    const void* tw;  // cplx<T>*
+    int ns[FFT_MAX_STAGES];         // product of the radices before the stage
+    unsigned mns[FFT_MAX_STAGES];   // reciprocal of ns (unused when ns == 1)
+    int nb[FFT_MAX_STAGES];         // butterflies per line, n / rad
+    unsigned mnb[FFT_MAX_STAGES];   // reciprocal of nb (unused when nb == 1)
+    int tstr[FFT_MAX_STAGES];       // twiddle stride n / (ns * rad)
+    const void* tw;                 // cplx<T>*
 };
+
+// a / d for a * d < 2^32, with m = floor((2^32 - 1) / d) + 1 (d >= 2)
+__host__ __device__ __forceinline__ unsigned magic_of(unsigned d) { return d > 1 ? 0xFFFFFFFFu / d + 1u : 0u; }
+__device__ __forceinline__ int fdiv(int a, int d, unsigned m) { return d == 1 ? a : (int)__umulhi((unsigned)a, m); }
 
 // radix-R DFT in registers, forward sign exp(-2 pi i k q / R)
 template <typename T, int R>
@@ -201,14 +212,16 @@ struct Dft<T, 7> {
 
 // One Stockham stage of radix R on `nl` lines of length n held in LDS
 // (line q at buf + q * ld).  Every thread of the block calls it; each thread
-// handles up to E/R butterflies held in registers between the two barriers.
+// handles up to E/R butterflies, one after the other, keeping only their
+// outputs in registers until all threads have read their inputs.
 template <typename T, int NT, int E, int R, bool INV>
-__device__ __forceinline__ void fft_stage(cplx<T>* buf, int ld, int nl, int n, int Ns, const cplx<T>* tw)
+__device__ __forceinline__ void fft_stage(cplx<T>* buf, int ld, int nl, const FftPlanDev& p, int st,
+                                          const cplx<T>* __restrict__ tw)
 {
     constexpr int MB = (E / R) > 0 ? (E / R) : 1;
-    const int nb = n / R;
+    const int nb = p.nb[st], Ns = p.ns[st], tstride = p.tstr[st];
+    const unsigned mnb = p.mnb[st], mns = p.mns[st];
     const int total = nl * nb;
-    const int tstride = n / (Ns * R);
     cplx<T> v[MB][R];
     int base[MB];
 #pragma unroll
@@ -216,15 +229,16 @@ __device__ __forceinline__ void fft_stage(cplx<T>* buf, int ld, int nl, int n, i
         int b = threadIdx.x + i * NT;
         base[i] = -1;
         if (b < total) {
-            int line = b / nb;
+            int line = fdiv(b, nb, mnb);
             int j = b - line * nb;
+            int jq = fdiv(j, Ns, mns);
+            int k = j - jq * Ns;
             const cplx<T>* src = buf + line * ld + j;
 #pragma unroll
             for (int q = 0; q < R; ++q) {
                 cplx<T> a = src[q * nb];
                 v[i][q] = INV ? cconj(a) : a;
             }
-            int k = j % Ns;
             if (k != 0) {
                 cplx<T> w1 = tw[k * tstride];
                 cplx<T> w = w1;
@@ -235,8 +249,9 @@ __device__ __forceinline__ void fft_stage(cplx<T>* buf, int ld, int nl, int n, i
                 }
             }
             Dft<T, R>::run(v[i]);
-            base[i] = line * ld + (j / Ns) * Ns * R + k;
+            base[i] = line * ld + jq * Ns * R + k;
         }
+        __builtin_amdgcn_sched_barrier(0);
     }
     __syncthreads();
 #pragma unroll
@@ -257,31 +272,33 @@ template <typename T, int NT, int E, bool INV>
 __device__ void lds_fft(cplx<T>* buf, int ld, int nl, const FftPlanDev& p)
 {
     const cplx<T>* tw = static_cast<const cplx<T>*>(p.tw);
-    int Ns = 1;
     for (int s = 0; s < p.nst; ++s) {
-        int r = p.rad[s];
-        switch (r) {
-            case 2: fft_stage<T, NT, E, 2, INV>(buf, ld, nl, p.n, Ns, tw); break;
-            case 3: fft_stage<T, NT, E, 3, INV>(buf, ld, nl, p.n, Ns, tw); break;
-            case 4: fft_stage<T, NT, E, 4, INV>(buf, ld, nl, p.n, Ns, tw); break;
-            case 5: fft_stage<T, NT, E, 5, INV>(buf, ld, nl, p.n, Ns, tw); break;
-            case 7: fft_stage<T, NT, E, 7, INV>(buf, ld, nl, p.n, Ns, tw); break;
-            default: fft_stage<T, NT, E, 8, INV>(buf, ld, nl, p.n, Ns, tw); break;
+        switch (p.rad[s]) {
+            case 2: fft_stage<T, NT, E, 2, INV>(buf, ld, nl, p, s, tw); break;
+            case 3: fft_stage<T, NT, E, 3, INV>(buf, ld, nl, p, s, tw); break;
+            case 4: fft_stage<T, NT, E, 4, INV>(buf, ld, nl, p, s, tw); break;
+            case 5: fft_stage<T, NT, E, 5, INV>(buf, ld, nl, p, s, tw); break;
+            case 7: fft_stage<T, NT, E, 7, INV>(buf, ld, nl, p, s, tw); break;
+            default: fft_stage<T, NT, E, 8, INV>(buf, ld, nl, p, s, tw); break;
         }
-        Ns *= r;
     }
 }
 
-// Truncated Green's function transforms (paper Sec. 5.2): the free-space
-// harmonic (kind 0) and biharmonic (kind 1) kernels cut off at radius R.
-//   H^R(k) = 8 pi sin^2(R k / 2) / k^2
-//   B^R(k) = 4 pi [(2 - R^2 k^2) cos Rk + 2 Rk sin Rk - 2] / k^4
-// B^R cancels catastrophically near k = 0 and is summed from its series
-// 4 pi R^4 sum_n (-1)^n (Rk)^{2n} / ((2n+1)! (2n+4)) there.
+// Truncated Green's function transforms (paper Sec. 5.2).
+//   kind 0, harmonic:    H^R(k) = 8 pi sin^2(R k / 2) / k^2, the transform of
+//                        (1/r) 1[r < R]
+//   kind 1, biharmonic:  the transform of (r - R) 1[r < R],
+//                        4 pi [2 cos Rk + Rk sin Rk - 2] / k^4.
+// The biharmonic kernel only enters through second and third derivatives
+// (stokeslet and stresslet multipliers), which annihilate the constant -R, so
+// inside the truncation radius it acts exactly as the paper's r 1[r < R]
+// (whose transform is 4 pi [(2 - R^2k^2) cos Rk + 2 Rk sin Rk - 2] / k^4).
+// Subtracting R removes the R^2 k^2 cos Rk edge term, which otherwise
+// dominates the samples by a factor ~ (Rk)^2 / 2 and costs about five digits
+// of the precomputed multiplier in double precision.  Near k = 0 both forms
+// cancel catastrophically and are summed from their series.
 __host__ __device__ inline double khat_truncated(int kind, double k, double R)
 {
-    // kind 0: H^R(k) = 8 pi sin^2(R k / 2) / k^2
-    // kind 1: B^R(k) = 4 pi [(2 - R^2 k^2) cos Rk + 2 Rk sin Rk - 2] / k^4, series for small Rk
     const double pi = 3.14159265358979323846;
     double x = R * k;
     if (kind == 0) {
@@ -290,19 +307,19 @@ __host__ __device__ inline double khat_truncated(int kind, double k, double R)
         return 8.0 * pi * s * s;
     }
     if (x < 0.5) {
-        // 4 pi R^4 sum_n (-1)^n x^{2n} / ((2n+1)! (2n+4))
-        double x2 = x * x, term = 1.0, acc = 0.0;
-        double fact = 1.0;  // (2n+1)!
-        for (int n = 0; n < 14; ++n) {
-            if (n > 0) fact *= (double)(2 * n) * (double)(2 * n + 1);
-            acc += term / (fact * (double)(2 * n + 4));
-            term *= -x2;
+        // 4 pi R^4 sum_{m >= 2} (-1)^m 2 (1 - m) x^{2m-4} / (2m)!
+        double x2 = x * x, pw = 1.0, acc = 0.0;
+        double fact = 24.0;  // (2m)! for m = 2
+        for (int m = 2; m < 16; ++m) {
+            double c = 2.0 * (1.0 - m) / fact;
+            acc += (m & 1) ? -c * pw : c * pw;
+            pw *= x2;
+            fact *= (double)(2 * m + 1) * (double)(2 * m + 2);
         }
         return 4.0 * pi * R * R * R * R * acc;
     }
     double k2 = k * k;
-    return 4.0 * pi * ((2.0 - x * x) * cos(x) + 2.0 * x * sin(x) - 2.0) / (k2 * k2);
+    return 4.0 * pi * (2.0 * cos(x) + x * sin(x) - 2.0) / (k2 * k2);
 }
-
 
 }  // namespace ehs

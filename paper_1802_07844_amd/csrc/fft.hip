@@ -26,7 +26,8 @@ constexpr int Z_E = 16;
 
 // ---------------------------------------------------------------------------
 // forward x pass: real lines of Mt values, zero-padded to 2Mt, half spectrum
-// k1 = 0..Mt.  Two real lines are packed into one complex line.
+// k1 = 0..Mt.  Two real lines are packed into one complex line; both padding
+// halves of every packed line are transformed together (2 * B/2 lines).
 // grid: (ceil(Mt / B), 2Mt, ncomp); B even.
 // ---------------------------------------------------------------------------
 template <typename T>
@@ -41,7 +42,7 @@ __global__ void __launch_bounds__(PASS_NT) k_fwd_x(const T* __restrict__ in, cpl
     const T* src = in + (long long)c * a.cs_in + ((long long)l * Mt + j0) * Mt;
     const int np = B / 2;
     for (int f = threadIdx.x; f < np * Mt; f += PASS_NT) {
-        int p = f / Mt, i = f - p * Mt;
+        int p = fdiv(f, Mt, a.mMt), i = f - p * Mt;
         T va = (2 * p < nb) ? src[(2 * p) * Mt + i] : (T)0;
         T vb = (2 * p + 1 < nb) ? src[(2 * p + 1) * Mt + i] : (T)0;
         cplx<T> z = cmk<T>(va, vb);
@@ -51,10 +52,10 @@ __global__ void __launch_bounds__(PASS_NT) k_fwd_x(const T* __restrict__ in, cpl
     __syncthreads();
     lds_fft<T, PASS_NT, PASS_E, false>(buf, ld, B, a.fM);
     // unpack the two real spectra: A = (Z[k] + conj Z[-k]) / 2, B = (Z[k] - conj Z[-k]) / 2i
-    cplx<T>* dst = out + (long long)c * a.cs_out;
+    cplx<T>* dst = out + (long long)c * a.cs_out + (long long)l * Mt + j0;
     const long long rowk = (long long)2 * Mt * Mt;  // stride of k1
     for (int f = threadIdx.x; f < (Mt + 1) * B; f += PASS_NT) {
-        int k = f / B, b = f - k * B;
+        int k = fdiv(f, B, a.mB), b = f - k * B;
         if (b >= nb) continue;
         int p = b >> 1, s = k & 1, m = k >> 1;
         int mm = Mt - m - s;
@@ -66,13 +67,14 @@ __global__ void __launch_bounds__(PASS_NT) k_fwd_x(const T* __restrict__ in, cpl
             r = cmk<T>((T)0.5 * (zk.x + zn.x), (T)0.5 * (zk.y + zn.y));
         else
             r = cmk<T>((T)0.5 * (zk.y - zn.y), (T)-0.5 * (zk.x - zn.x));
-        dst[k * rowk + (long long)l * Mt + j0 + b] = r;
+        dst[k * rowk + b] = r;
     }
 }
 
 // ---------------------------------------------------------------------------
 // forward y pass: complex lines along j (Mt values, contiguous), padded to
-// 2Mt; output Z[k1][k2][l] (l fastest).  grid: (ceil(2Mt / B), Mt + 1, ncomp)
+// 2Mt; both halves (even and odd k2) of the B lines are transformed together.
+// output Z[k1][k2][l] (l fastest).  grid: (ceil(2Mt / B), Mt + 1, ncomp)
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ void __launch_bounds__(PASS_NT) k_fwd_y(const cplx<T>* __restrict__ in, cplx<T>* __restrict__ out, PassArgs a)
@@ -85,39 +87,24 @@ __global__ void __launch_bounds__(PASS_NT) k_fwd_y(const cplx<T>* __restrict__ i
     const int nb = min(B, nl - l0);
     const cplx<T>* tw2 = static_cast<const cplx<T>*>(a.tw2);
     const cplx<T>* src = in + (long long)c * a.cs_in + ((long long)k1 * nl + l0) * Mt;
-    constexpr int MAXR = PASS_E;
-    cplx<T> x[MAXR];
-#pragma unroll
-    for (int i = 0; i < MAXR; ++i) {
-        int f = threadIdx.x + i * PASS_NT;
-        x[i] = cmk<T>(0, 0);
-        if (f < B * Mt) {
-            int b = f / Mt;
-            if (b < nb) x[i] = src[f];
-        }
+    for (int f = threadIdx.x; f < B * Mt; f += PASS_NT) {
+        int b = fdiv(f, Mt, a.mMt), j = f - b * Mt;
+        cplx<T> v = (b < nb) ? src[f] : cmk<T>(0, 0);
+        buf[b * ld + j] = v;
+        buf[(B + b) * ld + j] = cmul(v, tw2[j]);
     }
+    __syncthreads();
+    lds_fft<T, PASS_NT, PASS_E, false>(buf, ld, 2 * B, a.fM);
     cplx<T>* dst = out + (long long)c * a.cs_out + (long long)k1 * nl * nl + l0;
-    for (int s = 0; s < 2; ++s) {
-#pragma unroll
-        for (int i = 0; i < MAXR; ++i) {
-            int f = threadIdx.x + i * PASS_NT;
-            if (f < B * Mt) {
-                int b = f / Mt, j = f - b * Mt;
-                buf[b * ld + j] = s ? cmul(x[i], tw2[j]) : x[i];
-            }
-        }
-        __syncthreads();
-        lds_fft<T, PASS_NT, PASS_E, false>(buf, ld, B, a.fM);
-        for (int f = threadIdx.x; f < Mt * B; f += PASS_NT) {
-            int m = f / B, b = f - m * B;
-            if (b < nb) dst[(long long)(2 * m + s) * nl + b] = buf[b * ld + m];
-        }
-        __syncthreads();
+    for (int f = threadIdx.x; f < nl * B; f += PASS_NT) {
+        int k2 = fdiv(f, B, a.mB), b = f - k2 * B;
+        if (b < nb) dst[(long long)k2 * nl + b] = buf[((k2 & 1) * B + b) * ld + (k2 >> 1)];
     }
 }
 
 // ---------------------------------------------------------------------------
-// inverse y pass: lines along k2 (2Mt values, stride 2Mt), keep j < Mt.
+// inverse y pass: lines along k2 (2Mt values, stride 2Mt), keep j < Mt; the
+// even and odd k2 halves are transformed together.
 // output D[k1][l][j].  grid: (ceil(2Mt / B), Mt + 1, ncomp)
 // ---------------------------------------------------------------------------
 template <typename T>
@@ -131,37 +118,16 @@ __global__ void __launch_bounds__(PASS_NT) k_inv_y(const cplx<T>* __restrict__ i
     const int nb = min(B, nl - l0);
     const cplx<T>* tw2 = static_cast<const cplx<T>*>(a.tw2);
     const cplx<T>* src = in + (long long)c * a.cs_in + (long long)k1 * nl * nl + l0;
-    constexpr int MAXR = PASS_E;
-    cplx<T> acc[MAXR];
-    for (int s = 0; s < 2; ++s) {
-        for (int f = threadIdx.x; f < Mt * B; f += PASS_NT) {
-            int m = f / B, b = f - m * B;
-            buf[b * ld + m] = (b < nb) ? src[(long long)(2 * m + s) * nl + b] : cmk<T>(0, 0);
-        }
-        __syncthreads();
-        lds_fft<T, PASS_NT, PASS_E, true>(buf, ld, B, a.fM);
-#pragma unroll
-        for (int i = 0; i < MAXR; ++i) {
-            int f = threadIdx.x + i * PASS_NT;
-            if (f < B * Mt) {
-                int b = f / Mt, t = f - b * Mt;
-                cplx<T> v = buf[b * ld + t];
-                if (s == 0)
-                    acc[i] = v;
-                else
-                    acc[i] = cadd(acc[i], cmul(v, cconj(tw2[t])));
-            }
-        }
-        __syncthreads();
+    for (int f = threadIdx.x; f < nl * B; f += PASS_NT) {
+        int k2 = fdiv(f, B, a.mB), b = f - k2 * B;
+        buf[((k2 & 1) * B + b) * ld + (k2 >> 1)] = (b < nb) ? src[(long long)k2 * nl + b] : cmk<T>(0, 0);
     }
+    __syncthreads();
+    lds_fft<T, PASS_NT, PASS_E, true>(buf, ld, 2 * B, a.fM);
     cplx<T>* dst = out + (long long)c * a.cs_out + ((long long)k1 * nl + l0) * Mt;
-#pragma unroll
-    for (int i = 0; i < MAXR; ++i) {
-        int f = threadIdx.x + i * PASS_NT;
-        if (f < B * Mt) {
-            int b = f / Mt;
-            if (b < nb) dst[f] = acc[i];
-        }
+    for (int f = threadIdx.x; f < nb * Mt; f += PASS_NT) {
+        int b = fdiv(f, Mt, a.mMt), t = f - b * Mt;
+        dst[f] = cadd(buf[b * ld + t], cmul(buf[(B + b) * ld + t], cconj(tw2[t])));
     }
 }
 
@@ -181,11 +147,12 @@ __global__ void __launch_bounds__(PASS_NT) k_inv_x(const cplx<T>* __restrict__ i
     const cplx<T>* tw2 = static_cast<const cplx<T>*>(a.tw2);
     const cplx<T>* src = in + (long long)c * a.cs_in + (long long)l * Mt + j0;
     const long long rowk = (long long)2 * Mt * Mt;
+    const int hB = B / 2;
     // Z_p[k] = Ya[k] + i Yb[k] over the full padded range k < 2Mt; the
     // position k = 2m + s is stored at buf[(2p + s) * ld + m].
     for (int part = 0; part < 2; ++part) {
-        for (int f = threadIdx.x; f < (Mt + 1) * (B / 2); f += PASS_NT) {
-            int k = f / (B / 2), p = f - k * (B / 2);
+        for (int f = threadIdx.x; f < (Mt + 1) * hB; f += PASS_NT) {
+            int k = fdiv(f, hB, a.mB2), p = f - k * hB;
             int b = 2 * p + part;
             cplx<T> v = (b < nb) ? src[k * rowk + b] : cmk<T>(0, 0);
             if (k == 0 || k == Mt) v.y = 0;  // self-conjugate bins are real
@@ -206,7 +173,7 @@ __global__ void __launch_bounds__(PASS_NT) k_inv_x(const cplx<T>* __restrict__ i
     lds_fft<T, PASS_NT, PASS_E, true>(buf, ld, B, a.fM);
     T* dst = out + (long long)c * a.cs_out + ((long long)l * Mt + j0) * Mt;
     for (int f = threadIdx.x; f < nb * Mt; f += PASS_NT) {
-        int b = f / Mt, t = f - b * Mt;
+        int b = fdiv(f, Mt, a.mMt), t = f - b * Mt;
         int p = b >> 1;
         cplx<T> r0 = buf[(2 * p) * ld + t];
         cplx<T> r1 = buf[(2 * p + 1) * ld + t];
@@ -302,19 +269,17 @@ __device__ __forceinline__ void apply_mult(const cplx<U>* X, cplx<U>* Y, U kx, U
 
 // ---------------------------------------------------------------------------
 // fused x3 pass: forward padded transform of the ncin grids along x3, scaling
-// by the multipliers, inverse transform, truncation to l < 2Mt.  In place on
-// Z[k1][k2][l]; the six outputs overwrite components 0..5.
-// grid: (2Mt, Mt + 1).  RES: inputs and outputs held in registers (else the
-// inputs are re-read and outputs accumulated in memory phase by phase).
+// by the multipliers, inverse transform, truncation to l < 2Mt.
+// Z[k1][k2][l]; the six outputs go to zout (zout == zb is allowed when
+// MAXO > 0: the outputs are then kept in registers until every phase has read
+// the inputs).  MAXO == 0: outputs accumulate phase by phase in zout, which
+// must then be a separate array.
+// grid: (2Mt, Mt + 1).
 // ---------------------------------------------------------------------------
-template <typename T, int K, bool RES>
-__global__ void __launch_bounds__(Z_NT) k_z_scale(cplx<T>* zb, cplx<T>* zout, ZArgs a)
+template <typename T, int K, int MAXO>
+__global__ void __launch_bounds__(Z_NT) k_z_scale(const cplx<T>* zb, cplx<T>* zout, ZArgs a)
 {
     constexpr int ncin = Traits<K>::ncA + Traits<K>::ncB;
-    constexpr int nlines = ncin > NCOUT ? ncin : NCOUT;
-    constexpr int NZMAX = ZResident<K>::nz_max;
-    constexpr int MAXI = RES ? (ncin * NZMAX + Z_NT - 1) / Z_NT : 1;
-    constexpr int MAXO = RES ? (NCOUT * NZMAX + Z_NT - 1) / Z_NT : 1;
     extern __shared__ unsigned char smem_raw[];
     cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
     const int Mt = a.Mt, Q = a.Q;
@@ -323,21 +288,11 @@ __global__ void __launch_bounds__(Z_NT) k_z_scale(cplx<T>* zb, cplx<T>* zout, ZA
     const long long cs = a.cs;
     const long long base = ((long long)k1 * nz + k2) * nz;
     const cplx<T>* tw4 = static_cast<const cplx<T>*>(a.tw4);
+    const unsigned mnz = a.mnz, mnq = a.mnq, mn4 = a.mn4;
 
-    cplx<T> xin[MAXI];
-    cplx<T> yout[MAXO];
-    if (RES) {
+    cplx<T> yout[MAXO > 0 ? MAXO : 1];
 #pragma unroll
-        for (int i = 0; i < MAXI; ++i) {
-            int f = threadIdx.x + i * Z_NT;
-            if (f < ncin * nz) {
-                int c = f / nz, l = f - c * nz;
-                xin[i] = zb[c * cs + base + l];
-            }
-        }
-#pragma unroll
-        for (int i = 0; i < MAXO; ++i) yout[i] = cmk<T>(0, 0);
-    }
+    for (int i = 0; i < (MAXO > 0 ? MAXO : 1); ++i) yout[i] = cmk<T>(0, 0);
 
     // signed wave numbers of this line
     const int k2s = (k2 < Mt) ? k2 : k2 - nz;
@@ -345,36 +300,23 @@ __global__ void __launch_bounds__(Z_NT) k_z_scale(cplx<T>* zb, cplx<T>* zout, ZA
     const bool nyq12 = (k1 == Mt) || (k2 == Mt);
     const double kxd = a.dk12 * k1, kyd = a.dk12 * k2s;
     const long long oct_line = ((long long)k1 * (Mt + 1) + ak2) * (2 * Mt + 1);
+    const int nh = nz / nq;  // 1 (Q = 2), 2 (Q = 4) or 4 (Q = 8)
 
     for (int s = 0; s < Q; ++s) {
-        // fold and twist the inputs into LDS: line c holds
+        // fold and twist: line c of LDS holds
         //   sum_h x_c[l' + h nq] exp(-2 pi i s (l' + h nq) / 4Mt),  l' < nq
-        const int nh = (nz + nq - 1) / nq;
         for (int h = 0; h < nh; ++h) {
-            if (RES) {
-#pragma unroll
-                for (int i = 0; i < MAXI; ++i) {
-                    int f = threadIdx.x + i * Z_NT;
-                    if (f < ncin * nz) {
-                        int c = f / nz, l = f - c * nz;
-                        if (l / nq == h) {
-                            int lp = l - h * nq;
-                            cplx<T> v = cmul(xin[i], tw4[(long long)s * l % n4]);
-                            buf[c * ld + lp] = h ? cadd(buf[c * ld + lp], v) : v;
-                        }
-                    }
-                }
-            } else {
-                for (int f = threadIdx.x; f < ncin * nq; f += Z_NT) {
-                    int c = f / nq, lp = f - c * nq;
-                    int l = lp + h * nq;
-                    cplx<T> v = cmk<T>(0, 0);
-                    if (l < nz) v = cmul(zb[c * cs + base + l], tw4[(long long)s * l % n4]);
-                    buf[c * ld + lp] = h ? cadd(buf[c * ld + lp], v) : v;
-                }
+            for (int f = threadIdx.x; f < ncin * nq; f += Z_NT) {
+                int c = fdiv(f, nq, mnq), lp = f - c * nq;
+                int l = lp + h * nq;
+                int ti = s * l;
+                ti -= fdiv(ti, n4, mn4) * n4;
+                cplx<T> v = cmul(zb[c * cs + base + l], tw4[ti]);
+                buf[c * ld + lp] = h ? cadd(buf[c * ld + lp], v) : v;
             }
-            __syncthreads();
+            if (h + 1 < nh) __syncthreads();
         }
+        __syncthreads();
         lds_fft<T, Z_NT, Z_E, false>(buf, ld, ncin, a.fq);
 
         // scaling at k3 = Q m + s
@@ -426,34 +368,39 @@ __global__ void __launch_bounds__(Z_NT) k_z_scale(cplx<T>* zb, cplx<T>* zout, ZA
         lds_fft<T, Z_NT, Z_E, true>(buf, ld, NCOUT, a.fq);
 
         // unfold: out_c[l] += buf_c[l mod nq] exp(+2 pi i s l / 4Mt), l < 2Mt
-        if (RES) {
+        if (MAXO > 0) {
 #pragma unroll
-            for (int i = 0; i < MAXO; ++i) {
+            for (int i = 0; i < (MAXO > 0 ? MAXO : 1); ++i) {
                 int f = threadIdx.x + i * Z_NT;
                 if (f < NCOUT * nz) {
-                    int c = f / nz, l = f - c * nz;
-                    int lp = l % nq;
-                    yout[i] = cadd(yout[i], cmul(buf[c * ld + lp], cconj(tw4[(long long)s * l % n4])));
+                    int c = fdiv(f, nz, mnz), l = f - c * nz;
+                    int lq = fdiv(l, nq, mnq);
+                    int lp = l - lq * nq;
+                    int ti = s * l;
+                    ti -= fdiv(ti, n4, mn4) * n4;
+                    yout[i] = cadd(yout[i], cmul(buf[c * ld + lp], cconj(tw4[ti])));
                 }
             }
         } else {
-            // outputs accumulate phase by phase in the separate output grids
             for (int f = threadIdx.x; f < NCOUT * nz; f += Z_NT) {
-                int c = f / nz, l = f - c * nz;
-                int lp = l % nq;
-                cplx<T> v = cmul(buf[c * ld + lp], cconj(tw4[(long long)s * l % n4]));
+                int c = fdiv(f, nz, mnz), l = f - c * nz;
+                int lq = fdiv(l, nq, mnq);
+                int lp = l - lq * nq;
+                int ti = s * l;
+                ti -= fdiv(ti, n4, mn4) * n4;
+                cplx<T> v = cmul(buf[c * ld + lp], cconj(tw4[ti]));
                 cplx<T>* o = zout + c * a.cs_out + base + l;
                 *o = (s == 0) ? v : cadd(*o, v);
             }
         }
         __syncthreads();
     }
-    if (RES) {
+    if (MAXO > 0) {
 #pragma unroll
-        for (int i = 0; i < MAXO; ++i) {
+        for (int i = 0; i < (MAXO > 0 ? MAXO : 1); ++i) {
             int f = threadIdx.x + i * Z_NT;
             if (f < NCOUT * nz) {
-                int c = f / nz, l = f - c * nz;
+                int c = fdiv(f, nz, mnz), l = f - c * nz;
                 zout[c * a.cs_out + base + l] = yout[i];
             }
         }
@@ -513,7 +460,7 @@ __global__ void __launch_bounds__(PASS_NT) k_line_fft(const cplx<T>* __restrict_
     int l0 = blockIdx.x * per;
     int nb = min(per, nl - l0);
     for (int f = threadIdx.x; f < per * n; f += PASS_NT) {
-        int b = f / n, t = f - b * n;
+        int b = f / n, t = f - b * n;  // debug kernel: plain division
         buf[b * ld + t] = (b < nb) ? in[(long long)(l0 + b) * n + t] : cmk<T>(0, 0);
     }
     __syncthreads();
@@ -540,14 +487,14 @@ template <typename T>
 hipError_t launch_fwd_y(const cplx<T>* in, cplx<T>* out, const PassArgs& a, int ncomp, hipStream_t st)
 {
     dim3 grid((2 * a.Mt + a.B - 1) / a.B, a.Mt + 1, ncomp);
-    hipLaunchKernelGGL(k_fwd_y<T>, grid, dim3(PASS_NT), pass_lds(a.Mt, a.B, sizeof(T)), st, in, out, a);
+    hipLaunchKernelGGL(k_fwd_y<T>, grid, dim3(PASS_NT), pass_lds(a.Mt, 2 * a.B, sizeof(T)), st, in, out, a);
     return hipGetLastError();
 }
 template <typename T>
 hipError_t launch_inv_y(const cplx<T>* in, cplx<T>* out, const PassArgs& a, int ncomp, hipStream_t st)
 {
     dim3 grid((2 * a.Mt + a.B - 1) / a.B, a.Mt + 1, ncomp);
-    hipLaunchKernelGGL(k_inv_y<T>, grid, dim3(PASS_NT), pass_lds(a.Mt, a.B, sizeof(T)), st, in, out, a);
+    hipLaunchKernelGGL(k_inv_y<T>, grid, dim3(PASS_NT), pass_lds(a.Mt, 2 * a.B, sizeof(T)), st, in, out, a);
     return hipGetLastError();
 }
 template <typename T>
@@ -567,9 +514,8 @@ size_t z_lds_bytes(int family, int Mt, int Q, size_t esz)
 
 bool z_resident_ok(int family, int Mt)
 {
-    int nzmax = family == STRESSLET ? ZResident<STRESSLET>::nz_max
-                                    : (family == STOKESLET ? ZResident<STOKESLET>::nz_max : ZResident<ROTLET>::nz_max);
-    return 2 * Mt <= nzmax;
+    (void)family;
+    return NCOUT * 2 * Mt <= 18 * Z_NT;
 }
 
 template <typename T, int K>
@@ -577,10 +523,15 @@ static hipError_t launch_z_t(cplx<T>* zb, cplx<T>* zout, const ZArgs& a, bool re
 {
     dim3 grid(2 * a.Mt, a.Mt + 1);
     size_t lds = z_lds_bytes(K, a.Mt, a.Q, sizeof(T));
-    if (res)
-        hipLaunchKernelGGL((k_z_scale<T, K, true>), grid, dim3(Z_NT), lds, st, zb, zout, a);
+    const int need = (NCOUT * 2 * a.Mt + Z_NT - 1) / Z_NT;
+    if (!res)
+        hipLaunchKernelGGL((k_z_scale<T, K, 0>), grid, dim3(Z_NT), lds, st, zb, zout, a);
+    else if (need <= 6)
+        hipLaunchKernelGGL((k_z_scale<T, K, 6>), grid, dim3(Z_NT), lds, st, zb, zout, a);
+    else if (need <= 12)
+        hipLaunchKernelGGL((k_z_scale<T, K, 12>), grid, dim3(Z_NT), lds, st, zb, zout, a);
     else
-        hipLaunchKernelGGL((k_z_scale<T, K, false>), grid, dim3(Z_NT), lds, st, zb, zout, a);
+        hipLaunchKernelGGL((k_z_scale<T, K, 18>), grid, dim3(Z_NT), lds, st, zb, zout, a);
     return hipGetLastError();
 }
 

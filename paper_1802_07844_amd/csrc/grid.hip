@@ -293,12 +293,12 @@ __global__ void __launch_bounds__(256) k_gather(GridArgs g, const T* __restrict_
     }
     __syncthreads();
     const int rows = 64 / P;
-    const int xi = lane % P, row = lane / P;
+    const int row = fdiv(lane, P, g.mP), xi = lane - row * P;
     T acc[6] = {0, 0, 0, 0, 0, 0};
     if (row < rows) {
         const T wx = wsh[wv][xi];
         for (int rr = row; rr < P * P; rr += rows) {
-            int dz = rr / P, dy = rr - dz * P;
+            int dz = fdiv(rr, P, g.mP), dy = rr - dz * P;
             T w = wx * wsh[wv][P + dy] * wsh[wv][2 * P + dz];
             long long node = ((long long)(base[2] + dz) * Mt + base[1] + dy) * Mt + base[0] + xi;
 #pragma unroll

@@ -11,32 +11,18 @@ namespace ehs {
 struct PassArgs {
     int Mt;              // grid nodes along x1 and x2 (2 Mt along x3)
     int B;               // lines per block
+    unsigned mMt, mB, mB2;  // reciprocals for division by Mt, B and B/2 (see magic_of)
     long long cs_in;     // elements between components of the input
     long long cs_out;    // elements between components of the output
     const void* tw2;     // exp(-2 pi i t / 2Mt), t < 2Mt
     FftPlanDev fM;       // FFT of length Mt
 };
 
-// largest 2 Mt for which the fused x3 pass keeps its lines in registers
-template <int K>
-struct ZResident;
-template <>
-struct ZResident<STOKESLET> {
-    static constexpr int nz_max = 1280;
-};
-template <>
-struct ZResident<STRESSLET> {
-    static constexpr int nz_max = 1024;
-};
-template <>
-struct ZResident<ROTLET> {
-    static constexpr int nz_max = 1280;
-};
-
 // fused x3 transform + scaling
 struct ZArgs {
     int Mt;
     int Q;                 // phases of the 4Mt padded axis; line length 4Mt / Q
+    unsigned mnz, mnq, mn4;  // reciprocals for division by 2Mt, 4Mt / Q and 4Mt
     long long cs;          // elements between input components
     long long cs_out;      // elements between output components
     const void* tw4;       // exp(-2 pi i t / 4Mt), t < 4Mt
@@ -148,6 +134,7 @@ struct GridArgs {
     double o[3];        // grid origin
     double h;
     double a2;          // 2 xi^2 / eta (Gaussian exponent factor)
+    unsigned mP;        // reciprocal for division by P
     double pref;        // (2 xi^2 / (pi eta))^{3/2}
     int tile[3];        // spread tile edge per axis (nodes)
     int nt[3];          // tiles per axis

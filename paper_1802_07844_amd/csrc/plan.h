@@ -158,12 +158,15 @@ struct Plan {
 
 constexpr int EHS_MT_MAX = 2048;
 
-inline int choose_lines(int Mt, size_t esz, bool even)
+// lines per block of the x / y passes: the block transforms `mult` * B lines
+// of length Mt in LDS (x passes: B; y passes: both halves, 2B)
+inline int choose_lines(int Mt, size_t esz, int mult, bool even)
 {
     int cap = lds_fft_cap(Mt, 512);
-    int B = std::min(cap / Mt, 32);
+    int B = std::min(cap / (mult * Mt), 32);
     if (even) B &= ~1;
-    while (B > (even ? 2 : 1) && (size_t)B * (Mt + 1) * 2 * esz > 96 * 1024) B -= even ? 2 : 1;
+    // at most 78 KiB of LDS so that two blocks share a compute unit
+    while (B > (even ? 2 : 1) && (size_t)mult * B * (Mt + 1) * 2 * esz > 78 * 1024) B -= even ? 2 : 1;
     return B;
 }
 
@@ -245,8 +248,8 @@ inline int make_plan(const PlanInput& in, Plan* out)
     }
     if (!p.Qz) return -3;
     p.resident = z_resident_ok(in.family, Mt);
-    p.Bx = choose_lines(Mt, esz, true);
-    p.By = choose_lines(Mt, esz, false);
+    p.Bx = choose_lines(Mt, esz, 1, true);
+    p.By = choose_lines(Mt, esz, 2, false);
     if (p.Bx < 2 || p.By < 1) return -3;
 
     // real-space cells (side >= r_c; x3 measured from the wall)
@@ -273,6 +276,7 @@ inline int make_plan(const PlanInput& in, Plan* out)
     g.o[2] = -p.Lt;
     g.h = h;
     g.a2 = 2 * xi * xi / eta;
+    g.mP = magic_of((unsigned)P);
     g.pref = std::pow(2 * xi * xi / (pi * eta), 1.5);
     int tz = in.family == 1 ? 4 : 8;
     int dims[3] = {Mt, Mt, 2 * Mt};

@@ -46,8 +46,8 @@ def _quad_H(k, R):
 
 
 def _quad_B(k, R):
-    # FT of r restricted to r < R: (4 pi / k) int_0^R r^2 sin(k r) dr
-    v, _ = integrate.quad(lambda r: r * r * math.sin(k * r), 0.0, R, limit=400)
+    # FT of (r - R) restricted to r < R: (4 pi / k) int_0^R r (r - R) sin(k r) dr
+    v, _ = integrate.quad(lambda r: r * (r - R) * math.sin(k * r), 0.0, R, limit=400)
     return 4 * math.pi / k * v
 
 
@@ -57,14 +57,14 @@ def test_truncated_kernels_match_radial_quadrature(R, k):
     for kind, q in ((0, _quad_H), (1, _quad_B)):
         ref = q(k, R)
         got = ehs.truncated_kernel_hat(kind, k, R)
-        scale = 2 * math.pi * R * R if kind == 0 else math.pi * R**4
+        scale = 2 * math.pi * R * R if kind == 0 else math.pi * R**4 / 3
         assert abs(got - ref) <= 1e-10 * scale, (kind, k, R, got, ref)
 
 
 @pytest.mark.parametrize("R", [0.5, 2.449])
 def test_truncated_kernels_limits_at_zero(R):
     assert ehs.truncated_kernel_hat(0, 0.0, R) == pytest.approx(2 * math.pi * R * R, rel=1e-15)
-    assert ehs.truncated_kernel_hat(1, 0.0, R) == pytest.approx(math.pi * R**4, rel=1e-15)
+    assert ehs.truncated_kernel_hat(1, 0.0, R) == pytest.approx(-math.pi * R**4 / 3, rel=1e-15)
     # continuity across the switch between series and closed form (R k = 0.5)
     for kind in (0, 1):
         a = ehs.truncated_kernel_hat(kind, (0.5 - 1e-13) / R, R)
