@@ -51,9 +51,13 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--n", type=int, default=100_000)
     ap.add_argument("--neighbours", type=float, default=30.0)
+    ap.add_argument("--fp32-neighbours", type=float, default=300.0,
+                    help="neighbours per point for the FP32 variant (its rounding error grows with xi L)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target duration of the oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="run one 1 GiB device-to-device copy first (calibrates profiler byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (use --gpus 1)", file=sys.stderr)
@@ -77,6 +81,13 @@ def main():
     tol = 1e-10
     # the real-space estimate takes a quarter of the budget (xi_for_cutoff gives estimate = tol'/2)
     xi = ehs.xi_for_cutoff("stokeslet", rc, tol / 2)
+
+    if args.copy_probe:
+        src = torch.ones(2**27, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     ctx = ehs.Context(0)
     ctx.set_option(ehs.OPT_PRECISION, 1)
@@ -134,11 +145,12 @@ def main():
     if not args.no_fp32:
         tol32 = 1e-5
         ctx.set_option(ehs.OPT_PRECISION, 2)
-        xi32 = ehs.xi_for_cutoff("stokeslet", rc, tol32 / 2)
+        rc32 = (args.fp32_neighbours * 3.0 / (4.0 * math.pi * n)) ** (1.0 / 3.0)
+        xi32 = ehs.xi_for_cutoff("stokeslet", rc32, tol32 / 2)
         out32 = torch.empty_like(out)
 
         def step32():
-            return ctx.stokeslet(yd, fd, yd, xi32, rc, tol32, out=out32, report=True)[1]
+            return ctx.stokeslet(yd, fd, yd, xi32, rc32, tol32, out=out32, report=True)[1]
 
         for _ in range(args.warmup):
             step32()
@@ -152,7 +164,8 @@ def main():
         dt32 = time.perf_counter() - t0
         u32 = out32.cpu().numpy()
         result["fp32"] = {"value": n * args.steps / dt32, "unit": "points/s", "ms_per_step": dt32 / args.steps * 1e3,
-                          "tol": tol32, "xi": xi32, "M": r32.M, "P": r32.P, "Mt": r32.Mt,
+                          "tol": tol32, "xi": xi32, "r_c": rc32, "neighbours": args.fp32_neighbours,
+                          "M": r32.M, "P": r32.P, "Mt": r32.Mt,
                           "stage_ms": dict(zip(ehs.STAGES, (st32 / args.steps).tolist()))}
 
     # oracle on the host cores: a bounded sample of targets against all sources

@@ -84,6 +84,55 @@ int tw_table(ehs_ctx* c, int n, int esz, void** out)
     return EHS_OK;
 }
 
+// per-stage twiddles of the Stockham stages: for stage s with radix R and
+// span Ns, entries w^(k q), w = exp(-2 pi i / (Ns R)), k < Ns, 1 <= q < R
+int stage_table(ehs_ctx* c, int n, int esz, const std::vector<int>& r, FftPlanDev* p)
+{
+    auto key = std::make_pair(-n, esz);  // negative key: stage tables
+    auto it = c->tables.find(key);
+    std::vector<int> offs;
+    size_t total = 0;
+    int ns = 1;
+    for (int R : r) {
+        offs.push_back((int)total);
+        total += (size_t)ns * (R - 1);
+        ns *= R;
+    }
+    for (size_t i = 0; i < r.size(); ++i) p->toff[i] = offs[i];
+    if (it != c->tables.end()) {
+        p->tws = it->second;
+        return EHS_OK;
+    }
+    std::vector<double> h(2 * std::max<size_t>(total, 1));
+    const double tp = 6.283185307179586476925286766559;
+    ns = 1;
+    for (size_t s = 0; s < r.size(); ++s) {
+        int R = r[s];
+        for (int k = 0; k < ns; ++k)
+            for (int q = 1; q < R; ++q) {
+                // exp(-2 pi i k q / (ns R)) = table entry (k q n / (ns R)) mod n
+                long long t = ((long long)k * q * (n / (ns * R))) % n;
+                double a = tp * (double)t / (double)n;
+                size_t e = offs[s] + (size_t)k * (R - 1) + (q - 1);
+                h[2 * e] = std::cos(a);
+                h[2 * e + 1] = -std::sin(a);
+            }
+        ns *= R;
+    }
+    void* d = nullptr;
+    size_t bytes = (h.size() / 2) * 2 * esz;
+    if (hipMalloc(&d, bytes) != hipSuccess) return EHS_ENOMEM;
+    if (esz == 8) {
+        if (hipMemcpy(d, h.data(), bytes, hipMemcpyHostToDevice) != hipSuccess) return EHS_EHIP;
+    } else {
+        std::vector<float> f(h.begin(), h.end());
+        if (hipMemcpy(d, f.data(), bytes, hipMemcpyHostToDevice) != hipSuccess) return EHS_EHIP;
+    }
+    c->tables[key] = d;
+    p->tws = d;
+    return EHS_OK;
+}
+
 int fft_plan(ehs_ctx* c, int n, int esz, FftPlanDev* p)
 {
     std::vector<int> r;
@@ -105,7 +154,7 @@ int fft_plan(ehs_ctx* c, int n, int esz, FftPlanDev* p)
     int rc = tw_table(c, n, esz, &t);
     if (rc) return rc;
     p->tw = t;
-    return EHS_OK;
+    return stage_table(c, n, esz, r, p);
 }
 
 // ---------------------------------------------------------------------------
@@ -250,9 +299,9 @@ int check_extents(const Plan& p, const Layout& L, size_t esz)
     ok = ok && (4 * p.Mt) % p.Qz == 0 && z_lds_bytes(p.family, p.Mt, p.Qz, esz) <= 160 * 1024 &&
          std::max(p.ncin, 6) * nq <= lds_fft_cap(nq, 512);
     // x / y passes: B lines of Mt in LDS and in the 16-element register budget
-    ok = ok && p.Bx * p.Mt <= lds_fft_cap(p.Mt, 512) && 2 * p.By * p.Mt <= lds_fft_cap(p.Mt, 512) &&
-         (p.Bx % 2) == 0 && p.By >= 1 && (size_t)2 * p.By * (p.Mt + 1) * c <= 160 * 1024 &&
-         (size_t)p.Bx * (p.Mt + 1) * c <= 160 * 1024;
+    ok = ok && p.Bx * p.Mt <= lds_fft_cap(p.Mt, 256) && p.By * p.Mt <= lds_fft_cap(p.Mt, 256) &&
+         p.By * p.Mt <= 16 * 256 && (p.Bx % 2) == 0 && p.By >= 1 &&
+         (size_t)p.By * (p.Mt + 1) * c <= 160 * 1024 && (size_t)p.Bx * (p.Mt + 1) * c <= 160 * 1024;
     // magic-number division is exact for numerator * divisor < 2^32
     ok = ok && (long long)(p.Mt + 1) * std::max(p.Bx, 2 * p.By) * std::max(p.Mt, 2 * p.By) < (1LL << 31) &&
          (long long)std::max(p.ncin, 6) * 2 * p.Mt * 2 * p.Mt < (1LL << 31);
@@ -730,7 +779,7 @@ int ehs_debug_line_fft(ehs_ctx* c, int n, int nl, const void* in, void* out, int
     int esz = fp32 ? 4 : 8;
     int rc = fft_plan(c, n, esz, &p);
     if (rc) return rc;
-    int cap = lds_fft_cap(n, 512);
+    int cap = lds_fft_cap(n, 256);
     int per = std::max(1, std::min(cap / n, 16));
     if (n > cap) return EHS_ERANGE;
     if ((size_t)per * (n + 1) * 2 * esz > 160 * 1024) per = std::max(1, (int)(160 * 1024 / ((n + 1) * 2 * esz)));

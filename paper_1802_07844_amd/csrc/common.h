@@ -88,7 +88,9 @@ struct FftPlanDev {
     int nb[FFT_MAX_STAGES];         // butterflies per line, n / rad
     unsigned mnb[FFT_MAX_STAGES];   // reciprocal of nb (unused when nb == 1)
     int tstr[FFT_MAX_STAGES];       // twiddle stride n / (ns * rad)
-    const void* tw;                 // cplx<T>*
+    int toff[FFT_MAX_STAGES];       // offset of the stage's table in tws
+    const void* tw;                 // cplx<T>*: exp(-2 pi i t / n), t < n
+    const void* tws;                // cplx<T>*: per stage, w^(k q) for k < ns, 1 <= q < rad
 };
 
 // a / d for a * d < 2^32, with m = floor((2^32 - 1) / d) + 1 (d >= 2)
@@ -219,7 +221,8 @@ __device__ __forceinline__ void fft_stage(cplx<T>* buf, int ld, int nl, const Ff
                                           const cplx<T>* __restrict__ tw)
 {
     constexpr int MB = (E / R) > 0 ? (E / R) : 1;
-    const int nb = p.nb[st], Ns = p.ns[st], tstride = p.tstr[st];
+    const int nb = p.nb[st], Ns = p.ns[st];
+    const cplx<T>* __restrict__ tws = static_cast<const cplx<T>*>(p.tws) + p.toff[st];
     const unsigned mnb = p.mnb[st], mns = p.mns[st];
     const int total = nl * nb;
     cplx<T> v[MB][R];
@@ -240,13 +243,9 @@ __device__ __forceinline__ void fft_stage(cplx<T>* buf, int ld, int nl, const Ff
                 v[i][q] = INV ? cconj(a) : a;
             }
             if (k != 0) {
-                cplx<T> w1 = tw[k * tstride];
-                cplx<T> w = w1;
+                const cplx<T>* ws = tws + (k * (R - 1));
 #pragma unroll
-                for (int q = 1; q < R; ++q) {
-                    v[i][q] = cmul(v[i][q], w);
-                    if (q + 1 < R) w = cmul(w, w1);
-                }
+                for (int q = 1; q < R; ++q) v[i][q] = cmul(v[i][q], ws[q - 1]);
             }
             Dft<T, R>::run(v[i]);
             base[i] = line * ld + jq * Ns * R + k;

@@ -19,7 +19,8 @@
 
 namespace ehs {
 
-constexpr int PASS_NT = 512;  // threads of the x / y passes
+constexpr int PASS_NT = 256;  // threads of the y passes
+constexpr int XPASS_NT = 512; // threads of the x passes
 constexpr int PASS_E = 16;    // complex elements per thread in the LDS FFT
 constexpr int Z_NT = 512;
 constexpr int Z_E = 16;
@@ -31,7 +32,7 @@ constexpr int Z_E = 16;
 // grid: (ceil(Mt / B), 2Mt, ncomp); B even.
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ void __launch_bounds__(PASS_NT) k_fwd_x(const T* __restrict__ in, cplx<T>* __restrict__ out, PassArgs a)
+__global__ void __launch_bounds__(XPASS_NT) k_fwd_x(const T* __restrict__ in, cplx<T>* __restrict__ out, PassArgs a)
 {
     extern __shared__ unsigned char smem_raw[];
     cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
@@ -41,7 +42,7 @@ __global__ void __launch_bounds__(PASS_NT) k_fwd_x(const T* __restrict__ in, cpl
     const cplx<T>* tw2 = static_cast<const cplx<T>*>(a.tw2);
     const T* src = in + (long long)c * a.cs_in + ((long long)l * Mt + j0) * Mt;
     const int np = B / 2;
-    for (int f = threadIdx.x; f < np * Mt; f += PASS_NT) {
+    for (int f = threadIdx.x; f < np * Mt; f += XPASS_NT) {
         int p = fdiv(f, Mt, a.mMt), i = f - p * Mt;
         T va = (2 * p < nb) ? src[(2 * p) * Mt + i] : (T)0;
         T vb = (2 * p + 1 < nb) ? src[(2 * p + 1) * Mt + i] : (T)0;
@@ -50,11 +51,11 @@ __global__ void __launch_bounds__(PASS_NT) k_fwd_x(const T* __restrict__ in, cpl
         buf[(2 * p + 1) * ld + i] = cmul(z, tw2[i]);
     }
     __syncthreads();
-    lds_fft<T, PASS_NT, PASS_E, false>(buf, ld, B, a.fM);
+    lds_fft<T, XPASS_NT, PASS_E, false>(buf, ld, B, a.fM);
     // unpack the two real spectra: A = (Z[k] + conj Z[-k]) / 2, B = (Z[k] - conj Z[-k]) / 2i
     cplx<T>* dst = out + (long long)c * a.cs_out + (long long)l * Mt + j0;
     const long long rowk = (long long)2 * Mt * Mt;  // stride of k1
-    for (int f = threadIdx.x; f < (Mt + 1) * B; f += PASS_NT) {
+    for (int f = threadIdx.x; f < (Mt + 1) * B; f += XPASS_NT) {
         int k = fdiv(f, B, a.mB), b = f - k * B;
         if (b >= nb) continue;
         int p = b >> 1, s = k & 1, m = k >> 1;
@@ -73,10 +74,12 @@ __global__ void __launch_bounds__(PASS_NT) k_fwd_x(const T* __restrict__ in, cpl
 
 // ---------------------------------------------------------------------------
 // forward y pass: complex lines along j (Mt values, contiguous), padded to
-// 2Mt; both halves (even and odd k2) of the B lines are transformed together.
-// output Z[k1][k2][l] (l fastest).  grid: (ceil(2Mt / B), Mt + 1, ncomp)
+// 2Mt; the even and odd k2 halves are transformed one after the other with
+// the input lines kept in registers.  output Z[k1][k2][l] (l fastest): every
+// block writes B consecutive l (one 128-byte segment) per k2.
+// grid: (ceil(2Mt / B), Mt + 1, ncomp)
 // ---------------------------------------------------------------------------
-template <typename T>
+template <typename T, int MAXR>
 __global__ void __launch_bounds__(PASS_NT) k_fwd_y(const cplx<T>* __restrict__ in, cplx<T>* __restrict__ out, PassArgs a)
 {
     extern __shared__ unsigned char smem_raw[];
@@ -87,27 +90,42 @@ __global__ void __launch_bounds__(PASS_NT) k_fwd_y(const cplx<T>* __restrict__ i
     const int nb = min(B, nl - l0);
     const cplx<T>* tw2 = static_cast<const cplx<T>*>(a.tw2);
     const cplx<T>* src = in + (long long)c * a.cs_in + ((long long)k1 * nl + l0) * Mt;
-    for (int f = threadIdx.x; f < B * Mt; f += PASS_NT) {
-        int b = fdiv(f, Mt, a.mMt), j = f - b * Mt;
-        cplx<T> v = (b < nb) ? src[f] : cmk<T>(0, 0);
-        buf[b * ld + j] = v;
-        buf[(B + b) * ld + j] = cmul(v, tw2[j]);
+    cplx<T> x[MAXR];
+    int jj[MAXR], bb[MAXR];
+#pragma unroll
+    for (int i = 0; i < MAXR; ++i) {
+        int f = threadIdx.x + i * PASS_NT;
+        x[i] = cmk<T>(0, 0);
+        jj[i] = -1;
+        bb[i] = 0;
+        if (f < B * Mt) {
+            int b = fdiv(f, Mt, a.mMt);
+            jj[i] = f - b * Mt;
+            bb[i] = b;
+            if (b < nb) x[i] = src[f];
+        }
     }
-    __syncthreads();
-    lds_fft<T, PASS_NT, PASS_E, false>(buf, ld, 2 * B, a.fM);
     cplx<T>* dst = out + (long long)c * a.cs_out + (long long)k1 * nl * nl + l0;
-    for (int f = threadIdx.x; f < nl * B; f += PASS_NT) {
-        int k2 = fdiv(f, B, a.mB), b = f - k2 * B;
-        if (b < nb) dst[(long long)k2 * nl + b] = buf[((k2 & 1) * B + b) * ld + (k2 >> 1)];
+    for (int s = 0; s < 2; ++s) {
+#pragma unroll
+        for (int i = 0; i < MAXR; ++i)
+            if (jj[i] >= 0) buf[bb[i] * ld + jj[i]] = s ? cmul(x[i], tw2[jj[i]]) : x[i];
+        __syncthreads();
+        lds_fft<T, PASS_NT, PASS_E, false>(buf, ld, B, a.fM);
+        for (int f = threadIdx.x; f < Mt * B; f += PASS_NT) {
+            int m = fdiv(f, B, a.mB), b = f - m * B;
+            if (b < nb) dst[(long long)(2 * m + s) * nl + b] = buf[b * ld + m];
+        }
+        __syncthreads();
     }
 }
 
 // ---------------------------------------------------------------------------
 // inverse y pass: lines along k2 (2Mt values, stride 2Mt), keep j < Mt; the
-// even and odd k2 halves are transformed together.
-// output D[k1][l][j].  grid: (ceil(2Mt / B), Mt + 1, ncomp)
+// even and odd k2 halves are transformed one after the other and combined in
+// registers.  output D[k1][l][j].  grid: (ceil(2Mt / B), Mt + 1, ncomp)
 // ---------------------------------------------------------------------------
-template <typename T>
+template <typename T, int MAXR>
 __global__ void __launch_bounds__(PASS_NT) k_inv_y(const cplx<T>* __restrict__ in, cplx<T>* __restrict__ out, PassArgs a)
 {
     extern __shared__ unsigned char smem_raw[];
@@ -118,16 +136,30 @@ __global__ void __launch_bounds__(PASS_NT) k_inv_y(const cplx<T>* __restrict__ i
     const int nb = min(B, nl - l0);
     const cplx<T>* tw2 = static_cast<const cplx<T>*>(a.tw2);
     const cplx<T>* src = in + (long long)c * a.cs_in + (long long)k1 * nl * nl + l0;
-    for (int f = threadIdx.x; f < nl * B; f += PASS_NT) {
-        int k2 = fdiv(f, B, a.mB), b = f - k2 * B;
-        buf[((k2 & 1) * B + b) * ld + (k2 >> 1)] = (b < nb) ? src[(long long)k2 * nl + b] : cmk<T>(0, 0);
+    cplx<T> acc[MAXR];
+    for (int s = 0; s < 2; ++s) {
+        for (int f = threadIdx.x; f < Mt * B; f += PASS_NT) {
+            int m = fdiv(f, B, a.mB), b = f - m * B;
+            buf[b * ld + m] = (b < nb) ? src[(long long)(2 * m + s) * nl + b] : cmk<T>(0, 0);
+        }
+        __syncthreads();
+        lds_fft<T, PASS_NT, PASS_E, true>(buf, ld, B, a.fM);
+#pragma unroll
+        for (int i = 0; i < MAXR; ++i) {
+            int f = threadIdx.x + i * PASS_NT;
+            if (f < B * Mt) {
+                int b = fdiv(f, Mt, a.mMt), t = f - b * Mt;
+                cplx<T> v = buf[b * ld + t];
+                acc[i] = s ? cadd(acc[i], cmul(v, cconj(tw2[t]))) : v;
+            }
+        }
+        __syncthreads();
     }
-    __syncthreads();
-    lds_fft<T, PASS_NT, PASS_E, true>(buf, ld, 2 * B, a.fM);
     cplx<T>* dst = out + (long long)c * a.cs_out + ((long long)k1 * nl + l0) * Mt;
-    for (int f = threadIdx.x; f < nb * Mt; f += PASS_NT) {
-        int b = fdiv(f, Mt, a.mMt), t = f - b * Mt;
-        dst[f] = cadd(buf[b * ld + t], cmul(buf[(B + b) * ld + t], cconj(tw2[t])));
+#pragma unroll
+    for (int i = 0; i < MAXR; ++i) {
+        int f = threadIdx.x + i * PASS_NT;
+        if (f < nb * Mt) dst[f] = acc[i];
     }
 }
 
@@ -137,7 +169,7 @@ __global__ void __launch_bounds__(PASS_NT) k_inv_y(const cplx<T>* __restrict__ i
 // output R[l][j][i].  grid: (ceil(Mt / B), 2Mt, ncomp); B even.
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ void __launch_bounds__(PASS_NT) k_inv_x(const cplx<T>* __restrict__ in, T* __restrict__ out, PassArgs a)
+__global__ void __launch_bounds__(XPASS_NT) k_inv_x(const cplx<T>* __restrict__ in, T* __restrict__ out, PassArgs a)
 {
     extern __shared__ unsigned char smem_raw[];
     cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
@@ -151,7 +183,7 @@ __global__ void __launch_bounds__(PASS_NT) k_inv_x(const cplx<T>* __restrict__ i
     // Z_p[k] = Ya[k] + i Yb[k] over the full padded range k < 2Mt; the
     // position k = 2m + s is stored at buf[(2p + s) * ld + m].
     for (int part = 0; part < 2; ++part) {
-        for (int f = threadIdx.x; f < (Mt + 1) * hB; f += PASS_NT) {
+        for (int f = threadIdx.x; f < (Mt + 1) * hB; f += XPASS_NT) {
             int k = fdiv(f, hB, a.mB2), p = f - k * hB;
             int b = 2 * p + part;
             cplx<T> v = (b < nb) ? src[k * rowk + b] : cmk<T>(0, 0);
@@ -170,9 +202,9 @@ __global__ void __launch_bounds__(PASS_NT) k_inv_x(const cplx<T>* __restrict__ i
         }
         __syncthreads();
     }
-    lds_fft<T, PASS_NT, PASS_E, true>(buf, ld, B, a.fM);
+    lds_fft<T, XPASS_NT, PASS_E, true>(buf, ld, B, a.fM);
     T* dst = out + (long long)c * a.cs_out + ((long long)l * Mt + j0) * Mt;
-    for (int f = threadIdx.x; f < nb * Mt; f += PASS_NT) {
+    for (int f = threadIdx.x; f < nb * Mt; f += XPASS_NT) {
         int b = fdiv(f, Mt, a.mMt), t = f - b * Mt;
         int p = b >> 1;
         cplx<T> r0 = buf[(2 * p) * ld + t];
@@ -276,10 +308,14 @@ __device__ __forceinline__ void apply_mult(const cplx<U>* X, cplx<U>* Y, U kx, U
 // must then be a separate array.
 // grid: (2Mt, Mt + 1).
 // ---------------------------------------------------------------------------
-template <typename T, int K, int MAXO>
+template <typename T, int K, int TIER>
 __global__ void __launch_bounds__(Z_NT) k_z_scale(const cplx<T>* zb, cplx<T>* zout, ZArgs a)
 {
     constexpr int ncin = Traits<K>::ncA + Traits<K>::ncB;
+    // TIER t > 0: 2Mt <= 512 t, outputs (and, when they fit, inputs) held in
+    // registers; TIER 0: outputs accumulate in zout (a separate array)
+    constexpr int MAXO = 6 * TIER;
+    constexpr int MAXI = (TIER > 0 && ncin * TIER * (int)sizeof(T) <= 56) ? ncin * TIER : 0;
     extern __shared__ unsigned char smem_raw[];
     cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
     const int Mt = a.Mt, Q = a.Q;
@@ -293,6 +329,17 @@ __global__ void __launch_bounds__(Z_NT) k_z_scale(const cplx<T>* zb, cplx<T>* zo
     cplx<T> yout[MAXO > 0 ? MAXO : 1];
 #pragma unroll
     for (int i = 0; i < (MAXO > 0 ? MAXO : 1); ++i) yout[i] = cmk<T>(0, 0);
+    cplx<T> xin[MAXI > 0 ? MAXI : 1];
+    if (MAXI > 0) {
+#pragma unroll
+        for (int i = 0; i < (MAXI > 0 ? MAXI : 1); ++i) {
+            int f = threadIdx.x + i * Z_NT;
+            if (f < ncin * nz) {
+                int c = fdiv(f, nz, mnz), l = f - c * nz;
+                xin[i] = zb[c * cs + base + l];
+            }
+        }
+    }
 
     // signed wave numbers of this line
     const int k2s = (k2 < Mt) ? k2 : k2 - nz;
@@ -306,13 +353,31 @@ __global__ void __launch_bounds__(Z_NT) k_z_scale(const cplx<T>* zb, cplx<T>* zo
         // fold and twist: line c of LDS holds
         //   sum_h x_c[l' + h nq] exp(-2 pi i s (l' + h nq) / 4Mt),  l' < nq
         for (int h = 0; h < nh; ++h) {
-            for (int f = threadIdx.x; f < ncin * nq; f += Z_NT) {
-                int c = fdiv(f, nq, mnq), lp = f - c * nq;
-                int l = lp + h * nq;
-                int ti = s * l;
-                ti -= fdiv(ti, n4, mn4) * n4;
-                cplx<T> v = cmul(zb[c * cs + base + l], tw4[ti]);
-                buf[c * ld + lp] = h ? cadd(buf[c * ld + lp], v) : v;
+            if (MAXI > 0) {
+#pragma unroll
+                for (int i = 0; i < (MAXI > 0 ? MAXI : 1); ++i) {
+                    int f = threadIdx.x + i * Z_NT;
+                    if (f < ncin * nz) {
+                        int c = fdiv(f, nz, mnz), l = f - c * nz;
+                        int lq = fdiv(l, nq, mnq);
+                        if (lq == h) {
+                            int lp = l - lq * nq;
+                            int ti = s * l;
+                            ti -= fdiv(ti, n4, mn4) * n4;
+                            cplx<T> v = cmul(xin[i], tw4[ti]);
+                            buf[c * ld + lp] = h ? cadd(buf[c * ld + lp], v) : v;
+                        }
+                    }
+                }
+            } else {
+                for (int f = threadIdx.x; f < ncin * nq; f += Z_NT) {
+                    int c = fdiv(f, nq, mnq), lp = f - c * nq;
+                    int l = lp + h * nq;
+                    int ti = s * l;
+                    ti -= fdiv(ti, n4, mn4) * n4;
+                    cplx<T> v = cmul(zb[c * cs + base + l], tw4[ti]);
+                    buf[c * ld + lp] = h ? cadd(buf[c * ld + lp], v) : v;
+                }
             }
             if (h + 1 < nh) __syncthreads();
         }
@@ -480,28 +545,36 @@ template <typename T>
 hipError_t launch_fwd_x(const T* in, cplx<T>* out, const PassArgs& a, int ncomp, hipStream_t st)
 {
     dim3 grid((a.Mt + a.B - 1) / a.B, 2 * a.Mt, ncomp);
-    hipLaunchKernelGGL(k_fwd_x<T>, grid, dim3(PASS_NT), pass_lds(a.Mt, a.B, sizeof(T)), st, in, out, a);
+    hipLaunchKernelGGL(k_fwd_x<T>, grid, dim3(XPASS_NT), pass_lds(a.Mt, a.B, sizeof(T)), st, in, out, a);
     return hipGetLastError();
 }
 template <typename T>
 hipError_t launch_fwd_y(const cplx<T>* in, cplx<T>* out, const PassArgs& a, int ncomp, hipStream_t st)
 {
     dim3 grid((2 * a.Mt + a.B - 1) / a.B, a.Mt + 1, ncomp);
-    hipLaunchKernelGGL(k_fwd_y<T>, grid, dim3(PASS_NT), pass_lds(a.Mt, 2 * a.B, sizeof(T)), st, in, out, a);
+    size_t lds = pass_lds(a.Mt, a.B, sizeof(T));
+    if (a.B * a.Mt <= 8 * PASS_NT)
+        hipLaunchKernelGGL((k_fwd_y<T, 8>), grid, dim3(PASS_NT), lds, st, in, out, a);
+    else
+        hipLaunchKernelGGL((k_fwd_y<T, 16>), grid, dim3(PASS_NT), lds, st, in, out, a);  // B Mt <= 16 PASS_NT
     return hipGetLastError();
 }
 template <typename T>
 hipError_t launch_inv_y(const cplx<T>* in, cplx<T>* out, const PassArgs& a, int ncomp, hipStream_t st)
 {
     dim3 grid((2 * a.Mt + a.B - 1) / a.B, a.Mt + 1, ncomp);
-    hipLaunchKernelGGL(k_inv_y<T>, grid, dim3(PASS_NT), pass_lds(a.Mt, 2 * a.B, sizeof(T)), st, in, out, a);
+    size_t lds = pass_lds(a.Mt, a.B, sizeof(T));
+    if (a.B * a.Mt <= 8 * PASS_NT)
+        hipLaunchKernelGGL((k_inv_y<T, 8>), grid, dim3(PASS_NT), lds, st, in, out, a);
+    else
+        hipLaunchKernelGGL((k_inv_y<T, 16>), grid, dim3(PASS_NT), lds, st, in, out, a);
     return hipGetLastError();
 }
 template <typename T>
 hipError_t launch_inv_x(const cplx<T>* in, T* out, const PassArgs& a, int ncomp, hipStream_t st)
 {
     dim3 grid((a.Mt + a.B - 1) / a.B, 2 * a.Mt, ncomp);
-    hipLaunchKernelGGL(k_inv_x<T>, grid, dim3(PASS_NT), pass_lds(a.Mt, a.B, sizeof(T)), st, in, out, a);
+    hipLaunchKernelGGL(k_inv_x<T>, grid, dim3(XPASS_NT), pass_lds(a.Mt, a.B, sizeof(T)), st, in, out, a);
     return hipGetLastError();
 }
 
@@ -515,7 +588,7 @@ size_t z_lds_bytes(int family, int Mt, int Q, size_t esz)
 bool z_resident_ok(int family, int Mt)
 {
     (void)family;
-    return NCOUT * 2 * Mt <= 18 * Z_NT;
+    return 2 * Mt <= 3 * 512;
 }
 
 template <typename T, int K>
@@ -523,15 +596,15 @@ static hipError_t launch_z_t(cplx<T>* zb, cplx<T>* zout, const ZArgs& a, bool re
 {
     dim3 grid(2 * a.Mt, a.Mt + 1);
     size_t lds = z_lds_bytes(K, a.Mt, a.Q, sizeof(T));
-    const int need = (NCOUT * 2 * a.Mt + Z_NT - 1) / Z_NT;
+    const int nz = 2 * a.Mt;
     if (!res)
         hipLaunchKernelGGL((k_z_scale<T, K, 0>), grid, dim3(Z_NT), lds, st, zb, zout, a);
-    else if (need <= 6)
-        hipLaunchKernelGGL((k_z_scale<T, K, 6>), grid, dim3(Z_NT), lds, st, zb, zout, a);
-    else if (need <= 12)
-        hipLaunchKernelGGL((k_z_scale<T, K, 12>), grid, dim3(Z_NT), lds, st, zb, zout, a);
+    else if (nz <= 512)
+        hipLaunchKernelGGL((k_z_scale<T, K, 1>), grid, dim3(Z_NT), lds, st, zb, zout, a);
+    else if (nz <= 1024)
+        hipLaunchKernelGGL((k_z_scale<T, K, 2>), grid, dim3(Z_NT), lds, st, zb, zout, a);
     else
-        hipLaunchKernelGGL((k_z_scale<T, K, 18>), grid, dim3(Z_NT), lds, st, zb, zout, a);
+        hipLaunchKernelGGL((k_z_scale<T, K, 3>), grid, dim3(Z_NT), lds, st, zb, zout, a);
     return hipGetLastError();
 }
 

@@ -44,16 +44,19 @@ inline int next_smooth_even(double x)
     return (int)n;
 }
 
-// radices 8, 4, 2, then 7, 5, 3
+// radices: the odd ones (7, 5, 3) first, then 8, 4, 2.  The first Stockham
+// stage writes with a stride of its radix; an odd stride spreads over the LDS
+// banks, a power of two does not.
 inline bool factor_radices(int n, std::vector<int>& r)
 {
     r.clear();
-    if (n < 1) return false;
-    if (n == 1) {
-        r.push_back(2);  // never used: callers require n >= 2
-        return false;
-    }
+    if (n < 2) return false;
     int m = n;
+    for (int p : {7, 5, 3})
+        while (m % p == 0) {
+            r.push_back(p);
+            m /= p;
+        }
     while (m % 8 == 0) {
         r.push_back(8);
         m /= 8;
@@ -66,11 +69,6 @@ inline bool factor_radices(int n, std::vector<int>& r)
         r.push_back(2);
         m /= 2;
     }
-    for (int p : {7, 5, 3})
-        while (m % p == 0) {
-            r.push_back(p);
-            m /= p;
-        }
     return m == 1;
 }
 
@@ -158,15 +156,15 @@ struct Plan {
 
 constexpr int EHS_MT_MAX = 2048;
 
-// lines per block of the x / y passes: the block transforms `mult` * B lines
-// of length Mt in LDS (x passes: B; y passes: both halves, 2B)
-inline int choose_lines(int Mt, size_t esz, int mult, bool even)
+// lines per block of the x / y passes: one 128-byte segment of complex
+// values per written (or read) row, i.e. 8 (FP64) or 16 (FP32) lines, fewer
+// when the lines do not fit the LDS budget (78 KiB: two blocks per CU) or the
+// 16-element register budget of the FFT
+inline int choose_lines(int Mt, size_t esz)
 {
-    int cap = lds_fft_cap(Mt, 512);
-    int B = std::min(cap / (mult * Mt), 32);
-    if (even) B &= ~1;
-    // at most 78 KiB of LDS so that two blocks share a compute unit
-    while (B > (even ? 2 : 1) && (size_t)mult * B * (Mt + 1) * 2 * esz > 78 * 1024) B -= even ? 2 : 1;
+    int B = (int)(128 / (2 * esz));
+    int cap = lds_fft_cap(Mt, 256);
+    while (B > 2 && ((size_t)B * (Mt + 1) * 2 * esz > 78 * 1024 || B * Mt > cap)) B -= 2;
     return B;
 }
 
@@ -248,8 +246,8 @@ inline int make_plan(const PlanInput& in, Plan* out)
     }
     if (!p.Qz) return -3;
     p.resident = z_resident_ok(in.family, Mt);
-    p.Bx = choose_lines(Mt, esz, 1, true);
-    p.By = choose_lines(Mt, esz, 2, false);
+    p.Bx = choose_lines(Mt, esz);
+    p.By = p.Bx;
     if (p.Bx < 2 || p.By < 1) return -3;
 
     // real-space cells (side >= r_c; x3 measured from the wall)
