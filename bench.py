@@ -44,6 +44,124 @@ def _stage_bytes(rep, ncin, esz):
     }
 
 
+def _serve_rc(n, tol):
+    """Fixed cutoff rule of the serving stream: about 600 neighbours per point
+    at FP64 (balances the real-space and Fourier work on this device), 300 at
+    FP32 with r_c >= 0.075 so that xi stays below ~45 (the FP32 rounding error
+    grows with xi L)."""
+    nb = 600.0 if tol < 1e-6 else 300.0
+    rc = (nb * 3.0 / (4.0 * math.pi * n)) ** (1.0 / 3.0)
+    if tol >= 1e-6:
+        rc = max(rc, 0.075)
+    return min(rc, 0.45)
+
+
+def serve_bench(args, ehs, workloads, torch, np):
+    """Serving stream: Poisson arrivals of mixed requests through one ehs.Server."""
+    import queue
+    import threading
+
+    npool = args.serve_pool
+    seed = workloads.SEED_BASE + 5
+    y, f, gq, v = workloads.serving_pool(npool, seed)
+    dev = torch.device("cuda:0")
+    yd = torch.from_numpy(y).to(dev)
+    sd = {"stokeslet": torch.from_numpy(f).to(dev), "stresslet": torch.from_numpy(gq).to(dev),
+          "rotlet": torch.from_numpy(v).to(dev)}
+    sh = {"stokeslet": f, "stresslet": gq, "rotlet": v}
+    torch.cuda.synchronize()
+
+    def prep(d):
+        n = min(d["n"], npool)
+        off = d["seed"] % (npool - n + 1)
+        rc = _serve_rc(n, d["tol"])
+        xi = ehs.xi_for_cutoff(d["kernel"], rc, d["tol"] / 2)
+        prec = 2 if d["tol"] >= 1e-5 else 1
+        return n, off, rc, xi, prec
+
+    def submit(srv, d):
+        n, off, rc, xi, prec = prep(d)
+        ys = yd[off:off + n]
+        return srv.submit(d["kernel"], ys, sd[d["kernel"]][off:off + n], ys, xi, rc, d["tol"], precision=prec)
+
+    free = torch.cuda.mem_get_info()[0]
+    arena = int(min(args.serve_arena_gb * 2**30, 0.8 * free))
+    srv = ehs.Server(0, arena_bytes=arena, nslots=args.serve_slots)
+    # capacity from a closed-loop calibration batch of the same distribution
+    cal = workloads.serving_stream(args.serve_calib, seed + 1)
+    t0 = time.perf_counter()
+    for t in [submit(srv, d) for d in cal]:
+        srv.wait(t)
+    cal_wall = time.perf_counter() - t0
+    mu = len(cal) / cal_wall
+    lam = args.serve_util * mu
+    stream = workloads.serving_stream(args.serve_requests, seed)
+    q = queue.Queue()
+    tstart = time.perf_counter() + 0.05
+    deadline = tstart + args.serve_max_seconds
+
+    def feeder():
+        for i, d in enumerate(stream):
+            ts = tstart + d["arrival"] / lam
+            if ts > deadline:
+                break
+            now = time.perf_counter()
+            if ts > now:
+                time.sleep(ts - now)
+            tcall = time.perf_counter()
+            q.put((i, submit(srv, d), ts, tcall))
+        q.put(None)
+
+    th = threading.Thread(target=feeder, daemon=True)
+    th.start()
+    lat, que, svc, pts, rows = [], [], [], 0, []
+    t_end = tstart
+    while True:
+        item = q.get()
+        if item is None:
+            break
+        i, tk, ts, tcall = item
+        u, st = srv.wait(tk)
+        lag = tcall - ts
+        lat.append((st["t_done_ms"] - st["t_submit_ms"]) + lag * 1e3)
+        que.append((st["t_admit_ms"] - st["t_submit_ms"]) + lag * 1e3)
+        svc.append(st["t_done_ms"] - st["t_admit_ms"])
+        pts += stream[i]["n"]
+        t_end = max(t_end, time.perf_counter())
+        rows.append((i, u, st))
+    th.join()
+    stats = srv.stats()
+    # rel-RMS against the oracle on sampled targets of a few requests
+    errs = {1: [], 2: []}
+    if not args.no_cpu_baseline and rows:
+        import oracle
+
+        g = workloads.rng(seed + 2)
+        pick = rows[:: max(1, len(rows) // args.serve_checks)][: args.serve_checks]
+        for i, u, st in pick:
+            d = stream[i]
+            n, off, rc, xi, prec = prep(d)
+            idx = np.sort(g.choice(n, size=min(n, 48), replace=False))
+            ref = oracle.halfspace(d["kernel"], y[off:off + n], sh[d["kernel"]][off:off + n], y[off:off + n][idx])
+            errs[prec].append(oracle.rel_rms(ref, u.cpu().numpy()[idx]))
+    srv.close()
+    pc = lambda a, p: float(np.percentile(np.array(a), p)) if a else None
+    return {
+        "requests": len(lat), "requests_planned": args.serve_requests, "lambda_per_s": lam,
+        "capacity_per_s": mu, "utilization_target": args.serve_util,
+        "p50_ms": pc(lat, 50), "p99_ms": pc(lat, 99), "queue_p50_ms": pc(que, 50), "queue_p99_ms": pc(que, 99),
+        "service_p50_ms": pc(svc, 50), "service_p99_ms": pc(svc, 99),
+        "points_per_s": pts / max(t_end - tstart, 1e-9), "nslots": args.serve_slots, "arena_gb": arena / 2**30,
+        "arena_peak_gb": stats["arena_peak"] / 2**30, "cache_hits": stats["cache_hits"],
+        "cache_misses": stats["cache_misses"], "evictions": stats["evictions"], "failed": stats["failed"],
+        "rel_rms_fp64_max": max(errs[1]) if errs[1] else None, "rel_rms_fp32_max": max(errs[2]) if errs[2] else None,
+        "rel_rms_checked": len(errs[1]) + len(errs[2]),
+        "workload": "Poisson arrivals; N log-uniform in [1e3, 1e6]; kernel uniform over stokeslet/stresslet/rotlet; "
+                    "tol uniform over {1e-5 FP32, 1e-10 FP64}; uniform unit-cube positions (slices of a seeded pool); "
+                    "r_c for ~600 (FP64) / ~300 (FP32, r_c >= 0.075) neighbours, xi from the real-space estimate",
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -56,6 +174,15 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target duration of the oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving stream")
+    ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--serve-util", type=float, default=0.7, help="arrival rate as a fraction of measured capacity")
+    ap.add_argument("--serve-slots", type=int, default=4)
+    ap.add_argument("--serve-arena-gb", type=float, default=200.0)
+    ap.add_argument("--serve-calib", type=int, default=48, help="closed-loop calibration requests")
+    ap.add_argument("--serve-max-seconds", type=float, default=90.0, help="stop admitting arrivals after this")
+    ap.add_argument("--serve-pool", type=int, default=1_000_000)
+    ap.add_argument("--serve-checks", type=int, default=12, help="requests checked against the oracle")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run one 1 GiB device-to-device copy first (calibrates profiler byte counters)")
     args = ap.parse_args()
@@ -190,6 +317,13 @@ def main():
         result["rel_rms_fp64"] = oracle.rel_rms(ref, u64[idx])
         if u32 is not None:
             result["fp32"]["rel_rms"] = oracle.rel_rms(ref, u32[idx])
+    if not args.no_serve:
+        del out
+        if u32 is not None:
+            del out32
+        ctx.close()
+        torch.cuda.empty_cache()
+        result["serving"] = serve_bench(args, ehs, workloads, torch, np)
     print(json.dumps(result))
 
 

@@ -50,6 +50,7 @@ extern "C" {
 #define EHS_ERANGE (-3)  /* no admissible grid for the request (too fine, or eta >= 1) */
 #define EHS_ENOMEM (-4)  /* device allocation failed or the memory cap is too small */
 #define EHS_EHIP (-5)    /* a HIP runtime error */
+#define EHS_ETIMEDOUT (-6) /* ehs_wait: the request has not completed within the timeout */
 
 /* kernel families */
 #define EHS_STOKESLET 0
@@ -174,6 +175,77 @@ double ehs_truncated_kernel_hat(int kind, double k, double R);
  */
 int ehs_debug_line_fft(ehs_ctx* ctx, int n, int nl, const void* in, void* out, int inverse, int fp32,
                        void* stream);
+
+/*
+ * Serving: continuous batching of many summation requests on one device.
+ *
+ * A server owns one device arena of `arena_bytes`.  Each request's workspace
+ * (grids, cell lists, sort scratch) is carved from it when the request is
+ * admitted and returned when it completes; the truncated-kernel multipliers
+ * (one set per grid size M~) are cached in the same arena and shared by all
+ * requests, evicted least recently used when no running request needs them.
+ * `nslots` requests (1..16) run at once, each on its own stream and host
+ * worker thread, so their device work overlaps.  A request is admitted as
+ * soon as a slot is free and its footprint (workspace plus the multipliers it
+ * still lacks) fits the arena; younger requests may overtake a queued request
+ * that does not fit, a bounded number of times.  The arithmetic of a request
+ * is exactly that of the single-call entry points with the same arguments.
+ * There is no paper counterpart: the serving layer is an extension.
+ */
+typedef struct ehs_server ehs_server;
+
+typedef struct ehs_request {
+    int32_t family;    /* EHS_STOKESLET, EHS_STRESSLET or EHS_ROTLET */
+    int32_t precision; /* 0 auto (FP32 when tol >= 1e-5), 1 FP64, 2 FP32 */
+    int64_t N, T;
+    /* device pointers, layouts as in ewald_halfspace_*; inputs must be complete
+       on the device before ehs_submit, and every pointer stays valid and
+       untouched until ehs_wait has returned the request */
+    const double* sources;
+    const double* strengths;
+    const double* targets;
+    double xi, r_c, tol;
+    double* u_out;     /* T x 3, written by the request */
+} ehs_request;
+
+typedef struct ehs_request_status {
+    int32_t code;          /* EHS_OK or the request's error */
+    int32_t slot;          /* slot that ran it (-1: never admitted) */
+    double t_submit_ms;    /* host steady clock, ms since the server was created */
+    double t_admit_ms;     /* admission (slot and memory granted) */
+    double t_done_ms;      /* results complete on the device and visible */
+    double gpu_ms;         /* device time from the request's first to last operation */
+    double footprint_bytes; /* arena bytes it needed: workspace plus its multipliers */
+    ehs_report report;     /* the plan it ran with (ms_stage not filled) */
+} ehs_request_status;
+
+typedef struct ehs_server_stats {
+    int64_t submitted, completed, failed, rejected;
+    int32_t nslots, queued, running, cache_entries;
+    int64_t cache_hits, cache_misses, evictions;
+    double arena_bytes, arena_used, arena_peak, cache_bytes;
+} ehs_serve_stats;
+
+/* Create a server on `hip_device` with one arena of `arena_bytes` (allocated
+   now) and `nslots` slots.  Returns EHS_OK, EHS_EINVAL, EHS_ENOMEM or
+   EHS_EHIP; *out is NULL on error. */
+int ehs_server_create(ehs_server** out, int hip_device, size_t arena_bytes, int nslots);
+/* Wait for every submitted request to complete, then release the server and
+   its arena.  Tickets not yet collected with ehs_wait are discarded. */
+void ehs_server_destroy(ehs_server* srv);
+/* Validate and plan a request (one small blocking readback for the bounding
+   box, as in the single-call path) and queue it.  Argument and domain errors
+   are returned here (EHS_EINVAL, EHS_EDOMAIN, EHS_ERANGE), as is EHS_ENOMEM
+   when the request could never fit the arena; on EHS_OK *ticket identifies
+   it.  Thread safe. */
+int ehs_submit(ehs_server* srv, const ehs_request* req, uint64_t* ticket);
+/* Wait up to timeout_ms (negative: no limit) for a request.  Returns
+   EHS_ETIMEDOUT if it is still queued or running (the ticket stays valid);
+   otherwise fills *status (may be NULL), releases the ticket and returns the
+   request's own code.  EHS_EINVAL for an unknown ticket.  Thread safe. */
+int ehs_wait(ehs_server* srv, uint64_t ticket, int timeout_ms, ehs_request_status* status);
+/* Counters and arena occupancy.  Thread safe. */
+int ehs_server_stats(ehs_server* srv, ehs_serve_stats* out);
 
 #ifdef __cplusplus
 }

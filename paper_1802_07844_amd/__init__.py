@@ -27,7 +27,7 @@ STAGES = ["bbox", "precompute", "binning", "realspace", "spread", "fwd_x", "fwd_
           "gather", "total"]
 NSTAGES = len(STAGES)
 
-EHS_OK, EHS_EINVAL, EHS_EDOMAIN, EHS_ERANGE, EHS_ENOMEM, EHS_EHIP = 0, -1, -2, -3, -4, -5
+EHS_OK, EHS_EINVAL, EHS_EDOMAIN, EHS_ERANGE, EHS_ENOMEM, EHS_EHIP, EHS_ETIMEDOUT = 0, -1, -2, -3, -4, -5, -6
 
 
 class Report(ctypes.Structure):
@@ -96,25 +96,42 @@ def lib():
     return _lib
 
 
+class Request(ctypes.Structure):
+    _fields_ = [("family", ctypes.c_int32), ("precision", ctypes.c_int32), ("N", ctypes.c_int64),
+                ("T", ctypes.c_int64), ("sources", ctypes.c_void_p), ("strengths", ctypes.c_void_p),
+                ("targets", ctypes.c_void_p), ("xi", ctypes.c_double), ("r_c", ctypes.c_double),
+                ("tol", ctypes.c_double), ("u_out", ctypes.c_void_p)]
+
+
+class RequestStatus(ctypes.Structure):
+    _fields_ = [("code", ctypes.c_int32), ("slot", ctypes.c_int32), ("t_submit_ms", ctypes.c_double),
+                ("t_admit_ms", ctypes.c_double), ("t_done_ms", ctypes.c_double), ("gpu_ms", ctypes.c_double),
+                ("footprint_bytes", ctypes.c_double), ("report", Report)]
+
+
+class ServeStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64), ("failed", ctypes.c_int64),
+                ("rejected", ctypes.c_int64), ("nslots", ctypes.c_int32), ("queued", ctypes.c_int32),
+                ("running", ctypes.c_int32), ("cache_entries", ctypes.c_int32), ("cache_hits", ctypes.c_int64),
+                ("cache_misses", ctypes.c_int64), ("evictions", ctypes.c_int64), ("arena_bytes", ctypes.c_double),
+                ("arena_used", ctypes.c_double), ("arena_peak", ctypes.c_double), ("cache_bytes", ctypes.c_double)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 def _bind_serving(L):
-    if not hasattr(L, "ehs_server_create"):
-        return
-    vp, dp, i64 = ctypes.c_void_p, ctypes.c_double, ctypes.c_int64
+    vp = ctypes.c_void_p
     L.ehs_server_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int, ctypes.c_size_t, ctypes.c_int]
     L.ehs_server_create.restype = ctypes.c_int
     L.ehs_server_destroy.argtypes = [vp]
     L.ehs_server_destroy.restype = None
-    L.ehs_server_submit.argtypes = [vp, ctypes.c_int, vp, vp, i64, vp, i64, dp, dp, dp, vp,
-                                    ctypes.POINTER(ctypes.c_uint64)]
-    L.ehs_server_submit.restype = ctypes.c_int
-    L.ehs_server_wait.argtypes = [vp, ctypes.c_uint64, dp, ctypes.POINTER(ServeStats)]
-    L.ehs_server_wait.restype = ctypes.c_int
-
-
-class ServeStats(ctypes.Structure):
-    _fields_ = [("status", ctypes.c_int32), ("slot", ctypes.c_int32), ("precision", ctypes.c_int32),
-                ("Mt", ctypes.c_int32), ("t_submit", ctypes.c_double), ("t_admit", ctypes.c_double),
-                ("t_start", ctypes.c_double), ("t_done", ctypes.c_double), ("bytes", ctypes.c_double)]
+    L.ehs_submit.argtypes = [vp, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)]
+    L.ehs_submit.restype = ctypes.c_int
+    L.ehs_wait.argtypes = [vp, ctypes.c_uint64, ctypes.c_int, ctypes.POINTER(RequestStatus)]
+    L.ehs_wait.restype = ctypes.c_int
+    L.ehs_server_stats.argtypes = [vp, ctypes.POINTER(ServeStats)]
+    L.ehs_server_stats.restype = ctypes.c_int
 
 
 def strerror(code: int) -> str:
@@ -256,3 +273,80 @@ def stresslet(y, gq, x, xi, r_c, tol, **kw):
 
 def rotlet(y, v, x, xi, r_c, tol, **kw):
     return default_context(y.device.index or 0).rotlet(y, v, x, xi, r_c, tol, **kw)
+
+
+class Server:
+    """An ehs_server: continuous batching of requests on one device.
+
+    ``submit`` validates, plans and queues a request and returns a ticket;
+    ``wait`` returns ``(u, status)`` once it has completed.  The input tensors
+    of a request are kept referenced until its ``wait``.  Inputs must be
+    complete on the device when submitted (the current stream is synchronised
+    first).
+    """
+
+    def __init__(self, device: int = 0, arena_bytes: int = 8 << 30, nslots: int = 4):
+        self._h = ctypes.c_void_p()
+        check(lib().ehs_server_create(ctypes.byref(self._h), int(device), int(arena_bytes), int(nslots)))
+        self.device = int(device)
+        self._keep = {}
+
+    def submit(self, family, sources, strengths, targets, xi, r_c, tol, precision=0, out=None) -> int:
+        import torch
+
+        fam = FAMILIES[family] if isinstance(family, str) else int(family)
+        ncol = 6 if fam == STRESSLET else 3
+        req = Request()
+        req.family = fam
+        req.precision = int(precision)
+        req.N = int(sources.shape[0])
+        req.T = int(targets.shape[0])
+        req.sources = _dev_ptr(sources, "sources", 3).value
+        req.strengths = _dev_ptr(strengths, "strengths", ncol).value
+        if strengths.shape[0] != sources.shape[0]:
+            raise ValueError("strengths and sources differ in length")
+        req.targets = _dev_ptr(targets, "targets", 3).value
+        if out is None:
+            out = torch.empty((req.T, 3), dtype=torch.float64, device=targets.device)
+        req.u_out = _dev_ptr(out, "out", 3).value
+        req.xi, req.r_c, req.tol = float(xi), float(r_c), float(tol)
+        torch.cuda.current_stream().synchronize()
+        t = ctypes.c_uint64()
+        check(lib().ehs_submit(self._h, ctypes.byref(req), ctypes.byref(t)))
+        self._keep[t.value] = (sources, strengths, targets, out)
+        return t.value
+
+    def wait(self, ticket: int, timeout_ms: int = -1):
+        """(u, status dict) of a completed request; raises EhsError with its code on failure or timeout."""
+        st = RequestStatus()
+        rc = lib().ehs_wait(self._h, ctypes.c_uint64(ticket), int(timeout_ms), ctypes.byref(st))
+        if rc == EHS_ETIMEDOUT:
+            raise EhsError(rc, strerror(rc))
+        keep = self._keep.pop(ticket, None)
+        check(rc)
+        d = {k: getattr(st, k) for k, _ in st._fields_ if k != "report"}
+        d["report"] = st.report.as_dict()
+        return keep[3], d
+
+    def stats(self) -> dict:
+        s = ServeStats()
+        check(lib().ehs_server_stats(self._h, ctypes.byref(s)))
+        return s.as_dict()
+
+    def close(self):
+        if self._h:
+            lib().ehs_server_destroy(self._h)
+            self._h = ctypes.c_void_p()
+            self._keep.clear()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -13,6 +13,7 @@
 #include <vector>
 
 #include "../../include/ehs.h"
+#include "ctx.h"
 #include "kernels.h"
 #include "plan.h"
 
@@ -23,31 +24,6 @@ namespace {
 constexpr size_t ALIGN = 256;
 inline size_t al(size_t n) { return (n + ALIGN - 1) / ALIGN * ALIGN; }
 
-struct Octants {
-    double* B64 = nullptr;
-    double* H64 = nullptr;
-    float* B32 = nullptr;
-    float* H32 = nullptr;
-    int nf = 0, nf3 = 0;
-};
-
-}  // namespace
-
-struct ehs_ctx {
-    int device = 0;
-    void* ws = nullptr;
-    size_t ws_bytes = 0;
-    std::map<int, Octants> cache;                 // by M~
-    std::map<std::pair<int, int>, void*> tables;  // (n, 8 or 4 bytes) -> twiddle table
-    double* host_bbox = nullptr;                  // pinned, 16 doubles
-    hipEvent_t ev[EHS_NSTAGES + 1] = {};
-    bool ev_ok = false;
-    int opt_prec = 0, opt_timing = 0, force_M = 0, force_P = 0, force_Mt = 0;
-    double mem_cap = 0.0;
-};
-
-namespace {
-
 #define HIPCHK(x)                              \
     do {                                       \
         hipError_t e_ = (x);                   \
@@ -56,9 +32,11 @@ namespace {
 
 int tw_table(ehs_ctx* c, int n, int esz, void** out)
 {
+    std::lock_guard<std::mutex> lk(c->tables->mu);
     auto key = std::make_pair(n, esz);
-    auto it = c->tables.find(key);
-    if (it != c->tables.end()) {
+    auto& tables = c->tables->m;
+    auto it = tables.find(key);
+    if (it != tables.end()) {
         *out = it->second;
         return EHS_OK;
     }
@@ -79,7 +57,7 @@ int tw_table(ehs_ctx* c, int n, int esz, void** out)
         std::vector<float> f(h.begin(), h.end());
         if (hipMemcpy(d, f.data(), bytes, hipMemcpyHostToDevice) != hipSuccess) return EHS_EHIP;
     }
-    c->tables[key] = d;
+    tables[key] = d;
     *out = d;
     return EHS_OK;
 }
@@ -88,8 +66,10 @@ int tw_table(ehs_ctx* c, int n, int esz, void** out)
 // span Ns, entries w^(k q), w = exp(-2 pi i / (Ns R)), k < Ns, 1 <= q < R
 int stage_table(ehs_ctx* c, int n, int esz, const std::vector<int>& r, FftPlanDev* p)
 {
+    std::lock_guard<std::mutex> lk(c->tables->mu);
     auto key = std::make_pair(-n, esz);  // negative key: stage tables
-    auto it = c->tables.find(key);
+    auto& tables = c->tables->m;
+    auto it = tables.find(key);
     std::vector<int> offs;
     size_t total = 0;
     int ns = 1;
@@ -99,7 +79,7 @@ int stage_table(ehs_ctx* c, int n, int esz, const std::vector<int>& r, FftPlanDe
         ns *= R;
     }
     for (size_t i = 0; i < r.size(); ++i) p->toff[i] = offs[i];
-    if (it != c->tables.end()) {
+    if (it != tables.end()) {
         p->tws = it->second;
         return EHS_OK;
     }
@@ -128,7 +108,7 @@ int stage_table(ehs_ctx* c, int n, int esz, const std::vector<int>& r, FftPlanDe
         std::vector<float> f(h.begin(), h.end());
         if (hipMemcpy(d, f.data(), bytes, hipMemcpyHostToDevice) != hipSuccess) return EHS_EHIP;
     }
-    c->tables[key] = d;
+    tables[key] = d;
     p->tws = d;
     return EHS_OK;
 }
@@ -218,6 +198,17 @@ int precompute_kind(ehs_ctx* c, int Mt, int nf, int nf3, int kind, double* scrat
     return EHS_OK;
 }
 
+}  // namespace
+
+int ehs::precompute_octant(ehs_ctx* c, const Plan& p, int kind, double* oct, hipStream_t st)
+{
+    return precompute_kind(c, p.Mt, p.nf, p.nf3, kind, static_cast<double*>(c->ws), oct, st);
+}
+
+namespace {
+
+// standalone contexts: octants by M~ in the context's own cache; the stream is
+// synchronised after a precompute so that later calls on other streams see it
 int ensure_octants(ehs_ctx* c, const Plan& p, hipStream_t st, bool* ran, Octants** out)
 {
     Octants& o = c->cache[p.Mt];
@@ -367,25 +358,18 @@ int ensure_ws(ehs_ctx* c, size_t bytes, hipStream_t st)
 // one evaluation
 // ---------------------------------------------------------------------------
 template <typename T>
-int run(ehs_ctx* c, Plan& p, const double* y, const double* s, const double* x, double* u, hipStream_t st,
-        ehs_report* rep, bool alias)
+int run(ehs_ctx* c, Plan& p, const Octants& oct, const double* y, const double* s, const double* x, double* u,
+        hipStream_t st, bool alias)
 {
     const size_t esz = sizeof(T);
     Layout Lo = layout(p, esz);
     int rc = check_extents(p, Lo, esz);
     if (rc) return rc;
-    rc = ensure_ws(c, Lo.total, st);
-    if (rc) return rc;
+    if (!c->ws || c->ws_bytes < Lo.total) return EHS_ENOMEM;
     char* base = static_cast<char*>(c->ws);
     auto rec_ev = [&](int i) {
         if (c->opt_timing && c->ev_ok) hipEventRecord(c->ev[i], st);
     };
-    rec_ev(EHS_ST_PRECOMP);
-    bool ran = false;
-    Octants* oct = nullptr;
-    rc = ensure_octants(c, p, st, &ran, &oct);
-    if (rc) return rc;
-    if (ran) p.warnings |= 2;
     rec_ev(EHS_ST_BIN);
 
     const long long N = p.N, TT = p.T;
@@ -507,10 +491,10 @@ int run(ehs_ctx* c, Plan& p, const double* y, const double* s, const double* x, 
     double npad = 16.0 * (double)Mt * (double)Mt * (double)Mt;
     za.cB = std::pow(p.Lt, 4) / npad;
     za.cH = p.Lt * p.Lt / npad;
-    za.octB64 = oct->B64;
-    za.octH64 = oct->H64;
-    za.octB32 = oct->B32;
-    za.octH32 = oct->H32;
+    za.octB64 = oct.B64;
+    za.octH64 = oct.H64;
+    za.octB32 = oct.B32;
+    za.octH32 = oct.H32;
     za.near0 = 2;
     HIPCHK(launch_z<T>(p.family, Xc, Zo, za, p.resident, st));
     rec_ev(EHS_ST_INVY);
@@ -530,23 +514,29 @@ int run(ehs_ctx* c, Plan& p, const double* y, const double* s, const double* x, 
     // -- quadrature at the targets and FP64 combination with the real part
     HIPCHK(launch_gather<T>(p.g, X, csR, xs, tperm, TT, upart, u, st));
     rec_ev(EHS_ST_TOTAL);
-    (void)rep;
     return EHS_OK;
 }
 
-int validate_and_plan(ehs_ctx* c, int family, const double* y, const double* s, int64_t N, const double* x, int64_t T,
-                      double xi, double rc, double tol, hipStream_t st, Plan* p)
+}  // namespace
+
+int ehs::plan_request(ehs_ctx* c, int family, const double* y, const double* s, int64_t N, const double* x,
+                      int64_t T, double xi, double rc, double tol, int prec, hipStream_t st, Plan* p)
 {
+    if (family < 0 || family > 2) return EHS_EINVAL;
+    if (prec < 0 || prec > 2) return EHS_EINVAL;
     if (!y || !s || N < 1 || T < 0 || (T > 0 && !x)) return EHS_EINVAL;
     if (!(xi > 0) || !(rc > 0) || !std::isfinite(xi) || !std::isfinite(rc)) return EHS_EINVAL;
     if (!(tol >= 1e-14 && tol <= 1e-2)) return EHS_EINVAL;
     if (N >= (1LL << 30) || T >= (1LL << 31)) return EHS_EINVAL;
     // bounding box, validation and Q (one readback)
-    char* base = static_cast<char*>(c->ws);
     size_t need = al((size_t)(1024 * 10 + 16) * sizeof(double));
-    int rc0 = ensure_ws(c, std::max(need, c->ws_bytes), st);
-    if (rc0) return rc0;
-    base = static_cast<char*>(c->ws);
+    if (c->ws_external) {
+        if (c->ws_bytes < need) return EHS_ENOMEM;
+    } else {
+        int rc0 = ensure_ws(c, std::max(need, c->ws_bytes), st);
+        if (rc0) return rc0;
+    }
+    char* base = static_cast<char*>(c->ws);
     double* partial = reinterpret_cast<double*>(base);
     double* out16 = partial + 1024 * 10;
     int nb = bbox_blocks(N + T);
@@ -569,14 +559,32 @@ int validate_and_plan(ehs_ctx* c, int family, const double* y, const double* s, 
         in.hi[a] = b[3 + a];
     }
     in.Q = b[9];
-    in.prec = c->opt_prec;
+    in.prec = prec;
     in.force_M = c->force_M;
     in.force_P = c->force_P;
     in.force_Mt = c->force_Mt;
     return make_plan(in, p);
 }
 
-void fill_report(const Plan& p, ehs_report* r)
+int ehs::plan_workspace(const Plan& p, size_t* bytes)
+{
+    size_t esz = p.prec == 1 ? 8 : 4;
+    Layout Lo = layout(p, esz);
+    int rc = check_extents(p, Lo, esz);
+    if (rc) return rc;
+    *bytes = Lo.total;
+    return EHS_OK;
+}
+
+int ehs::execute(ehs_ctx* c, Plan& p, const Octants& o, const double* y, const double* s, const double* x, double* u,
+                 hipStream_t st)
+{
+    if (p.T == 0) return EHS_OK;
+    bool alias = (x == y) && (p.T == p.N);
+    return (p.prec == 1) ? run<double>(c, p, o, y, s, x, u, st, alias) : run<float>(c, p, o, y, s, x, u, st, alias);
+}
+
+void ehs::fill_report(const Plan& p, ehs_report* r)
 {
     std::memset(r, 0, sizeof(*r));
     r->M = p.M;
@@ -603,6 +611,8 @@ void fill_report(const Plan& p, ehs_report* r)
     r->est_fourier = p.est_f;
 }
 
+namespace {
+
 int evaluate(ehs_ctx* c, int family, const double* y, const double* s, int64_t N, const double* x, int64_t T,
              double xi, double rc, double tol, double* u, void* stream, ehs_report* rep)
 {
@@ -617,18 +627,24 @@ int evaluate(ehs_ctx* c, int family, const double* y, const double* s, int64_t N
     }
     if (c->opt_timing && c->ev_ok) hipEventRecord(c->ev[EHS_ST_BBOX], st);
     Plan p;
-    int rc0 = validate_and_plan(c, family, y, s, N, x, T, xi, rc, tol, st, &p);
-    if (rc0) return rc0;
+    int r = plan_request(c, family, y, s, N, x, T, xi, rc, tol, c->opt_prec, st, &p);
+    if (r) return r;
     if (T == 0) {
         if (rep) fill_report(p, rep);
         return EHS_OK;
     }
-    bool alias = (x == y) && (T == N);
-    int r = (p.prec == 1) ? run<double>(c, p, y, s, x, u, st, rep, alias) : run<float>(c, p, y, s, x, u, st, rep, alias);
-    if (r) return r;
+    size_t need = 0;
+    if ((r = plan_workspace(p, &need))) return r;
+    if ((r = ensure_ws(c, need, st))) return r;
+    if (c->opt_timing && c->ev_ok) hipEventRecord(c->ev[EHS_ST_PRECOMP], st);
+    bool ran = false;
+    Octants* oct = nullptr;
+    if ((r = ensure_octants(c, p, st, &ran, &oct))) return r;
+    if (ran) p.warnings |= 2;
+    if ((r = execute(c, p, *oct, y, s, x, u, st))) return r;
     if (rep) {
         fill_report(p, rep);
-        rep->workspace_bytes = (double)c->ws_bytes;
+        rep->workspace_bytes = (double)need;
         if (c->opt_timing && c->ev_ok) {
             if (hipEventSynchronize(c->ev[EHS_ST_TOTAL]) != hipSuccess) return EHS_EHIP;
             for (int i = 0; i < EHS_ST_TOTAL; ++i) {
@@ -646,6 +662,54 @@ int evaluate(ehs_ctx* c, int family, const double* y, const double* s, int64_t N
 
 }  // namespace
 
+void ehs::free_tables(Tables* t)
+{
+    if (!t) return;
+    for (auto& kv : t->m) hipFree(kv.second);
+    t->m.clear();
+}
+
+int ehs::ctx_init(ehs_ctx* c, int device, Tables* shared)
+{
+    c->device = device;
+    if (shared) {
+        c->tables = shared;
+        c->own_tables = false;
+    } else {
+        c->tables = new (std::nothrow) Tables();
+        c->own_tables = true;
+        if (!c->tables) return EHS_ENOMEM;
+    }
+    if (hipHostMalloc((void**)&c->host_bbox, 16 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+        c->host_bbox = nullptr;
+        return EHS_ENOMEM;
+    }
+    return EHS_OK;
+}
+
+void ehs::ctx_release(ehs_ctx* c)
+{
+    if (c->ws && !c->ws_external) hipFree(c->ws);
+    c->ws = nullptr;
+    for (auto& kv : c->cache) {
+        if (kv.second.B64) hipFree(kv.second.B64);
+        if (kv.second.H64) hipFree(kv.second.H64);
+        if (kv.second.B32) hipFree(kv.second.B32);
+        if (kv.second.H32) hipFree(kv.second.H32);
+    }
+    c->cache.clear();
+    if (c->own_tables && c->tables) {
+        free_tables(c->tables);
+        delete c->tables;
+    }
+    c->tables = nullptr;
+    if (c->ev_ok)
+        for (int i = 0; i <= EHS_NSTAGES; ++i) hipEventDestroy(c->ev[i]);
+    c->ev_ok = false;
+    if (c->host_bbox) hipHostFree(c->host_bbox);
+    c->host_bbox = nullptr;
+}
+
 extern "C" {
 
 int ehs_create(ehs_ctx** out, int hip_device, size_t arena_bytes)
@@ -658,10 +722,11 @@ int ehs_create(ehs_ctx** out, int hip_device, size_t arena_bytes)
     if (hipSetDevice(hip_device) != hipSuccess) return EHS_EHIP;
     ehs_ctx* c = new (std::nothrow) ehs_ctx();
     if (!c) return EHS_ENOMEM;
-    c->device = hip_device;
-    if (hipHostMalloc((void**)&c->host_bbox, 16 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+    int rc = ctx_init(c, hip_device, nullptr);
+    if (rc) {
+        ctx_release(c);
         delete c;
-        return EHS_ENOMEM;
+        return rc;
     }
     *out = c;
     return EHS_OK;
@@ -672,17 +737,7 @@ void ehs_destroy(ehs_ctx* c)
     if (!c) return;
     hipSetDevice(c->device);
     hipDeviceSynchronize();
-    if (c->ws) hipFree(c->ws);
-    for (auto& kv : c->cache) {
-        if (kv.second.B64) hipFree(kv.second.B64);
-        if (kv.second.H64) hipFree(kv.second.H64);
-        if (kv.second.B32) hipFree(kv.second.B32);
-        if (kv.second.H32) hipFree(kv.second.H32);
-    }
-    for (auto& kv : c->tables) hipFree(kv.second);
-    if (c->ev_ok)
-        for (int i = 0; i <= EHS_NSTAGES; ++i) hipEventDestroy(c->ev[i]);
-    if (c->host_bbox) hipHostFree(c->host_bbox);
+    ctx_release(c);
     delete c;
 }
 
@@ -732,6 +787,7 @@ const char* ehs_strerror(int code)
         case EHS_ERANGE: return "no admissible grid for the requested accuracy";
         case EHS_ENOMEM: return "device memory exhausted or above the memory cap";
         case EHS_EHIP: return "HIP runtime error";
+        case EHS_ETIMEDOUT: return "request not completed within the timeout";
         default: return "unknown error";
     }
 }

@@ -1,0 +1,83 @@
+// Internal host-side state shared by the single-call path (api.cpp) and the
+// serving scheduler (serve.cpp).  Not part of the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <map>
+#include <mutex>
+#include <utility>
+
+#include "../../include/ehs.h"
+#include "kernels.h"
+#include "plan.h"
+
+namespace ehs {
+
+// Truncated-kernel multipliers on the octant k1, k2 <= M~, |k3| <= 2M~
+// (FP64, plus FP32 copies for the FP32 path).
+struct Octants {
+    double* B64 = nullptr;
+    double* H64 = nullptr;
+    float* B32 = nullptr;
+    float* H32 = nullptr;
+    int nf = 0, nf3 = 0;
+};
+
+// Twiddle and Stockham stage tables by (length, element size); immutable once
+// built, the map is guarded by mu.  One per standalone context, one per server
+// (shared by its slots).
+struct Tables {
+    std::mutex mu;
+    std::map<std::pair<int, int>, void*> m;
+};
+
+void free_tables(Tables* t);
+
+}  // namespace ehs
+
+struct ehs_ctx {
+    int device = 0;
+    void* ws = nullptr;
+    size_t ws_bytes = 0;
+    bool ws_external = false;                // workspace lent by a server arena
+    std::map<int, ehs::Octants> cache;       // by M~ (standalone contexts only)
+    ehs::Tables* tables = nullptr;
+    bool own_tables = true;
+    double* host_bbox = nullptr;             // pinned, 16 doubles
+    hipEvent_t ev[EHS_NSTAGES + 1] = {};
+    bool ev_ok = false;
+    int opt_prec = 0, opt_timing = 0, force_M = 0, force_P = 0, force_Mt = 0;
+    double mem_cap = 0.0;
+};
+
+namespace ehs {
+
+// Context set-up on the current device; `shared` (may be null) lends the
+// table cache of a server.
+int ctx_init(ehs_ctx* c, int device, Tables* shared);
+void ctx_release(ehs_ctx* c);
+
+// Argument checks, bounding box / validation reduction (one readback on st)
+// and parameter selection with precision `prec` (0 auto, 1 FP64, 2 FP32).
+int plan_request(ehs_ctx* c, int family, const double* y, const double* s, int64_t N, const double* x, int64_t T,
+                 double xi, double rc, double tol, int prec, hipStream_t st, Plan* p);
+
+// Workspace bytes of one evaluation under plan p (after the extent audit).
+int plan_workspace(const Plan& p, size_t* bytes);
+
+// Elements of one octant array for grid size Mt.
+inline long long octant_elems(int Mt) { return (long long)(Mt + 1) * (Mt + 1) * (2 * Mt + 1); }
+
+// Enqueue the precompute of one FP64 octant (kind 0: harmonic, 1: biharmonic)
+// into `oct`, using the context workspace as scratch.
+int precompute_octant(ehs_ctx* c, const Plan& p, int kind, double* oct, hipStream_t st);
+
+// Enqueue one evaluation under plan p with ready octants (the workspace
+// c->ws must hold plan_workspace(p) bytes).
+int execute(ehs_ctx* c, Plan& p, const Octants& o, const double* y, const double* s, const double* x, double* u,
+            hipStream_t st);
+
+void fill_report(const Plan& p, ehs_report* r);
+
+}  // namespace ehs

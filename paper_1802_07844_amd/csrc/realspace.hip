@@ -206,8 +206,14 @@ __global__ void __launch_bounds__(256) k_realspace(RealArgs a, const double* __r
             }
         }
     }
+    // Image and correction terms in FP64 in both precisions: for a source and
+    // target near the wall they are of size 1/(x3 + y3)^2 and cancel to O(1)
+    // on the wall, beyond what FP32 can resolve.  Only sources within r_c of
+    // the wall have images here, so this is a small share of the work.
+    double acci[3] = {0.0, 0.0, 0.0};
     if (c3 == 0) {
-        const T x3 = (T)xd2;
+        const double x3 = xd2;
+        const double xid = a.xi, c2d = 2.0 * a.xi / 1.7724538509055160273;
         for (int d2 = -1; d2 <= 1; ++d2) {
             int cc2 = c2i + d2;
             if (cc2 < 0 || cc2 >= n1) continue;
@@ -218,19 +224,19 @@ __global__ void __launch_bounds__(256) k_realspace(RealArgs a, const double* __r
                 double dx = xd0 - ys[m], dy = xd1 - ys[N + m], dz = xd2 + y3;
                 double r2 = dx * dx + dy * dy + dz * dz;
                 if (r2 < rc2) {
-                    T sv[NS];
+                    double sv[NS];
 #pragma unroll
-                    for (int c = 0; c < NS; ++c) sv[c] = (T)ss[c * N + m];
-                    image_term<T, K>((T)dx, (T)dy, (T)dz, (T)r2, sv, (T)y3, x3, xi, c2, acc);
+                    for (int c = 0; c < NS; ++c) sv[c] = ss[c * N + m];
+                    image_term<double, K>(dx, dy, dz, r2, sv, y3, x3, xid, c2d, acci);
                 }
             }
         }
     }
     if (act) {
         long long o = a.tgt_perm[t];
-        upart[3 * o + 0] = (double)acc[0] + self[0];
-        upart[3 * o + 1] = (double)acc[1] + self[1];
-        upart[3 * o + 2] = (double)acc[2] + self[2];
+        upart[3 * o + 0] = (double)acc[0] + acci[0] + self[0];
+        upart[3 * o + 1] = (double)acc[1] + acci[1] + self[1];
+        upart[3 * o + 2] = (double)acc[2] + acci[2] + self[2];
     }
 }
 

@@ -109,6 +109,18 @@ def make(kernel: str, n: int, seed: int, layout: str = "uniform"):
     raise ValueError(kernel)
 
 
+def serving_pool(n: int, seed: int):
+    """Input pool for a serving stream: uniform positions with stokeslet forces,
+    stresslet (g, q) and rotlet torques for each point.  A request of size N
+    takes rows [o, o + N) of the pool (a uniform sample itself)."""
+    g = rng(seed)
+    y = uniform_positions(g, n)
+    f = g.standard_normal((n, 3))
+    gq = np.concatenate([g.standard_normal((n, 3)), unit_normals(g, n)], axis=1)
+    v = g.standard_normal((n, 3))
+    return y, f, gq, v
+
+
 def serving_stream(n_requests: int, seed: int, n_min: float = 1e3, n_max: float = 1e6):
     """Request descriptors: (kernel, N, tol, data seed) in arrival order.
 

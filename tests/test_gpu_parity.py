@@ -131,3 +131,20 @@ def test_deterministic_repeat(ctx):
     u1, _ = _run(ctx, "stokeslet", y, s, y, xi, rc, 1e-10, prec=1, alias=True)
     u2, _ = _run(ctx, "stokeslet", y, s, y, xi, rc, 1e-10, prec=1, alias=True)
     assert np.array_equal(u1, u2)
+
+
+@pytest.mark.parametrize("family", FAMILIES)
+def test_fp32_point_almost_on_the_wall(ctx, family):
+    """A source/target pair 1e-6 above the wall: its image and correction terms
+    are ~1e12 times larger than their sum, which the FP32 path must still
+    resolve (it evaluates them in FP64)."""
+    n = 2085
+    y, s = workloads.make(family, n, 1806)
+    y[7, 2] = 1e-6
+    y[11, 2] = 3e-5
+    xi, rc = _params(family, n, 1e-5, nb=150)
+    u, rep = _run(ctx, family, y, s, y, xi, rc, 1e-5, prec=2, alias=True)
+    ref = oracle.halfspace(family, y, s, y)
+    err = oracle.rel_rms(ref, u)
+    print(f"{family}: FP32 near-wall N={n} rel-RMS={err:.3e}")
+    assert err <= 1e-5

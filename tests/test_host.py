@@ -163,3 +163,14 @@ def test_plan_sweep_passes_extent_audit(family, prec):
                 assert (math.pi / (1.0 / 2048)) < 7 * xi or nb == 30
                 continue
             assert r.workspace_bytes > 0 and r.Mt >= r.M + r.P
+
+
+def test_server_create_without_device_fails_cleanly():
+    import torch
+
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    h = ctypes.c_void_p()
+    rc = ehs.lib().ehs_server_create(ctypes.byref(h), 0, 1 << 30, 2)
+    assert rc != 0 and not h.value
+    assert "timeout" in ehs.strerror(ehs.EHS_ETIMEDOUT)
