@@ -64,6 +64,8 @@ extern "C" {
 #define EHS_OPT_FORCE_P 3   /* > 0: use this Gaussian support P (even) */
 #define EHS_OPT_FORCE_MT 4  /* > 0: use this total grid size M~ (>= M + P, 7-smooth, even) */
 #define EHS_OPT_MEM_CAP 5   /* > 0: refuse a workspace larger than this many bytes (EHS_ENOMEM) */
+#define EHS_OPT_ZSLAB 6     /* > 0: k1 slabs per group of the y / x3 transform pipeline (default: sized for
+                               the last-level cache); M~ + 1 keeps the whole grid in one group */
 
 /* stage indices of ehs_report.ms_stage */
 #define EHS_ST_BBOX 0       /* bounding box + validation reduction and its readback */
@@ -97,6 +99,8 @@ typedef struct ehs_report {
     double origin[3];       /* grid origin (the wall is at x3 = 0) */
     double ms_stage[EHS_NSTAGES]; /* stage times when EHS_OPT_TIMING is on, else 0 */
     double workspace_bytes;
+    int32_t zslab;          /* k1 slabs per group of the y / x3 transform pipeline */
+    int32_t reserved;
 } ehs_report;
 
 /* Create a context on HIP device `hip_device`.  `arena_bytes` is reserved

@@ -252,7 +252,7 @@ int ensure_octants(ehs_ctx* c, const Plan& p, hipStream_t st, bool* ran, Octants
 // workspace layout
 // ---------------------------------------------------------------------------
 struct Layout {
-    size_t X, Y, Zo, rec, keys, sortsc, toff, soff, tgoff, chunks, ys, ss, xs, upart, bb, total;
+    size_t X, Y, ZS, Zo, rec, keys, sortsc, toff, soff, tgoff, chunks, ys, ss, xs, upart, bb, total;
 };
 
 // Host-side audit: the largest extent every pass writes or reads must fit the
@@ -264,16 +264,17 @@ int check_extents(const Plan& p, const Layout& L, size_t esz)
     const size_t c = 2 * esz;
     const size_t real = Mt * Mt * 2 * Mt * esz;
     const size_t a = (Mt + 1) * 2 * Mt * Mt * c;
-    const size_t z = (Mt + 1) * 2 * Mt * 2 * Mt * c;
+    const size_t zs = (size_t)p.zg * 2 * Mt * 2 * Mt * c;  // one component of the slab buffer
     const size_t nin = (size_t)p.ncin;
-    const size_t xreg = L.Y - L.X, yreg = L.Zo - L.Y, zreg = L.rec - L.Zo;
+    const size_t xreg = L.Y - L.X, yreg = L.ZS - L.Y, zsreg = L.Zo - L.ZS, zoreg = L.rec - L.Zo;
     auto fits = [](size_t need, size_t have) { return need <= have; };
-    bool ok = fits(nin * real, xreg)                  // spread -> X
-              && fits(nin * a, yreg)                  // forward x1 -> Y
-              && fits(nin * z, xreg)                  // forward x2 -> X
-              && fits(6 * z, p.resident ? xreg : zreg)  // fused x3 outputs
-              && fits(6 * a, yreg)                    // inverse x2 -> Y
-              && fits(6 * real, xreg)                 // inverse x1 -> X (read by the gather)
+    bool ok = p.zg >= 1 && p.zg <= p.Mt + 1
+              && fits(nin * real, xreg)                 // spread -> X
+              && fits(nin * a, yreg)                    // forward x1 -> Y
+              && fits(nin * zs, zsreg)                  // forward x2 -> slab buffer
+              && fits(6 * zs, p.resident ? zsreg : zoreg)  // fused x3 outputs
+              && fits(6 * a, yreg)                      // inverse x2 -> Y (in place of A)
+              && fits(6 * real, xreg)                   // inverse x1 -> X (read by the gather)
               && fits((size_t)2 * p.N * record_stride(p.family, p.P, esz) * esz, L.keys - L.rec)
               && fits((size_t)(4 * p.N + 4 * p.T + 8 * p.N) * 4, L.sortsc - L.keys)
               && fits((size_t)(p.ntiles + 1) * 4, L.soff - L.toff)
@@ -307,17 +308,18 @@ Layout layout(const Plan& p, size_t esz)
     const long long Mt = p.Mt;
     const int ncin = p.ncin;
     const int nl = std::max(ncin, 6);
-    size_t cz = (size_t)(Mt + 1) * 2 * Mt * 2 * Mt * 2 * esz;  // one Z component (complex)
-    size_t cy = (size_t)(Mt + 1) * 2 * Mt * Mt * 2 * esz;      // one A / D component
-    size_t x_bytes = std::max((size_t)nl * cz, (size_t)ncin * (size_t)(Mt * Mt * 2 * Mt) * esz);
+    size_t czs = (size_t)p.zg * 2 * Mt * 2 * Mt * 2 * esz;  // one slab-buffer component (complex)
+    size_t cy = (size_t)(Mt + 1) * 2 * Mt * Mt * 2 * esz;   // one A / D component
+    size_t x_bytes = (size_t)nl * (size_t)(Mt * Mt * 2 * Mt) * esz;
     // the precompute scratch also lives in X
     long long h1 = p.nf / 2 + 1;
     size_t pre = (size_t)(h1 * h1 * (2 * Mt + 1) + h1 * (Mt + 1) * (2 * Mt + 1)) * sizeof(double);
     x_bytes = std::max(x_bytes, pre);
     size_t off = 0;
     L.X = off; off += al(x_bytes);
-    L.Y = off; off += al((size_t)nl * cy);  // forward passes use ncin components, inverse passes 6
-    L.Zo = off; off += p.resident ? 0 : al((size_t)6 * cz);
+    L.Y = off; off += al((size_t)nl * cy);  // A (ncin components), then D (6) in place
+    L.ZS = off; off += al((size_t)nl * czs);
+    L.Zo = off; off += p.resident ? 0 : al((size_t)6 * czs);
     long long N = p.N, T = p.T;
     L.rec = off; off += al((size_t)2 * N * record_stride(p.family, p.P, esz) * esz);
     // keys / values: sources (4 N), targets (4 T), points (4 * 2N)
@@ -428,9 +430,7 @@ int run(ehs_ctx* c, Plan& p, const Octants& oct, const double* y, const double* 
 
     // -- spreading
     T* X = reinterpret_cast<T*>(base + Lo.X);
-    cplx<T>* Xc = reinterpret_cast<cplx<T>*>(base + Lo.X);
     cplx<T>* Yc = reinterpret_cast<cplx<T>*>(base + Lo.Y);
-    cplx<T>* Zo = p.resident ? Xc : reinterpret_cast<cplx<T>*>(base + Lo.Zo);
     T* rec = reinterpret_cast<T*>(base + Lo.rec);
     uint32_t *pk, *pperm;
     HIPCHK(launch_point_keys(y, N, p.g, kp, vp, st));
@@ -440,7 +440,6 @@ int run(ehs_ctx* c, Plan& p, const Octants& oct, const double* y, const double* 
     const long long Mt = p.Mt;
     const long long csR = Mt * Mt * 2 * Mt;          // real grid component
     const long long csA = (Mt + 1) * 2 * Mt * Mt;    // A / D component (complex)
-    const long long csZ = (Mt + 1) * 2 * Mt * 2 * Mt;  // Z component (complex)
     HIPCHK(launch_spread<T>(p.family, p.g, rec, toff, X, csR, st));
     rec_ev(EHS_ST_FWDX);
 
@@ -448,6 +447,8 @@ int run(ehs_ctx* c, Plan& p, const Octants& oct, const double* y, const double* 
     PassArgs pa;
     std::memset(&pa, 0, sizeof(pa));
     pa.Mt = p.Mt;
+    pa.k1base = 0;
+    pa.nk1 = p.Mt + 1;
     void* tw2 = nullptr;
     if ((rc = tw_table(c, 2 * p.Mt, (int)esz, &tw2))) return rc;
     pa.tw2 = tw2;
@@ -463,13 +464,10 @@ int run(ehs_ctx* c, Plan& p, const Octants& oct, const double* y, const double* 
     pa.cs_out = csA;
     HIPCHK(launch_fwd_x<T>(X, Yc, pa, p.ncin, st));
     rec_ev(EHS_ST_FWDY);
-    set_b(p.By);
-    pa.cs_in = csA;
-    pa.cs_out = csZ;
-    HIPCHK(launch_fwd_y<T>(Yc, Xc, pa, p.ncin, st));
-    rec_ev(EHS_ST_ZSCALE);
 
-    // -- fused x3 transform + scaling + inverse x3 transform
+    // -- y / x3 pipeline over groups of zg k1 slabs: forward y into the slab
+    //    buffer, fused x3 transform + scaling + inverse x3, inverse y back into
+    //    Y (D[k1] replaces A[k1], which the forward y pass of the group has read)
     ZArgs za;
     std::memset(&za, 0, sizeof(za));
     za.Mt = p.Mt;
@@ -477,8 +475,9 @@ int run(ehs_ctx* c, Plan& p, const Octants& oct, const double* y, const double* 
     za.mnz = magic_of((unsigned)(2 * p.Mt));
     za.mnq = magic_of((unsigned)(4 * p.Mt / p.Qz));
     za.mn4 = magic_of((unsigned)(4 * p.Mt));
-    za.cs = csZ;
-    za.cs_out = csZ;
+    const long long csS = (long long)p.zg * 2 * Mt * 2 * Mt;  // slab-buffer component
+    za.cs = csS;
+    za.cs_out = csS;
     void* tw4 = nullptr;
     if ((rc = tw_table(c, 4 * p.Mt, (int)esz, &tw4))) return rc;
     za.tw4 = tw4;
@@ -496,14 +495,41 @@ int run(ehs_ctx* c, Plan& p, const Octants& oct, const double* y, const double* 
     za.octB32 = oct.B32;
     za.octH32 = oct.H32;
     za.near0 = 2;
-    HIPCHK(launch_z<T>(p.family, Xc, Zo, za, p.resident, st));
+    cplx<T>* ZS = reinterpret_cast<cplx<T>*>(base + Lo.ZS);
+    cplx<T>* ZO = p.resident ? ZS : reinterpret_cast<cplx<T>*>(base + Lo.Zo);
+    const int ngroups = (p.Mt + p.zg) / p.zg;
+    const bool slab_ev = c->opt_timing && c->ev_ok;
+    if (slab_ev) {
+        size_t need = (size_t)3 * ngroups + 1;
+        while (c->sev.size() < need) {
+            hipEvent_t e;
+            HIPCHK(hipEventCreate(&e));
+            c->sev.push_back(e);
+        }
+        c->nsev = 0;
+        HIPCHK(hipEventRecord(c->sev[c->nsev++], st));
+    }
+    set_b(p.By);
+    for (int k0 = 0; k0 <= p.Mt; k0 += p.zg) {
+        const int cnt = std::min(p.zg, p.Mt + 1 - k0);
+        pa.k1base = k0;
+        pa.nk1 = cnt;
+        za.k1base = k0;
+        za.nk1 = cnt;
+        pa.cs_in = csA;
+        pa.cs_out = csS;
+        HIPCHK(launch_fwd_y<T>(Yc, ZS, pa, p.ncin, st));
+        if (slab_ev) HIPCHK(hipEventRecord(c->sev[c->nsev++], st));
+        HIPCHK(launch_z<T>(p.family, ZS, ZO, za, p.resident, st));
+        if (slab_ev) HIPCHK(hipEventRecord(c->sev[c->nsev++], st));
+        pa.cs_in = csS;
+        pa.cs_out = csA;
+        HIPCHK(launch_inv_y<T>(ZO, Yc, pa, 6, st));
+        if (slab_ev) HIPCHK(hipEventRecord(c->sev[c->nsev++], st));
+    }
+    rec_ev(EHS_ST_ZSCALE);
     rec_ev(EHS_ST_INVY);
 
-    // -- inverse transforms
-    set_b(p.By);
-    pa.cs_in = csZ;
-    pa.cs_out = csA;
-    HIPCHK(launch_inv_y<T>(Zo, Yc, pa, 6, st));
     rec_ev(EHS_ST_INVX);
     set_b(p.Bx);
     pa.cs_in = csA;
@@ -563,6 +589,7 @@ int ehs::plan_request(ehs_ctx* c, int family, const double* y, const double* s, 
     in.force_M = c->force_M;
     in.force_P = c->force_P;
     in.force_Mt = c->force_Mt;
+    in.force_zg = c->force_zg;
     return make_plan(in, p);
 }
 
@@ -609,6 +636,7 @@ void ehs::fill_report(const Plan& p, ehs_report* r)
     r->tol = p.tol;
     r->est_real = p.est_r;
     r->est_fourier = p.est_f;
+    r->zslab = p.zg;
 }
 
 namespace {
@@ -655,6 +683,22 @@ int evaluate(ehs_ctx* c, int family, const double* y, const double* s, int64_t N
             float tot = 0.f;
             hipEventElapsedTime(&tot, c->ev[EHS_ST_BBOX], c->ev[EHS_ST_TOTAL]);
             rep->ms_stage[EHS_ST_TOTAL] = tot;
+            // the y / x3 pipeline: per-kernel sums over the slab groups
+            double sy = 0, sz = 0, si = 0;
+            for (int g = 0; 3 * g + 3 < c->nsev; ++g) {
+                float m0 = 0.f, m1 = 0.f, m2 = 0.f;
+                hipEventElapsedTime(&m0, c->sev[3 * g], c->sev[3 * g + 1]);
+                hipEventElapsedTime(&m1, c->sev[3 * g + 1], c->sev[3 * g + 2]);
+                hipEventElapsedTime(&m2, c->sev[3 * g + 2], c->sev[3 * g + 3]);
+                sy += m0;
+                sz += m1;
+                si += m2;
+            }
+            if (c->nsev > 1) {
+                rep->ms_stage[EHS_ST_FWDY] = sy;
+                rep->ms_stage[EHS_ST_ZSCALE] = sz;
+                rep->ms_stage[EHS_ST_INVY] = si;
+            }
         }
     }
     return EHS_OK;
@@ -706,6 +750,8 @@ void ehs::ctx_release(ehs_ctx* c)
     if (c->ev_ok)
         for (int i = 0; i <= EHS_NSTAGES; ++i) hipEventDestroy(c->ev[i]);
     c->ev_ok = false;
+    for (hipEvent_t e : c->sev) hipEventDestroy(e);
+    c->sev.clear();
     if (c->host_bbox) hipHostFree(c->host_bbox);
     c->host_bbox = nullptr;
 }
@@ -754,6 +800,7 @@ int ehs_set_option(ehs_ctx* c, int option, double value)
         case EHS_OPT_FORCE_P: c->force_P = (int)value; return EHS_OK;
         case EHS_OPT_FORCE_MT: c->force_Mt = (int)value; return EHS_OK;
         case EHS_OPT_MEM_CAP: c->mem_cap = value; return EHS_OK;
+        case EHS_OPT_ZSLAB: c->force_zg = (int)value; return EHS_OK;
         default: return EHS_EINVAL;
     }
 }

@@ -212,6 +212,91 @@ struct Dft<T, 7> {
     }
 };
 
+// Radix 16 as 4 x 4 (Cooley-Tukey): n = 4 n1 + n2, k = k1 + 4 k2, with the
+// twiddles exp(-2 pi i n2 k1 / 16) between the two rounds of 4-point DFTs.
+template <typename T>
+struct Dft<T, 16> {
+    __device__ __forceinline__ static void run(cplx<T>* v)
+    {
+        const T c1 = (T)0.92387953251128675613;  // cos(pi / 8)
+        const T s1 = (T)0.38268343236508977173;  // sin(pi / 8)
+        const T h = (T)0.70710678118654752440;   // cos(pi / 4)
+        cplx<T> y[4][4];
+#pragma unroll
+        for (int n2 = 0; n2 < 4; ++n2) {
+#pragma unroll
+            for (int n1 = 0; n1 < 4; ++n1) y[n2][n1] = v[4 * n1 + n2];
+            Dft<T, 4>::run(y[n2]);  // y[n2][k1]
+        }
+        // w^1 = (c1, -s1), w^2 = (h, -h), w^3 = (s1, -c1), w^4 = -i, w^6 = (-h, -h), w^9 = (-c1, s1)
+        y[1][1] = cmul(y[1][1], cmk<T>(c1, -s1));
+        y[1][2] = cmul(y[1][2], cmk<T>(h, -h));
+        y[1][3] = cmul(y[1][3], cmk<T>(s1, -c1));
+        y[2][1] = cmul(y[2][1], cmk<T>(h, -h));
+        y[2][2] = cmul_mi(y[2][2]);
+        y[2][3] = cmul(y[2][3], cmk<T>(-h, -h));
+        y[3][1] = cmul(y[3][1], cmk<T>(s1, -c1));
+        y[3][2] = cmul(y[3][2], cmk<T>(-h, -h));
+        y[3][3] = cmul(y[3][3], cmk<T>(-c1, s1));
+#pragma unroll
+        for (int k1 = 0; k1 < 4; ++k1) {
+            cplx<T> t[4] = {y[0][k1], y[1][k1], y[2][k1], y[3][k1]};
+            Dft<T, 4>::run(t);
+#pragma unroll
+            for (int k2 = 0; k2 < 4; ++k2) v[k1 + 4 * k2] = t[k2];
+        }
+    }
+};
+
+// modular inverse of a (mod m), m >= 2, gcd(a, m) = 1 (compile-time use)
+__host__ __device__ constexpr int inv_mod(int a, int m)
+{
+    int x = 1;
+    while ((a * x) % m != 1) ++x;
+    return x;
+}
+
+// Radix N1 N2 with coprime factors as a prime-factor (Good-Thomas) transform:
+// input n = (N2 n1 + N1 n2) mod N, output by the Chinese remainder map; no
+// twiddles between the rounds.
+template <typename T, int N1, int N2>
+struct Pfa {
+    static constexpr int N = N1 * N2;
+    // output map: k = (k1 E1 + k2 E2) mod N is the k with k = k1 (mod N1),
+    // k = k2 (mod N2)
+    static constexpr int E1 = (N2 * inv_mod(N2 % N1, N1)) % N;
+    static constexpr int E2 = (N1 * inv_mod(N1 % N2, N2)) % N;
+    __device__ __forceinline__ static void run(cplx<T>* v)
+    {
+        cplx<T> y[N2][N1];
+#pragma unroll
+        for (int n2 = 0; n2 < N2; ++n2) {
+#pragma unroll
+            for (int n1 = 0; n1 < N1; ++n1) y[n2][n1] = v[(N2 * n1 + N1 * n2) % N];
+            Dft<T, N1>::run(y[n2]);
+        }
+#pragma unroll
+        for (int k1 = 0; k1 < N1; ++k1) {
+            cplx<T> t[N2];
+#pragma unroll
+            for (int n2 = 0; n2 < N2; ++n2) t[n2] = y[n2][k1];
+            Dft<T, N2>::run(t);
+#pragma unroll
+            for (int k2 = 0; k2 < N2; ++k2) v[(k1 * E1 + k2 * E2) % N] = t[k2];
+        }
+    }
+};
+template <typename T>
+struct Dft<T, 15> : Pfa<T, 3, 5> {};
+template <typename T>
+struct Dft<T, 6> : Pfa<T, 2, 3> {};
+template <typename T>
+struct Dft<T, 10> : Pfa<T, 2, 5> {};
+template <typename T>
+struct Dft<T, 12> : Pfa<T, 4, 3> {};
+template <typename T>
+struct Dft<T, 14> : Pfa<T, 2, 7> {};
+
 // One Stockham stage of radix R on `nl` lines of length n held in LDS
 // (line q at buf + q * ld).  Every thread of the block calls it; each thread
 // handles up to E/R butterflies, one after the other, keeping only their
@@ -277,7 +362,13 @@ __device__ void lds_fft(cplx<T>* buf, int ld, int nl, const FftPlanDev& p)
             case 3: fft_stage<T, NT, E, 3, INV>(buf, ld, nl, p, s, tw); break;
             case 4: fft_stage<T, NT, E, 4, INV>(buf, ld, nl, p, s, tw); break;
             case 5: fft_stage<T, NT, E, 5, INV>(buf, ld, nl, p, s, tw); break;
+            case 6: fft_stage<T, NT, E, 6, INV>(buf, ld, nl, p, s, tw); break;
             case 7: fft_stage<T, NT, E, 7, INV>(buf, ld, nl, p, s, tw); break;
+            case 10: fft_stage<T, NT, E, 10, INV>(buf, ld, nl, p, s, tw); break;
+            case 12: fft_stage<T, NT, E, 12, INV>(buf, ld, nl, p, s, tw); break;
+            case 14: fft_stage<T, NT, E, 14, INV>(buf, ld, nl, p, s, tw); break;
+            case 15: fft_stage<T, NT, E, 15, INV>(buf, ld, nl, p, s, tw); break;
+            case 16: fft_stage<T, NT, E, 16, INV>(buf, ld, nl, p, s, tw); break;
             default: fft_stage<T, NT, E, 8, INV>(buf, ld, nl, p, s, tw); break;
         }
     }

@@ -7,6 +7,7 @@
 #include <map>
 #include <mutex>
 #include <utility>
+#include <vector>
 
 #include "../../include/ehs.h"
 #include "kernels.h"
@@ -47,7 +48,9 @@ struct ehs_ctx {
     double* host_bbox = nullptr;             // pinned, 16 doubles
     hipEvent_t ev[EHS_NSTAGES + 1] = {};
     bool ev_ok = false;
-    int opt_prec = 0, opt_timing = 0, force_M = 0, force_P = 0, force_Mt = 0;
+    int opt_prec = 0, opt_timing = 0, force_M = 0, force_P = 0, force_Mt = 0, force_zg = 0;
+    std::vector<hipEvent_t> sev;             // per-launch events of the slab pipeline (timing)
+    int nsev = 0;                            // events recorded in the last evaluation
     double mem_cap = 0.0;
 };
 

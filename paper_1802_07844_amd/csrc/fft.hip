@@ -32,7 +32,7 @@ constexpr int Z_E = 16;
 // grid: (ceil(Mt / B), 2Mt, ncomp); B even.
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ void __launch_bounds__(XPASS_NT) k_fwd_x(const T* __restrict__ in, cplx<T>* __restrict__ out, PassArgs a)
+__global__ void __launch_bounds__(XPASS_NT, 4) k_fwd_x(const T* __restrict__ in, cplx<T>* __restrict__ out, PassArgs a)
 {
     extern __shared__ unsigned char smem_raw[];
     cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
@@ -85,7 +85,7 @@ __global__ void __launch_bounds__(PASS_NT) k_fwd_y(const cplx<T>* __restrict__ i
     extern __shared__ unsigned char smem_raw[];
     cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
     const int Mt = a.Mt, B = a.B, ld = Mt + 1;
-    const int l0 = blockIdx.x * B, k1 = blockIdx.y, c = blockIdx.z;
+    const int l0 = blockIdx.x * B, k1l = blockIdx.y, k1 = a.k1base + k1l, c = blockIdx.z;
     const int nl = 2 * Mt;
     const int nb = min(B, nl - l0);
     const cplx<T>* tw2 = static_cast<const cplx<T>*>(a.tw2);
@@ -105,7 +105,7 @@ __global__ void __launch_bounds__(PASS_NT) k_fwd_y(const cplx<T>* __restrict__ i
             if (b < nb) x[i] = src[f];
         }
     }
-    cplx<T>* dst = out + (long long)c * a.cs_out + (long long)k1 * nl * nl + l0;
+    cplx<T>* dst = out + (long long)c * a.cs_out + (long long)k1l * nl * nl + l0;
     for (int s = 0; s < 2; ++s) {
 #pragma unroll
         for (int i = 0; i < MAXR; ++i)
@@ -131,11 +131,11 @@ __global__ void __launch_bounds__(PASS_NT) k_inv_y(const cplx<T>* __restrict__ i
     extern __shared__ unsigned char smem_raw[];
     cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
     const int Mt = a.Mt, B = a.B, ld = Mt + 1;
-    const int l0 = blockIdx.x * B, k1 = blockIdx.y, c = blockIdx.z;
+    const int l0 = blockIdx.x * B, k1l = blockIdx.y, k1 = a.k1base + k1l, c = blockIdx.z;
     const int nl = 2 * Mt;
     const int nb = min(B, nl - l0);
     const cplx<T>* tw2 = static_cast<const cplx<T>*>(a.tw2);
-    const cplx<T>* src = in + (long long)c * a.cs_in + (long long)k1 * nl * nl + l0;
+    const cplx<T>* src = in + (long long)c * a.cs_in + (long long)k1l * nl * nl + l0;
     cplx<T> acc[MAXR];
     for (int s = 0; s < 2; ++s) {
         for (int f = threadIdx.x; f < Mt * B; f += PASS_NT) {
@@ -169,7 +169,7 @@ __global__ void __launch_bounds__(PASS_NT) k_inv_y(const cplx<T>* __restrict__ i
 // output R[l][j][i].  grid: (ceil(Mt / B), 2Mt, ncomp); B even.
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ void __launch_bounds__(XPASS_NT) k_inv_x(const cplx<T>* __restrict__ in, T* __restrict__ out, PassArgs a)
+__global__ void __launch_bounds__(XPASS_NT, 4) k_inv_x(const cplx<T>* __restrict__ in, T* __restrict__ out, PassArgs a)
 {
     extern __shared__ unsigned char smem_raw[];
     cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
@@ -320,9 +320,9 @@ __global__ void __launch_bounds__(Z_NT) k_z_scale(const cplx<T>* zb, cplx<T>* zo
     cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
     const int Mt = a.Mt, Q = a.Q;
     const int nz = 2 * Mt, n4 = 4 * Mt, nq = n4 / Q, ld = nq + 1;
-    const int k2 = blockIdx.x, k1 = blockIdx.y;
+    const int k2 = blockIdx.x, k1 = a.k1base + (int)blockIdx.y;
     const long long cs = a.cs;
-    const long long base = ((long long)k1 * nz + k2) * nz;
+    const long long base = ((long long)blockIdx.y * nz + k2) * nz;
     const cplx<T>* tw4 = static_cast<const cplx<T>*>(a.tw4);
     const unsigned mnz = a.mnz, mnq = a.mnq, mn4 = a.mn4;
 
@@ -551,7 +551,7 @@ hipError_t launch_fwd_x(const T* in, cplx<T>* out, const PassArgs& a, int ncomp,
 template <typename T>
 hipError_t launch_fwd_y(const cplx<T>* in, cplx<T>* out, const PassArgs& a, int ncomp, hipStream_t st)
 {
-    dim3 grid((2 * a.Mt + a.B - 1) / a.B, a.Mt + 1, ncomp);
+    dim3 grid((2 * a.Mt + a.B - 1) / a.B, a.nk1, ncomp);
     size_t lds = pass_lds(a.Mt, a.B, sizeof(T));
     if (a.B * a.Mt <= 8 * PASS_NT)
         hipLaunchKernelGGL((k_fwd_y<T, 8>), grid, dim3(PASS_NT), lds, st, in, out, a);
@@ -562,7 +562,7 @@ hipError_t launch_fwd_y(const cplx<T>* in, cplx<T>* out, const PassArgs& a, int 
 template <typename T>
 hipError_t launch_inv_y(const cplx<T>* in, cplx<T>* out, const PassArgs& a, int ncomp, hipStream_t st)
 {
-    dim3 grid((2 * a.Mt + a.B - 1) / a.B, a.Mt + 1, ncomp);
+    dim3 grid((2 * a.Mt + a.B - 1) / a.B, a.nk1, ncomp);
     size_t lds = pass_lds(a.Mt, a.B, sizeof(T));
     if (a.B * a.Mt <= 8 * PASS_NT)
         hipLaunchKernelGGL((k_inv_y<T, 8>), grid, dim3(PASS_NT), lds, st, in, out, a);
@@ -594,7 +594,7 @@ bool z_resident_ok(int family, int Mt)
 template <typename T, int K>
 static hipError_t launch_z_t(cplx<T>* zb, cplx<T>* zout, const ZArgs& a, bool res, hipStream_t st)
 {
-    dim3 grid(2 * a.Mt, a.Mt + 1);
+    dim3 grid(2 * a.Mt, a.nk1);
     size_t lds = z_lds_bytes(K, a.Mt, a.Q, sizeof(T));
     const int nz = 2 * a.Mt;
     if (!res)

@@ -16,6 +16,8 @@ struct PassArgs {
     long long cs_out;    // elements between components of the output
     const void* tw2;     // exp(-2 pi i t / 2Mt), t < 2Mt
     FftPlanDev fM;       // FFT of length Mt
+    int k1base, nk1;     // y passes: k1 slabs [k1base, k1base + nk1); the Z side
+                         // is a buffer of slabs indexed k1 - k1base
 };
 
 // fused x3 transform + scaling
@@ -36,6 +38,7 @@ struct ZArgs {
     const float* octB32;
     const float* octH32;
     int near0;             // index radius of the k ~ 0 region computed in FP64
+    int k1base, nk1;       // k1 slabs of this launch; data indexed k1 - k1base
 };
 
 // one even real line transform per block (precompute)

@@ -27,6 +27,7 @@
 namespace ehs {
 
 constexpr double C_SHAPE = 0.95;
+constexpr size_t ZSLAB_BUDGET = (size_t)2 << 30;
 
 inline bool smooth7(long long n)
 {
@@ -44,36 +45,43 @@ inline int next_smooth_even(double x)
     return (int)n;
 }
 
-// radices: the odd ones (7, 5, 3) first, then 8, 4, 2.  The first Stockham
-// stage writes with a stride of its radix; an odd stride spreads over the LDS
-// banks, a power of two does not.
+// Radices of the Stockham FFT of length n: the factorisation into
+// {2, 3, 4, 5, 6, 7, 8, 10, 12, 14, 15, 16} with the fewest stages (each stage
+// is one pass through LDS), ties broken by the larger per-thread capacity
+// (elements a thread holds, (16 / R) R at the smallest); odd radices come
+// first, since the first stage writes with a stride of its radix and an odd
+// stride spreads over the LDS banks, then the even ones in decreasing order.
 inline bool factor_radices(int n, std::vector<int>& r)
 {
     r.clear();
     if (n < 2) return false;
-    int m = n;
-    for (int p : {7, 5, 3})
-        while (m % p == 0) {
-            r.push_back(p);
-            m /= p;
+    static const int R[] = {16, 15, 14, 12, 10, 8, 7, 6, 5, 4, 3, 2};
+    // best[m] = (stages, capacity) for m, with the first radix used
+    std::vector<int> st(n + 1, 1 << 20), cap(n + 1, 0), first(n + 1, 0);
+    st[1] = 0;
+    cap[1] = 16;
+    for (int m = 2; m <= n; ++m) {
+        if (n % m) continue;
+        for (int x : R) {
+            if (m % x || st[m / x] >= (1 << 20)) continue;
+            int s2 = st[m / x] + 1, c2 = std::min(cap[m / x], (16 / x) * x);
+            if (s2 < st[m] || (s2 == st[m] && c2 > cap[m])) {
+                st[m] = s2;
+                cap[m] = c2;
+                first[m] = x;
+            }
         }
-    while (m % 8 == 0) {
-        r.push_back(8);
-        m /= 8;
     }
-    if (m % 4 == 0) {
-        r.push_back(4);
-        m /= 4;
-    }
-    if (m % 2 == 0) {
-        r.push_back(2);
-        m /= 2;
-    }
-    return m == 1;
+    if (st[n] >= (1 << 20)) return false;
+    for (int m = n; m > 1; m /= first[m]) r.push_back(first[m]);
+    std::stable_sort(r.begin(), r.end(), [](int a, int b) {
+        bool oa = a & 1, ob = b & 1;
+        if (oa != ob) return oa;
+        return a > b;
+    });
+    return true;
 }
 
-// elements a block of `nt` threads can transform in LDS (16 per thread,
-// rounded down to whole butterflies of every radix used)
 inline int lds_fft_cap(int n, int nt)
 {
     std::vector<int> r;
@@ -135,6 +143,7 @@ struct PlanInput {
     double Q;
     int prec;  // 0 auto, 1 fp64, 2 fp32
     int force_M, force_P, force_Mt;
+    int force_zg;  // > 0: k1 slabs per group of the y / x3 pipeline
 };
 
 struct Plan {
@@ -150,6 +159,7 @@ struct Plan {
     GridArgs g;
     long long ntiles;
     int Bx, By;
+    int zg;  // k1 slabs per group of the y / x3 pipeline
     long long max_chunks;
     int warnings;
 };
@@ -246,6 +256,15 @@ inline int make_plan(const PlanInput& in, Plan* out)
     }
     if (!p.Qz) return -3;
     p.resident = z_resident_ok(in.family, Mt);
+    // y / x3 pipeline: groups of zg k1 slabs pass through forward y, the fused
+    // x3 pass and inverse y back to back, through a buffer of zg slabs (at most
+    // ZSLAB_BUDGET bytes) instead of the whole padded spectrum
+    {
+        size_t slab = (size_t)nl * (2 * Mt) * (2 * Mt) * 2 * esz;
+        if (!p.resident) slab += (size_t)6 * (2 * Mt) * (2 * Mt) * 2 * esz;
+        long long g = in.force_zg > 0 ? in.force_zg : (long long)(ZSLAB_BUDGET / slab);
+        p.zg = (int)std::max(1LL, std::min(g, (long long)Mt + 1));
+    }
     p.Bx = choose_lines(Mt, esz);
     p.By = p.Bx;
     if (p.Bx < 2 || p.By < 1) return -3;

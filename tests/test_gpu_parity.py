@@ -40,7 +40,8 @@ def _run(ctx, family, y, s, x, xi, rc, tol, prec=0, alias=False):
     return u.cpu().numpy(), rep
 
 
-@pytest.mark.parametrize("n", [2, 3, 5, 7, 8, 12, 60, 105, 120, 343, 441, 480, 960, 1680])
+@pytest.mark.parametrize("n", [2, 3, 5, 6, 7, 8, 10, 12, 14, 15, 16, 60, 105, 120, 140, 343, 441, 480, 540, 960, 1080,
+                               1120, 1680, 2160])
 @pytest.mark.parametrize("fp32", [False, True])
 def test_line_fft_matches_numpy(ctx, n, fp32):
     g = np.random.default_rng(n)
