@@ -286,10 +286,11 @@ int check_extents(const Plan& p, const Layout& L, size_t esz)
     // precompute scratch in X
     size_t h1 = p.nf / 2 + 1;
     ok = ok && fits((h1 * h1 * (2 * Mt + 1) + h1 * (Mt + 1) * (2 * Mt + 1)) * 8, xreg);
-    // the fused x3 pass holds lines of length 4Mt/Q for max(ncin, 6) components
+    // the fused x3 pass holds lines of length 4Mt/Q for max(ncin, 6) components,
+    // each transformed by one wavefront
     int nq = 4 * p.Mt / p.Qz;
     ok = ok && (4 * p.Mt) % p.Qz == 0 && z_lds_bytes(p.family, p.Mt, p.Qz, esz) <= 160 * 1024 &&
-         std::max(p.ncin, 6) * nq <= lds_fft_cap(nq, 512);
+         nq <= lds_fft_cap(nq, 64);
     // x / y passes: B lines of Mt in LDS and in the 16-element register budget
     ok = ok && p.Bx * p.Mt <= lds_fft_cap(p.Mt, 256) && p.By * p.Mt <= lds_fft_cap(p.Mt, 256) &&
          p.By * p.Mt <= 16 * 256 && (p.Bx % 2) == 0 && p.By >= 1 &&

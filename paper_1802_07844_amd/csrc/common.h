@@ -297,11 +297,31 @@ struct Dft<T, 12> : Pfa<T, 4, 3> {};
 template <typename T>
 struct Dft<T, 14> : Pfa<T, 2, 7> {};
 
+// Ordering of LDS accesses among the lanes of one wavefront: the wave's LDS
+// operations execute in order, so a compiler barrier with wavefront-scope
+// fences is enough (no s_barrier, no wait on other waves).
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <bool WAVE>
+__device__ __forceinline__ void group_sync()
+{
+    if (WAVE)
+        wave_sync();
+    else
+        __syncthreads();
+}
+
 // One Stockham stage of radix R on `nl` lines of length n held in LDS
-// (line q at buf + q * ld).  Every thread of the block calls it; each thread
+// (line q at buf + q * ld).  Every thread of the group calls it -- the block
+// (WAVE false, NT threads) or one wavefront (WAVE true, NT = 64) -- and each
 // handles up to E/R butterflies, one after the other, keeping only their
 // outputs in registers until all threads have read their inputs.
-template <typename T, int NT, int E, int R, bool INV>
+template <typename T, int NT, int E, int R, bool INV, bool WAVE = false>
 __device__ __forceinline__ void fft_stage(cplx<T>* buf, int ld, int nl, const FftPlanDev& p, int st,
                                           const cplx<T>* __restrict__ tw)
 {
@@ -312,9 +332,10 @@ __device__ __forceinline__ void fft_stage(cplx<T>* buf, int ld, int nl, const Ff
     const int total = nl * nb;
     cplx<T> v[MB][R];
     int base[MB];
+    const int tid = WAVE ? (int)(threadIdx.x & 63) : (int)threadIdx.x;
 #pragma unroll
     for (int i = 0; i < MB; ++i) {
-        int b = threadIdx.x + i * NT;
+        int b = tid + i * NT;
         base[i] = -1;
         if (b < total) {
             int line = fdiv(b, nb, mnb);
@@ -337,7 +358,7 @@ __device__ __forceinline__ void fft_stage(cplx<T>* buf, int ld, int nl, const Ff
         }
         __builtin_amdgcn_sched_barrier(0);
     }
-    __syncthreads();
+    group_sync<WAVE>();
 #pragma unroll
     for (int i = 0; i < MB; ++i) {
         if (base[i] >= 0) {
@@ -346,30 +367,30 @@ __device__ __forceinline__ void fft_stage(cplx<T>* buf, int ld, int nl, const Ff
             for (int q = 0; q < R; ++q) dst[q * Ns] = INV ? cconj(v[i][q]) : v[i][q];
         }
     }
-    __syncthreads();
+    group_sync<WAVE>();
 }
 
 // Full in-place FFT (unnormalised) of nl lines of length p.n in LDS.
 // Requires nl * p.n <= E * NT (checked by the host planner).  Caller must
 // __syncthreads() before (data written) -- this routine ends with a barrier.
-template <typename T, int NT, int E, bool INV>
+template <typename T, int NT, int E, bool INV, bool WAVE = false>
 __device__ void lds_fft(cplx<T>* buf, int ld, int nl, const FftPlanDev& p)
 {
     const cplx<T>* tw = static_cast<const cplx<T>*>(p.tw);
     for (int s = 0; s < p.nst; ++s) {
         switch (p.rad[s]) {
-            case 2: fft_stage<T, NT, E, 2, INV>(buf, ld, nl, p, s, tw); break;
-            case 3: fft_stage<T, NT, E, 3, INV>(buf, ld, nl, p, s, tw); break;
-            case 4: fft_stage<T, NT, E, 4, INV>(buf, ld, nl, p, s, tw); break;
-            case 5: fft_stage<T, NT, E, 5, INV>(buf, ld, nl, p, s, tw); break;
-            case 6: fft_stage<T, NT, E, 6, INV>(buf, ld, nl, p, s, tw); break;
-            case 7: fft_stage<T, NT, E, 7, INV>(buf, ld, nl, p, s, tw); break;
-            case 10: fft_stage<T, NT, E, 10, INV>(buf, ld, nl, p, s, tw); break;
-            case 12: fft_stage<T, NT, E, 12, INV>(buf, ld, nl, p, s, tw); break;
-            case 14: fft_stage<T, NT, E, 14, INV>(buf, ld, nl, p, s, tw); break;
-            case 15: fft_stage<T, NT, E, 15, INV>(buf, ld, nl, p, s, tw); break;
-            case 16: fft_stage<T, NT, E, 16, INV>(buf, ld, nl, p, s, tw); break;
-            default: fft_stage<T, NT, E, 8, INV>(buf, ld, nl, p, s, tw); break;
+            case 2: fft_stage<T, NT, E, 2, INV, WAVE>(buf, ld, nl, p, s, tw); break;
+            case 3: fft_stage<T, NT, E, 3, INV, WAVE>(buf, ld, nl, p, s, tw); break;
+            case 4: fft_stage<T, NT, E, 4, INV, WAVE>(buf, ld, nl, p, s, tw); break;
+            case 5: fft_stage<T, NT, E, 5, INV, WAVE>(buf, ld, nl, p, s, tw); break;
+            case 6: fft_stage<T, NT, E, 6, INV, WAVE>(buf, ld, nl, p, s, tw); break;
+            case 7: fft_stage<T, NT, E, 7, INV, WAVE>(buf, ld, nl, p, s, tw); break;
+            case 10: fft_stage<T, NT, E, 10, INV, WAVE>(buf, ld, nl, p, s, tw); break;
+            case 12: fft_stage<T, NT, E, 12, INV, WAVE>(buf, ld, nl, p, s, tw); break;
+            case 14: fft_stage<T, NT, E, 14, INV, WAVE>(buf, ld, nl, p, s, tw); break;
+            case 15: fft_stage<T, NT, E, 15, INV, WAVE>(buf, ld, nl, p, s, tw); break;
+            case 16: fft_stage<T, NT, E, 16, INV, WAVE>(buf, ld, nl, p, s, tw); break;
+            default: fft_stage<T, NT, E, 8, INV, WAVE>(buf, ld, nl, p, s, tw); break;
         }
     }
 }

@@ -300,43 +300,57 @@ __device__ __forceinline__ void apply_mult(const cplx<U>* X, cplx<U>* Y, U kx, U
 }
 
 // ---------------------------------------------------------------------------
-// fused x3 pass: forward padded transform of the ncin grids along x3, scaling
-// by the multipliers, inverse transform, truncation to l < 2Mt.
-// Z[k1][k2][l]; the six outputs go to zout (zout == zb is allowed when
-// MAXO > 0: the outputs are then kept in registers until every phase has read
-// the inputs).  MAXO == 0: outputs accumulate phase by phase in zout, which
-// must then be a separate array.
-// grid: (2Mt, Mt + 1).
+// fused x3 pass: for one (k1, k2) line, zero-padded forward transform along
+// x3 (length 4Mt, input 2Mt), scaling by the multiplier, inverse transform,
+// keep l < 2Mt.  The padded axis is split into Q phases,
+//   X[Q m + s] = DFT_{4Mt/Q}( sum_h x[l' + h nq] w^{s (l' + h nq)} )[m],
+// w = exp(-2 pi i / 4Mt), and the inverse accumulates the phases back.
+//
+// One block of 8 wavefronts per line; wavefront w owns the input components
+// w, w + 8 and the output component w.  Folding, the forward and inverse
+// transforms and unfolding of a component touch only its own LDS line, so
+// they run at wavefront scope without block barriers and the waves proceed
+// independently; only the scaling, which couples the components at each k,
+// is bracketed by two block barriers per phase.  EPL > 0: each lane holds
+// its EPL output elements (l = lane + 64 e) in registers, and its input
+// elements too when they fit (HOLD), so inputs are read once and outputs
+// written once; EPL = 0: inputs re-read and outputs accumulated in zout.
+// grid: (2Mt, nk1)
 // ---------------------------------------------------------------------------
-template <typename T, int K, int TIER>
+constexpr int ZW = Z_NT / 64;  // wavefronts per block
+
+template <typename T, int K, int EPL>
 __global__ void __launch_bounds__(Z_NT) k_z_scale(const cplx<T>* zb, cplx<T>* zout, ZArgs a)
 {
     constexpr int ncin = Traits<K>::ncA + Traits<K>::ncB;
-    // TIER t > 0: 2Mt <= 512 t, outputs (and, when they fit, inputs) held in
-    // registers; TIER 0: outputs accumulate in zout (a separate array)
-    constexpr int MAXO = 6 * TIER;
-    constexpr int MAXI = (TIER > 0 && ncin * TIER * (int)sizeof(T) <= 56) ? ncin * TIER : 0;
+    constexpr int CPW = (ncin + ZW - 1) / ZW;  // input components per wavefront
+    constexpr bool HOLD = EPL > 0 && CPW * EPL * (int)sizeof(cplx<T>) <= 128;
+    constexpr int NX = HOLD ? CPW * EPL : 1;
+    constexpr int NY = EPL > 0 ? EPL : 1;
     extern __shared__ unsigned char smem_raw[];
     cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
     const int Mt = a.Mt, Q = a.Q;
     const int nz = 2 * Mt, n4 = 4 * Mt, nq = n4 / Q, ld = nq + 1;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int k2 = blockIdx.x, k1 = a.k1base + (int)blockIdx.y;
     const long long cs = a.cs;
     const long long base = ((long long)blockIdx.y * nz + k2) * nz;
     const cplx<T>* tw4 = static_cast<const cplx<T>*>(a.tw4);
-    const unsigned mnz = a.mnz, mnq = a.mnq, mn4 = a.mn4;
+    const unsigned mnq = a.mnq, mn4 = a.mn4;
+    const int nh = nz / nq;  // 1 (Q = 2), 2 (Q = 4) or 4 (Q = 8)
 
-    cplx<T> yout[MAXO > 0 ? MAXO : 1];
+    cplx<T> xin[NX];
+    cplx<T> yout[NY];
 #pragma unroll
-    for (int i = 0; i < (MAXO > 0 ? MAXO : 1); ++i) yout[i] = cmk<T>(0, 0);
-    cplx<T> xin[MAXI > 0 ? MAXI : 1];
-    if (MAXI > 0) {
+    for (int e = 0; e < NY; ++e) yout[e] = cmk<T>(0, 0);
+    if (HOLD) {
 #pragma unroll
-        for (int i = 0; i < (MAXI > 0 ? MAXI : 1); ++i) {
-            int f = threadIdx.x + i * Z_NT;
-            if (f < ncin * nz) {
-                int c = fdiv(f, nz, mnz), l = f - c * nz;
-                xin[i] = zb[c * cs + base + l];
+        for (int ci = 0; ci < CPW; ++ci) {
+            const int c = w + ci * ZW;
+#pragma unroll
+            for (int e = 0; e < (HOLD ? EPL : 1); ++e) {
+                const int l = lane + 64 * e;
+                xin[ci * (HOLD ? EPL : 1) + e] = (c < ncin && l < nz) ? zb[c * cs + base + l] : cmk<T>(0, 0);
             }
         }
     }
@@ -347,44 +361,54 @@ __global__ void __launch_bounds__(Z_NT) k_z_scale(const cplx<T>* zb, cplx<T>* zo
     const bool nyq12 = (k1 == Mt) || (k2 == Mt);
     const double kxd = a.dk12 * k1, kyd = a.dk12 * k2s;
     const long long oct_line = ((long long)k1 * (Mt + 1) + ak2) * (2 * Mt + 1);
-    const int nh = nz / nq;  // 1 (Q = 2), 2 (Q = 4) or 4 (Q = 8)
 
     for (int s = 0; s < Q; ++s) {
-        // fold and twist: line c of LDS holds
-        //   sum_h x_c[l' + h nq] exp(-2 pi i s (l' + h nq) / 4Mt),  l' < nq
-        for (int h = 0; h < nh; ++h) {
-            if (MAXI > 0) {
+        // fold and twist each owned input component into its LDS line:
+        //   line c holds sum_h x_c[l' + h nq] w^{s (l' + h nq)},  l' < nq
 #pragma unroll
-                for (int i = 0; i < (MAXI > 0 ? MAXI : 1); ++i) {
-                    int f = threadIdx.x + i * Z_NT;
-                    if (f < ncin * nz) {
-                        int c = fdiv(f, nz, mnz), l = f - c * nz;
-                        int lq = fdiv(l, nq, mnq);
-                        if (lq == h) {
-                            int lp = l - lq * nq;
-                            int ti = s * l;
-                            ti -= fdiv(ti, n4, mn4) * n4;
-                            cplx<T> v = cmul(xin[i], tw4[ti]);
-                            buf[c * ld + lp] = h ? cadd(buf[c * ld + lp], v) : v;
+        for (int ci = 0; ci < CPW; ++ci) {
+            const int c = w + ci * ZW;
+            if (c >= ncin) break;  // wavefront-uniform
+            cplx<T>* line = buf + c * ld;
+            for (int h = 0; h < nh; ++h) {
+                if (h) wave_sync();
+                if (HOLD) {
+#pragma unroll
+                    for (int e = 0; e < (HOLD ? EPL : 1); ++e) {
+                        const int l = lane + 64 * e;
+                        if (l < nz) {
+                            const int lq = fdiv(l, nq, mnq);
+                            if (lq == h) {
+                                cplx<T> v = xin[ci * (HOLD ? EPL : 1) + e];
+                                if (s) {
+                                    int ti = s * l;
+                                    ti -= fdiv(ti, n4, mn4) * n4;
+                                    v = cmul(v, tw4[ti]);
+                                }
+                                const int lp = l - lq * nq;
+                                line[lp] = h ? cadd(line[lp], v) : v;
+                            }
                         }
                     }
-                }
-            } else {
-                for (int f = threadIdx.x; f < ncin * nq; f += Z_NT) {
-                    int c = fdiv(f, nq, mnq), lp = f - c * nq;
-                    int l = lp + h * nq;
-                    int ti = s * l;
-                    ti -= fdiv(ti, n4, mn4) * n4;
-                    cplx<T> v = cmul(zb[c * cs + base + l], tw4[ti]);
-                    buf[c * ld + lp] = h ? cadd(buf[c * ld + lp], v) : v;
+                } else {
+                    for (int lp = lane; lp < nq; lp += 64) {
+                        const int l = lp + h * nq;
+                        cplx<T> v = zb[c * cs + base + l];
+                        if (s) {
+                            int ti = s * l;
+                            ti -= fdiv(ti, n4, mn4) * n4;
+                            v = cmul(v, tw4[ti]);
+                        }
+                        line[lp] = h ? cadd(line[lp], v) : v;
+                    }
                 }
             }
-            if (h + 1 < nh) __syncthreads();
+            wave_sync();
+            lds_fft<T, 64, Z_E, false, true>(line, ld, 1, a.fq);
         }
         __syncthreads();
-        lds_fft<T, Z_NT, Z_E, false>(buf, ld, ncin, a.fq);
 
-        // scaling at k3 = Q m + s
+        // scaling at k3 = Q m + s (couples the components)
         for (int m = threadIdx.x; m < nq; m += Z_NT) {
             int k3 = Q * m + s;
             int k3s = (k3 < nz) ? k3 : k3 - n4;
@@ -430,44 +454,48 @@ __global__ void __launch_bounds__(Z_NT) k_z_scale(const cplx<T>* zb, cplx<T>* zo
             for (int c = 0; c < NCOUT; ++c) buf[c * ld + m] = Y[c];
         }
         __syncthreads();
-        lds_fft<T, Z_NT, Z_E, true>(buf, ld, NCOUT, a.fq);
 
-        // unfold: out_c[l] += buf_c[l mod nq] exp(+2 pi i s l / 4Mt), l < 2Mt
-        if (MAXO > 0) {
+        // inverse transform and unfold of the owned output component:
+        //   out_c[l] += line_c[l mod nq] w^{-s l},  l < 2Mt
+        if (w < NCOUT) {
+            cplx<T>* line = buf + w * ld;
+            lds_fft<T, 64, Z_E, true, true>(line, ld, 1, a.fq);
+            if (EPL > 0) {
 #pragma unroll
-            for (int i = 0; i < (MAXO > 0 ? MAXO : 1); ++i) {
-                int f = threadIdx.x + i * Z_NT;
-                if (f < NCOUT * nz) {
-                    int c = fdiv(f, nz, mnz), l = f - c * nz;
-                    int lq = fdiv(l, nq, mnq);
-                    int lp = l - lq * nq;
-                    int ti = s * l;
-                    ti -= fdiv(ti, n4, mn4) * n4;
-                    yout[i] = cadd(yout[i], cmul(buf[c * ld + lp], cconj(tw4[ti])));
+                for (int e = 0; e < NY; ++e) {
+                    const int l = lane + 64 * e;
+                    if (l < nz) {
+                        const int lq = fdiv(l, nq, mnq);
+                        cplx<T> v = line[l - lq * nq];
+                        if (s) {
+                            int ti = s * l;
+                            ti -= fdiv(ti, n4, mn4) * n4;
+                            v = cmul(v, cconj(tw4[ti]));
+                        }
+                        yout[e] = cadd(yout[e], v);
+                    }
+                }
+            } else {
+                for (int l = lane; l < nz; l += 64) {
+                    const int lq = fdiv(l, nq, mnq);
+                    cplx<T> v = line[l - lq * nq];
+                    if (s) {
+                        int ti = s * l;
+                        ti -= fdiv(ti, n4, mn4) * n4;
+                        v = cmul(v, cconj(tw4[ti]));
+                    }
+                    cplx<T>* o = zout + w * a.cs_out + base + l;
+                    *o = (s == 0) ? v : cadd(*o, v);
                 }
             }
-        } else {
-            for (int f = threadIdx.x; f < NCOUT * nz; f += Z_NT) {
-                int c = fdiv(f, nz, mnz), l = f - c * nz;
-                int lq = fdiv(l, nq, mnq);
-                int lp = l - lq * nq;
-                int ti = s * l;
-                ti -= fdiv(ti, n4, mn4) * n4;
-                cplx<T> v = cmul(buf[c * ld + lp], cconj(tw4[ti]));
-                cplx<T>* o = zout + c * a.cs_out + base + l;
-                *o = (s == 0) ? v : cadd(*o, v);
-            }
+            wave_sync();
         }
-        __syncthreads();
     }
-    if (MAXO > 0) {
+    if (EPL > 0 && w < NCOUT) {
 #pragma unroll
-        for (int i = 0; i < (MAXO > 0 ? MAXO : 1); ++i) {
-            int f = threadIdx.x + i * Z_NT;
-            if (f < NCOUT * nz) {
-                int c = fdiv(f, nz, mnz), l = f - c * nz;
-                zout[c * a.cs_out + base + l] = yout[i];
-            }
+        for (int e = 0; e < NY; ++e) {
+            const int l = lane + 64 * e;
+            if (l < nz) zout[w * a.cs_out + base + l] = yout[e];
         }
     }
 }
@@ -599,12 +627,14 @@ static hipError_t launch_z_t(cplx<T>* zb, cplx<T>* zout, const ZArgs& a, bool re
     const int nz = 2 * a.Mt;
     if (!res)
         hipLaunchKernelGGL((k_z_scale<T, K, 0>), grid, dim3(Z_NT), lds, st, zb, zout, a);
+    else if (nz <= 256)
+        hipLaunchKernelGGL((k_z_scale<T, K, 4>), grid, dim3(Z_NT), lds, st, zb, zout, a);
     else if (nz <= 512)
-        hipLaunchKernelGGL((k_z_scale<T, K, 1>), grid, dim3(Z_NT), lds, st, zb, zout, a);
+        hipLaunchKernelGGL((k_z_scale<T, K, 8>), grid, dim3(Z_NT), lds, st, zb, zout, a);
     else if (nz <= 1024)
-        hipLaunchKernelGGL((k_z_scale<T, K, 2>), grid, dim3(Z_NT), lds, st, zb, zout, a);
+        hipLaunchKernelGGL((k_z_scale<T, K, 16>), grid, dim3(Z_NT), lds, st, zb, zout, a);
     else
-        hipLaunchKernelGGL((k_z_scale<T, K, 3>), grid, dim3(Z_NT), lds, st, zb, zout, a);
+        hipLaunchKernelGGL((k_z_scale<T, K, 24>), grid, dim3(Z_NT), lds, st, zb, zout, a);
     return hipGetLastError();
 }
 

@@ -241,7 +241,8 @@ inline int make_plan(const PlanInput& in, Plan* out)
     p.est_r = est_real_rel(in.family, in.rc, xi, L);
     if (p.est_r > tol / 2) p.warnings |= 1;
 
-    // fused x3 pass: smallest number of phases that fits registers and LDS
+    // fused x3 pass: smallest number of phases whose lines fit one wavefront's
+    // FFT and whose max(ncin, 6) lines fit the LDS
     const size_t esz = p.prec == 1 ? 8 : 4;
     const int nl = std::max(p.ncin, 6);
     p.Qz = 0;
@@ -249,7 +250,7 @@ inline int make_plan(const PlanInput& in, Plan* out)
         if ((4 * Mt) % Q) continue;
         int nq = 4 * Mt / Q;
         if (!smooth7(nq)) continue;
-        if (nl * nq > lds_fft_cap(nq, 512)) continue;
+        if (nq > lds_fft_cap(nq, 64)) continue;  // one line per wavefront
         if (z_lds_bytes(in.family, Mt, Q, esz) > 150 * 1024) continue;
         p.Qz = Q;
         break;
