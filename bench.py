@@ -28,31 +28,83 @@ HBM_PEAK_GBS = 8000.0
 
 
 def _stage_bytes(rep, ncin, esz):
-    """Algorithmic HBM bytes of each transform pass (inputs read once, outputs written once)."""
+    """Algorithmic HBM bytes of each transform pass per evaluation (inputs read
+    once, outputs written once; the multiplier octants read once)."""
     Mt = rep.Mt
     c = 2 * esz
     real = Mt * Mt * 2 * Mt * esz
     a = (Mt + 1) * 2 * Mt * Mt * c
     z = (Mt + 1) * 4 * Mt * Mt * c
-    oct_bytes = (Mt + 1) * (Mt + 1) * (2 * Mt + 1) * 8 * (1 if rep.family == 2 else 2)
+    kinds = 1 if rep.family == 2 else 2
+    oct_bytes = (Mt + 1) * (Mt + 1) * (2 * Mt + 1) * (8 if esz == 8 else 4) * kinds
     return {
         "fwd_x": ncin * (real + a),
         "fwd_y": ncin * (a + z),
-        "z_scale": ncin * z + 6 * z + oct_bytes,
+        "z_scale": (ncin + 6) * z + oct_bytes,
         "inv_y": 6 * (z + a),
         "inv_x": 6 * (a + real),
     }
 
 
-def _serve_rc(n, tol):
+# kernels whose sources determine the fused x3 pass (a change voids the traffic counters)
+_Z_SOURCES = ["paper_1802_07844_amd/csrc/fft.hip", "paper_1802_07844_amd/csrc/common.h",
+              "paper_1802_07844_amd/csrc/kernels.h"]
+
+
+def _sources_sha():
+    import hashlib
+
+    h = hashlib.sha256()
+    for p in _Z_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def _measured_traffic(name):
+    """HBM bytes per launch from a committed rocprofv3 counter summary (a line
+    'traffic-json: {...}' in profiles/<name>), if it was taken on the current
+    kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", name)
+    if not os.path.exists(path):
+        return None
+    for line in open(path):
+        if line.startswith("traffic-json:"):
+            d = json.loads(line.split(":", 1)[1])
+            if d.get("sources_sha") == _sources_sha():
+                return d
+    return None
+
+
+def _roofline(rep, stage_ms, ncin, esz, traffic_file=None):
+    sb = _stage_bytes(rep, ncin, esz)
+    dom = max(sb.keys(), key=lambda k: stage_ms[k])
+    launches = 1
+    if dom in ("fwd_y", "z_scale", "inv_y"):
+        launches = (rep.Mt + rep.zslab) // rep.zslab  # one launch per group of k1 slabs
+    per_launch = sb[dom] / launches
+    ms_launch = stage_ms[dom] / launches
+    achieved = per_launch / (ms_launch * 1e-3) / 1e9
+    traffic = None
+    if traffic_file and dom == "z_scale":
+        t = _measured_traffic(traffic_file)
+        if t is not None:
+            traffic = t["bytes_per_launch"] * (per_launch / t["algorithmic_bytes_per_launch"])
+    return {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "bytes_per_launch": per_launch,
+            "launches_per_step": launches, "ms_per_launch": ms_launch}
+
+
+def _serve_rc(kernel, n, tol):
     """Fixed cutoff rule of the serving stream: about 600 neighbours per point
     at FP64 (balances the real-space and Fourier work on this device), 300 at
-    FP32 with r_c >= 0.075 so that xi stays below ~45 (the FP32 rounding error
-    grows with xi L)."""
+    FP32 with a lower bound on r_c per kernel so that xi L stays where the
+    planner's FP32 rounding estimate admits FP32 at tol 1e-5 (stokeslet
+    xi L <~ 45, stresslet <~ 30; the rotlet's rounding does not grow)."""
     nb = 600.0 if tol < 1e-6 else 300.0
     rc = (nb * 3.0 / (4.0 * math.pi * n)) ** (1.0 / 3.0)
     if tol >= 1e-6:
-        rc = max(rc, 0.075)
+        rc = max(rc, {"stokeslet": 0.08, "stresslet": 0.15, "rotlet": 0.0}[kernel])
     return min(rc, 0.45)
 
 
@@ -74,9 +126,9 @@ def serve_bench(args, ehs, workloads, torch, np):
     def prep(d):
         n = min(d["n"], npool)
         off = d["seed"] % (npool - n + 1)
-        rc = _serve_rc(n, d["tol"])
+        rc = _serve_rc(d["kernel"], n, d["tol"])
         xi = ehs.xi_for_cutoff(d["kernel"], rc, d["tol"] / 2)
-        prec = 2 if d["tol"] >= 1e-5 else 1
+        prec = 0  # auto: FP32 at tol 1e-5 where its rounding estimate allows, else FP64
         return n, off, rc, xi, prec
 
     def submit(srv, d):
@@ -133,6 +185,7 @@ def serve_bench(args, ehs, workloads, torch, np):
     stats = srv.stats()
     # rel-RMS against the oracle on sampled targets of a few requests
     errs = {1: [], 2: []}
+    checked = []
     if not args.no_cpu_baseline and rows:
         import oracle
 
@@ -141,9 +194,13 @@ def serve_bench(args, ehs, workloads, torch, np):
         for i, u, st in pick:
             d = stream[i]
             n, off, rc, xi, prec = prep(d)
-            idx = np.sort(g.choice(n, size=min(n, 48), replace=False))
+            idx = np.sort(g.choice(n, size=min(n, 256), replace=False))
             ref = oracle.halfspace(d["kernel"], y[off:off + n], sh[d["kernel"]][off:off + n], y[off:off + n][idx])
-            errs[prec].append(oracle.rel_rms(ref, u.cpu().numpy()[idx]))
+            err = oracle.rel_rms(ref, u.cpu().numpy()[idx])
+            ran = st["report"]["precision"]
+            errs[ran].append(err)
+            checked.append({"kernel": d["kernel"], "N": n, "tol": d["tol"], "precision": ran, "xi": round(xi, 3),
+                            "r_c": round(rc, 5), "Mt": st["report"]["Mt"], "rel_rms": err})
     srv.close()
     pc = lambda a, p: float(np.percentile(np.array(a), p)) if a else None
     return {
@@ -155,10 +212,11 @@ def serve_bench(args, ehs, workloads, torch, np):
         "arena_peak_gb": stats["arena_peak"] / 2**30, "cache_hits": stats["cache_hits"],
         "cache_misses": stats["cache_misses"], "evictions": stats["evictions"], "failed": stats["failed"],
         "rel_rms_fp64_max": max(errs[1]) if errs[1] else None, "rel_rms_fp32_max": max(errs[2]) if errs[2] else None,
-        "rel_rms_checked": len(errs[1]) + len(errs[2]),
+        "rel_rms_checked": len(errs[1]) + len(errs[2]), "checked": checked,
         "workload": "Poisson arrivals; N log-uniform in [1e3, 1e6]; kernel uniform over stokeslet/stresslet/rotlet; "
                     "tol uniform over {1e-5 FP32, 1e-10 FP64}; uniform unit-cube positions (slices of a seeded pool); "
-                    "r_c for ~600 (FP64) / ~300 (FP32, r_c >= 0.075) neighbours, xi from the real-space estimate",
+                    "r_c for ~600 (FP64) / ~300 (FP32; r_c >= 0.08 stokeslet, >= 0.15 stresslet) neighbours, "
+                    "xi from the real-space estimate, auto precision",
     }
 
 
@@ -171,7 +229,7 @@ def main():
     ap.add_argument("--neighbours", type=float, default=30.0)
     ap.add_argument("--fp32-neighbours", type=float, default=300.0,
                     help="neighbours per point for the FP32 variant (its rounding error grows with xi L)")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target duration of the oracle sample")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target duration of the oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving stream")
@@ -182,7 +240,7 @@ def main():
     ap.add_argument("--serve-calib", type=int, default=48, help="closed-loop calibration requests")
     ap.add_argument("--serve-max-seconds", type=float, default=90.0, help="stop admitting arrivals after this")
     ap.add_argument("--serve-pool", type=int, default=1_000_000)
-    ap.add_argument("--serve-checks", type=int, default=12, help="requests checked against the oracle")
+    ap.add_argument("--serve-checks", type=int, default=12, help="requests checked against the oracle (256 targets each)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run one 1 GiB device-to-device copy first (calibrates profiler byte counters)")
     args = ap.parse_args()
@@ -238,13 +296,9 @@ def main():
     stage_ms = dict(zip(ehs.STAGES, (stage_sum / args.steps).tolist()))
     u64 = out.cpu().numpy()
 
-    # dominant transform kernel and its roofline (algorithmic bytes / launch time)
-    esz = 8
-    sb = _stage_bytes(rep, 7, esz)
-    dom = max(sb.keys(), key=lambda k: stage_ms[k])
-    achieved = sb[dom] / (stage_ms[dom] * 1e-3) / 1e9
-    roofline = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": None, "bytes_per_launch": sb[dom]}
+    # dominant kernel and its roofline: algorithmic bytes per launch / average
+    # launch duration (HIP events on the evaluation's stream)
+    roofline = _roofline(rep, stage_ms, 7, 8, "z_scale_stokeslet_N100k_fp64_counters.md")
 
     result = {
         "metric": "points/sec at rel-RMS 1e-10 (FP64)",
@@ -262,7 +316,7 @@ def main():
         "config": {"workload": f"half-space stokeslet, N={n} sources=targets uniform in [0,1)^2x(0,1], "
                                f"forces N(0,1), FP64 tol 1e-10, ~{args.neighbours:g} neighbours",
                    "N": n, "xi": xi, "r_c": rc, "tol": tol, "M": rep.M, "P": rep.P, "Mt": rep.Mt,
-                   "eta": rep.eta, "seed": seed},
+                   "eta": rep.eta, "zslab": rep.zslab, "seed": seed},
         "stage_ms": stage_ms,
         "roofline": roofline,
     }
@@ -290,22 +344,27 @@ def main():
         torch.cuda.synchronize()
         dt32 = time.perf_counter() - t0
         u32 = out32.cpu().numpy()
+        sm32 = dict(zip(ehs.STAGES, (st32 / args.steps).tolist()))
         result["fp32"] = {"value": n * args.steps / dt32, "unit": "points/s", "ms_per_step": dt32 / args.steps * 1e3,
-                          "tol": tol32, "xi": xi32, "r_c": rc32, "neighbours": args.fp32_neighbours,
-                          "M": r32.M, "P": r32.P, "Mt": r32.Mt,
-                          "stage_ms": dict(zip(ehs.STAGES, (st32 / args.steps).tolist()))}
+                          "dtype": "f32", "tol": tol32, "xi": xi32, "r_c": rc32, "neighbours": args.fp32_neighbours,
+                          "M": r32.M, "P": r32.P, "Mt": r32.Mt, "stage_ms": sm32,
+                          "roofline": _roofline(r32, sm32, 7, 4)}
 
     # oracle on the host cores: a bounded sample of targets against all sources
     if not args.no_cpu_baseline:
         import oracle
 
         cores = oracle.max_threads()
-        # size the sample from a short probe
-        probe = 64
-        t0 = time.perf_counter()
-        oracle.halfspace("stokeslet", y, f, y[:probe])
-        tp = time.perf_counter() - t0
-        S = int(max(probe, min(n, probe * args.cpu_seconds / max(tp, 1e-6))))
+        # size the sample from two short probes (the first also absorbs thread start-up)
+        S = 64
+        for target_s in (0.5, args.cpu_seconds):
+            t0 = time.perf_counter()
+            oracle.halfspace("stokeslet", y, f, y[:S])
+            tp = time.perf_counter() - t0
+            if target_s == args.cpu_seconds:
+                break
+            S = int(max(64, min(n, S * target_s / max(tp, 1e-6))))
+        S = int(max(64, min(n, S * args.cpu_seconds / max(tp, 1e-6))))
         g = workloads.rng(seed + 1000)
         idx = np.sort(g.choice(n, size=S, replace=False))
         t0 = time.perf_counter()

@@ -58,7 +58,7 @@ extern "C" {
 #define EHS_ROTLET 2
 
 /* options (ehs_set_option) */
-#define EHS_OPT_PRECISION 0 /* 0: auto (FP32 when tol >= 1e-5, else FP64), 1: FP64, 2: FP32 */
+#define EHS_OPT_PRECISION 0 /* 0: auto (FP32 when tol >= 1e-5 and est_fp32 <= tol/2, else FP64), 1: FP64, 2: FP32 */
 #define EHS_OPT_TIMING 1    /* 1: record per-stage times into the report (adds a synchronisation) */
 #define EHS_OPT_FORCE_M 2   /* > 0: use this M (grid intervals over the box) instead of the estimate */
 #define EHS_OPT_FORCE_P 3   /* > 0: use this Gaussian support P (even) */
@@ -90,7 +90,8 @@ typedef struct ehs_report {
     int32_t Q;              /* phases of the fused x3 pass */
     int32_t nf, nf3;        /* oversampled precompute grid (in-plane, x3) */
     int32_t warnings;       /* bit 0: real-space estimate above tol/2 (r_c too small for xi);
-                               bit 1: the precompute ran in this call */
+                               bit 1: the precompute ran in this call;
+                               bit 2: FP32 requested but its rounding estimate exceeds tol/2 */
     int32_t ncell[3];       /* real-space cells per axis */
     int32_t family;
     double L, h, Lt, eta;   /* box, grid spacing, extended box M~ h, Gaussian shape */
@@ -101,6 +102,7 @@ typedef struct ehs_report {
     double workspace_bytes;
     int32_t zslab;          /* k1 slabs per group of the y / x3 transform pipeline */
     int32_t reserved;
+    double est_fp32;        /* estimated FP32 rounding error (relative RMS, uniform point sets) */
 } ehs_report;
 
 /* Create a context on HIP device `hip_device`.  `arena_bytes` is reserved

@@ -42,6 +42,7 @@ class Report(ctypes.Structure):
         ("ms_stage", ctypes.c_double * NSTAGES),
         ("workspace_bytes", ctypes.c_double),
         ("zslab", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("est_fp32", ctypes.c_double),
     ]
 
     def as_dict(self) -> dict:

@@ -638,6 +638,7 @@ void ehs::fill_report(const Plan& p, ehs_report* r)
     r->est_real = p.est_r;
     r->est_fourier = p.est_f;
     r->zslab = p.zg;
+    r->est_fp32 = p.est32;
 }
 
 namespace {

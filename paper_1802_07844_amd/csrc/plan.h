@@ -7,7 +7,7 @@
 //    rotlet, whose correction terms are of the same order as the kernel and
 //    are not covered by the free-space estimate -- paper Sec. 6);
 //  * P (Gaussian support, even) from exp(-pi P c^2 / 2) <= tol/40 (tol/4 when
-//    tol >= 1e-6, where the FP32 rounding dominates), c = 0.95,
+//    tol >= 1e-6 except for the stresslet), c = 0.95,
 //    eta = P xi^2 h^2 / (c^2 pi) (Algorithm 1 step 4), M raised until eta < 0.95;
 //  * the box is extended by max(P, m / (sqrt2 xi h)) nodes with
 //    m = sqrt(2 ln(1/tol)): the Gaussian support of Algorithm 1 step 3 plus a
@@ -15,7 +15,9 @@
 //    applied to the window-truncated kernel and must not reach the window's
 //    edge; M~ is then rounded up to an even 7-smooth size (FFT radices 2..8);
 //  * the real-space estimate of Table 2 (Q -> 2Q) is reported and flagged
-//    when above tol/2.
+//    when above tol/2;
+//  * precision: FP32 in auto mode when tol >= 1e-5 and the FP32 rounding
+//    estimate is at most tol/2, FP64 otherwise.
 #pragma once
 #include <algorithm>
 #include <cmath>
@@ -153,7 +155,7 @@ struct Plan {
     double L, h, Lt, eta, Q;
     int M, P, Mt, Qz, nf, nf3, ncin;
     bool resident;
-    double est_r, est_f;
+    double est_r, est_f, est32;
     CellGeom cg;
     long long ncell;
     GridArgs g;
@@ -190,7 +192,23 @@ inline int make_plan(const PlanInput& in, Plan* out)
     p.tol = in.tol;
     p.Q = in.Q;
     p.ncin = ncomp_in(in.family);
-    p.prec = in.prec == 0 ? (in.tol >= 1e-5 ? 2 : 1) : in.prec;
+    {
+        // FP32 rounding error of the grid path for uniform point sets, fitted
+        // to the error at typical targets (FP32 minus FP64 under one plan):
+        // the grid values near a source carry its own smooth field, of size
+        // xi |f| (stokeslet) or xi^3 |S| (stresslet), whose FP32 quantisation
+        // does not cancel at the source's own position; the rotlet's stays
+        // near 1e-6.  Clustered sets have a larger RMS velocity, so their
+        // relative rounding error is smaller.
+        double box = std::max(std::max(in.hi[0] - in.lo[0], in.hi[1] - in.lo[1]), in.hi[2]);
+        double xl = in.xi * box;
+        double e32 = in.family == 0 ? 1.7e-6 * std::pow(xl / 25.0, 1.6)
+                   : in.family == 1 ? 1.1e-5 * std::pow(xl / 45.0, 2.5)
+                                    : 1e-6;
+        p.est32 = e32;
+        p.prec = in.prec == 0 ? ((in.tol >= 1e-5 && e32 <= 0.5 * in.tol) ? 2 : 1) : in.prec;
+        if (p.prec == 2 && e32 > 0.5 * in.tol) p.warnings |= 4;
+    }
     const double pi = 3.14159265358979323846;
     double ext1 = in.hi[0] - in.lo[0], ext2 = in.hi[1] - in.lo[1], ext3 = in.hi[2];
     double L = std::max(std::max(ext1, ext2), ext3);
@@ -203,7 +221,9 @@ inline int make_plan(const PlanInput& in, Plan* out)
     int P = in.force_P;
     if (P <= 0) {
         P = 4;
-        const double pbudget = tol < 1e-6 ? tol / 40 : tol / 4;
+        // the stresslet's near-field Fourier part (third derivatives)
+        // amplifies the support truncation about tenfold
+        const double pbudget = (tol < 1e-6 || in.family == 1) ? tol / 40 : tol / 4;
         while (std::exp(-pi * P * C_SHAPE * C_SHAPE / 2) > pbudget) P += 2;
     }
     if (P < 2 || P > 30 || (P & 1)) return -1;

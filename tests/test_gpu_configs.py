@@ -1,0 +1,183 @@
+"""GPU parity at the benchmark configurations' full sizes, plus edge cases.
+
+The HIP path is compared with the FP64 direct-sum oracle.  For N = 1000 the
+oracle covers every target; for N = 1e5 to 4e6 it covers a seeded random
+sample of targets, each evaluated exactly against all N sources.  The bar is
+the relative RMS error over the compared targets: <= 1e-10 for FP64 at
+tol = 1e-10 and <= 1e-5 for FP32 at tol = 1e-5 (paper Sec. 5-6: errors
+measured against direct summation).
+"""
+import math
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle  # noqa: E402
+import paper_1802_07844_amd as ehs  # noqa: E402
+from paper_1802_07844_amd import workloads  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = ehs.Context(0)
+    yield c
+    c.close()
+
+
+def _rc(nb, n):
+    return (nb * 3.0 / (4.0 * math.pi * n)) ** (1.0 / 3.0)
+
+
+def _eval(ctx, fam, y, s, xi, rc, tol, prec):
+    ctx.set_option(ehs.OPT_PRECISION, prec)
+    yd = torch.from_numpy(y).to("cuda:0")
+    u, rep = ctx.evaluate(fam, yd, torch.from_numpy(s).to("cuda:0"), yd, xi, rc, tol, report=True)
+    torch.cuda.synchronize()
+    out = u.cpu().numpy()
+    del u, yd
+    return out, rep
+
+
+def _check(fam, y, s, u, rep, tol, nsample, seed, label):
+    n = y.shape[0]
+    idx = np.arange(n) if nsample >= n else np.sort(workloads.rng(seed).choice(n, nsample, replace=False))
+    ref = oracle.halfspace(fam, y, s, y[idx])
+    err = oracle.rel_rms(ref, u[idx])
+    print(f"{label}: {fam} N={n} prec={rep.precision} M={rep.M} P={rep.P} Mt={rep.Mt} xi={rep.xi:.2f} "
+          f"r_c={rep.r_c:.4f} targets={len(idx)} rel-RMS={err:.3e} est_fp32={rep.est_fp32:.1e}")
+    assert np.all(np.isfinite(u))
+    assert err <= tol
+
+
+def test_c1_stokeslet_n1000_all_targets(ctx):
+    """N = 1000 uniform stokeslet, self excluded, FP64 tol 1e-10, ~300 neighbours."""
+    n = 1000
+    y, f = workloads.uniform_stokeslet(n, workloads.SEED_BASE)
+    rc = _rc(300, n)
+    xi = ehs.xi_for_cutoff("stokeslet", rc, 0.5e-10)
+    u, rep = _eval(ctx, "stokeslet", y, f, xi, rc, 1e-10, 1)
+    _check("stokeslet", y, f, u, rep, 1e-10, n, 0, "C1")
+
+
+@pytest.mark.parametrize("prec,tol,nb", [(1, 1e-10, 30), (2, 1e-5, 300)])
+def test_c2_stokeslet_n100k(ctx, prec, tol, nb):
+    """N = 1e5 uniform stokeslet in the benchmark's launch configuration."""
+    n = 100_000
+    y, f = workloads.uniform_stokeslet(n, workloads.SEED_BASE + 1)
+    rc = _rc(nb, n)
+    xi = ehs.xi_for_cutoff("stokeslet", rc, tol / 2)
+    u, rep = _eval(ctx, "stokeslet", y, f, xi, rc, tol, prec)
+    _check("stokeslet", y, f, u, rep, tol, 1024, 11, "C2")
+
+
+def _fp32_cutoff(fam, n, tol, nb):
+    """The smallest cutoff from about nb neighbours up for which the planner's
+    FP32 rounding estimate admits FP32 at tol (auto precision picks FP32)."""
+    rc = _rc(nb, n)
+    while True:
+        xi = ehs.xi_for_cutoff(fam, rc, tol / 2)
+        rep = ehs.plan_query(fam, n, n, (0, 0, 0), (1, 1, 1), 3.0 * n, xi, rc, tol, 0)
+        if rep.precision == 2:
+            return rc, xi
+        rc *= 1.05
+
+
+@pytest.mark.parametrize("fam", ["stresslet", "rotlet"])
+@pytest.mark.parametrize("prec,tol,nb", [(1, 1e-10, 2000), (2, 1e-5, 300)])
+def test_c3_n1m(ctx, fam, prec, tol, nb):
+    """N = 1e6 uniform stresslet (unit orientations) and rotlet, FP64 and FP32
+    (FP32 with the cutoff the rounding estimate admits: ~300 neighbours for
+    the rotlet, more for the stresslet)."""
+    n = 1_000_000
+    y, s = workloads.make(fam, n, workloads.SEED_BASE + 2)
+    if prec == 2:
+        rc, xi = _fp32_cutoff(fam, n, tol, nb)
+    else:
+        rc = _rc(nb, n)
+        xi = ehs.xi_for_cutoff(fam, rc, tol / 2)
+    u, rep = _eval(ctx, fam, y, s, xi, rc, tol, prec)
+    _check(fam, y, s, u, rep, tol, 1024, 12, "C3")
+
+
+@pytest.mark.parametrize("prec,tol,rc", [(2, 1e-5, 0.03), (1, 1e-10, 0.035)])
+def test_c4_clustered_n4m(ctx, prec, tol, rc):
+    """N = 4e6 stokeslet clustered near the wall (x3 ~ Exp(0.05)), FP32 and FP64."""
+    n = 4_000_000
+    y, f = workloads.clustered_stokeslet(n, workloads.SEED_BASE + 3)
+    xi = ehs.xi_for_cutoff("stokeslet", rc, tol / 2)
+    u, rep = _eval(ctx, "stokeslet", y, f, xi, rc, tol, prec)
+    _check("stokeslet", y, f, u, rep, tol, 512, 13, "C4")
+
+
+# ---------------------------------------------------------------- edge cases
+
+
+@pytest.mark.parametrize("fam", ["stokeslet", "stresslet", "rotlet"])
+def test_single_source_and_empty_targets(ctx, fam):
+    """N = 1 (only the source's own image and corrections act on it) and T = 0."""
+    y, s = workloads.make(fam, 1, 21)
+    x = np.array([[0.3, 0.6, 0.2], [y[0, 0], y[0, 1], y[0, 2]], [0.9, 0.1, 0.0]])
+    ctx.set_option(ehs.OPT_PRECISION, 1)
+    yd = torch.from_numpy(y).to("cuda:0")
+    xi = ehs.xi_for_cutoff(fam, 0.5, 0.5e-10)
+    u = ctx.evaluate(fam, yd, torch.from_numpy(s).to("cuda:0"), torch.from_numpy(x).to("cuda:0"), xi, 0.5, 1e-10)
+    ref = oracle.halfspace(fam, y, s, x)
+    assert oracle.rel_rms(ref, u.cpu().numpy()) <= 1e-10
+    empty = torch.empty((0, 3), dtype=torch.float64, device="cuda:0")
+    out = ctx.evaluate(fam, yd, torch.from_numpy(s).to("cuda:0"), empty, xi, 0.5, 1e-10)
+    assert out.shape == (0, 3)
+
+
+def test_ragged_sizes_and_planes(ctx):
+    """Sizes off every tile multiple; all sources at one height; repeated points."""
+    g = workloads.rng(31)
+    n = 1237
+    y = np.empty((n, 3))
+    y[:, 0] = g.random(n)
+    y[:, 1] = g.random(n)
+    y[:, 2] = 0.37  # one plane parallel to the wall
+    y[-5:] = y[:5]  # coincident sources: their mutual direct terms are excluded like the self term
+    f = g.standard_normal((n, 3))
+    rc = _rc(200, n)
+    xi = ehs.xi_for_cutoff("stokeslet", rc, 0.5e-10)
+    u, rep = _eval(ctx, "stokeslet", y, f, xi, rc, 1e-10, 1)
+    ref = oracle.halfspace("stokeslet", y, f, y)
+    assert oracle.rel_rms(ref, u) <= 1e-10
+
+
+def test_error_codes(ctx):
+    y, f = workloads.uniform_stokeslet(100, 41)
+    yd, fd = torch.from_numpy(y).to("cuda:0"), torch.from_numpy(f).to("cuda:0")
+    bad = y.copy()
+    bad[4, 2] = 0.0  # a source on the wall
+    with pytest.raises(ehs.EhsError) as e:
+        ctx.evaluate("stokeslet", torch.from_numpy(bad).to("cuda:0"), fd, yd, 8.0, 0.3, 1e-10)
+    assert e.value.code == ehs.EHS_EDOMAIN
+    nan = y.copy()
+    nan[7, 0] = np.nan
+    with pytest.raises(ehs.EhsError) as e:
+        ctx.evaluate("stokeslet", torch.from_numpy(nan).to("cuda:0"), fd, yd, 8.0, 0.3, 1e-10)
+    assert e.value.code == ehs.EHS_EDOMAIN
+    below = y.copy()
+    below[0, 2] = -1e-3  # a target below the wall
+    with pytest.raises(ehs.EhsError) as e:
+        ctx.evaluate("stokeslet", yd, fd, torch.from_numpy(below).to("cuda:0"), 8.0, 0.3, 1e-10)
+    assert e.value.code == ehs.EHS_EDOMAIN
+    with pytest.raises(ehs.EhsError) as e:
+        ctx.evaluate("stokeslet", yd, fd, yd, 8.0, 0.3, 0.5)
+    assert e.value.code == ehs.EHS_EINVAL
+    ctx.set_option(ehs.OPT_MEM_CAP, 1e6)  # 1 MB cap: the workspace does not fit
+    try:
+        with pytest.raises(ehs.EhsError) as e:
+            ctx.evaluate("stokeslet", yd, fd, yd, 30.0, 0.1, 1e-10)
+        assert e.value.code == ehs.EHS_ENOMEM
+    finally:
+        ctx.set_option(ehs.OPT_MEM_CAP, 0)
+    # the context still works after every error
+    xi = ehs.xi_for_cutoff("stokeslet", 0.3, 0.5e-10)
+    u = ctx.evaluate("stokeslet", yd, fd, yd, xi, 0.3, 1e-10)
+    assert oracle.rel_rms(oracle.halfspace("stokeslet", y, f, y), u.cpu().numpy()) <= 1e-10

@@ -97,8 +97,9 @@ def _smooth7(n):
 @pytest.mark.parametrize("tol", [1e-10, 1e-5])
 def test_plan_invariants(family, tol):
     r = _plan(family, tol)
-    # Gaussian support from exp(-pi P c^2 / 2) <= tol / 40 (tol / 4 for tol >= 1e-6), c = 0.95
-    assert r.P == (20 if tol == 1e-10 else 10)
+    # Gaussian support from exp(-pi P c^2 / 2) <= tol / 40 (tol / 4 for tol >= 1e-6 except the
+    # stresslet), c = 0.95
+    assert r.P == (20 if tol == 1e-10 else 12 if family == "stresslet" else 10)
     assert r.Mt % 2 == 0 and _smooth7(r.Mt) and r.Mt >= r.M + r.P
     assert 0.0 < r.eta < 1.0
     assert r.precision == (1 if tol < 1e-5 else 2)
@@ -174,3 +175,21 @@ def test_server_create_without_device_fails_cleanly():
     rc = ehs.lib().ehs_server_create(ctypes.byref(h), 0, 1 << 30, 2)
     assert rc != 0 and not h.value
     assert "timeout" in ehs.strerror(ehs.EHS_ETIMEDOUT)
+
+
+def test_fp32_estimate_and_auto_precision():
+    """Auto precision takes FP32 at tol >= 1e-5 only while the FP32 rounding
+    estimate stays within tol/2; a forced FP32 run beyond it is flagged."""
+    lo, hi = (0, 0, 0), (1, 1, 1)
+    small = ehs.plan_query("stokeslet", 10**5, 10**5, lo, hi, 3e5, 30.0, 0.12, 1e-5, 0)
+    large = ehs.plan_query("stokeslet", 10**5, 10**5, lo, hi, 3e5, 118.0, 0.0415, 1e-5, 0)
+    assert small.precision == 2 and small.est_fp32 <= 0.5e-5 and not (small.warnings & 4)
+    assert large.precision == 1 and large.est_fp32 > 0.5e-5
+    forced = ehs.plan_query("stokeslet", 10**5, 10**5, lo, hi, 3e5, 118.0, 0.0415, 1e-5, 2)
+    assert forced.precision == 2 and (forced.warnings & 4)
+    # the estimate grows with xi L
+    e = [ehs.plan_query("stokeslet", 1000, 1000, lo, hi, 3e3, x, 3.5 / x, 1e-5, 2).est_fp32 for x in (10, 30, 90)]
+    assert e[0] < e[1] < e[2]
+    # the rotlet's rounding does not grow with xi: FP32 stays available
+    rot = ehs.plan_query("rotlet", 10**5, 10**5, lo, hi, 3e5, 118.0, 0.0415, 1e-5, 0)
+    assert rot.precision == 2
