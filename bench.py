@@ -36,13 +36,14 @@ def _stage_bytes(rep, ncin, esz):
     a = (Mt + 1) * 2 * Mt * Mt * c
     z = (Mt + 1) * 4 * Mt * Mt * c
     kinds = 1 if rep.family == 2 else 2
+    nout = 4 if esz == 8 else 6  # output grids: T1 and phi (FP64) or T1 and grad phi (FP32)
     oct_bytes = (Mt + 1) * (Mt + 1) * (2 * Mt + 1) * (8 if esz == 8 else 4) * kinds
     return {
         "fwd_x": ncin * (real + a),
         "fwd_y": ncin * (a + z),
-        "z_scale": (ncin + 6) * z + oct_bytes,
-        "inv_y": 6 * (z + a),
-        "inv_x": 6 * (a + real),
+        "z_scale": (ncin + nout) * z + oct_bytes,
+        "inv_y": nout * (z + a),
+        "inv_x": nout * (a + real),
     }
 
 

@@ -66,6 +66,8 @@ extern "C" {
 #define EHS_OPT_MEM_CAP 5   /* > 0: refuse a workspace larger than this many bytes (EHS_ENOMEM) */
 #define EHS_OPT_ZSLAB 6     /* > 0: k1 slabs per group of the y / x3 transform pipeline (default: sized for
                                the last-level cache); M~ + 1 keeps the whole grid in one group */
+#define EHS_OPT_GATHER_EXTRA 7 /* >= 0 (even): support nodes the quadrature adds to P; -1: default (2 for
+                                  FP64, whose quadrature forms the correction gradient, 0 for FP32) */
 
 /* stage indices of ehs_report.ms_stage */
 #define EHS_ST_BBOX 0       /* bounding box + validation reduction and its readback */
@@ -101,7 +103,7 @@ typedef struct ehs_report {
     double ms_stage[EHS_NSTAGES]; /* stage times when EHS_OPT_TIMING is on, else 0 */
     double workspace_bytes;
     int32_t zslab;          /* k1 slabs per group of the y / x3 transform pipeline */
-    int32_t reserved;
+    int32_t Pg;             /* Gaussian support of the quadrature at the targets (>= P) */
     double est_fp32;        /* estimated FP32 rounding error (relative RMS, uniform point sets) */
 } ehs_report;
 

@@ -266,15 +266,16 @@ int check_extents(const Plan& p, const Layout& L, size_t esz)
     const size_t a = (Mt + 1) * 2 * Mt * Mt * c;
     const size_t zs = (size_t)p.zg * 2 * Mt * 2 * Mt * c;  // one component of the slab buffer
     const size_t nin = (size_t)p.ncin;
+    const size_t nout = (size_t)ncout_for(p.prec);
     const size_t xreg = L.Y - L.X, yreg = L.ZS - L.Y, zsreg = L.Zo - L.ZS, zoreg = L.rec - L.Zo;
     auto fits = [](size_t need, size_t have) { return need <= have; };
     bool ok = p.zg >= 1 && p.zg <= p.Mt + 1
               && fits(nin * real, xreg)                 // spread -> X
               && fits(nin * a, yreg)                    // forward x1 -> Y
               && fits(nin * zs, zsreg)                  // forward x2 -> slab buffer
-              && fits(6 * zs, p.resident ? zsreg : zoreg)  // fused x3 outputs
-              && fits(6 * a, yreg)                      // inverse x2 -> Y (in place of A)
-              && fits(6 * real, xreg)                   // inverse x1 -> X (read by the gather)
+              && fits(nout * zs, p.resident ? zsreg : zoreg)  // fused x3 outputs
+              && fits(nout * a, yreg)                  // inverse x2 -> Y (in place of A)
+              && fits(nout * real, xreg)               // inverse x1 -> X (read by the gather)
               && fits((size_t)2 * p.N * record_stride(p.family, p.P, esz) * esz, L.keys - L.rec)
               && fits((size_t)(4 * p.N + 4 * p.T + 8 * p.N) * 4, L.sortsc - L.keys)
               && fits((size_t)(p.ntiles + 1) * 4, L.soff - L.toff)
@@ -286,7 +287,7 @@ int check_extents(const Plan& p, const Layout& L, size_t esz)
     // precompute scratch in X
     size_t h1 = p.nf / 2 + 1;
     ok = ok && fits((h1 * h1 * (2 * Mt + 1) + h1 * (Mt + 1) * (2 * Mt + 1)) * 8, xreg);
-    // the fused x3 pass holds lines of length 4Mt/Q for max(ncin, 6) components,
+    // the fused x3 pass holds lines of length 4Mt/Q for max(ncin, outputs) components,
     // each transformed by one wavefront
     int nq = 4 * p.Mt / p.Qz;
     ok = ok && (4 * p.Mt) % p.Qz == 0 && z_lds_bytes(p.family, p.Mt, p.Qz, esz) <= 160 * 1024 &&
@@ -297,9 +298,9 @@ int check_extents(const Plan& p, const Layout& L, size_t esz)
          (size_t)p.By * (p.Mt + 1) * c <= 160 * 1024 && (size_t)p.Bx * (p.Mt + 1) * c <= 160 * 1024;
     // magic-number division is exact for numerator * divisor < 2^32
     ok = ok && (long long)(p.Mt + 1) * std::max(p.Bx, 2 * p.By) * std::max(p.Mt, 2 * p.By) < (1LL << 31) &&
-         (long long)std::max(p.ncin, 6) * 2 * p.Mt * 2 * p.Mt < (1LL << 31);
+         (long long)std::max(p.ncin, ncout_for(p.prec)) * 2 * p.Mt * 2 * p.Mt < (1LL << 31);
     // gather weights table (3P <= 96) and spread support within the grid
-    ok = ok && 3 * p.P <= 96 && p.P <= p.Mt;
+    ok = ok && 3 * p.Pg <= 96 && p.P <= p.Mt && p.Pg <= p.Mt && p.Pg >= p.P;
     return ok ? EHS_OK : EHS_ERANGE;
 }
 
@@ -308,7 +309,7 @@ Layout layout(const Plan& p, size_t esz)
     Layout L;
     const long long Mt = p.Mt;
     const int ncin = p.ncin;
-    const int nl = std::max(ncin, 6);
+    const int nl = std::max(ncin, ncout_for(p.prec));
     size_t czs = (size_t)p.zg * 2 * Mt * 2 * Mt * 2 * esz;  // one slab-buffer component (complex)
     size_t cy = (size_t)(Mt + 1) * 2 * Mt * Mt * 2 * esz;   // one A / D component
     size_t x_bytes = (size_t)nl * (size_t)(Mt * Mt * 2 * Mt) * esz;
@@ -318,9 +319,9 @@ Layout layout(const Plan& p, size_t esz)
     x_bytes = std::max(x_bytes, pre);
     size_t off = 0;
     L.X = off; off += al(x_bytes);
-    L.Y = off; off += al((size_t)nl * cy);  // A (ncin components), then D (6) in place
+    L.Y = off; off += al((size_t)nl * cy);  // A (ncin components), then D (outputs) in place
     L.ZS = off; off += al((size_t)nl * czs);
-    L.Zo = off; off += p.resident ? 0 : al((size_t)6 * czs);
+    L.Zo = off; off += p.resident ? 0 : al((size_t)ncout_for(p.prec) * czs);
     long long N = p.N, T = p.T;
     L.rec = off; off += al((size_t)2 * N * record_stride(p.family, p.P, esz) * esz);
     // keys / values: sources (4 N), targets (4 T), points (4 * 2N)
@@ -525,7 +526,7 @@ int run(ehs_ctx* c, Plan& p, const Octants& oct, const double* y, const double* 
         if (slab_ev) HIPCHK(hipEventRecord(c->sev[c->nsev++], st));
         pa.cs_in = csS;
         pa.cs_out = csA;
-        HIPCHK(launch_inv_y<T>(ZO, Yc, pa, 6, st));
+        HIPCHK(launch_inv_y<T>(ZO, Yc, pa, Out<T>::n, st));
         if (slab_ev) HIPCHK(hipEventRecord(c->sev[c->nsev++], st));
     }
     rec_ev(EHS_ST_ZSCALE);
@@ -535,11 +536,11 @@ int run(ehs_ctx* c, Plan& p, const Octants& oct, const double* y, const double* 
     set_b(p.Bx);
     pa.cs_in = csA;
     pa.cs_out = csR;
-    HIPCHK(launch_inv_x<T>(Yc, X, pa, 6, st));
+    HIPCHK(launch_inv_x<T>(Yc, X, pa, Out<T>::n, st));
     rec_ev(EHS_ST_GATHER);
 
     // -- quadrature at the targets and FP64 combination with the real part
-    HIPCHK(launch_gather<T>(p.g, X, csR, xs, tperm, TT, upart, u, st));
+    HIPCHK(launch_gather<T>(p.gg, X, csR, xs, tperm, TT, upart, u, st));
     rec_ev(EHS_ST_TOTAL);
     return EHS_OK;
 }
@@ -591,6 +592,7 @@ int ehs::plan_request(ehs_ctx* c, int family, const double* y, const double* s, 
     in.force_P = c->force_P;
     in.force_Mt = c->force_Mt;
     in.force_zg = c->force_zg;
+    in.gather_extra = c->gather_extra;
     return make_plan(in, p);
 }
 
@@ -638,6 +640,7 @@ void ehs::fill_report(const Plan& p, ehs_report* r)
     r->est_real = p.est_r;
     r->est_fourier = p.est_f;
     r->zslab = p.zg;
+    r->Pg = p.Pg;
     r->est_fp32 = p.est32;
 }
 
@@ -803,6 +806,7 @@ int ehs_set_option(ehs_ctx* c, int option, double value)
         case EHS_OPT_FORCE_MT: c->force_Mt = (int)value; return EHS_OK;
         case EHS_OPT_MEM_CAP: c->mem_cap = value; return EHS_OK;
         case EHS_OPT_ZSLAB: c->force_zg = (int)value; return EHS_OK;
+        case EHS_OPT_GATHER_EXTRA: c->gather_extra = (int)value; return EHS_OK;
         default: return EHS_EINVAL;
     }
 }
@@ -862,6 +866,7 @@ int ehs_plan_query(int family, int64_t N, int64_t T, const double* lo, const dou
     }
     in.Q = Q;
     in.prec = precision;
+    in.gather_extra = -1;
     Plan p;
     int rc = make_plan(in, &p);
     if (rc) return rc;

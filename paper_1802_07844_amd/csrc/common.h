@@ -70,7 +70,18 @@ struct Traits<ROTLET> {
     static constexpr int ncA = 3;   // v at y, v^I at y^I
     static constexpr int ncB = 2;   // w = 2(-v2, v1) at y^I
 };
-constexpr int NCOUT = 6;  // Y1 (3) and Y2 (3)
+// output grids of the transform pipeline: FP64 keeps Y1 (3 components) and
+// the correction potential phi (1), whose gradient the quadrature forms with
+// the gradient of the Gaussian; FP32 keeps Y1 and grad phi = IFFT(i k phi^)
+// (3), because the FP32 quantisation of the long-range potential would be
+// amplified by that gradient
+constexpr int NCOUT_MAX = 6;
+template <typename T>
+struct Out {
+    static constexpr int n = sizeof(T) == 8 ? 4 : 6;
+    static constexpr bool grad_quad = sizeof(T) == 8;  // gradient by quadrature
+};
+inline int ncout_for(int prec) { return prec == 1 ? 4 : 6; }
 
 // ---------------------------------------------------------------------------
 // FFT plan for one line length: radices (each 2,3,4,5,7 or 8), the twiddle
@@ -96,6 +107,18 @@ struct FftPlanDev {
 // a / d for a * d < 2^32, with m = floor((2^32 - 1) / d) + 1 (d >= 2)
 __host__ __device__ __forceinline__ unsigned magic_of(unsigned d) { return d > 1 ? 0xFFFFFFFFu / d + 1u : 0u; }
 __device__ __forceinline__ int fdiv(int a, int d, unsigned m) { return d == 1 ? a : (int)__umulhi((unsigned)a, m); }
+
+// MI355X dispatches consecutive workgroups of a 1D grid round robin over its
+// 8 XCDs, each with its own L2.  This maps the hardware block index to a
+// logical one such that every XCD receives one contiguous range of logical
+// blocks (in order), so neighbouring work shares an L2.  The result may reach
+// 8 * ceil(nb / 8) - 1; callers treat logical indices >= nb as empty.
+constexpr int NXCD = 8;
+__device__ __forceinline__ long long xcd_block(long long b, long long nb)
+{
+    const long long per = (nb + NXCD - 1) / NXCD;
+    return (b % NXCD) * per + b / NXCD;
+}
 
 // radix-R DFT in registers, forward sign exp(-2 pi i k q / R)
 template <typename T, int R>

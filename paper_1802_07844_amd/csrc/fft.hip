@@ -220,7 +220,7 @@ __global__ void __launch_bounds__(XPASS_NT, 4) k_inv_x(const cplx<T>* __restrict
 //   gB = (1 + k^2/4xi^2) e^{-(1-eta) k^2/4xi^2} B^R(k) / Npad
 //   gH =                e^{-(1-eta) k^2/4xi^2} H^R(k) / Npad
 // ---------------------------------------------------------------------------
-template <typename U>
+template <typename U, bool GQ>
 __device__ __forceinline__ void mult_stokeslet(const cplx<U>* X, cplx<U>* Y, U kx, U ky, U kz, U gB, U gH)
 {
     U k2 = kx * kx + ky * ky + kz * kz;
@@ -231,14 +231,17 @@ __device__ __forceinline__ void mult_stokeslet(const cplx<U>* X, cplx<U>* Y, U k
     cplx<U> kc3 = cmk<U>(kx * X[4].x + ky * X[5].x + kz * X[6].x, kx * X[4].y + ky * X[5].y + kz * X[6].y);
     cplx<U> phi = cmk<U>(gH * (-2 * X[3].x + 2 * kc3.y), gH * (-2 * X[3].y - 2 * kc3.x));
 #pragma unroll
-    for (int q = 0; q < 3; ++q) {
-        Y[q] = cmk<U>(-gB * (k2 * X[q].x - kv[q] * kc.x), -gB * (k2 * X[q].y - kv[q] * kc.y));
-        Y[3 + q] = cmk<U>(-kv[q] * phi.y, kv[q] * phi.x);  // i k phi
-    }
+    for (int q = 0; q < 3; ++q) Y[q] = cmk<U>(-gB * (k2 * X[q].x - kv[q] * kc.x), -gB * (k2 * X[q].y - kv[q] * kc.y));
     Y[2] = cadd(Y[2], phi);
+    if (GQ) {
+        Y[3] = phi;
+    } else {
+#pragma unroll
+        for (int q = 0; q < 3; ++q) Y[3 + q] = cmk<U>(-kv[q] * phi.y, kv[q] * phi.x);  // i k phi
+    }
 }
 
-template <typename U>
+template <typename U, bool GQ>
 __device__ __forceinline__ void mult_stresslet(const cplx<U>* X, cplx<U>* Y, U kx, U ky, U kz, U gB, U gH)
 {
     U k2 = kx * kx + ky * ky + kz * kz;
@@ -263,12 +266,17 @@ __device__ __forceinline__ void mult_stresslet(const cplx<U>* X, cplx<U>* Y, U k
         cplx<U> s = cmk<U>(k2 * (2 * ck[q].x + kv[q] * tr.x) - 2 * kv[q] * kck.x,
                            k2 * (2 * ck[q].y + kv[q] * tr.y) - 2 * kv[q] * kck.y);
         Y[q] = cmk<U>(gB * s.y, -gB * s.x);
-        Y[3 + q] = cmk<U>(-kv[q] * phi.y, kv[q] * phi.x);
     }
     Y[2] = cadd(Y[2], phi);
+    if (GQ) {
+        Y[3] = phi;
+    } else {
+#pragma unroll
+        for (int q = 0; q < 3; ++q) Y[3 + q] = cmk<U>(-kv[q] * phi.y, kv[q] * phi.x);  // i k phi
+    }
 }
 
-template <typename U>
+template <typename U, bool GQ>
 __device__ __forceinline__ void mult_rotlet(const cplx<U>* X, cplx<U>* Y, U kx, U ky, U kz, U gH)
 {
     // t1 = -2 i gH (C1 x k)
@@ -281,22 +289,25 @@ __device__ __forceinline__ void mult_rotlet(const cplx<U>* X, cplx<U>* Y, U kx, 
     cplx<U> phi = cmk<U>(-2 * gH * kw.y, 2 * gH * kw.x);
     U kv[3] = {kx, ky, kz};
 #pragma unroll
-    for (int q = 0; q < 3; ++q) {
-        Y[q] = cmk<U>(2 * gH * cx[q].y, -2 * gH * cx[q].x);
-        Y[3 + q] = cmk<U>(-kv[q] * phi.y, kv[q] * phi.x);
-    }
+    for (int q = 0; q < 3; ++q) Y[q] = cmk<U>(2 * gH * cx[q].y, -2 * gH * cx[q].x);
     Y[2] = cadd(Y[2], phi);
+    if (GQ) {
+        Y[3] = phi;
+    } else {
+#pragma unroll
+        for (int q = 0; q < 3; ++q) Y[3 + q] = cmk<U>(-kv[q] * phi.y, kv[q] * phi.x);  // i k phi
+    }
 }
 
-template <typename U, int K>
+template <typename U, int K, bool GQ>
 __device__ __forceinline__ void apply_mult(const cplx<U>* X, cplx<U>* Y, U kx, U ky, U kz, U gB, U gH)
 {
     if (K == STOKESLET)
-        mult_stokeslet<U>(X, Y, kx, ky, kz, gB, gH);
+        mult_stokeslet<U, GQ>(X, Y, kx, ky, kz, gB, gH);
     else if (K == STRESSLET)
-        mult_stresslet<U>(X, Y, kx, ky, kz, gB, gH);
+        mult_stresslet<U, GQ>(X, Y, kx, ky, kz, gB, gH);
     else
-        mult_rotlet<U>(X, Y, kx, ky, kz, gH);
+        mult_rotlet<U, GQ>(X, Y, kx, ky, kz, gH);
 }
 
 // ---------------------------------------------------------------------------
@@ -323,6 +334,8 @@ template <typename T, int K, int EPL>
 __global__ void __launch_bounds__(Z_NT) k_z_scale(const cplx<T>* zb, cplx<T>* zout, ZArgs a)
 {
     constexpr int ncin = Traits<K>::ncA + Traits<K>::ncB;
+    constexpr int NCOUT = Out<T>::n;
+    constexpr bool GQ = Out<T>::grad_quad;
     constexpr int CPW = (ncin + ZW - 1) / ZW;  // input components per wavefront
     constexpr bool HOLD = EPL > 0 && CPW * EPL * (int)sizeof(cplx<T>) <= 128;
     constexpr int NX = HOLD ? CPW * EPL : 1;
@@ -429,10 +442,10 @@ __global__ void __launch_bounds__(Z_NT) k_z_scale(const cplx<T>* zb, cplx<T>* zo
                     double ep = exp(-a.c_exp * k2v);
                     double gB = 0.0, gH = ep * a.cH * a.octH64[oi];
                     if (K != ROTLET) gB = (1.0 + a.c_has * k2v) * ep * a.cB * a.octB64[oi];
-                    cplx<double> Xd[ncin], Yd[NCOUT];
+                    cplx<double> Xd[ncin], Yd[NCOUT_MAX];
 #pragma unroll
                     for (int c = 0; c < ncin; ++c) Xd[c] = cmk<double>((double)X[c].x, (double)X[c].y);
-                    apply_mult<double, K>(Xd, Yd, kxd, kyd, kzd, gB, gH);
+                    apply_mult<double, K, GQ>(Xd, Yd, kxd, kyd, kzd, gB, gH);
 #pragma unroll
                     for (int c = 0; c < NCOUT; ++c) Y[c] = cmk<T>((T)Yd[c].x, (T)Yd[c].y);
                 } else {
@@ -442,10 +455,10 @@ __global__ void __launch_bounds__(Z_NT) k_z_scale(const cplx<T>* zb, cplx<T>* zo
                     float gH = ep * (float)a.cH * a.octH32[oi];
                     float gB = 0.f;
                     if (K != ROTLET) gB = (1.f + (float)a.c_has * k2v) * ep * (float)a.cB * a.octB32[oi];
-                    cplx<float> Xf[ncin], Yf[NCOUT];
+                    cplx<float> Xf[ncin], Yf[NCOUT_MAX];
 #pragma unroll
                     for (int c = 0; c < ncin; ++c) Xf[c] = cmk<float>((float)X[c].x, (float)X[c].y);
-                    apply_mult<float, K>(Xf, Yf, kx, ky, kz, gB, gH);
+                    apply_mult<float, K, GQ>(Xf, Yf, kx, ky, kz, gB, gH);
 #pragma unroll
                     for (int c = 0; c < NCOUT; ++c) Y[c] = cmk<T>((T)Yf[c].x, (T)Yf[c].y);
                 }
@@ -609,7 +622,8 @@ hipError_t launch_inv_x(const cplx<T>* in, T* out, const PassArgs& a, int ncomp,
 size_t z_lds_bytes(int family, int Mt, int Q, size_t esz)
 {
     int ncin = family == STOKESLET ? 7 : family == STRESSLET ? 13 : 5;
-    int nl = ncin > NCOUT ? ncin : NCOUT;
+    int nout = esz == 8 ? Out<double>::n : Out<float>::n;
+    int nl = ncin > nout ? ncin : nout;
     return (size_t)nl * (4 * Mt / Q + 1) * 2 * esz;
 }
 

@@ -264,8 +264,12 @@ hipError_t launch_spread(int family, GridArgs g, const T* rec, const uint32_t* t
 
 // ---------------------------------------------------------------------------
 // gather (quadrature) and the FP64 combination u = u_R + self + u_F:
-//   u_F(x) = h^3 sum_nodes W(x - x_g) [T1(x_g) - x3 T2(x_g)]
-// one wavefront per target; lanes cover P consecutive x1 nodes of
+//   u_F(x) = h^3 sum_nodes W(x - x_g) [T1(x_g) - x3 T2(x_g)],  T2 = grad phi.
+// FP64 (GQ): the grids hold T1 (0..2) and the potential phi (3), and T2 is
+// formed here as the gradient of the potential's quadrature,
+//   grad_x W(x - x_g) = 2 a (x_g - x) W,  separable like W;
+// FP32: the grids hold T1 (0..2) and T2 (3..5).
+// One wavefront per target; lanes cover P consecutive x1 nodes of
 // floor(64 / P) rows at a time.
 // ---------------------------------------------------------------------------
 template <typename T>
@@ -274,9 +278,14 @@ __global__ void __launch_bounds__(256) k_gather(GridArgs g, const T* __restrict_
                                                 long long TT, const double* __restrict__ upart,
                                                 double* __restrict__ uout)
 {
-    __shared__ T wsh[4][3 * 32];
+    constexpr bool GQ = Out<T>::grad_quad;
+    __shared__ T wsh[4][3 * 32];              // W factors along x1, x2, x3
+    __shared__ T dsh[4][GQ ? 3 * 32 : 1];     // their derivatives with respect to the target
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const long long t_raw = blockIdx.x * 4LL + wv;
+    // blocks of 4 consecutive (cell-sorted, so nearby) targets, spread over the
+    // XCDs in contiguous ranges so that overlapping supports share an L2
+    const long long nblk = (TT + 3) / 4;
+    const long long t_raw = xcd_block(blockIdx.x, nblk) * 4LL + wv;
     const bool valid = t_raw < TT;  // no early exit: every wave reaches the barrier
     const long long t = valid ? t_raw : TT - 1;
     const int P = g.P, Mt = g.Mt;
@@ -290,6 +299,7 @@ __global__ void __launch_bounds__(256) k_gather(GridArgs g, const T* __restrict_
         double v = exp(-g.a2 * d * d);
         if (a == 0) v *= g.pref;
         wsh[wv][f] = (T)v;
+        if (GQ) dsh[wv][f] = (T)(2.0 * g.a2 * d * v);
     }
     __syncthreads();
     const int rows = 64 / P;
@@ -297,12 +307,25 @@ __global__ void __launch_bounds__(256) k_gather(GridArgs g, const T* __restrict_
     T acc[6] = {0, 0, 0, 0, 0, 0};
     if (row < rows) {
         const T wx = wsh[wv][xi];
+        const T dx = GQ ? dsh[wv][xi] : (T)0;
         for (int rr = row; rr < P * P; rr += rows) {
             int dz = fdiv(rr, P, g.mP), dy = rr - dz * P;
-            T w = wx * wsh[wv][P + dy] * wsh[wv][2 * P + dz];
+            const T wy = wsh[wv][P + dy], wz = wsh[wv][2 * P + dz];
+            const T wyz = wy * wz;
+            const T w = wx * wyz;
             long long node = ((long long)(base[2] + dz) * Mt + base[1] + dy) * Mt + base[0] + xi;
 #pragma unroll
-            for (int c = 0; c < 6; ++c) acc[c] += w * grids[c * cs + node];
+            for (int c = 0; c < 3; ++c) acc[c] += w * grids[c * cs + node];
+            if (GQ) {
+                const T gx = dx * wyz, gy = wx * dsh[wv][P + dy] * wz, gz = wx * wy * dsh[wv][2 * P + dz];
+                const T ph = grids[3 * cs + node];
+                acc[3] += gx * ph;
+                acc[4] += gy * ph;
+                acc[5] += gz * ph;
+            } else {
+#pragma unroll
+                for (int c = 3; c < 6; ++c) acc[c] += w * grids[c * cs + node];
+            }
         }
     }
 #pragma unroll
@@ -324,8 +347,10 @@ hipError_t launch_gather(GridArgs g, const T* grids, long long cs, const double*
                          long long T_, const double* upart, double* uout, hipStream_t st)
 {
     if (T_ <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_gather<T>, dim3((unsigned)((T_ + 3) / 4)), dim3(256), 0, st, g, grids, cs, xs, tperm, T_,
-                       upart, uout);
+    const long long nblk = (T_ + 3) / 4;
+    const long long nlaunch = (nblk + NXCD - 1) / NXCD * NXCD;  // every XCD range padded to full length
+    hipLaunchKernelGGL(k_gather<T>, dim3((unsigned)nlaunch), dim3(256), 0, st, g, grids, cs, xs, tperm, T_, upart,
+                       uout);
     return hipGetLastError();
 }
 

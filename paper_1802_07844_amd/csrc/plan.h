@@ -146,6 +146,7 @@ struct PlanInput {
     int prec;  // 0 auto, 1 fp64, 2 fp32
     int force_M, force_P, force_Mt;
     int force_zg;  // > 0: k1 slabs per group of the y / x3 pipeline
+    int gather_extra;  // >= 0: extra gather support nodes (even); < 0: default
 };
 
 struct Plan {
@@ -153,12 +154,13 @@ struct Plan {
     long long N, T;
     double xi, rc, tol;
     double L, h, Lt, eta, Q;
-    int M, P, Mt, Qz, nf, nf3, ncin;
+    int M, P, Pg, Mt, Qz, nf, nf3, ncin;
     bool resident;
     double est_r, est_f, est32;
     CellGeom cg;
     long long ncell;
-    GridArgs g;
+    GridArgs g;   // spreading (support P)
+    GridArgs gg;  // quadrature at the targets (support Pg >= P, same Gaussian)
     long long ntiles;
     int Bx, By;
     int zg;  // k1 slabs per group of the y / x3 pipeline
@@ -227,6 +229,14 @@ inline int make_plan(const PlanInput& in, Plan* out)
         while (std::exp(-pi * P * C_SHAPE * C_SHAPE / 2) > pbudget) P += 2;
     }
     if (P < 2 || P > 30 || (P & 1)) return -1;
+    // the quadrature forms the gradient of the correction potential with the
+    // gradient of the Gaussian: it weights the smooth potential by grad W,
+    // whose truncation error is larger by about sqrt(a) times the potential's
+    // length scale, so the gather truncates the same Gaussian further out
+    // (FP64 only: the FP32 path transforms the gradient spectrally)
+    int Pg = P + (in.gather_extra >= 0 ? in.gather_extra : (p.prec == 1 ? 2 : 0));
+    if (Pg > 30 || (Pg & 1)) return -1;
+    const int Pe = std::max(P, Pg);
     // grid intervals over the box
     int M = in.force_M;
     if (M <= 0) {
@@ -243,11 +253,12 @@ inline int make_plan(const PlanInput& in, Plan* out)
     double eta = P * xi * xi * h * h / (C_SHAPE * C_SHAPE * pi);
     if (!(eta < 1.0)) return -3;
     double m = std::sqrt(2.0 * std::log(1.0 / tol));
-    int ext = std::max(P, (int)std::ceil(m / (std::sqrt(2.0) * xi * h)));
+    int ext = std::max(Pe, (int)std::ceil(m / (std::sqrt(2.0) * xi * h)));
     int Mt = in.force_Mt > 0 ? in.force_Mt : next_smooth_even(M + ext);
-    if (Mt < M + P || (Mt & 1) || !smooth7(Mt) || Mt > EHS_MT_MAX) return -3;
+    if (Mt < M + Pe || (Mt & 1) || !smooth7(Mt) || Mt > EHS_MT_MAX) return -3;
     p.M = M;
     p.P = P;
+    p.Pg = Pg;
     p.Mt = Mt;
     p.h = h;
     p.Lt = Mt * h;
@@ -264,7 +275,7 @@ inline int make_plan(const PlanInput& in, Plan* out)
     // fused x3 pass: smallest number of phases whose lines fit one wavefront's
     // FFT and whose max(ncin, 6) lines fit the LDS
     const size_t esz = p.prec == 1 ? 8 : 4;
-    const int nl = std::max(p.ncin, 6);
+    const int nl = std::max(p.ncin, ncout_for(p.prec));
     p.Qz = 0;
     for (int Q : {2, 4, 8}) {
         if ((4 * Mt) % Q) continue;
@@ -282,7 +293,7 @@ inline int make_plan(const PlanInput& in, Plan* out)
     // ZSLAB_BUDGET bytes) instead of the whole padded spectrum
     {
         size_t slab = (size_t)nl * (2 * Mt) * (2 * Mt) * 2 * esz;
-        if (!p.resident) slab += (size_t)6 * (2 * Mt) * (2 * Mt) * 2 * esz;
+        if (!p.resident) slab += (size_t)ncout_for(p.prec) * (2 * Mt) * (2 * Mt) * 2 * esz;
         long long g = in.force_zg > 0 ? in.force_zg : (long long)(ZSLAB_BUDGET / slab);
         p.zg = (int)std::max(1LL, std::min(g, (long long)Mt + 1));
     }
@@ -309,8 +320,8 @@ inline int make_plan(const PlanInput& in, Plan* out)
     GridArgs& g = p.g;
     g.Mt = Mt;
     g.P = P;
-    g.o[0] = in.lo[0] - P * h / 2;
-    g.o[1] = in.lo[1] - P * h / 2;
+    g.o[0] = in.lo[0] - Pe * h / 2;
+    g.o[1] = in.lo[1] - Pe * h / 2;
     g.o[2] = -p.Lt;
     g.h = h;
     g.a2 = 2 * xi * xi / eta;
@@ -326,6 +337,9 @@ inline int make_plan(const PlanInput& in, Plan* out)
         g.K[a] = (P - 1 + tl[a] - 1) / tl[a];
         p.ntiles *= g.nt[a];
     }
+    p.gg = g;
+    p.gg.P = Pg;
+    p.gg.mP = magic_of((unsigned)Pg);
     *out = p;
     return 0;
 }

@@ -100,7 +100,7 @@ def test_plan_invariants(family, tol):
     # Gaussian support from exp(-pi P c^2 / 2) <= tol / 40 (tol / 4 for tol >= 1e-6 except the
     # stresslet), c = 0.95
     assert r.P == (20 if tol == 1e-10 else 12 if family == "stresslet" else 10)
-    assert r.Mt % 2 == 0 and _smooth7(r.Mt) and r.Mt >= r.M + r.P
+    assert r.Mt % 2 == 0 and _smooth7(r.Mt) and r.Mt >= r.M + max(r.P, r.Pg)
     assert 0.0 < r.eta < 1.0
     assert r.precision == (1 if tol < 1e-5 else 2)
     assert r.h == pytest.approx(r.L / r.M)
@@ -129,9 +129,11 @@ def test_plan_box_covers_points_and_margin():
     r = _plan(lo=(0.25, -0.5, 0), hi=(0.9, 0.2, 0.8))
     L = max(0.65, 0.7, 0.8)
     assert r.L == pytest.approx(L, rel=1e-9)
-    # in-plane origin half a support below the lowest point
-    assert r.origin[0] == pytest.approx(0.25 - r.P * r.h / 2)
-    assert r.origin[1] == pytest.approx(-0.5 - r.P * r.h / 2)
+    # in-plane origin half the wider (quadrature) support below the lowest point
+    pe = max(r.P, r.Pg)
+    assert r.Pg == r.P + (2 if r.precision == 1 else 0)
+    assert r.origin[0] == pytest.approx(0.25 - pe * r.h / 2)
+    assert r.origin[1] == pytest.approx(-0.5 - pe * r.h / 2)
     # the screening margin: (M~ - M) h >= sqrt(2 ln(1/tol)) / (sqrt2 xi)
     assert (r.Mt - r.M) * r.h >= math.sqrt(2 * math.log(1e10)) / (math.sqrt(2) * 12.0) - 1e-12
 
