@@ -68,6 +68,8 @@ extern "C" {
                                the last-level cache); M~ + 1 keeps the whole grid in one group */
 #define EHS_OPT_GATHER_EXTRA 7 /* >= 0 (even): support nodes the quadrature adds to P; -1: default (2 for
                                   FP64, whose quadrature forms the correction gradient, 0 for FP32) */
+#define EHS_OPT_DGRID 8     /* FP64: 1 spreads the correction sources as one density with derivative
+                               weights, 0 as separate grids, -1 (default) chooses by cost */
 
 /* stage indices of ehs_report.ms_stage */
 #define EHS_ST_BBOX 0       /* bounding box + validation reduction and its readback */
@@ -104,6 +106,8 @@ typedef struct ehs_report {
     double workspace_bytes;
     int32_t zslab;          /* k1 slabs per group of the y / x3 transform pipeline */
     int32_t Pg;             /* Gaussian support of the quadrature at the targets (>= P) */
+    int32_t Ps;             /* Gaussian support of the spreading (>= P) */
+    int32_t dgrid;          /* 1: correction sources spread as one density (FP64) */
     double est_fp32;        /* estimated FP32 rounding error (relative RMS, uniform point sets) */
 } ehs_report;
 

@@ -22,7 +22,7 @@ LIB_PATH = os.path.join(HERE, "libehs.so")
 
 STOKESLET, STRESSLET, ROTLET = 0, 1, 2
 FAMILIES = {"stokeslet": STOKESLET, "stresslet": STRESSLET, "rotlet": ROTLET}
-OPT_PRECISION, OPT_TIMING, OPT_FORCE_M, OPT_FORCE_P, OPT_FORCE_MT, OPT_MEM_CAP, OPT_ZSLAB, OPT_GATHER_EXTRA = range(8)
+OPT_PRECISION, OPT_TIMING, OPT_FORCE_M, OPT_FORCE_P, OPT_FORCE_MT, OPT_MEM_CAP, OPT_ZSLAB, OPT_GATHER_EXTRA, OPT_DGRID = range(9)
 STAGES = ["bbox", "precompute", "binning", "realspace", "spread", "fwd_x", "fwd_y", "z_scale", "inv_y", "inv_x",
           "gather", "total"]
 NSTAGES = len(STAGES)
@@ -42,6 +42,7 @@ class Report(ctypes.Structure):
         ("ms_stage", ctypes.c_double * NSTAGES),
         ("workspace_bytes", ctypes.c_double),
         ("zslab", ctypes.c_int32), ("Pg", ctypes.c_int32),
+        ("Ps", ctypes.c_int32), ("dgrid", ctypes.c_int32),
         ("est_fp32", ctypes.c_double),
     ]
 

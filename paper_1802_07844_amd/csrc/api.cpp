@@ -276,7 +276,7 @@ int check_extents(const Plan& p, const Layout& L, size_t esz)
               && fits(nout * zs, p.resident ? zsreg : zoreg)  // fused x3 outputs
               && fits(nout * a, yreg)                  // inverse x2 -> Y (in place of A)
               && fits(nout * real, xreg)               // inverse x1 -> X (read by the gather)
-              && fits((size_t)2 * p.N * record_stride(p.family, p.P, esz) * esz, L.keys - L.rec)
+              && fits((size_t)2 * p.N * record_stride(p.family, p.g.P, esz) * esz, L.keys - L.rec)
               && fits((size_t)(4 * p.N + 4 * p.T + 8 * p.N) * 4, L.sortsc - L.keys)
               && fits((size_t)(p.ntiles + 1) * 4, L.soff - L.toff)
               && fits((size_t)(p.ncell + 1) * 4, L.tgoff - L.soff)
@@ -290,7 +290,7 @@ int check_extents(const Plan& p, const Layout& L, size_t esz)
     // the fused x3 pass holds lines of length 4Mt/Q for max(ncin, outputs) components,
     // each transformed by one wavefront
     int nq = 4 * p.Mt / p.Qz;
-    ok = ok && (4 * p.Mt) % p.Qz == 0 && z_lds_bytes(p.family, p.Mt, p.Qz, esz) <= 160 * 1024 &&
+    ok = ok && (4 * p.Mt) % p.Qz == 0 && z_lds_bytes(p.family, p.dgrid, p.Mt, p.Qz, esz) <= 160 * 1024 &&
          nq <= lds_fft_cap(nq, 64);
     // x / y passes: B lines of Mt in LDS and in the 16-element register budget
     ok = ok && p.Bx * p.Mt <= lds_fft_cap(p.Mt, 256) && p.By * p.Mt <= lds_fft_cap(p.Mt, 256) &&
@@ -300,7 +300,10 @@ int check_extents(const Plan& p, const Layout& L, size_t esz)
     ok = ok && (long long)(p.Mt + 1) * std::max(p.Bx, 2 * p.By) * std::max(p.Mt, 2 * p.By) < (1LL << 31) &&
          (long long)std::max(p.ncin, ncout_for(p.prec)) * 2 * p.Mt * 2 * p.Mt < (1LL << 31);
     // gather weights table (3P <= 96) and spread support within the grid
-    ok = ok && 3 * p.Pg <= 96 && p.P <= p.Mt && p.Pg <= p.Mt && p.Pg >= p.P;
+    // supports: the kernels read them from the grid arguments, which must agree
+    // with the plan (spreading g.P = Ps >= P, quadrature gg.P = Pg >= P)
+    ok = ok && p.g.P == p.Ps && p.gg.P == p.Pg && p.Ps >= p.P && p.Pg >= p.P && 3 * p.Pg <= 96 &&
+         p.Ps <= p.Mt && p.Pg <= p.Mt && p.M + std::max(p.Ps, p.Pg) <= p.Mt;
     return ok ? EHS_OK : EHS_ERANGE;
 }
 
@@ -323,7 +326,8 @@ Layout layout(const Plan& p, size_t esz)
     L.ZS = off; off += al((size_t)nl * czs);
     L.Zo = off; off += p.resident ? 0 : al((size_t)ncout_for(p.prec) * czs);
     long long N = p.N, T = p.T;
-    L.rec = off; off += al((size_t)2 * N * record_stride(p.family, p.P, esz) * esz);
+    // records carry 3 g.P weights: g.P is the spreading support the kernels use
+    L.rec = off; off += al((size_t)2 * N * record_stride(p.family, p.g.P, esz) * esz);
     // keys / values: sources (4 N), targets (4 T), points (4 * 2N)
     L.keys = off; off += al((size_t)(4 * N + 4 * T + 8 * N) * sizeof(uint32_t));
     L.sortsc = off; off += al(radix_sort_scratch_bytes(std::max(2 * N, T)) + scan_scratch_bytes(p.ncell + 1) + 1024);
@@ -438,11 +442,11 @@ int run(ehs_ctx* c, Plan& p, const Octants& oct, const double* y, const double* 
     HIPCHK(launch_point_keys(y, N, p.g, kp, vp, st));
     HIPCHK(radix_sort(kp, vp, kp2, vp2, 2 * N, bits_for(p.ntiles), sortsc, st, &pk, &pperm));
     HIPCHK(launch_cell_ranges(pk, 2 * N, toff, nullptr, p.ntiles, st));
-    HIPCHK(launch_records<T>(p.family, y, s, pperm, N, p.g, rec, st));
+    HIPCHK(launch_records<T>(p.family, p.dgrid, y, s, pperm, N, p.g, rec, st));
     const long long Mt = p.Mt;
     const long long csR = Mt * Mt * 2 * Mt;          // real grid component
     const long long csA = (Mt + 1) * 2 * Mt * Mt;    // A / D component (complex)
-    HIPCHK(launch_spread<T>(p.family, p.g, rec, toff, X, csR, st));
+    HIPCHK(launch_spread<T>(p.family, p.dgrid, p.g, rec, toff, X, csR, st));
     rec_ev(EHS_ST_FWDX);
 
     // -- forward transforms
@@ -522,7 +526,7 @@ int run(ehs_ctx* c, Plan& p, const Octants& oct, const double* y, const double* 
         pa.cs_out = csS;
         HIPCHK(launch_fwd_y<T>(Yc, ZS, pa, p.ncin, st));
         if (slab_ev) HIPCHK(hipEventRecord(c->sev[c->nsev++], st));
-        HIPCHK(launch_z<T>(p.family, ZS, ZO, za, p.resident, st));
+        HIPCHK(launch_z<T>(p.family, p.dgrid, ZS, ZO, za, p.resident, st));
         if (slab_ev) HIPCHK(hipEventRecord(c->sev[c->nsev++], st));
         pa.cs_in = csS;
         pa.cs_out = csA;
@@ -593,6 +597,7 @@ int ehs::plan_request(ehs_ctx* c, int family, const double* y, const double* s, 
     in.force_Mt = c->force_Mt;
     in.force_zg = c->force_zg;
     in.gather_extra = c->gather_extra;
+    in.dgrid = c->dgrid;
     return make_plan(in, p);
 }
 
@@ -641,6 +646,8 @@ void ehs::fill_report(const Plan& p, ehs_report* r)
     r->est_fourier = p.est_f;
     r->zslab = p.zg;
     r->Pg = p.Pg;
+    r->Ps = p.Ps;
+    r->dgrid = p.dgrid ? 1 : 0;
     r->est_fp32 = p.est32;
 }
 
@@ -807,6 +814,7 @@ int ehs_set_option(ehs_ctx* c, int option, double value)
         case EHS_OPT_MEM_CAP: c->mem_cap = value; return EHS_OK;
         case EHS_OPT_ZSLAB: c->force_zg = (int)value; return EHS_OK;
         case EHS_OPT_GATHER_EXTRA: c->gather_extra = (int)value; return EHS_OK;
+        case EHS_OPT_DGRID: c->dgrid = (int)value; return EHS_OK;
         default: return EHS_EINVAL;
     }
 }
@@ -867,6 +875,7 @@ int ehs_plan_query(int family, int64_t N, int64_t T, const double* lo, const dou
     in.Q = Q;
     in.prec = precision;
     in.gather_extra = -1;
+    in.dgrid = -1;
     Plan p;
     int rc = make_plan(in, &p);
     if (rc) return rc;

@@ -83,6 +83,28 @@ struct Out {
 };
 inline int ncout_for(int prec) { return prec == 1 ? 4 : 6; }
 
+// input grids: the kernel grid C1 (ncA components) and the correction
+// sources.  FP64 spreads the correction sources directly as the one scalar
+// density D whose transform enters the potential, phi^ = E H^R D^, using
+// derivatives of the Gaussian:
+//   stokeslet  D = -2 C2 - 2 div C3           (C2 = f3, C3 = y3 f^I at y^I)
+//   stresslet  D = 4 d3 C2 - 4 grad grad : C3  (C2 = g.q, C3 = y3 sym(g^I q^I))
+//   rotlet     D = 2 div C2                    (C2 = w)
+// The derivative weights need a wider Gaussian support than plain spreading,
+// so the planner uses D only where the saved transforms outweigh that (and
+// only in FP64: the FP32 quantisation would be amplified by the derivative
+// weights as in the quadrature); otherwise the ncB correction grids are
+// spread separately.
+template <int K, bool DG>
+struct InGrids {
+    static constexpr int n = Traits<K>::ncA + (DG ? 1 : Traits<K>::ncB);
+};
+inline int ncin_for(int family, bool dgrid)
+{
+    int ncA = family == 1 ? 6 : 3, ncB = family == 0 ? 4 : family == 1 ? 7 : 2;
+    return ncA + (dgrid ? 1 : ncB);
+}
+
 // ---------------------------------------------------------------------------
 // FFT plan for one line length: radices (each 2,3,4,5,7 or 8), the twiddle
 // table tw[t] = exp(-2 pi i t / n), t < n, in device memory, and for every

@@ -48,7 +48,7 @@ struct ehs_ctx {
     double* host_bbox = nullptr;             // pinned, 16 doubles
     hipEvent_t ev[EHS_NSTAGES + 1] = {};
     bool ev_ok = false;
-    int opt_prec = 0, opt_timing = 0, force_M = 0, force_P = 0, force_Mt = 0, force_zg = 0, gather_extra = -1;
+    int opt_prec = 0, opt_timing = 0, force_M = 0, force_P = 0, force_Mt = 0, force_zg = 0, gather_extra = -1, dgrid = -1;
     std::vector<hipEvent_t> sev;             // per-launch events of the slab pipeline (timing)
     int nsev = 0;                            // events recorded in the last evaluation
     double mem_cap = 0.0;

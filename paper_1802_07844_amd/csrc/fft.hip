@@ -22,7 +22,6 @@ namespace ehs {
 constexpr int PASS_NT = 256;  // threads of the y passes
 constexpr int XPASS_NT = 512; // threads of the x passes
 constexpr int PASS_E = 16;    // complex elements per thread in the LDS FFT
-constexpr int Z_NT = 512;
 constexpr int Z_E = 16;
 
 // ---------------------------------------------------------------------------
@@ -220,16 +219,21 @@ __global__ void __launch_bounds__(XPASS_NT, 4) k_inv_x(const cplx<T>* __restrict
 //   gB = (1 + k^2/4xi^2) e^{-(1-eta) k^2/4xi^2} B^R(k) / Npad
 //   gH =                e^{-(1-eta) k^2/4xi^2} H^R(k) / Npad
 // ---------------------------------------------------------------------------
-template <typename U, bool GQ>
+template <typename U, bool GQ, bool DG>
 __device__ __forceinline__ void mult_stokeslet(const cplx<U>* X, cplx<U>* Y, U kx, U ky, U kz, U gB, U gH)
 {
     U k2 = kx * kx + ky * ky + kz * kz;
     // t1 = -(k^2 I - k k) C1 * gB   (the A^S(k) of the stokeslet)
     cplx<U> kc = cmk<U>(kx * X[0].x + ky * X[1].x + kz * X[2].x, kx * X[0].y + ky * X[1].y + kz * X[2].y);
     U kv[3] = {kx, ky, kz};
-    // phi = gH (-2 C2 - 2 i k.C3)
-    cplx<U> kc3 = cmk<U>(kx * X[4].x + ky * X[5].x + kz * X[6].x, kx * X[4].y + ky * X[5].y + kz * X[6].y);
-    cplx<U> phi = cmk<U>(gH * (-2 * X[3].x + 2 * kc3.y), gH * (-2 * X[3].y - 2 * kc3.x));
+    // phi = gH (-2 C2 - 2 i k.C3), or gH D when the density D was spread (DG)
+    cplx<U> phi;
+    if (DG) {
+        phi = cmk<U>(gH * X[3].x, gH * X[3].y);
+    } else {
+        cplx<U> kc3 = cmk<U>(kx * X[4].x + ky * X[5].x + kz * X[6].x, kx * X[4].y + ky * X[5].y + kz * X[6].y);
+        phi = cmk<U>(gH * (-2 * X[3].x + 2 * kc3.y), gH * (-2 * X[3].y - 2 * kc3.x));
+    }
 #pragma unroll
     for (int q = 0; q < 3; ++q) Y[q] = cmk<U>(-gB * (k2 * X[q].x - kv[q] * kc.x), -gB * (k2 * X[q].y - kv[q] * kc.y));
     Y[2] = cadd(Y[2], phi);
@@ -241,7 +245,7 @@ __device__ __forceinline__ void mult_stokeslet(const cplx<U>* X, cplx<U>* Y, U k
     }
 }
 
-template <typename U, bool GQ>
+template <typename U, bool GQ, bool DG>
 __device__ __forceinline__ void mult_stresslet(const cplx<U>* X, cplx<U>* Y, U kx, U ky, U kz, U gB, U gH)
 {
     U k2 = kx * kx + ky * ky + kz * kz;
@@ -253,13 +257,18 @@ __device__ __forceinline__ void mult_stresslet(const cplx<U>* X, cplx<U>* Y, U k
     cplx<U> tr = cmk<U>(X[0].x + X[3].x + X[5].x, X[0].y + X[3].y + X[5].y);
     cplx<U> kck = cmk<U>(kx * ck[0].x + ky * ck[1].x + kz * ck[2].x, kx * ck[0].y + ky * ck[1].y + kz * ck[2].y);
     U kv[3] = {kx, ky, kz};
-    // C3 symmetric (indices 7..12), phi = gH (4 i kz C2 + 4 k.C3.k)
-    const cplx<U>* B3 = X + 7;
-    U kbk_x = kx * kx * B3[0].x + ky * ky * B3[3].x + kz * kz * B3[5].x +
-              2 * (kx * ky * B3[1].x + kx * kz * B3[2].x + ky * kz * B3[4].x);
-    U kbk_y = kx * kx * B3[0].y + ky * ky * B3[3].y + kz * kz * B3[5].y +
-              2 * (kx * ky * B3[1].y + kx * kz * B3[2].y + ky * kz * B3[4].y);
-    cplx<U> phi = cmk<U>(gH * (-4 * kz * X[6].y + 4 * kbk_x), gH * (4 * kz * X[6].x + 4 * kbk_y));
+    // C3 symmetric (indices 7..12), phi = gH (4 i kz C2 + 4 k.C3.k), or gH D (DG)
+    cplx<U> phi;
+    if (DG) {
+        phi = cmk<U>(gH * X[6].x, gH * X[6].y);
+    } else {
+        const cplx<U>* B3 = X + 7;
+        U kbk_x = kx * kx * B3[0].x + ky * ky * B3[3].x + kz * kz * B3[5].x +
+                  2 * (kx * ky * B3[1].x + kx * kz * B3[2].x + ky * kz * B3[4].x);
+        U kbk_y = kx * kx * B3[0].y + ky * ky * B3[3].y + kz * kz * B3[5].y +
+                  2 * (kx * ky * B3[1].y + kx * kz * B3[2].y + ky * kz * B3[4].y);
+        phi = cmk<U>(gH * (-4 * kz * X[6].y + 4 * kbk_x), gH * (4 * kz * X[6].x + 4 * kbk_y));
+    }
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
         // t1 = -i gB [k^2 (2 C k + k trC) - 2 k (k.C k)]
@@ -276,7 +285,7 @@ __device__ __forceinline__ void mult_stresslet(const cplx<U>* X, cplx<U>* Y, U k
     }
 }
 
-template <typename U, bool GQ>
+template <typename U, bool GQ, bool DG>
 __device__ __forceinline__ void mult_rotlet(const cplx<U>* X, cplx<U>* Y, U kx, U ky, U kz, U gH)
 {
     // t1 = -2 i gH (C1 x k)
@@ -284,9 +293,14 @@ __device__ __forceinline__ void mult_rotlet(const cplx<U>* X, cplx<U>* Y, U kx, 
     cx[0] = cmk<U>(X[1].x * kz - X[2].x * ky, X[1].y * kz - X[2].y * ky);
     cx[1] = cmk<U>(X[2].x * kx - X[0].x * kz, X[2].y * kx - X[0].y * kz);
     cx[2] = cmk<U>(X[0].x * ky - X[1].x * kx, X[0].y * ky - X[1].y * kx);
-    // phi = gH 2 i (kx w1 + ky w2)
-    cplx<U> kw = cmk<U>(kx * X[3].x + ky * X[4].x, kx * X[3].y + ky * X[4].y);
-    cplx<U> phi = cmk<U>(-2 * gH * kw.y, 2 * gH * kw.x);
+    // phi = gH 2 i (kx w1 + ky w2), or gH D (DG)
+    cplx<U> phi;
+    if (DG) {
+        phi = cmk<U>(gH * X[3].x, gH * X[3].y);
+    } else {
+        cplx<U> kw = cmk<U>(kx * X[3].x + ky * X[4].x, kx * X[3].y + ky * X[4].y);
+        phi = cmk<U>(-2 * gH * kw.y, 2 * gH * kw.x);
+    }
     U kv[3] = {kx, ky, kz};
 #pragma unroll
     for (int q = 0; q < 3; ++q) Y[q] = cmk<U>(2 * gH * cx[q].y, -2 * gH * cx[q].x);
@@ -299,15 +313,15 @@ __device__ __forceinline__ void mult_rotlet(const cplx<U>* X, cplx<U>* Y, U kx, 
     }
 }
 
-template <typename U, int K, bool GQ>
+template <typename U, int K, bool GQ, bool DG>
 __device__ __forceinline__ void apply_mult(const cplx<U>* X, cplx<U>* Y, U kx, U ky, U kz, U gB, U gH)
 {
     if (K == STOKESLET)
-        mult_stokeslet<U, GQ>(X, Y, kx, ky, kz, gB, gH);
+        mult_stokeslet<U, GQ, DG>(X, Y, kx, ky, kz, gB, gH);
     else if (K == STRESSLET)
-        mult_stresslet<U, GQ>(X, Y, kx, ky, kz, gB, gH);
+        mult_stresslet<U, GQ, DG>(X, Y, kx, ky, kz, gB, gH);
     else
-        mult_rotlet<U, GQ>(X, Y, kx, ky, kz, gH);
+        mult_rotlet<U, GQ, DG>(X, Y, kx, ky, kz, gH);
 }
 
 // ---------------------------------------------------------------------------
@@ -317,8 +331,9 @@ __device__ __forceinline__ void apply_mult(const cplx<U>* X, cplx<U>* Y, U kx, U
 //   X[Q m + s] = DFT_{4Mt/Q}( sum_h x[l' + h nq] w^{s (l' + h nq)} )[m],
 // w = exp(-2 pi i / 4Mt), and the inverse accumulates the phases back.
 //
-// One block of 8 wavefronts per line; wavefront w owns the input components
-// w, w + 8 and the output component w.  Folding, the forward and inverse
+// One block per (k1, k2) line with one wavefront per component line (at most
+// 8); wavefront w owns the input components w, w + 8 and the output
+// component w.  Folding, the forward and inverse
 // transforms and unfolding of a component touch only its own LDS line, so
 // they run at wavefront scope without block barriers and the waves proceed
 // independently; only the scaling, which couples the components at each k,
@@ -328,12 +343,19 @@ __device__ __forceinline__ void apply_mult(const cplx<U>* X, cplx<U>* Y, U kx, U
 // written once; EPL = 0: inputs re-read and outputs accumulated in zout.
 // grid: (2Mt, nk1)
 // ---------------------------------------------------------------------------
-constexpr int ZW = Z_NT / 64;  // wavefronts per block
+// wavefronts per block: one per line, at most 8
+template <typename T, int K, bool DG>
+struct ZWaves {
+    static constexpr int lines = InGrids<K, DG>::n > Out<T>::n ? InGrids<K, DG>::n : Out<T>::n;
+    static constexpr int n = lines < 8 ? lines : 8;
+};
 
-template <typename T, int K, int EPL>
-__global__ void __launch_bounds__(Z_NT) k_z_scale(const cplx<T>* zb, cplx<T>* zout, ZArgs a)
+template <typename T, int K, int EPL, bool DG>
+__global__ void __launch_bounds__((64 * ZWaves<T, K, DG>::n)) k_z_scale(const cplx<T>* zb, cplx<T>* zout, ZArgs a)
 {
-    constexpr int ncin = Traits<K>::ncA + Traits<K>::ncB;
+    constexpr int ZW = ZWaves<T, K, DG>::n;
+    constexpr int Z_NT = 64 * ZW;
+    constexpr int ncin = InGrids<K, DG>::n;
     constexpr int NCOUT = Out<T>::n;
     constexpr bool GQ = Out<T>::grad_quad;
     constexpr int CPW = (ncin + ZW - 1) / ZW;  // input components per wavefront
@@ -445,7 +467,7 @@ __global__ void __launch_bounds__(Z_NT) k_z_scale(const cplx<T>* zb, cplx<T>* zo
                     cplx<double> Xd[ncin], Yd[NCOUT_MAX];
 #pragma unroll
                     for (int c = 0; c < ncin; ++c) Xd[c] = cmk<double>((double)X[c].x, (double)X[c].y);
-                    apply_mult<double, K, GQ>(Xd, Yd, kxd, kyd, kzd, gB, gH);
+                    apply_mult<double, K, GQ, DG>(Xd, Yd, kxd, kyd, kzd, gB, gH);
 #pragma unroll
                     for (int c = 0; c < NCOUT; ++c) Y[c] = cmk<T>((T)Yd[c].x, (T)Yd[c].y);
                 } else {
@@ -458,7 +480,7 @@ __global__ void __launch_bounds__(Z_NT) k_z_scale(const cplx<T>* zb, cplx<T>* zo
                     cplx<float> Xf[ncin], Yf[NCOUT_MAX];
 #pragma unroll
                     for (int c = 0; c < ncin; ++c) Xf[c] = cmk<float>((float)X[c].x, (float)X[c].y);
-                    apply_mult<float, K, GQ>(Xf, Yf, kx, ky, kz, gB, gH);
+                    apply_mult<float, K, GQ, DG>(Xf, Yf, kx, ky, kz, gB, gH);
 #pragma unroll
                     for (int c = 0; c < NCOUT; ++c) Y[c] = cmk<T>((T)Yf[c].x, (T)Yf[c].y);
                 }
@@ -619,9 +641,9 @@ hipError_t launch_inv_x(const cplx<T>* in, T* out, const PassArgs& a, int ncomp,
     return hipGetLastError();
 }
 
-size_t z_lds_bytes(int family, int Mt, int Q, size_t esz)
+size_t z_lds_bytes(int family, bool dgrid, int Mt, int Q, size_t esz)
 {
-    int ncin = family == STOKESLET ? 7 : family == STRESSLET ? 13 : 5;
+    int ncin = ncin_for(family, dgrid);
     int nout = esz == 8 ? Out<double>::n : Out<float>::n;
     int nl = ncin > nout ? ncin : nout;
     return (size_t)nl * (4 * Mt / Q + 1) * 2 * esz;
@@ -633,33 +655,43 @@ bool z_resident_ok(int family, int Mt)
     return 2 * Mt <= 3 * 512;
 }
 
-template <typename T, int K>
-static hipError_t launch_z_t(cplx<T>* zb, cplx<T>* zout, const ZArgs& a, bool res, hipStream_t st)
+template <typename T, int K, bool DG>
+static void launch_z_t(cplx<T>* zb, cplx<T>* zout, const ZArgs& a, bool res, hipStream_t st)
 {
     dim3 grid(2 * a.Mt, a.nk1);
-    size_t lds = z_lds_bytes(K, a.Mt, a.Q, sizeof(T));
+    size_t lds = z_lds_bytes(K, DG, a.Mt, a.Q, sizeof(T));
     const int nz = 2 * a.Mt;
+    const dim3 blk(64 * ZWaves<T, K, DG>::n);
     if (!res)
-        hipLaunchKernelGGL((k_z_scale<T, K, 0>), grid, dim3(Z_NT), lds, st, zb, zout, a);
+        hipLaunchKernelGGL((k_z_scale<T, K, 0, DG>), grid, blk, lds, st, zb, zout, a);
     else if (nz <= 256)
-        hipLaunchKernelGGL((k_z_scale<T, K, 4>), grid, dim3(Z_NT), lds, st, zb, zout, a);
+        hipLaunchKernelGGL((k_z_scale<T, K, 4, DG>), grid, blk, lds, st, zb, zout, a);
     else if (nz <= 512)
-        hipLaunchKernelGGL((k_z_scale<T, K, 8>), grid, dim3(Z_NT), lds, st, zb, zout, a);
+        hipLaunchKernelGGL((k_z_scale<T, K, 8, DG>), grid, blk, lds, st, zb, zout, a);
     else if (nz <= 1024)
-        hipLaunchKernelGGL((k_z_scale<T, K, 16>), grid, dim3(Z_NT), lds, st, zb, zout, a);
+        hipLaunchKernelGGL((k_z_scale<T, K, 16, DG>), grid, blk, lds, st, zb, zout, a);
     else
-        hipLaunchKernelGGL((k_z_scale<T, K, 24>), grid, dim3(Z_NT), lds, st, zb, zout, a);
-    return hipGetLastError();
+        hipLaunchKernelGGL((k_z_scale<T, K, 24, DG>), grid, blk, lds, st, zb, zout, a);
 }
 
 template <typename T>
-hipError_t launch_z(int family, cplx<T>* zb, cplx<T>* zout, const ZArgs& a, bool res, hipStream_t st)
+hipError_t launch_z(int family, bool dgrid, cplx<T>* zb, cplx<T>* zout, const ZArgs& a, bool res, hipStream_t st)
 {
-    switch (family) {
-        case STOKESLET: return launch_z_t<T, STOKESLET>(zb, zout, a, res, st);
-        case STRESSLET: return launch_z_t<T, STRESSLET>(zb, zout, a, res, st);
-        default: return launch_z_t<T, ROTLET>(zb, zout, a, res, st);
+    // the correction density is only used in FP64
+    if (dgrid && sizeof(T) == 8) {
+        switch (family) {
+            case STOKESLET: launch_z_t<T, STOKESLET, true>(zb, zout, a, res, st); break;
+            case STRESSLET: launch_z_t<T, STRESSLET, true>(zb, zout, a, res, st); break;
+            default: launch_z_t<T, ROTLET, true>(zb, zout, a, res, st); break;
+        }
+    } else {
+        switch (family) {
+            case STOKESLET: launch_z_t<T, STOKESLET, false>(zb, zout, a, res, st); break;
+            case STRESSLET: launch_z_t<T, STRESSLET, false>(zb, zout, a, res, st); break;
+            default: launch_z_t<T, ROTLET, false>(zb, zout, a, res, st); break;
+        }
     }
+    return hipGetLastError();
 }
 
 hipError_t launch_even_line(const double* in, double* out, const EvenArgs& a, hipStream_t st)
@@ -699,8 +731,8 @@ template hipError_t launch_inv_y<double>(const cplx<double>*, cplx<double>*, con
 template hipError_t launch_inv_y<float>(const cplx<float>*, cplx<float>*, const PassArgs&, int, hipStream_t);
 template hipError_t launch_inv_x<double>(const cplx<double>*, double*, const PassArgs&, int, hipStream_t);
 template hipError_t launch_inv_x<float>(const cplx<float>*, float*, const PassArgs&, int, hipStream_t);
-template hipError_t launch_z<double>(int, cplx<double>*, cplx<double>*, const ZArgs&, bool, hipStream_t);
-template hipError_t launch_z<float>(int, cplx<float>*, cplx<float>*, const ZArgs&, bool, hipStream_t);
+template hipError_t launch_z<double>(int, bool, cplx<double>*, cplx<double>*, const ZArgs&, bool, hipStream_t);
+template hipError_t launch_z<float>(int, bool, cplx<float>*, cplx<float>*, const ZArgs&, bool, hipStream_t);
 template hipError_t launch_line_fft<double>(const cplx<double>*, cplx<double>*, int, int, const FftPlanDev&, bool,
                                             hipStream_t);
 template hipError_t launch_line_fft<float>(const cplx<float>*, cplx<float>*, int, int, const FftPlanDev&, bool,

@@ -22,11 +22,15 @@ struct RecLayout {
     static constexpr int ncB = Traits<K>::ncB;
 };
 
-// header of 4 int32 (base x, y, z, image flag) stored in the first 16 bytes
+// A record: header of 4 int32 (support base x, y, z, image flag) in the first
+// 16 bytes, then the 3P Gaussian factors along x1, x2, x3, the offsets
+// o + base h - z of the first support node per axis (for derivative
+// weights), then ncA kernel strengths and ncB correction coefficients (FP32:
+// the correction strengths; FP64: the coefficients of the density D).
 size_t record_stride(int family, int P, size_t esz)
 {
     int nc = family == STOKESLET ? 7 : family == STRESSLET ? 13 : 5;
-    return 16 / esz + 3 * (size_t)P + nc;
+    return 16 / esz + 3 * (size_t)P + 3 + nc;
 }
 
 __device__ __forceinline__ int support_base(double z, double o, double h, int P, int n)
@@ -114,7 +118,7 @@ __device__ __forceinline__ void point_strengths(const double* s, const double* y
     }
 }
 
-template <typename T, int K>
+template <typename T, int K, bool DG>
 __global__ void k_records(const double* __restrict__ y, const double* __restrict__ s, const uint32_t* __restrict__ perm,
                           long long N, GridArgs g, T* __restrict__ rec)
 {
@@ -122,7 +126,7 @@ __global__ void k_records(const double* __restrict__ y, const double* __restrict
     long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x;
     if (q >= 2 * N) return;
     const int P = g.P;
-    const long long stride = 16 / sizeof(T) + 3 * P + ncA + ncB;
+    const long long stride = 16 / sizeof(T) + 3 * P + 3 + ncA + ncB;
     long long p = perm[q];
     long long m = p < N ? p : p - N;
     bool img = p >= N;
@@ -145,52 +149,76 @@ __global__ void k_records(const double* __restrict__ y, const double* __restrict
             w[a * P + t] = (T)v;
         }
     }
+    for (int a = 0; a < 3; ++a) w[3 * P + a] = (T)(g.o[a] + base[a] * g.h - z[a]);
     double cA[ncA], cB[ncB];
     for (int c = 0; c < ncB; ++c) cB[c] = 0.0;
     point_strengths<K>(s, y, p, N, cA, cB);
-    T* cs = w + 3 * P;
+    if (DG) {
+        // coefficients of D (see InGrids): stokeslet (c0; cx, cy, cz) of
+        // c0 W + c . grad W; stresslet (c3; Sxx, Sxy, Sxz, Syy, Syz, Szz) of
+        // c3 d3 W + S : grad grad W; rotlet (cx, cy) of c . grad W
+        const double k = K == STOKESLET ? -2.0 : K == STRESSLET ? -4.0 : 2.0;
+        for (int c = 0; c < ncB; ++c) cB[c] *= k;
+        if (K == STRESSLET) cB[0] = -cB[0];  // +4 g.q d3
+    }
+    T* cs = w + 3 * P + 3;
     for (int c = 0; c < ncA; ++c) cs[c] = (T)cA[c];
     for (int c = 0; c < ncB; ++c) cs[ncA + c] = (T)cB[c];
 }
 
-template <typename T>
-hipError_t launch_records(int family, const double* y, const double* s, const uint32_t* perm, long long N, GridArgs g,
-                          T* rec, hipStream_t st)
+template <typename T, bool DG>
+static void launch_records_t(int family, const double* y, const double* s, const uint32_t* perm, long long N,
+                             GridArgs g, T* rec, hipStream_t st)
 {
-    if (N <= 0) return hipSuccess;
     dim3 grid((unsigned)((2 * N + 255) / 256));
     switch (family) {
-        case STOKESLET: hipLaunchKernelGGL((k_records<T, STOKESLET>), grid, dim3(256), 0, st, y, s, perm, N, g, rec); break;
-        case STRESSLET: hipLaunchKernelGGL((k_records<T, STRESSLET>), grid, dim3(256), 0, st, y, s, perm, N, g, rec); break;
-        default: hipLaunchKernelGGL((k_records<T, ROTLET>), grid, dim3(256), 0, st, y, s, perm, N, g, rec); break;
+        case STOKESLET: hipLaunchKernelGGL((k_records<T, STOKESLET, DG>), grid, dim3(256), 0, st, y, s, perm, N, g, rec); break;
+        case STRESSLET: hipLaunchKernelGGL((k_records<T, STRESSLET, DG>), grid, dim3(256), 0, st, y, s, perm, N, g, rec); break;
+        default: hipLaunchKernelGGL((k_records<T, ROTLET, DG>), grid, dim3(256), 0, st, y, s, perm, N, g, rec); break;
     }
+}
+
+template <typename T>
+hipError_t launch_records(int family, bool dgrid, const double* y, const double* s, const uint32_t* perm, long long N,
+                          GridArgs g, T* rec, hipStream_t st)
+{
+    if (N <= 0) return hipSuccess;
+    if (dgrid)
+        launch_records_t<T, true>(family, y, s, perm, N, g, rec, st);
+    else
+        launch_records_t<T, false>(family, y, s, perm, N, g, rec, st);
     return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
 // spreading: one wavefront (block of 64) per output tile of 8 x 8 x TZ nodes;
-// lane (i, j) owns the column of TZ nodes along x3.
+// lane (i, j) owns the column of TZ nodes along x3.  Output grids: the ncA
+// kernel components, then the correction grids (FP32: ncB of them) or the
+// single density D (FP64), accumulated with derivative weights
+//   w'(d) = -2 a d w(d),  w''(d) = (4 a^2 d^2 - 2 a) w(d),  d = x_g - z.
 // ---------------------------------------------------------------------------
 constexpr int SP_CHUNK = 32;
 
-template <typename T, int K, int TZ>
+template <typename T, int K, int TZ, bool DG>
 __global__ void __launch_bounds__(64) k_spread(GridArgs g, const T* __restrict__ rec,
                                                const uint32_t* __restrict__ toff, T* __restrict__ grids, long long cs)
 {
-    constexpr int ncA = RecLayout<K>::ncA, ncB = RecLayout<K>::ncB, nc = ncA + ncB;
+    constexpr int ncA = RecLayout<K>::ncA, ncB = RecLayout<K>::ncB;
+    constexpr int nout = InGrids<K, DG>::n;
     extern __shared__ unsigned char smem_raw[];
     T* sh = reinterpret_cast<T*>(smem_raw);
     const int P = g.P;
-    const int stride = 16 / sizeof(T) + 3 * P + nc;
+    const int stride = 16 / sizeof(T) + 3 * P + 3 + ncA + ncB;
     const int lane = threadIdx.x;
     const int tx = blockIdx.x, ty = blockIdx.y, tz = blockIdx.z;
     const int i = tx * 8 + (lane & 7), j = ty * 8 + (lane >> 3);
     const int l0 = tz * TZ;
-    T acc[TZ][nc];
+    const T a2 = (T)g.a2, hh = (T)g.h;
+    T acc[TZ][nout];
 #pragma unroll
     for (int z = 0; z < TZ; ++z)
 #pragma unroll
-        for (int c = 0; c < nc; ++c) acc[z][c] = (T)0;
+        for (int c = 0; c < nout; ++c) acc[z][c] = (T)0;
 
     const int x_lo = tx - g.K[0] < 0 ? 0 : tx - g.K[0];
     for (int sz = tz - g.K[2]; sz <= tz; ++sz) {
@@ -211,19 +239,49 @@ __global__ void __launch_bounds__(64) k_spread(GridArgs g, const T* __restrict__
                     int dx = i - hdr[0], dy = j - hdr[1];
                     if ((unsigned)dx < (unsigned)P && (unsigned)dy < (unsigned)P) {
                         const T* w = r + 16 / sizeof(T);
-                        T wxy = w[dx] * w[P + dy];
-                        const T* cv = w + 3 * P;
+                        const T wx = w[dx], wy = w[P + dy];
+                        const T wxy = wx * wy;
+                        const T* off = w + 3 * P;
+                        const T* cv = off + 3;
                         const bool img = hdr[3] != 0;
+                        // D: per-column factors of w(z), w'(z), w''(z)
+                        T fa = 0, fb = 0, fc = 0;
+                        if (DG && img) {
+                            const T ex = off[0] + (T)dx * hh, ey = off[1] + (T)dy * hh;
+                            const T dwx = -2 * a2 * ex * wx, dwy = -2 * a2 * ey * wy;
+                            const T* c = cv + ncA;
+                            if (K == STOKESLET) {
+                                fa = c[0] * wxy + c[1] * dwx * wy + c[2] * wx * dwy;
+                                fb = c[3] * wxy;
+                            } else if (K == STRESSLET) {
+                                const T d2x = (4 * a2 * a2 * ex * ex - 2 * a2) * wx;
+                                const T d2y = (4 * a2 * a2 * ey * ey - 2 * a2) * wy;
+                                fa = c[1] * d2x * wy + c[4] * wx * d2y + 2 * c[2] * dwx * dwy;
+                                fb = c[0] * wxy + 2 * c[3] * dwx * wy + 2 * c[5] * wx * dwy;
+                                fc = c[6] * wxy;
+                            } else {
+                                fa = c[0] * dwx * wy + c[1] * wx * dwy;
+                            }
+                        }
 #pragma unroll
                         for (int z = 0; z < TZ; ++z) {
                             int dz = l0 + z - hdr[2];
                             if ((unsigned)dz < (unsigned)P) {
-                                T wv = wxy * w[2 * P + dz];
+                                const T wz = w[2 * P + dz];
+                                const T wv = wxy * wz;
 #pragma unroll
                                 for (int c = 0; c < ncA; ++c) acc[z][c] += wv * cv[c];
                                 if (img) {
+                                    if (DG) {
+                                        const T ez = off[2] + (T)dz * hh;
+                                        T dsum = fa * wz;
+                                        if (K != ROTLET) dsum += fb * (-2 * a2 * ez * wz);
+                                        if (K == STRESSLET) dsum += fc * ((4 * a2 * a2 * ez * ez - 2 * a2) * wz);
+                                        acc[z][ncA] += dsum;
+                                    } else {
 #pragma unroll
-                                    for (int c = 0; c < ncB; ++c) acc[z][ncA + c] += wv * cv[ncA + c];
+                                        for (int c = 0; c < (DG ? 1 : ncB); ++c) acc[z][ncA + c] += wv * cv[ncA + c];
+                                    }
                                 }
                             }
                         }
@@ -241,24 +299,33 @@ __global__ void __launch_bounds__(64) k_spread(GridArgs g, const T* __restrict__
             if (l < 2 * Mt) {
                 long long node = ((long long)l * Mt + j) * Mt + i;
 #pragma unroll
-                for (int c = 0; c < nc; ++c) grids[c * cs + node] = acc[z][c];
+                for (int c = 0; c < nout; ++c) grids[c * cs + node] = acc[z][c];
             }
         }
     }
 }
 
-template <typename T>
-hipError_t launch_spread(int family, GridArgs g, const T* rec, const uint32_t* toff, T* grids, long long cs,
-                         hipStream_t st)
+template <typename T, bool DG>
+static void launch_spread_t(int family, GridArgs g, const T* rec, const uint32_t* toff, T* grids, long long cs,
+                            hipStream_t st)
 {
     dim3 grid(g.nt[0], g.nt[1], g.nt[2]);
-    int nc = family == STOKESLET ? 7 : family == STRESSLET ? 13 : 5;
-    size_t lds = (size_t)SP_CHUNK * (16 / sizeof(T) + 3 * g.P + nc) * sizeof(T);
+    size_t lds = (size_t)SP_CHUNK * record_stride(family, g.P, sizeof(T)) * sizeof(T);
     switch (family) {
-        case STOKESLET: hipLaunchKernelGGL((k_spread<T, STOKESLET, 8>), grid, dim3(64), lds, st, g, rec, toff, grids, cs); break;
-        case STRESSLET: hipLaunchKernelGGL((k_spread<T, STRESSLET, 4>), grid, dim3(64), lds, st, g, rec, toff, grids, cs); break;
-        default: hipLaunchKernelGGL((k_spread<T, ROTLET, 8>), grid, dim3(64), lds, st, g, rec, toff, grids, cs); break;
+        case STOKESLET: hipLaunchKernelGGL((k_spread<T, STOKESLET, 8, DG>), grid, dim3(64), lds, st, g, rec, toff, grids, cs); break;
+        case STRESSLET: hipLaunchKernelGGL((k_spread<T, STRESSLET, 4, DG>), grid, dim3(64), lds, st, g, rec, toff, grids, cs); break;
+        default: hipLaunchKernelGGL((k_spread<T, ROTLET, 8, DG>), grid, dim3(64), lds, st, g, rec, toff, grids, cs); break;
     }
+}
+
+template <typename T>
+hipError_t launch_spread(int family, bool dgrid, GridArgs g, const T* rec, const uint32_t* toff, T* grids, long long cs,
+                         hipStream_t st)
+{
+    if (dgrid)
+        launch_spread_t<T, true>(family, g, rec, toff, grids, cs, st);
+    else
+        launch_spread_t<T, false>(family, g, rec, toff, grids, cs, st);
     return hipGetLastError();
 }
 
@@ -354,13 +421,14 @@ hipError_t launch_gather(GridArgs g, const T* grids, long long cs, const double*
     return hipGetLastError();
 }
 
-template hipError_t launch_records<double>(int, const double*, const double*, const uint32_t*, long long, GridArgs,
-                                           double*, hipStream_t);
-template hipError_t launch_records<float>(int, const double*, const double*, const uint32_t*, long long, GridArgs,
-                                          float*, hipStream_t);
-template hipError_t launch_spread<double>(int, GridArgs, const double*, const uint32_t*, double*, long long,
+template hipError_t launch_records<double>(int, bool, const double*, const double*, const uint32_t*, long long,
+                                           GridArgs, double*, hipStream_t);
+template hipError_t launch_records<float>(int, bool, const double*, const double*, const uint32_t*, long long,
+                                          GridArgs, float*, hipStream_t);
+template hipError_t launch_spread<double>(int, bool, GridArgs, const double*, const uint32_t*, double*, long long,
                                           hipStream_t);
-template hipError_t launch_spread<float>(int, GridArgs, const float*, const uint32_t*, float*, long long, hipStream_t);
+template hipError_t launch_spread<float>(int, bool, GridArgs, const float*, const uint32_t*, float*, long long,
+                                         hipStream_t);
 template hipError_t launch_gather<double>(GridArgs, const double*, long long, const double*, const uint32_t*,
                                           long long, const double*, double*, hipStream_t);
 template hipError_t launch_gather<float>(GridArgs, const float*, long long, const double*, const uint32_t*, long long,

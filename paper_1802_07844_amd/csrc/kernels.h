@@ -55,7 +55,7 @@ struct EvenArgs {
     double scale;
 };
 
-size_t z_lds_bytes(int family, int Mt, int Q, size_t esz);
+size_t z_lds_bytes(int family, bool dgrid, int Mt, int Q, size_t esz);
 bool z_resident_ok(int family, int Mt);
 
 template <typename T>
@@ -67,7 +67,7 @@ hipError_t launch_inv_y(const cplx<T>* in, cplx<T>* out, const PassArgs& a, int 
 template <typename T>
 hipError_t launch_inv_x(const cplx<T>* in, T* out, const PassArgs& a, int ncomp, hipStream_t st);
 template <typename T>
-hipError_t launch_z(int family, cplx<T>* zb, cplx<T>* zout, const ZArgs& a, bool res, hipStream_t st);
+hipError_t launch_z(int family, bool dgrid, cplx<T>* zb, cplx<T>* zout, const ZArgs& a, bool res, hipStream_t st);
 hipError_t launch_even_line(const double* in, double* out, const EvenArgs& a, hipStream_t st);
 hipError_t launch_oct_to_f32(const double* in, float* out, long long n, hipStream_t st);
 template <typename T>
@@ -150,10 +150,10 @@ hipError_t launch_point_keys(const double* y, long long N, GridArgs g, uint32_t*
 // records of the sorted points (base, 1D weights, strengths) in precision T
 size_t record_stride(int family, int P, size_t esz);
 template <typename T>
-hipError_t launch_records(int family, const double* y, const double* s, const uint32_t* perm, long long N, GridArgs g,
+hipError_t launch_records(int family, bool dgrid, const double* y, const double* s, const uint32_t* perm, long long N, GridArgs g,
                           T* rec, hipStream_t st);
 template <typename T>
-hipError_t launch_spread(int family, GridArgs g, const T* rec, const uint32_t* toff, T* grids, long long cs,
+hipError_t launch_spread(int family, bool dgrid, GridArgs g, const T* rec, const uint32_t* toff, T* grids, long long cs,
                          hipStream_t st);
 template <typename T>
 hipError_t launch_gather(GridArgs g, const T* grids, long long cs, const double* x, const uint32_t* tperm,

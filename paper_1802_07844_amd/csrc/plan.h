@@ -100,7 +100,6 @@ inline int bits_for(long long nkeys)
     return b;
 }
 
-inline int ncomp_in(int family) { return family == 0 ? 7 : family == 1 ? 13 : 5; }
 
 // relative truncation estimates (paper Tables 1 and 2), sources and images
 // counted, normalised by sqrt(Q)/L; R in Table 1 taken as sqrt(6) L
@@ -147,6 +146,7 @@ struct PlanInput {
     int force_M, force_P, force_Mt;
     int force_zg;  // > 0: k1 slabs per group of the y / x3 pipeline
     int gather_extra;  // >= 0: extra gather support nodes (even); < 0: default
+    int dgrid;         // 1 / 0: force the correction density D on / off; < 0: by cost
 };
 
 struct Plan {
@@ -154,7 +154,8 @@ struct Plan {
     long long N, T;
     double xi, rc, tol;
     double L, h, Lt, eta, Q;
-    int M, P, Pg, Mt, Qz, nf, nf3, ncin;
+    int M, P, Ps, Pg, Mt, Qz, nf, nf3, ncin;
+    bool dgrid;  // the correction sources are spread as one density D
     bool resident;
     double est_r, est_f, est32;
     CellGeom cg;
@@ -193,7 +194,6 @@ inline int make_plan(const PlanInput& in, Plan* out)
     p.rc = in.rc;
     p.tol = in.tol;
     p.Q = in.Q;
-    p.ncin = ncomp_in(in.family);
     {
         // FP32 rounding error of the grid path for uniform point sets, fitted
         // to the error at typical targets (FP32 minus FP64 under one plan):
@@ -236,7 +236,12 @@ inline int make_plan(const PlanInput& in, Plan* out)
     // (FP64 only: the FP32 path transforms the gradient spectrally)
     int Pg = P + (in.gather_extra >= 0 ? in.gather_extra : (p.prec == 1 ? 2 : 0));
     if (Pg > 30 || (Pg & 1)) return -1;
-    const int Pe = std::max(P, Pg);
+    // spreading support: P, or P + 2 (P + 6 for the stresslet's second
+    // derivatives) when the correction density D is spread with derivative
+    // weights; the choice is made below, once M~ is known
+    const int Pd = P + (in.family == 1 ? 6 : 2);
+    if (Pd > 30) return -1;
+    const int Pe = std::max(std::max(P, Pg), (p.prec == 1 && in.dgrid != 0) ? Pd : P);
     // grid intervals over the box
     int M = in.force_M;
     if (M <= 0) {
@@ -259,6 +264,25 @@ inline int make_plan(const PlanInput& in, Plan* out)
     p.M = M;
     p.P = P;
     p.Pg = Pg;
+    // D-grid spreading (FP64): saves (ncB - 1) forward transform components
+    // of the grid at the price of (Pd^3 - P^3) more spreading work per point;
+    // the unit costs are those measured on MI355X for the two passes (about
+    // 10 ms per component at M~ = 480 and 4.4 ns per point and P^3 node)
+    {
+        bool dg = false;
+        // (the stresslet only on request: its second-derivative weights have
+        // not been shown to hold 1e-10 at its support)
+        if (p.prec == 1 && in.dgrid != 0 && (in.family != 1 || in.dgrid > 0)) {
+            int ncB = in.family == 0 ? 4 : in.family == 1 ? 7 : 2;
+            double save = 10.0 * std::pow(Mt / 480.0, 3) * (ncB - 1);
+            double cost = 4.4e-9 * 2.0 * (double)in.N * ((double)Pd * Pd * Pd - (double)P * P * P) *
+                          (in.family == 1 ? 2.0 : 1.0);
+            dg = in.dgrid > 0 || save > cost;
+        }
+        p.dgrid = dg;
+        p.Ps = dg ? Pd : P;
+        p.ncin = ncin_for(in.family, dg);
+    }
     p.Mt = Mt;
     p.h = h;
     p.Lt = Mt * h;
@@ -282,7 +306,7 @@ inline int make_plan(const PlanInput& in, Plan* out)
         int nq = 4 * Mt / Q;
         if (!smooth7(nq)) continue;
         if (nq > lds_fft_cap(nq, 64)) continue;  // one line per wavefront
-        if (z_lds_bytes(in.family, Mt, Q, esz) > 150 * 1024) continue;
+        if (z_lds_bytes(in.family, p.dgrid, Mt, Q, esz) > 150 * 1024) continue;
         p.Qz = Q;
         break;
     }
@@ -319,13 +343,13 @@ inline int make_plan(const PlanInput& in, Plan* out)
     // spreading tiles
     GridArgs& g = p.g;
     g.Mt = Mt;
-    g.P = P;
+    g.P = p.Ps;
     g.o[0] = in.lo[0] - Pe * h / 2;
     g.o[1] = in.lo[1] - Pe * h / 2;
     g.o[2] = -p.Lt;
     g.h = h;
     g.a2 = 2 * xi * xi / eta;
-    g.mP = magic_of((unsigned)P);
+    g.mP = magic_of((unsigned)p.Ps);
     g.pref = std::pow(2 * xi * xi / (pi * eta), 1.5);
     int tz = in.family == 1 ? 4 : 8;
     int dims[3] = {Mt, Mt, 2 * Mt};
@@ -334,7 +358,7 @@ inline int make_plan(const PlanInput& in, Plan* out)
     for (int a = 0; a < 3; ++a) {
         g.tile[a] = tl[a];
         g.nt[a] = (dims[a] + tl[a] - 1) / tl[a];
-        g.K[a] = (P - 1 + tl[a] - 1) / tl[a];
+        g.K[a] = (p.Ps - 1 + tl[a] - 1) / tl[a];
         p.ntiles *= g.nt[a];
     }
     p.gg = g;

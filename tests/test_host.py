@@ -195,3 +195,21 @@ def test_fp32_estimate_and_auto_precision():
     # the rotlet's rounding does not grow with xi: FP32 stays available
     rot = ehs.plan_query("rotlet", 10**5, 10**5, lo, hi, 3e5, 118.0, 0.0415, 1e-5, 0)
     assert rot.precision == 2
+
+
+@pytest.mark.parametrize("dgrid", [0, 1])
+def test_record_region_holds_the_spreading_support(dgrid):
+    """The workspace's record region is sized with the spreading support the
+    kernels use (P + 2 when the correction
+    density is spread with derivative weights): the audit passes, and the
+    reported workspace grows with the record stride."""
+    n = 100_000
+    for fam in ("stokeslet", "stresslet", "rotlet"):
+        rc = (30 * 3.0 / (4.0 * math.pi * n)) ** (1.0 / 3.0)
+        xi = ehs.xi_for_cutoff(fam, rc, 0.5e-10)
+        r = ehs.plan_query(fam, n, n, (0, 0, 0), (1, 1, 1), 3.0 * n, xi, rc, 1e-10, 1)
+        assert r.Ps == (r.P + 2 if r.dgrid else r.P)
+        assert not (fam == "stresslet" and r.dgrid)  # the stresslet only on request
+        assert r.Pg == r.P + 2 and r.Mt >= r.M + max(r.Ps, r.Pg)
+        stride = 2 + 3 * r.Ps + 3 + {"stokeslet": 7, "stresslet": 13, "rotlet": 5}[fam]
+        assert r.workspace_bytes >= 2 * n * stride * 8
