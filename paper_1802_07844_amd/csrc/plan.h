@@ -270,8 +270,9 @@ inline int make_plan(const PlanInput& in, Plan* out)
     // 10 ms per component at M~ = 480 and 4.4 ns per point and P^3 node)
     {
         bool dg = false;
-        // (the stresslet only on request: its second-derivative weights have
-        // not been shown to hold 1e-10 at its support)
+        // (the stresslet only on request: with its second-derivative weights
+        // the error stays near 1e-10 at N = 1e5 whatever the support, so
+        // the finer structure of that density needs a finer grid)
         if (p.prec == 1 && in.dgrid != 0 && (in.family != 1 || in.dgrid > 0)) {
             int ncB = in.family == 0 ? 4 : in.family == 1 ? 7 : 2;
             double save = 10.0 * std::pow(Mt / 480.0, 3) * (ncB - 1);
