@@ -41,13 +41,27 @@ __global__ void __launch_bounds__(XPASS_NT, 4) k_fwd_x(const T* __restrict__ in,
     const cplx<T>* tw2 = static_cast<const cplx<T>*>(a.tw2);
     const T* src = in + (long long)c * a.cs_in + ((long long)l * Mt + j0) * Mt;
     const int np = B / 2;
-    for (int f = threadIdx.x; f < np * Mt; f += XPASS_NT) {
-        int p = fdiv(f, Mt, a.mMt), i = f - p * Mt;
-        T va = (2 * p < nb) ? src[(2 * p) * Mt + i] : (T)0;
-        T vb = (2 * p + 1 < nb) ? src[(2 * p + 1) * Mt + i] : (T)0;
-        cplx<T> z = cmk<T>(va, vb);
-        buf[(2 * p) * ld + i] = z;
-        buf[(2 * p + 1) * ld + i] = cmul(z, tw2[i]);
+    constexpr int LB = 4;  // independent loads in flight per thread
+    for (int f0 = threadIdx.x; f0 < np * Mt; f0 += LB * XPASS_NT) {
+        T va[LB], vb[LB];
+#pragma unroll
+        for (int u = 0; u < LB; ++u) {
+            int f = f0 + u * XPASS_NT;
+            int p = fdiv(f, Mt, a.mMt), i = f - p * Mt;
+            const bool ok = f < np * Mt;
+            va[u] = (ok && 2 * p < nb) ? src[(2 * p) * Mt + i] : (T)0;
+            vb[u] = (ok && 2 * p + 1 < nb) ? src[(2 * p + 1) * Mt + i] : (T)0;
+        }
+#pragma unroll
+        for (int u = 0; u < LB; ++u) {
+            int f = f0 + u * XPASS_NT;
+            if (f < np * Mt) {
+                int p = fdiv(f, Mt, a.mMt), i = f - p * Mt;
+                cplx<T> z = cmk<T>(va[u], vb[u]);
+                buf[(2 * p) * ld + i] = z;
+                buf[(2 * p + 1) * ld + i] = cmul(z, tw2[i]);
+            }
+        }
     }
     __syncthreads();
     lds_fft<T, XPASS_NT, PASS_E, false>(buf, ld, B, a.fM);
@@ -137,9 +151,25 @@ __global__ void __launch_bounds__(PASS_NT) k_inv_y(const cplx<T>* __restrict__ i
     const cplx<T>* src = in + (long long)c * a.cs_in + (long long)k1l * nl * nl + l0;
     cplx<T> acc[MAXR];
     for (int s = 0; s < 2; ++s) {
-        for (int f = threadIdx.x; f < Mt * B; f += PASS_NT) {
-            int m = fdiv(f, B, a.mB), b = f - m * B;
-            buf[b * ld + m] = (b < nb) ? src[(long long)(2 * m + s) * nl + b] : cmk<T>(0, 0);
+        // rows of B values (one 128-byte segment) spread over 2Mt rows: issue
+        // LB independent loads per thread before their LDS stores
+        constexpr int LB = 4;
+        for (int f0 = threadIdx.x; f0 < Mt * B; f0 += LB * PASS_NT) {
+            cplx<T> v[LB];
+#pragma unroll
+            for (int u = 0; u < LB; ++u) {
+                int f = f0 + u * PASS_NT;
+                int m = fdiv(f, B, a.mB), b = f - m * B;
+                v[u] = (f < Mt * B && b < nb) ? src[(long long)(2 * m + s) * nl + b] : cmk<T>(0, 0);
+            }
+#pragma unroll
+            for (int u = 0; u < LB; ++u) {
+                int f = f0 + u * PASS_NT;
+                if (f < Mt * B) {
+                    int m = fdiv(f, B, a.mB), b = f - m * B;
+                    buf[b * ld + m] = v[u];
+                }
+            }
         }
         __syncthreads();
         lds_fft<T, PASS_NT, PASS_E, true>(buf, ld, B, a.fM);
@@ -351,7 +381,7 @@ struct ZWaves {
 };
 
 template <typename T, int K, int EPL, bool DG>
-__global__ void __launch_bounds__((64 * ZWaves<T, K, DG>::n)) k_z_scale(const cplx<T>* zb, cplx<T>* zout, ZArgs a)
+__global__ void __launch_bounds__((64 * ZWaves<T, K, DG>::n), 2) k_z_scale(const cplx<T>* zb, cplx<T>* zout, ZArgs a)
 {
     constexpr int ZW = ZWaves<T, K, DG>::n;
     constexpr int Z_NT = 64 * ZW;
@@ -426,15 +456,29 @@ __global__ void __launch_bounds__((64 * ZWaves<T, K, DG>::n)) k_z_scale(const cp
                         }
                     }
                 } else {
-                    for (int lp = lane; lp < nq; lp += 64) {
-                        const int l = lp + h * nq;
-                        cplx<T> v = zb[c * cs + base + l];
-                        if (s) {
-                            int ti = s * l;
-                            ti -= fdiv(ti, n4, mn4) * n4;
-                            v = cmul(v, tw4[ti]);
+                    // LB independent loads per lane before the stores
+                    constexpr int LB = 4;
+                    for (int lp0 = lane; lp0 < nq; lp0 += LB * 64) {
+                        cplx<T> v[LB];
+#pragma unroll
+                        for (int u = 0; u < LB; ++u) {
+                            const int lp = lp0 + u * 64;
+                            v[u] = lp < nq ? zb[c * cs + base + lp + h * nq] : cmk<T>(0, 0);
                         }
-                        line[lp] = h ? cadd(line[lp], v) : v;
+#pragma unroll
+                        for (int u = 0; u < LB; ++u) {
+                            const int lp = lp0 + u * 64;
+                            if (lp < nq) {
+                                const int l = lp + h * nq;
+                                cplx<T> x = v[u];
+                                if (s) {
+                                    int ti = s * l;
+                                    ti -= fdiv(ti, n4, mn4) * n4;
+                                    x = cmul(x, tw4[ti]);
+                                }
+                                line[lp] = h ? cadd(line[lp], x) : x;
+                            }
+                        }
                     }
                 }
             }
