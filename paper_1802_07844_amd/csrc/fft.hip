@@ -211,11 +211,23 @@ __global__ void __launch_bounds__(XPASS_NT, 4) k_inv_x(const cplx<T>* __restrict
     const int hB = B / 2;
     // Z_p[k] = Ya[k] + i Yb[k] over the full padded range k < 2Mt; the
     // position k = 2m + s is stored at buf[(2p + s) * ld + m].
+    constexpr int LB = 4;  // independent loads in flight per thread
     for (int part = 0; part < 2; ++part) {
-        for (int f = threadIdx.x; f < (Mt + 1) * hB; f += XPASS_NT) {
+        for (int f0 = threadIdx.x; f0 < (Mt + 1) * hB; f0 += LB * XPASS_NT) {
+          cplx<T> vv[LB];
+#pragma unroll
+          for (int u = 0; u < LB; ++u) {
+            int f = f0 + u * XPASS_NT;
             int k = fdiv(f, hB, a.mB2), p = f - k * hB;
             int b = 2 * p + part;
-            cplx<T> v = (b < nb) ? src[k * rowk + b] : cmk<T>(0, 0);
+            vv[u] = (f < (Mt + 1) * hB && b < nb) ? src[k * rowk + b] : cmk<T>(0, 0);
+          }
+#pragma unroll
+          for (int u = 0; u < LB; ++u) {
+            int f = f0 + u * XPASS_NT;
+            if (f >= (Mt + 1) * hB) break;
+            int k = fdiv(f, hB, a.mB2), p = f - k * hB;
+            cplx<T> v = vv[u];
             if (k == 0 || k == Mt) v.y = 0;  // self-conjugate bins are real
             cplx<T> w1 = part ? cmul_pi(v) : v;
             int s = k & 1, m = k >> 1;
@@ -228,6 +240,7 @@ __global__ void __launch_bounds__(XPASS_NT, 4) k_inv_x(const cplx<T>* __restrict
                 cplx<T>* d2 = &buf[(2 * p + (k2 & 1)) * ld + (k2 >> 1)];
                 *d2 = part ? cadd(*d2, w2) : w2;
             }
+          }
         }
         __syncthreads();
     }

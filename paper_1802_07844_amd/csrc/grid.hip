@@ -229,9 +229,17 @@ __global__ void __launch_bounds__(64) k_spread(GridArgs g, const T* __restrict__
             uint32_t r0 = toff[row + x_lo], r1 = toff[row + tx + 1];
             for (uint32_t c0 = r0; c0 < r1; c0 += SP_CHUNK) {
                 int nr = (int)min((uint32_t)SP_CHUNK, r1 - c0);
-                // stage the records of this chunk
+                // stage the records of this chunk (8 independent loads per lane
+                // in flight before the LDS stores)
                 const T* src = rec + (long long)c0 * stride;
-                for (int f = lane; f < nr * stride; f += 64) sh[f] = src[f];
+                for (int f0 = lane; f0 < nr * stride; f0 += 8 * 64) {
+                    T v[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) v[u] = (f0 + 64 * u < nr * stride) ? src[f0 + 64 * u] : (T)0;
+#pragma unroll
+                    for (int u = 0; u < 8; ++u)
+                        if (f0 + 64 * u < nr * stride) sh[f0 + 64 * u] = v[u];
+                }
                 __syncthreads();
                 for (int q = 0; q < nr; ++q) {
                     const T* r = sh + q * stride;
@@ -375,6 +383,7 @@ __global__ void __launch_bounds__(256) k_gather(GridArgs g, const T* __restrict_
     if (row < rows) {
         const T wx = wsh[wv][xi];
         const T dx = GQ ? dsh[wv][xi] : (T)0;
+#pragma unroll 4
         for (int rr = row; rr < P * P; rr += rows) {
             int dz = fdiv(rr, P, g.mP), dy = rr - dz * P;
             const T wy = wsh[wv][P + dy], wz = wsh[wv][2 * P + dz];
