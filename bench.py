@@ -77,6 +77,14 @@ def _measured_traffic(name):
     return None
 
 
+def _ncin(rep):
+    """Input grids of the plan: the kernel grid and either the correction
+    density (FP64 D-grid plans) or the separate correction grids."""
+    nca = 6 if rep.family == 1 else 3
+    ncb = {0: 4, 1: 7, 2: 2}[rep.family]
+    return nca + (1 if rep.dgrid else ncb)
+
+
 def _roofline(rep, stage_ms, ncin, esz, traffic_file=None):
     sb = _stage_bytes(rep, ncin, esz)
     dom = max(sb.keys(), key=lambda k: stage_ms[k])
@@ -299,7 +307,7 @@ def main():
 
     # dominant kernel and its roofline: algorithmic bytes per launch / average
     # launch duration (HIP events on the evaluation's stream)
-    roofline = _roofline(rep, stage_ms, 7, 8, "z_scale_stokeslet_N100k_fp64_counters.md")
+    roofline = _roofline(rep, stage_ms, _ncin(rep), 8, "z_scale_stokeslet_N100k_fp64_counters.md")
 
     result = {
         "metric": "points/sec at rel-RMS 1e-10 (FP64)",
@@ -317,7 +325,8 @@ def main():
         "config": {"workload": f"half-space stokeslet, N={n} sources=targets uniform in [0,1)^2x(0,1], "
                                f"forces N(0,1), FP64 tol 1e-10, ~{args.neighbours:g} neighbours",
                    "N": n, "xi": xi, "r_c": rc, "tol": tol, "M": rep.M, "P": rep.P, "Mt": rep.Mt,
-                   "eta": rep.eta, "zslab": rep.zslab, "seed": seed},
+                   "eta": rep.eta, "zslab": rep.zslab, "Ps": rep.Ps, "Pg": rep.Pg, "dgrid": rep.dgrid,
+                   "seed": seed},
         "stage_ms": stage_ms,
         "roofline": roofline,
     }
@@ -349,7 +358,7 @@ def main():
         result["fp32"] = {"value": n * args.steps / dt32, "unit": "points/s", "ms_per_step": dt32 / args.steps * 1e3,
                           "dtype": "f32", "tol": tol32, "xi": xi32, "r_c": rc32, "neighbours": args.fp32_neighbours,
                           "M": r32.M, "P": r32.P, "Mt": r32.Mt, "stage_ms": sm32,
-                          "roofline": _roofline(r32, sm32, 7, 4)}
+                          "roofline": _roofline(r32, sm32, _ncin(r32), 4)}
 
     # oracle on the host cores: a bounded sample of targets against all sources
     if not args.no_cpu_baseline:
