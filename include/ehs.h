@@ -109,6 +109,9 @@ typedef struct ehs_report {
     int32_t Ps;             /* Gaussian support of the spreading (>= P) */
     int32_t dgrid;          /* 1: correction sources spread as one density (FP64) */
     double est_fp32;        /* estimated FP32 rounding error (relative RMS, uniform point sets) */
+    int32_t x3_first;       /* first x3 grid node the inverse transforms produce: the quadrature
+                               of the lowest target reads no node below it */
+    int32_t reserved;
 } ehs_report;
 
 /* Create a context on HIP device `hip_device`.  `arena_bytes` is reserved

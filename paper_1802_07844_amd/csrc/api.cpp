@@ -252,7 +252,7 @@ int ensure_octants(ehs_ctx* c, const Plan& p, hipStream_t st, bool* ran, Octants
 // workspace layout
 // ---------------------------------------------------------------------------
 struct Layout {
-    size_t X, Y, ZS, Zo, rec, keys, sortsc, toff, soff, tgoff, chunks, ys, ss, xs, upart, bb, total;
+    size_t X, Y, ZS, Zo, rec, keys, sortsc, toff, soff, tgoff, chunks, ys, ss, xs, upart, bb, ez, total;
 };
 
 // Host-side audit: the largest extent every pass writes or reads must fit the
@@ -269,7 +269,7 @@ int check_extents(const Plan& p, const Layout& L, size_t esz)
     const size_t nout = (size_t)ncout_for(p.prec);
     const size_t xreg = L.Y - L.X, yreg = L.ZS - L.Y, zsreg = L.Zo - L.ZS, zoreg = L.rec - L.Zo;
     auto fits = [](size_t need, size_t have) { return need <= have; };
-    bool ok = p.zg >= 1 && p.zg <= p.Mt + 1
+    bool ok = p.zg >= 1 && p.zg <= p.Mt + 1 && p.l3lo >= 0 && p.l3lo < 2 * p.Mt
               && fits(nin * real, xreg)                 // spread -> X
               && fits(nin * a, yreg)                    // forward x1 -> Y
               && fits(nin * zs, zsreg)                  // forward x2 -> slab buffer
@@ -283,7 +283,8 @@ int check_extents(const Plan& p, const Layout& L, size_t esz)
               && fits((size_t)(p.ncell + 1) * 4, L.chunks - L.tgoff)
               && fits((size_t)(2 * p.ncell + 2 * p.max_chunks + 1) * 4, L.ys - L.chunks)
               && fits((size_t)3 * p.N * 8, L.ss - L.ys) && fits((size_t)6 * p.N * 8, L.xs - L.ss)
-              && fits((size_t)3 * p.T * 8, L.upart - L.xs) && fits((size_t)3 * p.T * 8, L.bb - L.upart);
+              && fits((size_t)3 * p.T * 8, L.upart - L.xs) && fits((size_t)3 * p.T * 8, L.bb - L.upart)
+              && fits((size_t)(2 * Mt + 1) * 8, L.total - L.ez);
     // precompute scratch in X
     size_t h1 = p.nf / 2 + 1;
     ok = ok && fits((h1 * h1 * (2 * Mt + 1) + h1 * (Mt + 1) * (2 * Mt + 1)) * 8, xreg);
@@ -341,6 +342,7 @@ Layout layout(const Plan& p, size_t esz)
     L.xs = off; off += al((size_t)3 * T * sizeof(double));
     L.upart = off; off += al((size_t)3 * T * sizeof(double));
     L.bb = off; off += al((size_t)(1024 * 10 + 16) * sizeof(double));
+    L.ez = off; off += al((size_t)(2 * Mt + 1) * sizeof(double));
     L.total = off;
     return L;
 }
@@ -501,6 +503,9 @@ int run(ehs_ctx* c, Plan& p, const Octants& oct, const double* y, const double* 
     za.octB32 = oct.B32;
     za.octH32 = oct.H32;
     za.near0 = 2;
+    double* ez = reinterpret_cast<double*>(base + Lo.ez);
+    HIPCHK(launch_exp_table(ez, 2 * p.Mt + 1, za.c_exp, za.dk3, st));
+    za.ez = ez;
     cplx<T>* ZS = reinterpret_cast<cplx<T>*>(base + Lo.ZS);
     cplx<T>* ZO = p.resident ? ZS : reinterpret_cast<cplx<T>*>(base + Lo.Zo);
     const int ngroups = (p.Mt + p.zg) / p.zg;
@@ -516,6 +521,7 @@ int run(ehs_ctx* c, Plan& p, const Octants& oct, const double* y, const double* 
         HIPCHK(hipEventRecord(c->sev[c->nsev++], st));
     }
     set_b(p.By);
+    za.l3lo = p.l3lo;
     for (int k0 = 0; k0 <= p.Mt; k0 += p.zg) {
         const int cnt = std::min(p.zg, p.Mt + 1 - k0);
         pa.k1base = k0;
@@ -530,7 +536,9 @@ int run(ehs_ctx* c, Plan& p, const Octants& oct, const double* y, const double* 
         if (slab_ev) HIPCHK(hipEventRecord(c->sev[c->nsev++], st));
         pa.cs_in = csS;
         pa.cs_out = csA;
+        pa.l3lo = p.l3lo;
         HIPCHK(launch_inv_y<T>(ZO, Yc, pa, Out<T>::n, st));
+        pa.l3lo = 0;
         if (slab_ev) HIPCHK(hipEventRecord(c->sev[c->nsev++], st));
     }
     rec_ev(EHS_ST_ZSCALE);
@@ -540,6 +548,7 @@ int run(ehs_ctx* c, Plan& p, const Octants& oct, const double* y, const double* 
     set_b(p.Bx);
     pa.cs_in = csA;
     pa.cs_out = csR;
+    pa.l3lo = p.l3lo;
     HIPCHK(launch_inv_x<T>(Yc, X, pa, Out<T>::n, st));
     rec_ev(EHS_ST_GATHER);
 
@@ -598,6 +607,7 @@ int ehs::plan_request(ehs_ctx* c, int family, const double* y, const double* s, 
     in.force_zg = c->force_zg;
     in.gather_extra = c->gather_extra;
     in.dgrid = c->dgrid;
+    in.tlo3 = T > 0 ? b[7] : 0.0;
     return make_plan(in, p);
 }
 
@@ -649,6 +659,7 @@ void ehs::fill_report(const Plan& p, ehs_report* r)
     r->Ps = p.Ps;
     r->dgrid = p.dgrid ? 1 : 0;
     r->est_fp32 = p.est32;
+    r->x3_first = p.l3lo;
 }
 
 namespace {
@@ -876,6 +887,7 @@ int ehs_plan_query(int family, int64_t N, int64_t T, const double* lo, const dou
     in.prec = precision;
     in.gather_extra = -1;
     in.dgrid = -1;
+    in.tlo3 = std::max(lo[2], 0.0);  // lowest point of the box: no target lies lower
     Plan p;
     int rc = make_plan(in, &p);
     if (rc) return rc;

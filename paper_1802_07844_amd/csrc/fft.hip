@@ -136,7 +136,8 @@ __global__ void __launch_bounds__(PASS_NT) k_fwd_y(const cplx<T>* __restrict__ i
 // ---------------------------------------------------------------------------
 // inverse y pass: lines along k2 (2Mt values, stride 2Mt), keep j < Mt; the
 // even and odd k2 halves are transformed one after the other and combined in
-// registers.  output D[k1][l][j].  grid: (ceil(2Mt / B), Mt + 1, ncomp)
+// registers.  output D[k1][l][j] for l >= l3lo.
+// grid: (ceil((2Mt - l3lo) / B), nk1, ncomp)
 // ---------------------------------------------------------------------------
 template <typename T, int MAXR>
 __global__ void __launch_bounds__(PASS_NT) k_inv_y(const cplx<T>* __restrict__ in, cplx<T>* __restrict__ out, PassArgs a)
@@ -144,7 +145,7 @@ __global__ void __launch_bounds__(PASS_NT) k_inv_y(const cplx<T>* __restrict__ i
     extern __shared__ unsigned char smem_raw[];
     cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
     const int Mt = a.Mt, B = a.B, ld = Mt + 1;
-    const int l0 = blockIdx.x * B, k1l = blockIdx.y, k1 = a.k1base + k1l, c = blockIdx.z;
+    const int l0 = a.l3lo + blockIdx.x * B, k1l = blockIdx.y, k1 = a.k1base + k1l, c = blockIdx.z;
     const int nl = 2 * Mt;
     const int nb = min(B, nl - l0);
     const cplx<T>* tw2 = static_cast<const cplx<T>*>(a.tw2);
@@ -195,7 +196,7 @@ __global__ void __launch_bounds__(PASS_NT) k_inv_y(const cplx<T>* __restrict__ i
 // ---------------------------------------------------------------------------
 // inverse x pass (complex-to-real): lines along k1 (Mt + 1 values of the half
 // spectrum), keep i < Mt.  Two real output lines share one complex line.
-// output R[l][j][i].  grid: (ceil(Mt / B), 2Mt, ncomp); B even.
+// output R[l][j][i] for l >= l3lo.  grid: (ceil(Mt / B), 2Mt - l3lo, ncomp); B even.
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ void __launch_bounds__(XPASS_NT, 4) k_inv_x(const cplx<T>* __restrict__ in, T* __restrict__ out, PassArgs a)
@@ -203,7 +204,7 @@ __global__ void __launch_bounds__(XPASS_NT, 4) k_inv_x(const cplx<T>* __restrict
     extern __shared__ unsigned char smem_raw[];
     cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
     const int Mt = a.Mt, B = a.B, ld = Mt + 1;
-    const int j0 = blockIdx.x * B, l = blockIdx.y, c = blockIdx.z;
+    const int j0 = blockIdx.x * B, l = a.l3lo + blockIdx.y, c = blockIdx.z;
     const int nb = min(B, Mt - j0);
     const cplx<T>* tw2 = static_cast<const cplx<T>*>(a.tw2);
     const cplx<T>* src = in + (long long)c * a.cs_in + (long long)l * Mt + j0;
@@ -380,10 +381,12 @@ __device__ __forceinline__ void apply_mult(const cplx<U>* X, cplx<U>* Y, U kx, U
 // transforms and unfolding of a component touch only its own LDS line, so
 // they run at wavefront scope without block barriers and the waves proceed
 // independently; only the scaling, which couples the components at each k,
-// is bracketed by two block barriers per phase.  EPL > 0: each lane holds
-// its EPL output elements (l = lane + 64 e) in registers, and its input
-// elements too when they fit (HOLD), so inputs are read once and outputs
-// written once; EPL = 0: inputs re-read and outputs accumulated in zout.
+// is bracketed by two block barriers per phase.  Outputs are produced for
+// l >= l3lo only (the nodes the quadrature reads).  EPL > 0: each lane holds
+// its EPL output elements (l = l3lo + lane + 64 e) in registers, and with
+// HOLD its 2 EPL input elements (l = lane + 64 e) too, so inputs are read
+// once and outputs written once; EPL = 0: inputs re-read and outputs
+// accumulated in zout.
 // grid: (2Mt, nk1)
 // ---------------------------------------------------------------------------
 // wavefronts per block: one per line, at most 8
@@ -393,7 +396,18 @@ struct ZWaves {
     static constexpr int n = lines < 8 ? lines : 8;
 };
 
-template <typename T, int K, int EPL, bool DG>
+// inputs held in registers (HOLD): 2 EPL elements per lane cover the whole
+// input line when 128 EPL >= 2Mt; only where they fit a register budget of
+// 32 per lane (more spills in the FP64 variants)
+template <typename T, int K, bool DG, int EPL>
+constexpr bool z_hold_fits()
+{
+    constexpr int zw = ZWaves<T, K, DG>::n;
+    constexpr int cpw = (InGrids<K, DG>::n + zw - 1) / zw;
+    return EPL > 0 && EPL <= 8 && cpw * 2 * EPL * (int)sizeof(cplx<T>) <= 128;
+}
+
+template <typename T, int K, int EPL, bool HOLD, bool DG>
 __global__ void __launch_bounds__((64 * ZWaves<T, K, DG>::n), 2) k_z_scale(const cplx<T>* zb, cplx<T>* zout, ZArgs a)
 {
     constexpr int ZW = ZWaves<T, K, DG>::n;
@@ -402,8 +416,9 @@ __global__ void __launch_bounds__((64 * ZWaves<T, K, DG>::n), 2) k_z_scale(const
     constexpr int NCOUT = Out<T>::n;
     constexpr bool GQ = Out<T>::grad_quad;
     constexpr int CPW = (ncin + ZW - 1) / ZW;  // input components per wavefront
-    constexpr bool HOLD = EPL > 0 && CPW * EPL * (int)sizeof(cplx<T>) <= 128;
-    constexpr int NX = HOLD ? CPW * EPL : 1;
+    static_assert(!HOLD || z_hold_fits<T, K, DG, EPL>(), "held inputs exceed the register budget");
+    constexpr int EPI = HOLD ? 2 * EPL : 1;  // held input elements per lane and component
+    constexpr int NX = HOLD ? CPW * EPI : 1;
     constexpr int NY = EPL > 0 ? EPL : 1;
     extern __shared__ unsigned char smem_raw[];
     cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
@@ -416,6 +431,7 @@ __global__ void __launch_bounds__((64 * ZWaves<T, K, DG>::n), 2) k_z_scale(const
     const cplx<T>* tw4 = static_cast<const cplx<T>*>(a.tw4);
     const unsigned mnq = a.mnq, mn4 = a.mn4;
     const int nh = nz / nq;  // 1 (Q = 2), 2 (Q = 4) or 4 (Q = 8)
+    const int l3lo = a.l3lo;  // output element e of a lane is l = l3lo + lane + 64 e
 
     cplx<T> xin[NX];
     cplx<T> yout[NY];
@@ -426,9 +442,9 @@ __global__ void __launch_bounds__((64 * ZWaves<T, K, DG>::n), 2) k_z_scale(const
         for (int ci = 0; ci < CPW; ++ci) {
             const int c = w + ci * ZW;
 #pragma unroll
-            for (int e = 0; e < (HOLD ? EPL : 1); ++e) {
+            for (int e = 0; e < EPI; ++e) {
                 const int l = lane + 64 * e;
-                xin[ci * (HOLD ? EPL : 1) + e] = (c < ncin && l < nz) ? zb[c * cs + base + l] : cmk<T>(0, 0);
+                xin[ci * EPI + e] = (c < ncin && l < nz) ? zb[c * cs + base + l] : cmk<T>(0, 0);
             }
         }
     }
@@ -439,6 +455,9 @@ __global__ void __launch_bounds__((64 * ZWaves<T, K, DG>::n), 2) k_z_scale(const
     const bool nyq12 = (k1 == Mt) || (k2 == Mt);
     const double kxd = a.dk12 * k1, kyd = a.dk12 * k2s;
     const long long oct_line = ((long long)k1 * (Mt + 1) + ak2) * (2 * Mt + 1);
+    // the screening factor exp(-c k^2) is separable: the in-plane part once
+    // per line, the x3 part from the table ez[|k3|]
+    const double exy = exp(-a.c_exp * (kxd * kxd + kyd * kyd));
 
     for (int s = 0; s < Q; ++s) {
         // fold and twist each owned input component into its LDS line:
@@ -452,15 +471,15 @@ __global__ void __launch_bounds__((64 * ZWaves<T, K, DG>::n), 2) k_z_scale(const
                 if (h) wave_sync();
                 if (HOLD) {
 #pragma unroll
-                    for (int e = 0; e < (HOLD ? EPL : 1); ++e) {
+                    for (int e = 0; e < EPI; ++e) {
                         const int l = lane + 64 * e;
                         if (l < nz) {
-                            const int lq = fdiv(l, nq, mnq);
+                            const int lq = nh == 1 ? 0 : fdiv(l, nq, mnq);
                             if (lq == h) {
-                                cplx<T> v = xin[ci * (HOLD ? EPL : 1) + e];
+                                cplx<T> v = xin[ci * EPI + e];
                                 if (s) {
-                                    int ti = s * l;
-                                    ti -= fdiv(ti, n4, mn4) * n4;
+                                    int ti = s * l;  // < 4Mt when Q = 2 (nh = 1)
+                                    if (nh != 1) ti -= fdiv(ti, n4, mn4) * n4;
                                     v = cmul(v, tw4[ti]);
                                 }
                                 const int lp = l - lq * nq;
@@ -486,7 +505,7 @@ __global__ void __launch_bounds__((64 * ZWaves<T, K, DG>::n), 2) k_z_scale(const
                                 cplx<T> x = v[u];
                                 if (s) {
                                     int ti = s * l;
-                                    ti -= fdiv(ti, n4, mn4) * n4;
+                                    if (nh != 1) ti -= fdiv(ti, n4, mn4) * n4;
                                     x = cmul(x, tw4[ti]);
                                 }
                                 line[lp] = h ? cadd(line[lp], x) : x;
@@ -518,7 +537,7 @@ __global__ void __launch_bounds__((64 * ZWaves<T, K, DG>::n), 2) k_z_scale(const
                 bool near0 = (k1 <= a.near0) && (ak2 <= a.near0) && (ak3 <= 2 * a.near0);
                 if (sizeof(T) == 8 || near0) {
                     double k2v = kxd * kxd + kyd * kyd + kzd * kzd;
-                    double ep = exp(-a.c_exp * k2v);
+                    double ep = exy * a.ez[ak3];
                     double gB = 0.0, gH = ep * a.cH * a.octH64[oi];
                     if (K != ROTLET) gB = (1.0 + a.c_has * k2v) * ep * a.cB * a.octB64[oi];
                     cplx<double> Xd[ncin], Yd[NCOUT_MAX];
@@ -530,7 +549,7 @@ __global__ void __launch_bounds__((64 * ZWaves<T, K, DG>::n), 2) k_z_scale(const
                 } else {
                     float kx = (float)kxd, ky = (float)kyd, kz = (float)kzd;
                     float k2v = kx * kx + ky * ky + kz * kz;
-                    float ep = expf(-(float)a.c_exp * k2v);
+                    float ep = (float)(exy * a.ez[ak3]);
                     float gH = ep * (float)a.cH * a.octH32[oi];
                     float gB = 0.f;
                     if (K != ROTLET) gB = (1.f + (float)a.c_has * k2v) * ep * (float)a.cB * a.octB32[oi];
@@ -555,25 +574,25 @@ __global__ void __launch_bounds__((64 * ZWaves<T, K, DG>::n), 2) k_z_scale(const
             if (EPL > 0) {
 #pragma unroll
                 for (int e = 0; e < NY; ++e) {
-                    const int l = lane + 64 * e;
+                    const int l = l3lo + lane + 64 * e;
                     if (l < nz) {
-                        const int lq = fdiv(l, nq, mnq);
+                        const int lq = nh == 1 ? 0 : fdiv(l, nq, mnq);
                         cplx<T> v = line[l - lq * nq];
                         if (s) {
                             int ti = s * l;
-                            ti -= fdiv(ti, n4, mn4) * n4;
+                            if (nh != 1) ti -= fdiv(ti, n4, mn4) * n4;
                             v = cmul(v, cconj(tw4[ti]));
                         }
                         yout[e] = cadd(yout[e], v);
                     }
                 }
             } else {
-                for (int l = lane; l < nz; l += 64) {
-                    const int lq = fdiv(l, nq, mnq);
+                for (int l = l3lo + lane; l < nz; l += 64) {
+                    const int lq = nh == 1 ? 0 : fdiv(l, nq, mnq);
                     cplx<T> v = line[l - lq * nq];
                     if (s) {
                         int ti = s * l;
-                        ti -= fdiv(ti, n4, mn4) * n4;
+                        if (nh != 1) ti -= fdiv(ti, n4, mn4) * n4;
                         v = cmul(v, cconj(tw4[ti]));
                     }
                     cplx<T>* o = zout + w * a.cs_out + base + l;
@@ -586,7 +605,7 @@ __global__ void __launch_bounds__((64 * ZWaves<T, K, DG>::n), 2) k_z_scale(const
     if (EPL > 0 && w < NCOUT) {
 #pragma unroll
         for (int e = 0; e < NY; ++e) {
-            const int l = lane + 64 * e;
+            const int l = l3lo + lane + 64 * e;
             if (l < nz) zout[w * a.cs_out + base + l] = yout[e];
         }
     }
@@ -625,6 +644,22 @@ __global__ void __launch_bounds__(256) k_even_line(const double* __restrict__ in
     lds_fft<double, 256, 16, false>(buf, n, 1, a.f);
     for (int k = threadIdx.x; k < a.nkeep; k += 256)
         out[(long long)o1 * a.so1 + (long long)o2 * a.so2 + (long long)k * a.sk] = a.scale * buf[k].x;
+}
+
+// ez[t] = exp(-c (dk t)^2), t < n: the x3 factor of the screening exponential
+__global__ void k_exp_table(double* __restrict__ ez, int n, double c, double dk)
+{
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) {
+        double k = dk * t;
+        ez[t] = exp(-c * k * k);
+    }
+}
+
+hipError_t launch_exp_table(double* ez, int n, double c, double dk, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_exp_table, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, ez, n, c, dk);
+    return hipGetLastError();
 }
 
 __global__ void k_oct_to_f32(const double* __restrict__ in, float* __restrict__ out, long long n)
@@ -682,7 +717,7 @@ hipError_t launch_fwd_y(const cplx<T>* in, cplx<T>* out, const PassArgs& a, int 
 template <typename T>
 hipError_t launch_inv_y(const cplx<T>* in, cplx<T>* out, const PassArgs& a, int ncomp, hipStream_t st)
 {
-    dim3 grid((2 * a.Mt + a.B - 1) / a.B, a.nk1, ncomp);
+    dim3 grid((2 * a.Mt - a.l3lo + a.B - 1) / a.B, a.nk1, ncomp);
     size_t lds = pass_lds(a.Mt, a.B, sizeof(T));
     if (a.B * a.Mt <= 8 * PASS_NT)
         hipLaunchKernelGGL((k_inv_y<T, 8>), grid, dim3(PASS_NT), lds, st, in, out, a);
@@ -693,7 +728,7 @@ hipError_t launch_inv_y(const cplx<T>* in, cplx<T>* out, const PassArgs& a, int 
 template <typename T>
 hipError_t launch_inv_x(const cplx<T>* in, T* out, const PassArgs& a, int ncomp, hipStream_t st)
 {
-    dim3 grid((a.Mt + a.B - 1) / a.B, 2 * a.Mt, ncomp);
+    dim3 grid((a.Mt + a.B - 1) / a.B, 2 * a.Mt - a.l3lo, ncomp);
     hipLaunchKernelGGL(k_inv_x<T>, grid, dim3(XPASS_NT), pass_lds(a.Mt, a.B, sizeof(T)), st, in, out, a);
     return hipGetLastError();
 }
@@ -712,23 +747,35 @@ bool z_resident_ok(int family, int Mt)
     return 2 * Mt <= 3 * 512;
 }
 
-template <typename T, int K, bool DG>
-static void launch_z_t(cplx<T>* zb, cplx<T>* zout, const ZArgs& a, bool res, hipStream_t st)
+template <typename T, int K, bool DG, int EPL>
+static void launch_z_e(cplx<T>* zb, cplx<T>* zout, const ZArgs& a, hipStream_t st)
 {
     dim3 grid(2 * a.Mt, a.nk1);
     size_t lds = z_lds_bytes(K, DG, a.Mt, a.Q, sizeof(T));
-    const int nz = 2 * a.Mt;
     const dim3 blk(64 * ZWaves<T, K, DG>::n);
+    if constexpr (z_hold_fits<T, K, DG, EPL>()) {
+        if (128 * EPL >= 2 * a.Mt) {
+            hipLaunchKernelGGL((k_z_scale<T, K, EPL, true, DG>), grid, blk, lds, st, zb, zout, a);
+            return;
+        }
+    }
+    hipLaunchKernelGGL((k_z_scale<T, K, EPL, false, DG>), grid, blk, lds, st, zb, zout, a);
+}
+
+template <typename T, int K, bool DG>
+static void launch_z_t(cplx<T>* zb, cplx<T>* zout, const ZArgs& a, bool res, hipStream_t st)
+{
+    const int no = 2 * a.Mt - a.l3lo;  // outputs per line
     if (!res)
-        hipLaunchKernelGGL((k_z_scale<T, K, 0, DG>), grid, blk, lds, st, zb, zout, a);
-    else if (nz <= 256)
-        hipLaunchKernelGGL((k_z_scale<T, K, 4, DG>), grid, blk, lds, st, zb, zout, a);
-    else if (nz <= 512)
-        hipLaunchKernelGGL((k_z_scale<T, K, 8, DG>), grid, blk, lds, st, zb, zout, a);
-    else if (nz <= 1024)
-        hipLaunchKernelGGL((k_z_scale<T, K, 16, DG>), grid, blk, lds, st, zb, zout, a);
+        launch_z_e<T, K, DG, 0>(zb, zout, a, st);
+    else if (no <= 256)
+        launch_z_e<T, K, DG, 4>(zb, zout, a, st);
+    else if (no <= 512)
+        launch_z_e<T, K, DG, 8>(zb, zout, a, st);
+    else if (no <= 1024)
+        launch_z_e<T, K, DG, 16>(zb, zout, a, st);
     else
-        hipLaunchKernelGGL((k_z_scale<T, K, 24, DG>), grid, blk, lds, st, zb, zout, a);
+        launch_z_e<T, K, DG, 24>(zb, zout, a, st);
 }
 
 template <typename T>

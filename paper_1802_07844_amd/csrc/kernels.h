@@ -18,6 +18,7 @@ struct PassArgs {
     FftPlanDev fM;       // FFT of length Mt
     int k1base, nk1;     // y passes: k1 slabs [k1base, k1base + nk1); the Z side
                          // is a buffer of slabs indexed k1 - k1base
+    int l3lo;            // inverse passes: only x3 nodes l >= l3lo are produced
 };
 
 // fused x3 transform + scaling
@@ -39,6 +40,8 @@ struct ZArgs {
     const float* octH32;
     int near0;             // index radius of the k ~ 0 region computed in FP64
     int k1base, nk1;       // k1 slabs of this launch; data indexed k1 - k1base
+    int l3lo;              // outputs are written for l >= l3lo only
+    const double* ez;      // exp(-c_exp (dk3 t)^2), t <= 2Mt
 };
 
 // one even real line transform per block (precompute)
@@ -70,6 +73,7 @@ template <typename T>
 hipError_t launch_z(int family, bool dgrid, cplx<T>* zb, cplx<T>* zout, const ZArgs& a, bool res, hipStream_t st);
 hipError_t launch_even_line(const double* in, double* out, const EvenArgs& a, hipStream_t st);
 hipError_t launch_oct_to_f32(const double* in, float* out, long long n, hipStream_t st);
+hipError_t launch_exp_table(double* ez, int n, double c, double dk, hipStream_t st);
 template <typename T>
 hipError_t launch_line_fft(const cplx<T>* in, cplx<T>* out, int nl, int per, const FftPlanDev& p, bool inv,
                            hipStream_t st);

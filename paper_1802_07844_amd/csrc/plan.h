@@ -147,6 +147,7 @@ struct PlanInput {
     int force_zg;  // > 0: k1 slabs per group of the y / x3 pipeline
     int gather_extra;  // >= 0: extra gather support nodes (even); < 0: default
     int dgrid;         // 1 / 0: force the correction density D on / off; < 0: by cost
+    double tlo3;       // lowest target x3 (>= 0)
 };
 
 struct Plan {
@@ -165,6 +166,7 @@ struct Plan {
     long long ntiles;
     int Bx, By;
     int zg;  // k1 slabs per group of the y / x3 pipeline
+    int l3lo;  // first x3 node the inverse transforms produce (the quadrature reads no lower node)
     long long max_chunks;
     int warnings;
 };
@@ -365,6 +367,17 @@ inline int make_plan(const PlanInput& in, Plan* out)
     p.gg = g;
     p.gg.P = Pg;
     p.gg.mP = magic_of((unsigned)Pg);
+    // The targets lie at x3 >= tlo3 >= 0, so the quadrature never reads the
+    // lower part of the x3 range (the image side of the box): the inverse
+    // transforms produce only nodes from the support base of the lowest
+    // target, less one node of margin, rounded down to a multiple of 16 (one
+    // 128-byte row segment of the y passes).
+    {
+        double zt = std::max(in.tlo3, 0.0);
+        long long b = (long long)std::floor((zt - g.o[2]) / h) - Pg / 2;
+        b = std::max(0LL, std::min(b, (long long)(2 * Mt - Pg)));
+        p.l3lo = (int)(b / 16) * 16;
+    }
     *out = p;
     return 0;
 }

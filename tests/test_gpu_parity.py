@@ -110,6 +110,29 @@ def test_separate_targets_including_wall(ctx, family):
 
 
 @pytest.mark.parametrize("family", FAMILIES)
+@pytest.mark.parametrize("prec,tol", [(1, 1e-10), (2, 1e-5)])
+def test_targets_far_above_the_wall(ctx, family, prec, tol):
+    """All targets in the upper part of the box: the inverse transforms then
+    produce only the x3 nodes from the lowest target's support up
+    (report.x3_first well above the wall node)."""
+    n, t = 400, 300
+    y, s = workloads.make(family, n, 1806)
+    g = workloads.rng(8)
+    x = np.empty((t, 3))
+    x[:, 0] = g.random(t)
+    x[:, 1] = g.random(t)
+    x[:, 2] = 0.55 + 0.45 * g.random(t)
+    xi, rc = _params(family, n, tol, nb=150 if prec == 1 else 300)
+    u, rep = _run(ctx, family, y, s, x, xi, rc, tol, prec=prec)
+    ref = oracle.halfspace(family, y, s, x)
+    err = oracle.rel_rms(ref, u)
+    print(f"{family} prec={rep.precision}: Mt={rep.Mt} x3_first={rep.x3_first} rel-RMS={err:.3e}")
+    assert rep.precision == prec
+    assert rep.x3_first >= rep.Mt - rep.Pg // 2 - 16  # nothing below the wall's support
+    assert err <= tol
+
+
+@pytest.mark.parametrize("family", FAMILIES)
 def test_xi_independence(ctx, family):
     """The Ewald parameter introduces no error (Sec. 6): three splits agree."""
     n = 300

@@ -213,3 +213,20 @@ def test_record_region_holds_the_spreading_support(dgrid):
         assert r.Pg == r.P + 2 and r.Mt >= r.M + max(r.Ps, r.Pg)
         stride = 2 + 3 * r.Ps + 3 + {"stokeslet": 7, "stresslet": 13, "rotlet": 5}[fam]
         assert r.workspace_bytes >= 2 * n * stride * 8
+
+
+@pytest.mark.parametrize("prec", [1, 2])
+@pytest.mark.parametrize("z0", [0.0, 0.3, 0.9])
+def test_inverse_transforms_cover_the_lowest_target(prec, z0):
+    """The inverse transforms produce x3 nodes from x3_first up; the Gaussian
+    support of the lowest target (base floor((z - o3) / h) - Pg/2 + 1) must
+    start at or above it, and the image half of the box below the wall is
+    skipped."""
+    r = _plan(lo=(0.0, 0.0, z0), hi=(1.0, 1.0, 1.0), prec=prec)
+    first = math.floor((z0 - r.origin[2]) / r.h) - r.Pg // 2 + 1
+    assert 0 <= r.x3_first <= first
+    assert r.x3_first % 16 == 0
+    assert r.x3_first >= first - 17  # one node of margin, rounded down to 16
+    assert r.origin[2] == pytest.approx(-r.Lt)
+    if z0 == 0.0:
+        assert r.x3_first >= r.Mt - r.Pg // 2 - 17
