@@ -93,7 +93,7 @@ int stage_table(ehs_ctx* c, int n, int esz, const std::vector<int>& r, FftPlanDe
                 // exp(-2 pi i k q / (ns R)) = table entry (k q n / (ns R)) mod n
                 long long t = ((long long)k * q * (n / (ns * R))) % n;
                 double a = tp * (double)t / (double)n;
-                size_t e = offs[s] + (size_t)k * (R - 1) + (q - 1);
+                size_t e = offs[s] + (size_t)(q - 1) * ns + k;
                 h[2 * e] = std::cos(a);
                 h[2 * e + 1] = -std::sin(a);
             }
@@ -269,7 +269,9 @@ int check_extents(const Plan& p, const Layout& L, size_t esz)
     const size_t nout = (size_t)ncout_for(p.prec);
     const size_t xreg = L.Y - L.X, yreg = L.ZS - L.Y, zsreg = L.Zo - L.ZS, zoreg = L.rec - L.Zo;
     auto fits = [](size_t need, size_t have) { return need <= have; };
-    bool ok = p.zg >= 1 && p.zg <= p.Mt + 1 && p.l3lo >= 0 && p.l3lo < 2 * p.Mt
+    // in place (resident), the fused x3 pass keeps at most 16 outputs per lane
+    bool ok = p.zg >= 1 && p.zg <= p.Mt + 1 && p.l3lo >= 0 && p.l3lo < 2 * p.Mt &&
+              (!p.resident || 2 * p.Mt - p.l3lo <= 1024)
               && fits(nin * real, xreg)                 // spread -> X
               && fits(nin * a, yreg)                    // forward x1 -> Y
               && fits(nin * zs, zsreg)                  // forward x2 -> slab buffer
@@ -296,7 +298,7 @@ int check_extents(const Plan& p, const Layout& L, size_t esz)
     // x / y passes: B lines of Mt in LDS and in the 16-element register budget
     ok = ok && p.Bx * p.Mt <= lds_fft_cap(p.Mt, 256) && p.By * p.Mt <= lds_fft_cap(p.Mt, 256) &&
          p.By * p.Mt <= 16 * 256 && (p.Bx % 2) == 0 && p.By >= 1 &&
-         (size_t)p.By * (p.Mt + 1) * c <= 160 * 1024 && (size_t)p.Bx * (p.Mt + 1) * c <= 160 * 1024;
+         pass_lds(p.Mt, p.By, esz) <= 160 * 1024 && pass_lds(p.Mt, p.Bx, esz) <= 160 * 1024;
     // magic-number division is exact for numerator * divisor < 2^32
     ok = ok && (long long)(p.Mt + 1) * std::max(p.Bx, 2 * p.By) * std::max(p.Mt, 2 * p.By) < (1LL << 31) &&
          (long long)std::max(p.ncin, ncout_for(p.prec)) * 2 * p.Mt * 2 * p.Mt < (1LL << 31);

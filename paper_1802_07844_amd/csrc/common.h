@@ -36,6 +36,10 @@ template <typename T>
 __host__ __device__ __forceinline__ cplx<T> cconj(cplx<T> a) { return cmk<T>(a.x, -a.y); }
 template <typename T>
 __host__ __device__ __forceinline__ cplx<T> cscale(cplx<T> a, T s) { return cmk<T>(a.x * s, a.y * s); }
+// exchange of the real and imaginary parts: swap(z) = i conj(z), so that
+// the inverse DFT is swap(DFT(swap(v))) (free in registers, unlike conj)
+template <typename T>
+__host__ __device__ __forceinline__ cplx<T> cswap(cplx<T> a) { return cmk<T>(a.y, a.x); }
 // multiply by -i
 template <typename T>
 __host__ __device__ __forceinline__ cplx<T> cmul_mi(cplx<T> a) { return cmk<T>(a.y, -a.x); }
@@ -123,7 +127,8 @@ struct FftPlanDev {
     int tstr[FFT_MAX_STAGES];       // twiddle stride n / (ns * rad)
     int toff[FFT_MAX_STAGES];       // offset of the stage's table in tws
     const void* tw;                 // cplx<T>*: exp(-2 pi i t / n), t < n
-    const void* tws;                // cplx<T>*: per stage, w^(k q) for k < ns, 1 <= q < rad
+    const void* tws;                // cplx<T>*: per stage, w^(k q) at (q - 1) ns + k, k < ns,
+                                    // 1 <= q < rad; n - 1 entries in all
 };
 
 // a / d for a * d < 2^32, with m = floor((2^32 - 1) / d) + 1 (d >= 2)
@@ -342,6 +347,15 @@ struct Dft<T, 12> : Pfa<T, 4, 3> {};
 template <typename T>
 struct Dft<T, 14> : Pfa<T, 2, 7> {};
 
+// Copy of the n - 1 stage twiddles of plan p into LDS (all NT threads of the
+// block; the caller synchronises before the first transform).
+template <typename T, int NT>
+__device__ __forceinline__ void load_stage_twiddles(cplx<T>* dst, const FftPlanDev& p)
+{
+    const cplx<T>* __restrict__ src = static_cast<const cplx<T>*>(p.tws);
+    for (int t = threadIdx.x; t < p.n - 1; t += NT) dst[t] = src[t];
+}
+
 // Ordering of LDS accesses among the lanes of one wavefront: the wave's LDS
 // operations execute in order, so a compiler barrier with wavefront-scope
 // fences is enough (no s_barrier, no wait on other waves).
@@ -368,11 +382,11 @@ __device__ __forceinline__ void group_sync()
 // outputs in registers until all threads have read their inputs.
 template <typename T, int NT, int E, int R, bool INV, bool WAVE = false>
 __device__ __forceinline__ void fft_stage(cplx<T>* buf, int ld, int nl, const FftPlanDev& p, int st,
-                                          const cplx<T>* __restrict__ tw)
+                                          const cplx<T>* __restrict__ tws_all)
 {
     constexpr int MB = (E / R) > 0 ? (E / R) : 1;
     const int nb = p.nb[st], Ns = p.ns[st];
-    const cplx<T>* __restrict__ tws = static_cast<const cplx<T>*>(p.tws) + p.toff[st];
+    const cplx<T>* __restrict__ tws = tws_all + p.toff[st];
     const unsigned mnb = p.mnb[st], mns = p.mns[st];
     const int total = nl * nb;
     cplx<T> v[MB][R];
@@ -391,12 +405,12 @@ __device__ __forceinline__ void fft_stage(cplx<T>* buf, int ld, int nl, const Ff
 #pragma unroll
             for (int q = 0; q < R; ++q) {
                 cplx<T> a = src[q * nb];
-                v[i][q] = INV ? cconj(a) : a;
+                v[i][q] = INV ? cswap(a) : a;
             }
             if (k != 0) {
-                const cplx<T>* ws = tws + (k * (R - 1));
+                const cplx<T>* ws = tws + k;
 #pragma unroll
-                for (int q = 1; q < R; ++q) v[i][q] = cmul(v[i][q], ws[q - 1]);
+                for (int q = 1; q < R; ++q) v[i][q] = cmul(v[i][q], ws[(q - 1) * Ns]);
             }
             Dft<T, R>::run(v[i]);
             base[i] = line * ld + jq * Ns * R + k;
@@ -409,7 +423,7 @@ __device__ __forceinline__ void fft_stage(cplx<T>* buf, int ld, int nl, const Ff
         if (base[i] >= 0) {
             cplx<T>* dst = buf + base[i];
 #pragma unroll
-            for (int q = 0; q < R; ++q) dst[q * Ns] = INV ? cconj(v[i][q]) : v[i][q];
+            for (int q = 0; q < R; ++q) dst[q * Ns] = INV ? cswap(v[i][q]) : v[i][q];
         }
     }
     group_sync<WAVE>();
@@ -418,10 +432,10 @@ __device__ __forceinline__ void fft_stage(cplx<T>* buf, int ld, int nl, const Ff
 // Full in-place FFT (unnormalised) of nl lines of length p.n in LDS.
 // Requires nl * p.n <= E * NT (checked by the host planner).  Caller must
 // __syncthreads() before (data written) -- this routine ends with a barrier.
+// tw: the stage twiddle tables (p.tws, or a copy of its n - 1 entries in LDS).
 template <typename T, int NT, int E, bool INV, bool WAVE = false>
-__device__ void lds_fft(cplx<T>* buf, int ld, int nl, const FftPlanDev& p)
+__device__ void lds_fft(cplx<T>* buf, int ld, int nl, const FftPlanDev& p, const cplx<T>* __restrict__ tw)
 {
-    const cplx<T>* tw = static_cast<const cplx<T>*>(p.tw);
     for (int s = 0; s < p.nst; ++s) {
         switch (p.rad[s]) {
             case 2: fft_stage<T, NT, E, 2, INV, WAVE>(buf, ld, nl, p, s, tw); break;

@@ -41,6 +41,8 @@ __global__ void __launch_bounds__(XPASS_NT, 4) k_fwd_x(const T* __restrict__ in,
     const cplx<T>* tw2 = static_cast<const cplx<T>*>(a.tw2);
     const T* src = in + (long long)c * a.cs_in + ((long long)l * Mt + j0) * Mt;
     const int np = B / 2;
+    cplx<T>* twl = buf + B * ld;
+    load_stage_twiddles<T, XPASS_NT>(twl, a.fM);
     constexpr int LB = 4;  // independent loads in flight per thread
     for (int f0 = threadIdx.x; f0 < np * Mt; f0 += LB * XPASS_NT) {
         T va[LB], vb[LB];
@@ -64,7 +66,7 @@ __global__ void __launch_bounds__(XPASS_NT, 4) k_fwd_x(const T* __restrict__ in,
         }
     }
     __syncthreads();
-    lds_fft<T, XPASS_NT, PASS_E, false>(buf, ld, B, a.fM);
+    lds_fft<T, XPASS_NT, PASS_E, false>(buf, ld, B, a.fM, twl);
     // unpack the two real spectra: A = (Z[k] + conj Z[-k]) / 2, B = (Z[k] - conj Z[-k]) / 2i
     cplx<T>* dst = out + (long long)c * a.cs_out + (long long)l * Mt + j0;
     const long long rowk = (long long)2 * Mt * Mt;  // stride of k1
@@ -103,6 +105,8 @@ __global__ void __launch_bounds__(PASS_NT) k_fwd_y(const cplx<T>* __restrict__ i
     const int nb = min(B, nl - l0);
     const cplx<T>* tw2 = static_cast<const cplx<T>*>(a.tw2);
     const cplx<T>* src = in + (long long)c * a.cs_in + ((long long)k1 * nl + l0) * Mt;
+    cplx<T>* twl = buf + B * ld;
+    load_stage_twiddles<T, PASS_NT>(twl, a.fM);
     cplx<T> x[MAXR];
     int jj[MAXR], bb[MAXR];
 #pragma unroll
@@ -124,7 +128,7 @@ __global__ void __launch_bounds__(PASS_NT) k_fwd_y(const cplx<T>* __restrict__ i
         for (int i = 0; i < MAXR; ++i)
             if (jj[i] >= 0) buf[bb[i] * ld + jj[i]] = s ? cmul(x[i], tw2[jj[i]]) : x[i];
         __syncthreads();
-        lds_fft<T, PASS_NT, PASS_E, false>(buf, ld, B, a.fM);
+        lds_fft<T, PASS_NT, PASS_E, false>(buf, ld, B, a.fM, twl);
         for (int f = threadIdx.x; f < Mt * B; f += PASS_NT) {
             int m = fdiv(f, B, a.mB), b = f - m * B;
             if (b < nb) dst[(long long)(2 * m + s) * nl + b] = buf[b * ld + m];
@@ -150,6 +154,8 @@ __global__ void __launch_bounds__(PASS_NT) k_inv_y(const cplx<T>* __restrict__ i
     const int nb = min(B, nl - l0);
     const cplx<T>* tw2 = static_cast<const cplx<T>*>(a.tw2);
     const cplx<T>* src = in + (long long)c * a.cs_in + (long long)k1l * nl * nl + l0;
+    cplx<T>* twl = buf + B * ld;
+    load_stage_twiddles<T, PASS_NT>(twl, a.fM);
     cplx<T> acc[MAXR];
     for (int s = 0; s < 2; ++s) {
         // rows of B values (one 128-byte segment) spread over 2Mt rows: issue
@@ -173,7 +179,7 @@ __global__ void __launch_bounds__(PASS_NT) k_inv_y(const cplx<T>* __restrict__ i
             }
         }
         __syncthreads();
-        lds_fft<T, PASS_NT, PASS_E, true>(buf, ld, B, a.fM);
+        lds_fft<T, PASS_NT, PASS_E, true>(buf, ld, B, a.fM, twl);
 #pragma unroll
         for (int i = 0; i < MAXR; ++i) {
             int f = threadIdx.x + i * PASS_NT;
@@ -210,6 +216,8 @@ __global__ void __launch_bounds__(XPASS_NT, 4) k_inv_x(const cplx<T>* __restrict
     const cplx<T>* src = in + (long long)c * a.cs_in + (long long)l * Mt + j0;
     const long long rowk = (long long)2 * Mt * Mt;
     const int hB = B / 2;
+    cplx<T>* twl = buf + B * ld;
+    load_stage_twiddles<T, XPASS_NT>(twl, a.fM);
     // Z_p[k] = Ya[k] + i Yb[k] over the full padded range k < 2Mt; the
     // position k = 2m + s is stored at buf[(2p + s) * ld + m].
     constexpr int LB = 4;  // independent loads in flight per thread
@@ -245,7 +253,7 @@ __global__ void __launch_bounds__(XPASS_NT, 4) k_inv_x(const cplx<T>* __restrict
         }
         __syncthreads();
     }
-    lds_fft<T, XPASS_NT, PASS_E, true>(buf, ld, B, a.fM);
+    lds_fft<T, XPASS_NT, PASS_E, true>(buf, ld, B, a.fM, twl);
     T* dst = out + (long long)c * a.cs_out + ((long long)l * Mt + j0) * Mt;
     for (int f = threadIdx.x; f < nb * Mt; f += XPASS_NT) {
         int b = fdiv(f, Mt, a.mMt), t = f - b * Mt;
@@ -432,6 +440,11 @@ __global__ void __launch_bounds__((64 * ZWaves<T, K, DG>::n), 2) k_z_scale(const
     const unsigned mnq = a.mnq, mn4 = a.mn4;
     const int nh = nz / nq;  // 1 (Q = 2), 2 (Q = 4) or 4 (Q = 8)
     const int l3lo = a.l3lo;  // output element e of a lane is l = l3lo + lane + 64 e
+    constexpr int NL = ncin > NCOUT ? ncin : NCOUT;  // LDS lines
+    cplx<T>* twl = buf + NL * ld;                    // stage twiddles of the line FFT
+    load_stage_twiddles<T, Z_NT>(twl, a.fq);
+    __syncthreads();
+    constexpr int MJ = (1024 + Z_NT - 1) / Z_NT;  // wave numbers per thread (4Mt / Q <= 1024)
 
     cplx<T> xin[NX];
     cplx<T> yout[NY];
@@ -460,6 +473,32 @@ __global__ void __launch_bounds__((64 * ZWaves<T, K, DG>::n), 2) k_z_scale(const
     const double exy = exp(-a.c_exp * (kxd * kxd + kyd * kyd));
 
     for (int s = 0; s < Q; ++s) {
+        // the multipliers of this phase's wave numbers k3 = Q m + s, loaded
+        // before the fold so that their latency overlaps the forward transform:
+        //   pgh = exp(-c k^2) L~^2 H^R(k) / Npad,  pgb = exp(-c k^2) L~^4 B^R(k) / Npad
+        T pgh[MJ], pgb[MJ];
+#pragma unroll
+        for (int j = 0; j < MJ; ++j) {
+            const int m = threadIdx.x + j * Z_NT;
+            pgh[j] = 0;
+            pgb[j] = 0;
+            if (m < nq) {
+                const int k3 = Q * m + s;
+                const int k3s = (k3 < nz) ? k3 : k3 - n4;
+                const int ak3 = k3s < 0 ? -k3s : k3s;
+                if (!(nyq12 || k3 == nz)) {
+                    const long long oi = oct_line + ak3;
+                    const double ep = exy * a.ez[ak3];
+                    if (sizeof(T) == 8) {
+                        pgh[j] = (T)(ep * a.cH * a.octH64[oi]);
+                        if (K != ROTLET) pgb[j] = (T)(ep * a.cB * a.octB64[oi]);
+                    } else {
+                        pgh[j] = (T)(ep * a.cH) * a.octH32[oi];
+                        if (K != ROTLET) pgb[j] = (T)(ep * a.cB) * a.octB32[oi];
+                    }
+                }
+            }
+        }
         // fold and twist each owned input component into its LDS line:
         //   line c holds sum_h x_c[l' + h nq] w^{s (l' + h nq)},  l' < nq
 #pragma unroll
@@ -488,8 +527,9 @@ __global__ void __launch_bounds__((64 * ZWaves<T, K, DG>::n), 2) k_z_scale(const
                         }
                     }
                 } else {
-                    // LB independent loads per lane before the stores
-                    constexpr int LB = 4;
+                    // LB loads per lane in flight before their stores: the whole
+                    // line (<= 1024 elements) where the registers allow
+                    constexpr int LB = EPL >= 16 ? 4 : 16;
                     for (int lp0 = lane; lp0 < nq; lp0 += LB * 64) {
                         cplx<T> v[LB];
 #pragma unroll
@@ -515,12 +555,15 @@ __global__ void __launch_bounds__((64 * ZWaves<T, K, DG>::n), 2) k_z_scale(const
                 }
             }
             wave_sync();
-            lds_fft<T, 64, Z_E, false, true>(line, ld, 1, a.fq);
+            lds_fft<T, 64, Z_E, false, true>(line, ld, 1, a.fq, twl);
         }
         __syncthreads();
 
         // scaling at k3 = Q m + s (couples the components)
-        for (int m = threadIdx.x; m < nq; m += Z_NT) {
+#pragma unroll
+        for (int j = 0; j < MJ; ++j) {
+            const int m = threadIdx.x + j * Z_NT;
+            if (m >= nq) break;
             int k3 = Q * m + s;
             int k3s = (k3 < nz) ? k3 : k3 - n4;
             int ak3 = k3s < 0 ? -k3s : k3s;
@@ -533,13 +576,20 @@ __global__ void __launch_bounds__((64 * ZWaves<T, K, DG>::n), 2) k_z_scale(const
                 for (int c = 0; c < NCOUT; ++c) Y[c] = cmk<T>(0, 0);
             } else {
                 double kzd = a.dk3 * k3s;
-                long long oi = oct_line + ak3;
                 bool near0 = (k1 <= a.near0) && (ak2 <= a.near0) && (ak3 <= 2 * a.near0);
                 if (sizeof(T) == 8 || near0) {
                     double k2v = kxd * kxd + kyd * kyd + kzd * kzd;
-                    double ep = exy * a.ez[ak3];
-                    double gB = 0.0, gH = ep * a.cH * a.octH64[oi];
-                    if (K != ROTLET) gB = (1.0 + a.c_has * k2v) * ep * a.cB * a.octB64[oi];
+                    double gB, gH;
+                    if (sizeof(T) == 8) {
+                        gH = (double)pgh[j];
+                        gB = (1.0 + a.c_has * k2v) * (double)pgb[j];
+                    } else {
+                        // FP32 path near k = 0: FP64 multipliers
+                        const long long oi = oct_line + ak3;
+                        const double ep = exy * a.ez[ak3];
+                        gH = ep * a.cH * a.octH64[oi];
+                        gB = K != ROTLET ? (1.0 + a.c_has * k2v) * (ep * a.cB * a.octB64[oi]) : 0.0;
+                    }
                     cplx<double> Xd[ncin], Yd[NCOUT_MAX];
 #pragma unroll
                     for (int c = 0; c < ncin; ++c) Xd[c] = cmk<double>((double)X[c].x, (double)X[c].y);
@@ -549,10 +599,8 @@ __global__ void __launch_bounds__((64 * ZWaves<T, K, DG>::n), 2) k_z_scale(const
                 } else {
                     float kx = (float)kxd, ky = (float)kyd, kz = (float)kzd;
                     float k2v = kx * kx + ky * ky + kz * kz;
-                    float ep = (float)(exy * a.ez[ak3]);
-                    float gH = ep * (float)a.cH * a.octH32[oi];
-                    float gB = 0.f;
-                    if (K != ROTLET) gB = (1.f + (float)a.c_has * k2v) * ep * (float)a.cB * a.octB32[oi];
+                    float gH = (float)pgh[j];
+                    float gB = (1.f + (float)a.c_has * k2v) * (float)pgb[j];
                     cplx<float> Xf[ncin], Yf[NCOUT_MAX];
 #pragma unroll
                     for (int c = 0; c < ncin; ++c) Xf[c] = cmk<float>((float)X[c].x, (float)X[c].y);
@@ -570,7 +618,7 @@ __global__ void __launch_bounds__((64 * ZWaves<T, K, DG>::n), 2) k_z_scale(const
         //   out_c[l] += line_c[l mod nq] w^{-s l},  l < 2Mt
         if (w < NCOUT) {
             cplx<T>* line = buf + w * ld;
-            lds_fft<T, 64, Z_E, true, true>(line, ld, 1, a.fq);
+            lds_fft<T, 64, Z_E, true, true>(line, ld, 1, a.fq, twl);
             if (EPL > 0) {
 #pragma unroll
                 for (int e = 0; e < NY; ++e) {
@@ -641,7 +689,7 @@ __global__ void __launch_bounds__(256) k_even_line(const double* __restrict__ in
         buf[t] = cmk<double>(v, 0.0);
     }
     __syncthreads();
-    lds_fft<double, 256, 16, false>(buf, n, 1, a.f);
+    lds_fft<double, 256, 16, false>(buf, n, 1, a.f, static_cast<const cplx<double>*>(a.f.tws));
     for (int k = threadIdx.x; k < a.nkeep; k += 256)
         out[(long long)o1 * a.so1 + (long long)o2 * a.so2 + (long long)k * a.sk] = a.scale * buf[k].x;
 }
@@ -684,7 +732,7 @@ __global__ void __launch_bounds__(PASS_NT) k_line_fft(const cplx<T>* __restrict_
         buf[b * ld + t] = (b < nb) ? in[(long long)(l0 + b) * n + t] : cmk<T>(0, 0);
     }
     __syncthreads();
-    lds_fft<T, PASS_NT, PASS_E, INV>(buf, ld, per, p);
+    lds_fft<T, PASS_NT, PASS_E, INV>(buf, ld, per, p, static_cast<const cplx<T>*>(p.tws));
     for (int f = threadIdx.x; f < nb * n; f += PASS_NT) {
         int b = f / n, t = f - b * n;
         out[(long long)(l0 + b) * n + t] = buf[b * ld + t];
@@ -694,7 +742,8 @@ __global__ void __launch_bounds__(PASS_NT) k_line_fft(const cplx<T>* __restrict_
 // ---------------------------------------------------------------------------
 // host launchers
 // ---------------------------------------------------------------------------
-static size_t pass_lds(int Mt, int B, size_t esz) { return (size_t)B * (Mt + 1) * 2 * esz; }
+// B lines of Mt + 1 complex values and the Mt - 1 stage twiddles (rounded up to Mt)
+size_t pass_lds(int Mt, int B, size_t esz) { return ((size_t)B * (Mt + 1) + Mt) * 2 * esz; }
 
 template <typename T>
 hipError_t launch_fwd_x(const T* in, cplx<T>* out, const PassArgs& a, int ncomp, hipStream_t st)
@@ -738,7 +787,8 @@ size_t z_lds_bytes(int family, bool dgrid, int Mt, int Q, size_t esz)
     int ncin = ncin_for(family, dgrid);
     int nout = esz == 8 ? Out<double>::n : Out<float>::n;
     int nl = ncin > nout ? ncin : nout;
-    return (size_t)nl * (4 * Mt / Q + 1) * 2 * esz;
+    int nq = 4 * Mt / Q;
+    return ((size_t)nl * (nq + 1) + nq) * 2 * esz;  // lines and the nq - 1 stage twiddles
 }
 
 bool z_resident_ok(int family, int Mt)
@@ -772,10 +822,8 @@ static void launch_z_t(cplx<T>* zb, cplx<T>* zout, const ZArgs& a, bool res, hip
         launch_z_e<T, K, DG, 4>(zb, zout, a, st);
     else if (no <= 512)
         launch_z_e<T, K, DG, 8>(zb, zout, a, st);
-    else if (no <= 1024)
-        launch_z_e<T, K, DG, 16>(zb, zout, a, st);
     else
-        launch_z_e<T, K, DG, 24>(zb, zout, a, st);
+        launch_z_e<T, K, DG, 16>(zb, zout, a, st);  // no <= 1024 (the planner's audit)
 }
 
 template <typename T>

@@ -59,6 +59,7 @@ struct EvenArgs {
 };
 
 size_t z_lds_bytes(int family, bool dgrid, int Mt, int Q, size_t esz);
+size_t pass_lds(int Mt, int B, size_t esz);
 bool z_resident_ok(int family, int Mt);
 
 template <typename T>

@@ -175,13 +175,14 @@ constexpr int EHS_MT_MAX = 2048;
 
 // lines per block of the x / y passes: one 128-byte segment of complex
 // values per written (or read) row, i.e. 8 (FP64) or 16 (FP32) lines, fewer
-// when the lines do not fit the LDS budget (78 KiB: two blocks per CU) or the
-// 16-element register budget of the FFT
+// when the lines and the twiddle tables do not fit the LDS budget (78 KiB:
+// two blocks per CU) or the 16-element register budget of the FFT
 inline int choose_lines(int Mt, size_t esz)
 {
     int B = (int)(128 / (2 * esz));
     int cap = lds_fft_cap(Mt, 256);
-    while (B > 2 && ((size_t)B * (Mt + 1) * 2 * esz > 78 * 1024 || B * Mt > cap)) B -= 2;
+    // LDS per block: B lines of Mt + 1 values and the stage twiddles (Mt)
+    while (B > 2 && (((size_t)B * (Mt + 1) + Mt) * 2 * esz > 78 * 1024 || B * Mt > cap)) B -= 2;
     return B;
 }
 
