@@ -14,6 +14,8 @@
 // line x_t, t < n, padded to 2n, the even outputs X[2m] are DFT_n(x)[m] and the
 // odd outputs X[2m+1] are DFT_n(x_t e^{-i pi t/n})[m].  Along x3 the same
 // identity is used with Q "phases" k3 = Q m + s.
+#include <type_traits>
+
 #include "common.h"
 #include "kernels.h"
 
@@ -404,6 +406,18 @@ struct ZWaves {
     static constexpr int n = lines < 8 ? lines : 8;
 };
 
+// occupancy target (wavefronts per SIMD): two blocks per CU.  With four
+// wavefronts per block that is two per SIMD.  FP32 stokeslet and rotlet
+// blocks have six or seven wavefronts and need four per SIMD (128 registers,
+// which their variants with at most 4 outputs per lane and no held inputs
+// fit; their LDS allows it); FP64 blocks of more wavefronts are held to one
+// block per CU by the LDS anyway, and the FP32 stresslet's 13 input lines do
+// not fit 128 registers.
+template <typename T, int K, bool DG, int EPL>
+struct ZOcc {
+    static constexpr int n = (sizeof(T) == 4 && ZWaves<T, K, DG>::n > 4 && K != STRESSLET && EPL <= 4) ? 4 : 2;
+};
+
 // inputs held in registers (HOLD): 2 EPL elements per lane cover the whole
 // input line when 128 EPL >= 2Mt; only where they fit a register budget of
 // 32 per lane (more spills in the FP64 variants)
@@ -412,11 +426,12 @@ constexpr bool z_hold_fits()
 {
     constexpr int zw = ZWaves<T, K, DG>::n;
     constexpr int cpw = (InGrids<K, DG>::n + zw - 1) / zw;
-    return EPL > 0 && EPL <= 8 && cpw * 2 * EPL * (int)sizeof(cplx<T>) <= 128;
+    return EPL > 0 && EPL <= 8 && cpw * 2 * EPL * (int)sizeof(cplx<T>) <= 128 && ZOcc<T, K, DG, EPL>::n == 2;
 }
 
 template <typename T, int K, int EPL, bool HOLD, bool DG>
-__global__ void __launch_bounds__((64 * ZWaves<T, K, DG>::n), 2) k_z_scale(const cplx<T>* zb, cplx<T>* zout, ZArgs a)
+__global__ void __launch_bounds__((64 * ZWaves<T, K, DG>::n), (ZOcc<T, K, DG, EPL>::n))
+    k_z_scale(const cplx<T>* zb, cplx<T>* zout, ZArgs a)
 {
     constexpr int ZW = ZWaves<T, K, DG>::n;
     constexpr int Z_NT = 64 * ZW;
@@ -473,34 +488,34 @@ __global__ void __launch_bounds__((64 * ZWaves<T, K, DG>::n), 2) k_z_scale(const
     const double exy = exp(-a.c_exp * (kxd * kxd + kyd * kyd));
 
     for (int s = 0; s < Q; ++s) {
-        // the multipliers of this phase's wave numbers k3 = Q m + s, loaded
-        // before the fold so that their latency overlaps the forward transform:
-        //   pgh = exp(-c k^2) L~^2 H^R(k) / Npad,  pgb = exp(-c k^2) L~^4 B^R(k) / Npad
-        T pgh[MJ], pgb[MJ];
+        // the multiplier samples of this phase's wave numbers k3 = Q m + s:
+        // raw loads (every index valid, m clamped), issued before the fold so
+        // that their latency overlaps the forward transform; they are combined
+        // into the multipliers only in the scaling step
+        using OT = typename std::conditional<sizeof(T) == 8, double, float>::type;
+        const OT* octH = sizeof(T) == 8 ? (const OT*)a.octH64 : (const OT*)a.octH32;
+        const OT* octB = sizeof(T) == 8 ? (const OT*)a.octB64 : (const OT*)a.octB32;
+        // (with 16 outputs per lane the registers do not allow it: loaded in
+        // the scaling step instead)
+        constexpr bool PREF = EPL < 16;
+        double pez[MJ];
+        OT poh[MJ], pob[MJ];
+        auto load_mult = [&](int j) {
+            const int m = min((int)threadIdx.x + j * Z_NT, nq - 1);
+            const int k3 = Q * m + s;
+            const int k3s = (k3 < nz) ? k3 : k3 - n4;
+            const int ak3 = k3s < 0 ? -k3s : k3s;
+            pez[j] = a.ez[ak3];
+            poh[j] = octH[oct_line + ak3];
+            pob[j] = K != ROTLET ? octB[oct_line + ak3] : (OT)0;
+        };
+        if (PREF) {
 #pragma unroll
-        for (int j = 0; j < MJ; ++j) {
-            const int m = threadIdx.x + j * Z_NT;
-            pgh[j] = 0;
-            pgb[j] = 0;
-            if (m < nq) {
-                const int k3 = Q * m + s;
-                const int k3s = (k3 < nz) ? k3 : k3 - n4;
-                const int ak3 = k3s < 0 ? -k3s : k3s;
-                if (!(nyq12 || k3 == nz)) {
-                    const long long oi = oct_line + ak3;
-                    const double ep = exy * a.ez[ak3];
-                    if (sizeof(T) == 8) {
-                        pgh[j] = (T)(ep * a.cH * a.octH64[oi]);
-                        if (K != ROTLET) pgb[j] = (T)(ep * a.cB * a.octB64[oi]);
-                    } else {
-                        pgh[j] = (T)(ep * a.cH) * a.octH32[oi];
-                        if (K != ROTLET) pgb[j] = (T)(ep * a.cB) * a.octB32[oi];
-                    }
-                }
-            }
+            for (int j = 0; j < MJ; ++j) load_mult(j);
         }
         // fold and twist each owned input component into its LDS line:
         //   line c holds sum_h x_c[l' + h nq] w^{s (l' + h nq)},  l' < nq
+        // (the twist factors are loaded with the data, ahead of their use)
 #pragma unroll
         for (int ci = 0; ci < CPW; ++ci) {
             const int c = w + ci * ZW;
@@ -509,6 +524,14 @@ __global__ void __launch_bounds__((64 * ZWaves<T, K, DG>::n), 2) k_z_scale(const
             for (int h = 0; h < nh; ++h) {
                 if (h) wave_sync();
                 if (HOLD) {
+                    cplx<T> t[EPI];
+#pragma unroll
+                    for (int e = 0; e < EPI; ++e) {
+                        const int l = min(lane + 64 * e, nz - 1);
+                        int ti = s * l;  // < 4Mt when Q = 2 (nh = 1)
+                        if (nh != 1) ti -= fdiv(ti, n4, mn4) * n4;
+                        t[e] = s ? tw4[ti] : cmk<T>(1, 0);
+                    }
 #pragma unroll
                     for (int e = 0; e < EPI; ++e) {
                         const int l = lane + 64 * e;
@@ -516,38 +539,31 @@ __global__ void __launch_bounds__((64 * ZWaves<T, K, DG>::n), 2) k_z_scale(const
                             const int lq = nh == 1 ? 0 : fdiv(l, nq, mnq);
                             if (lq == h) {
                                 cplx<T> v = xin[ci * EPI + e];
-                                if (s) {
-                                    int ti = s * l;  // < 4Mt when Q = 2 (nh = 1)
-                                    if (nh != 1) ti -= fdiv(ti, n4, mn4) * n4;
-                                    v = cmul(v, tw4[ti]);
-                                }
+                                if (s) v = cmul(v, t[e]);
                                 const int lp = l - lq * nq;
                                 line[lp] = h ? cadd(line[lp], v) : v;
                             }
                         }
                     }
                 } else {
-                    // LB loads per lane in flight before their stores: the whole
-                    // line (<= 1024 elements) where the registers allow
-                    constexpr int LB = EPL >= 16 ? 4 : 16;
+                    // LB loads of data and twist factors per lane in flight
+                    // before their stores
+                    constexpr int LB = EPL >= 16 ? (CPW > 1 ? 2 : 4) : 8;
                     for (int lp0 = lane; lp0 < nq; lp0 += LB * 64) {
-                        cplx<T> v[LB];
+                        cplx<T> v[LB], t[LB];
 #pragma unroll
                         for (int u = 0; u < LB; ++u) {
                             const int lp = lp0 + u * 64;
                             v[u] = lp < nq ? zb[c * cs + base + lp + h * nq] : cmk<T>(0, 0);
+                            int ti = s * (min(lp, nq - 1) + h * nq);
+                            if (nh != 1) ti -= fdiv(ti, n4, mn4) * n4;
+                            t[u] = s ? tw4[ti] : cmk<T>(1, 0);
                         }
 #pragma unroll
                         for (int u = 0; u < LB; ++u) {
                             const int lp = lp0 + u * 64;
                             if (lp < nq) {
-                                const int l = lp + h * nq;
-                                cplx<T> x = v[u];
-                                if (s) {
-                                    int ti = s * l;
-                                    if (nh != 1) ti -= fdiv(ti, n4, mn4) * n4;
-                                    x = cmul(x, tw4[ti]);
-                                }
+                                cplx<T> x = s ? cmul(v[u], t[u]) : v[u];
                                 line[lp] = h ? cadd(line[lp], x) : x;
                             }
                         }
@@ -564,6 +580,7 @@ __global__ void __launch_bounds__((64 * ZWaves<T, K, DG>::n), 2) k_z_scale(const
         for (int j = 0; j < MJ; ++j) {
             const int m = threadIdx.x + j * Z_NT;
             if (m >= nq) break;
+            if (!PREF) load_mult(j);
             int k3 = Q * m + s;
             int k3s = (k3 < nz) ? k3 : k3 - n4;
             int ak3 = k3s < 0 ? -k3s : k3s;
@@ -581,8 +598,9 @@ __global__ void __launch_bounds__((64 * ZWaves<T, K, DG>::n), 2) k_z_scale(const
                     double k2v = kxd * kxd + kyd * kyd + kzd * kzd;
                     double gB, gH;
                     if (sizeof(T) == 8) {
-                        gH = (double)pgh[j];
-                        gB = (1.0 + a.c_has * k2v) * (double)pgb[j];
+                        const double ep = exy * pez[j];
+                        gH = ep * a.cH * (double)poh[j];
+                        gB = K != ROTLET ? (1.0 + a.c_has * k2v) * (ep * a.cB * (double)pob[j]) : 0.0;
                     } else {
                         // FP32 path near k = 0: FP64 multipliers
                         const long long oi = oct_line + ak3;
@@ -599,8 +617,9 @@ __global__ void __launch_bounds__((64 * ZWaves<T, K, DG>::n), 2) k_z_scale(const
                 } else {
                     float kx = (float)kxd, ky = (float)kyd, kz = (float)kzd;
                     float k2v = kx * kx + ky * ky + kz * kz;
-                    float gH = (float)pgh[j];
-                    float gB = (1.f + (float)a.c_has * k2v) * (float)pgb[j];
+                    const double ep = exy * pez[j];
+                    float gH = (float)(ep * a.cH) * (float)poh[j];
+                    float gB = K != ROTLET ? (1.f + (float)a.c_has * k2v) * ((float)(ep * a.cB) * (float)pob[j]) : 0.f;
                     cplx<float> Xf[ncin], Yf[NCOUT_MAX];
 #pragma unroll
                     for (int c = 0; c < ncin; ++c) Xf[c] = cmk<float>((float)X[c].x, (float)X[c].y);
@@ -620,18 +639,28 @@ __global__ void __launch_bounds__((64 * ZWaves<T, K, DG>::n), 2) k_z_scale(const
             cplx<T>* line = buf + w * ld;
             lds_fft<T, 64, Z_E, true, true>(line, ld, 1, a.fq, twl);
             if (EPL > 0) {
+                // twist factors loaded in batches of UB ahead of their use
+                constexpr int UB = NY >= 16 ? 4 : (NY < 8 ? NY : 8);
 #pragma unroll
-                for (int e = 0; e < NY; ++e) {
-                    const int l = l3lo + lane + 64 * e;
-                    if (l < nz) {
-                        const int lq = nh == 1 ? 0 : fdiv(l, nq, mnq);
-                        cplx<T> v = line[l - lq * nq];
-                        if (s) {
-                            int ti = s * l;
+                for (int e0 = 0; e0 < NY; e0 += UB) {
+                    cplx<T> t[UB];
+                    if (s) {
+#pragma unroll
+                        for (int u = 0; u < UB; ++u) {
+                            int ti = s * min(l3lo + lane + 64 * (e0 + u), nz - 1);
                             if (nh != 1) ti -= fdiv(ti, n4, mn4) * n4;
-                            v = cmul(v, cconj(tw4[ti]));
+                            t[u] = tw4[ti];
                         }
-                        yout[e] = cadd(yout[e], v);
+                    }
+#pragma unroll
+                    for (int u = 0; u < UB; ++u) {
+                        const int l = l3lo + lane + 64 * (e0 + u);
+                        if (l < nz) {
+                            const int lq = nh == 1 ? 0 : fdiv(l, nq, mnq);
+                            cplx<T> v = line[l - lq * nq];
+                            if (s) v = cmul(v, cconj(t[u]));
+                            yout[e0 + u] = cadd(yout[e0 + u], v);
+                        }
                     }
                 }
             } else {
