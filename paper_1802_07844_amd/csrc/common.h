@@ -407,10 +407,22 @@ __device__ __forceinline__ void fft_stage(cplx<T>* buf, int ld, int nl, const Ff
                 cplx<T> a = src[q * nb];
                 v[i][q] = INV ? cswap(a) : a;
             }
-            if (k != 0) {
+            // the stage's twiddles w^(k q) (w^0 = 1 for k = 0; none in the
+            // first stage, Ns = 1), read in batches of TB before their use so
+            // that a batch is in flight together
+            if (Ns > 1) {
+                constexpr int TB = sizeof(T) == 8 ? 4 : 2;
                 const cplx<T>* ws = tws + k;
 #pragma unroll
-                for (int q = 1; q < R; ++q) v[i][q] = cmul(v[i][q], ws[(q - 1) * Ns]);
+                for (int q0 = 1; q0 < R; q0 += TB) {
+                    cplx<T> wv[TB];
+#pragma unroll
+                    for (int u = 0; u < TB; ++u)
+                        if (q0 + u < R) wv[u] = ws[(q0 + u - 1) * Ns];
+#pragma unroll
+                    for (int u = 0; u < TB; ++u)
+                        if (q0 + u < R) v[i][q0 + u] = cmul(v[i][q0 + u], wv[u]);
+                }
             }
             Dft<T, R>::run(v[i]);
             base[i] = line * ld + jq * Ns * R + k;
