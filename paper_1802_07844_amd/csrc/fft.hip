@@ -541,7 +541,10 @@ __global__ void __launch_bounds__((64 * ZWaves<T, K, DG>::n), (ZOcc<T, K, DG, EP
                                 cplx<T> v = xin[ci * EPI + e];
                                 if (s) v = cmul(v, t[e]);
                                 const int lp = l - lq * nq;
-                                line[lp] = h ? cadd(line[lp], v) : v;
+                                if (h == 0)
+                                    line[lp] = v;
+                                else
+                                    line[lp] = cadd(line[lp], v);
                             }
                         }
                     }
@@ -559,12 +562,17 @@ __global__ void __launch_bounds__((64 * ZWaves<T, K, DG>::n), (ZOcc<T, K, DG, EP
                             if (nh != 1) ti -= fdiv(ti, n4, mn4) * n4;
                             t[u] = s ? tw4[ti] : cmk<T>(1, 0);
                         }
+                        if (h == 0) {
 #pragma unroll
-                        for (int u = 0; u < LB; ++u) {
-                            const int lp = lp0 + u * 64;
-                            if (lp < nq) {
-                                cplx<T> x = s ? cmul(v[u], t[u]) : v[u];
-                                line[lp] = h ? cadd(line[lp], x) : x;
+                            for (int u = 0; u < LB; ++u) {
+                                const int lp = lp0 + u * 64;
+                                if (lp < nq) line[lp] = s ? cmul(v[u], t[u]) : v[u];
+                            }
+                        } else {
+#pragma unroll
+                            for (int u = 0; u < LB; ++u) {
+                                const int lp = lp0 + u * 64;
+                                if (lp < nq) line[lp] = cadd(line[lp], s ? cmul(v[u], t[u]) : v[u]);
                             }
                         }
                     }
@@ -652,15 +660,19 @@ __global__ void __launch_bounds__((64 * ZWaves<T, K, DG>::n), (ZOcc<T, K, DG, EP
                             t[u] = tw4[ti];
                         }
                     }
+                    // with at most 8 outputs per lane no branch per element
+                    // (the LDS reads of a batch are in flight together):
+                    // positions past the line are clamped, and their sums are
+                    // never written; with more the registers do not allow it
 #pragma unroll
                     for (int u = 0; u < UB; ++u) {
                         const int l = l3lo + lane + 64 * (e0 + u);
-                        if (l < nz) {
-                            const int lq = nh == 1 ? 0 : fdiv(l, nq, mnq);
-                            cplx<T> v = line[l - lq * nq];
-                            if (s) v = cmul(v, cconj(t[u]));
-                            yout[e0 + u] = cadd(yout[e0 + u], v);
-                        }
+                        if (NY > 8 && l >= nz) continue;
+                        const int lc = min(l, nz - 1);
+                        const int lq = nh == 1 ? 0 : fdiv(lc, nq, mnq);
+                        cplx<T> v = line[lc - lq * nq];
+                        if (s) v = cmul(v, cconj(t[u]));
+                        yout[e0 + u] = cadd(yout[e0 + u], v);
                     }
                 }
             } else {
