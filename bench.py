@@ -235,8 +235,8 @@ def serve_bench(args, ehs, workloads, torch, np):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=100_000)
     ap.add_argument("--neighbours", type=float, default=30.0)
     ap.add_argument("--fp32-neighbours", type=float, default=300.0,
@@ -250,7 +250,7 @@ def main():
     ap.add_argument("--serve-slots", type=int, default=4)
     ap.add_argument("--serve-arena-gb", type=float, default=200.0)
     ap.add_argument("--serve-calib", type=int, default=48, help="closed-loop calibration requests")
-    ap.add_argument("--serve-max-seconds", type=float, default=90.0, help="stop admitting arrivals after this")
+    ap.add_argument("--serve-max-seconds", type=float, default=120.0, help="stop admitting arrivals after this")
     ap.add_argument("--serve-pool", type=int, default=1_000_000)
     ap.add_argument("--serve-checks", type=int, default=12, help="requests checked against the oracle (256 targets each)")
     ap.add_argument("--copy-probe", action="store_true",
