@@ -39,12 +39,15 @@ def _stage_bytes(rep, ncin, esz):
     nout = 4 if esz == 8 else 6  # output grids: T1 and phi (FP64) or T1 and grad phi (FP32)
     oct_bytes = (Mt + 1) * (Mt + 1) * (2 * Mt + 1) * (8 if esz == 8 else 4) * kinds
     # the inverse side produces only the x3 nodes from x3_first up (the ones
-    # the quadrature at the targets reads)
+    # the quadrature at the targets reads); the correction grids (components
+    # from nca on, spread at the images) are read only below x3_corr_end
     keep = (2 * Mt - rep.x3_first) / (2 * Mt)
+    nca = 6 if rep.family == 1 else 3
+    nin = nca + (ncin - nca) * rep.x3_corr_end / (2 * Mt)
     return {
-        "fwd_x": ncin * (real + a),
-        "fwd_y": ncin * (a + z),
-        "z_scale": ncin * z + nout * z * keep + oct_bytes,
+        "fwd_x": nin * (real + a),
+        "fwd_y": nin * (a + z),
+        "z_scale": nin * z + nout * z * keep + oct_bytes,
         "inv_y": nout * (z + a) * keep,
         "inv_x": nout * (a + real) * keep,
     }
@@ -329,7 +332,7 @@ def main():
                                f"forces N(0,1), FP64 tol 1e-10, ~{args.neighbours:g} neighbours",
                    "N": n, "xi": xi, "r_c": rc, "tol": tol, "M": rep.M, "P": rep.P, "Mt": rep.Mt,
                    "eta": rep.eta, "zslab": rep.zslab, "Ps": rep.Ps, "Pg": rep.Pg, "dgrid": rep.dgrid,
-                   "x3_first": rep.x3_first,
+                   "x3_first": rep.x3_first, "x3_corr_end": rep.x3_corr_end,
                    "seed": seed},
         "stage_ms": stage_ms,
         "roofline": roofline,

@@ -111,7 +111,8 @@ typedef struct ehs_report {
     double est_fp32;        /* estimated FP32 rounding error (relative RMS, uniform point sets) */
     int32_t x3_first;       /* first x3 grid node the inverse transforms produce: the quadrature
                                of the lowest target reads no node below it */
-    int32_t reserved;
+    int32_t x3_corr_end;    /* x3 grid nodes from this one up lie above every image's Gaussian
+                               support: the correction grids vanish there */
 } ehs_report;
 
 /* Create a context on HIP device `hip_device`.  `arena_bytes` is reserved

@@ -44,7 +44,7 @@ class Report(ctypes.Structure):
         ("zslab", ctypes.c_int32), ("Pg", ctypes.c_int32),
         ("Ps", ctypes.c_int32), ("dgrid", ctypes.c_int32),
         ("est_fp32", ctypes.c_double),
-        ("x3_first", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("x3_first", ctypes.c_int32), ("x3_corr_end", ctypes.c_int32),
     ]
 
     def as_dict(self) -> dict:

@@ -270,7 +270,8 @@ int check_extents(const Plan& p, const Layout& L, size_t esz)
     const size_t xreg = L.Y - L.X, yreg = L.ZS - L.Y, zsreg = L.Zo - L.ZS, zoreg = L.rec - L.Zo;
     auto fits = [](size_t need, size_t have) { return need <= have; };
     // in place (resident), the fused x3 pass keeps at most 16 outputs per lane
-    bool ok = p.zg >= 1 && p.zg <= p.Mt + 1 && p.l3lo >= 0 && p.l3lo < 2 * p.Mt &&
+    bool ok = p.zg >= 1 && p.zg <= p.Mt + 1 && p.l3lo >= 0 && p.l3lo < 2 * p.Mt && p.lzc >= 0 &&
+              p.lzc <= 2 * p.Mt &&
               (!p.resident || 2 * p.Mt - p.l3lo <= 1024)
               && fits(nin * real, xreg)                 // spread -> X
               && fits(nin * a, yreg)                    // forward x1 -> Y
@@ -472,6 +473,10 @@ int run(ehs_ctx* c, Plan& p, const Octants& oct, const double* y, const double* 
     set_b(p.Bx);
     pa.cs_in = csR;
     pa.cs_out = csA;
+    // components from ncA on (the correction grids, spread at the images)
+    // vanish at x3 nodes >= lzc: the forward passes skip them there
+    pa.czero = p.family == STRESSLET ? 6 : 3;  // the kernel-grid components come first
+    pa.lzc = p.lzc;
     HIPCHK(launch_fwd_x<T>(X, Yc, pa, p.ncin, st));
     rec_ev(EHS_ST_FWDY);
 
@@ -524,6 +529,8 @@ int run(ehs_ctx* c, Plan& p, const Octants& oct, const double* y, const double* 
     }
     set_b(p.By);
     za.l3lo = p.l3lo;
+    za.czero = pa.czero;
+    za.lzc = p.lzc;
     for (int k0 = 0; k0 <= p.Mt; k0 += p.zg) {
         const int cnt = std::min(p.zg, p.Mt + 1 - k0);
         pa.k1base = k0;
@@ -610,6 +617,7 @@ int ehs::plan_request(ehs_ctx* c, int family, const double* y, const double* s, 
     in.gather_extra = c->gather_extra;
     in.dgrid = c->dgrid;
     in.tlo3 = T > 0 ? b[7] : 0.0;
+    in.slo3 = b[6];
     return make_plan(in, p);
 }
 
@@ -662,6 +670,7 @@ void ehs::fill_report(const Plan& p, ehs_report* r)
     r->dgrid = p.dgrid ? 1 : 0;
     r->est_fp32 = p.est32;
     r->x3_first = p.l3lo;
+    r->x3_corr_end = p.lzc;
 }
 
 namespace {
@@ -890,6 +899,7 @@ int ehs_plan_query(int family, int64_t N, int64_t T, const double* lo, const dou
     in.gather_extra = -1;
     in.dgrid = -1;
     in.tlo3 = std::max(lo[2], 0.0);  // lowest point of the box: no target lies lower
+    in.slo3 = std::max(lo[2], 0.0);  // nor any source
     Plan p;
     int rc = make_plan(in, &p);
     if (rc) return rc;

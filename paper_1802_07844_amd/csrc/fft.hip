@@ -39,6 +39,7 @@ __global__ void __launch_bounds__(XPASS_NT, 4) k_fwd_x(const T* __restrict__ in,
     cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
     const int Mt = a.Mt, B = a.B, ld = Mt + 1;
     const int j0 = blockIdx.x * B, l = blockIdx.y, c = blockIdx.z;
+    if (c >= a.czero && l >= a.lzc) return;  // a vanishing row: never read downstream
     const int nb = min(B, Mt - j0);
     const cplx<T>* tw2 = static_cast<const cplx<T>*>(a.tw2);
     const T* src = in + (long long)c * a.cs_in + ((long long)l * Mt + j0) * Mt;
@@ -103,8 +104,12 @@ __global__ void __launch_bounds__(PASS_NT) k_fwd_y(const cplx<T>* __restrict__ i
     cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
     const int Mt = a.Mt, B = a.B, ld = Mt + 1;
     const int l0 = blockIdx.x * B, k1l = blockIdx.y, k1 = a.k1base + k1l, c = blockIdx.z;
+    // rows l >= lzc of the vanishing components: skipped here, treated as
+    // zero by the x3 pass
+    if (c >= a.czero && l0 >= a.lzc) return;
     const int nl = 2 * Mt;
     const int nb = min(B, nl - l0);
+    const int nbr = c >= a.czero ? min(nb, a.lzc - l0) : nb;  // rows read (the rest are zero)
     const cplx<T>* tw2 = static_cast<const cplx<T>*>(a.tw2);
     const cplx<T>* src = in + (long long)c * a.cs_in + ((long long)k1 * nl + l0) * Mt;
     cplx<T>* twl = buf + B * ld;
@@ -121,7 +126,7 @@ __global__ void __launch_bounds__(PASS_NT) k_fwd_y(const cplx<T>* __restrict__ i
             int b = fdiv(f, Mt, a.mMt);
             jj[i] = f - b * Mt;
             bb[i] = b;
-            if (b < nb) x[i] = src[f];
+            if (b < nbr) x[i] = src[f];
         }
     }
     cplx<T>* dst = out + (long long)c * a.cs_out + (long long)k1l * nl * nl + l0;
@@ -472,7 +477,8 @@ __global__ void __launch_bounds__((64 * ZWaves<T, K, DG>::n), (ZOcc<T, K, DG, EP
 #pragma unroll
             for (int e = 0; e < EPI; ++e) {
                 const int l = lane + 64 * e;
-                xin[ci * EPI + e] = (c < ncin && l < nz) ? zb[c * cs + base + l] : cmk<T>(0, 0);
+                const bool rd = c < ncin && l < nz && (c < a.czero || l < a.lzc);
+                xin[ci * EPI + e] = rd ? zb[c * cs + base + l] : cmk<T>(0, 0);
             }
         }
     }
@@ -557,7 +563,8 @@ __global__ void __launch_bounds__((64 * ZWaves<T, K, DG>::n), (ZOcc<T, K, DG, EP
 #pragma unroll
                         for (int u = 0; u < LB; ++u) {
                             const int lp = lp0 + u * 64;
-                            v[u] = lp < nq ? zb[c * cs + base + lp + h * nq] : cmk<T>(0, 0);
+                            const bool rd = lp < nq && (c < a.czero || lp + h * nq < a.lzc);
+                            v[u] = rd ? zb[c * cs + base + lp + h * nq] : cmk<T>(0, 0);
                             int ti = s * (min(lp, nq - 1) + h * nq);
                             if (nh != 1) ti -= fdiv(ti, n4, mn4) * n4;
                             t[u] = s ? tw4[ti] : cmk<T>(1, 0);

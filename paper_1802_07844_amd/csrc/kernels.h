@@ -19,6 +19,8 @@ struct PassArgs {
     int k1base, nk1;     // y passes: k1 slabs [k1base, k1base + nk1); the Z side
                          // is a buffer of slabs indexed k1 - k1base
     int l3lo;            // inverse passes: only x3 nodes l >= l3lo are produced
+    int czero, lzc;      // forward passes: components >= czero vanish at x3 nodes l >= lzc
+                         // (neither read nor written there)
 };
 
 // fused x3 transform + scaling
@@ -42,6 +44,7 @@ struct ZArgs {
     int k1base, nk1;       // k1 slabs of this launch; data indexed k1 - k1base
     int l3lo;              // outputs are written for l >= l3lo only
     const double* ez;      // exp(-c_exp (dk3 t)^2), t <= 2Mt
+    int czero, lzc;        // input components >= czero are zero at l >= lzc (not read)
 };
 
 // one even real line transform per block (precompute)

@@ -148,6 +148,7 @@ struct PlanInput {
     int gather_extra;  // >= 0: extra gather support nodes (even); < 0: default
     int dgrid;         // 1 / 0: force the correction density D on / off; < 0: by cost
     double tlo3;       // lowest target x3 (>= 0)
+    double slo3;       // lowest source x3 (> 0): the images lie at x3 <= -slo3
 };
 
 struct Plan {
@@ -167,6 +168,7 @@ struct Plan {
     int Bx, By;
     int zg;  // k1 slabs per group of the y / x3 pipeline
     int l3lo;  // first x3 node the inverse transforms produce (the quadrature reads no lower node)
+    int lzc;   // the correction grids (components >= ncA, spread at the images only) vanish at x3 nodes >= lzc
     long long max_chunks;
     int warnings;
 };
@@ -378,6 +380,16 @@ inline int make_plan(const PlanInput& in, Plan* out)
         long long b = (long long)std::floor((zt - g.o[2]) / h) - Pg / 2;
         b = std::max(0LL, std::min(b, (long long)(2 * Mt - Pg)));
         p.l3lo = (int)(b / 16) * 16;
+    }
+    // The correction sources sit at the images, x3 <= -slo3 < 0: the grids
+    // spread from them (every component from ncA on) vanish above the top of
+    // the highest image's support, which the forward transforms skip.  One
+    // node of margin, rounded up to a multiple of 16.
+    {
+        double zi = -std::max(in.slo3, 0.0);
+        long long t = (long long)std::floor((zi - g.o[2]) / h) + p.Ps / 2 + 2;
+        t = std::max(0LL, std::min(t, (long long)(2 * Mt)));
+        p.lzc = (int)std::min((long long)(2 * Mt), ((t + 15) / 16) * 16);
     }
     *out = p;
     return 0;

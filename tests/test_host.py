@@ -230,3 +230,17 @@ def test_inverse_transforms_cover_the_lowest_target(prec, z0):
     assert r.origin[2] == pytest.approx(-r.Lt)
     if z0 == 0.0:
         assert r.x3_first >= r.Mt - r.Pg // 2 - 17
+
+
+@pytest.mark.parametrize("dgrid_family", ["stokeslet", "stresslet", "rotlet"])
+@pytest.mark.parametrize("z0", [1e-4, 0.2, 0.6])
+def test_correction_grids_end_above_the_highest_image_support(dgrid_family, z0):
+    """The correction sources sit at the images, x3 = -y3 <= -z0: every node
+    of their Gaussian support (top node floor((-z0 - o3) / h) + Ps/2) lies
+    below x3_corr_end, which the forward transforms use as the end of those
+    grids."""
+    r = _plan(family=dgrid_family, lo=(0.0, 0.0, z0), hi=(1.0, 1.0, 1.0), prec=1)
+    top = math.floor((-z0 - r.origin[2]) / r.h) + r.Ps // 2
+    assert top < r.x3_corr_end <= 2 * r.Mt
+    assert r.x3_corr_end <= top + 2 + 16
+    assert r.x3_corr_end <= r.Mt + r.Ps // 2 + 18  # never above the wall's support
