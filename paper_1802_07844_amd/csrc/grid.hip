@@ -197,7 +197,9 @@ hipError_t launch_records(int family, bool dgrid, const double* y, const double*
 // single density D (FP64), accumulated with derivative weights
 //   w'(d) = -2 a d w(d),  w''(d) = (4 a^2 d^2 - 2 a) w(d),  d = x_g - z.
 // ---------------------------------------------------------------------------
-constexpr int SP_CHUNK = 32;
+// records staged in LDS per chunk: few, so that the LDS leaves room for many
+// one-wavefront blocks per CU (32 records allowed two per SIMD; 8 allow eight)
+constexpr int SP_CHUNK = 8;
 
 template <typename T, int K, int TZ, bool DG>
 __global__ void __launch_bounds__(64) k_spread(GridArgs g, const T* __restrict__ rec,
