@@ -1,14 +1,16 @@
 // Real-space (short-range) part of the half-space Ewald sum.
 //
 // One wavefront per chunk of <= 64 targets of one cell (cells have side
-// >= r_c).  All lanes walk the same neighbour-cell source ranges, so source
-// loads are wave-uniform; each lane accumulates its own target.  Direct terms
+// >= r_c).  All lanes walk the same neighbour-cell source ranges (staged in
+// LDS per batch); each lane accumulates its own target.  Direct terms
 // use the Ewald real-space kernels S_R, T_R, W_R (paper Sec. 4 and Appendix);
 // image and correction terms use the same kernels at r~ = x - y^I together
 // with the real-space parts of G, grad G, grad grad G and grad grad grad G
 // (paper eq. (G_R), written with erfc instead of 1 - erf).  Only targets in
 // the bottom cell layer can be within r_c of an image.
 #include <math.h>
+
+#include <type_traits>
 
 #include "common.h"
 #include "kernels.h"
@@ -152,15 +154,37 @@ __device__ __forceinline__ void image_term(T rx, T ry, T rz, T r2, const T* s, T
     acc[2] += phi - x3 * g2;
 }
 
+// Pair compaction.  A wavefront owns <= 64 targets of one cell (one lane
+// each) and walks the sources of the neighbour cells in batches of SB.  Only
+// about a sixth of the (target, source) candidates lie within r_c, and a
+// lane-per-target loop would evaluate the kernel for every candidate with
+// most lanes idle.  Instead, per batch:
+//   1. each lane tests its target against the SB sources (wave-uniform
+//      loads); the hits of source j form the ballot mask[j], and the hits
+//      are written, in (j, lane) order, to a pair list in LDS;
+//   2. the lanes evaluate the listed pairs, one pair per lane, and store
+//      the contributions in LDS;
+//   3. each lane adds its own target's contributions in source order.
+// The sum over sources is therefore in the same order as a plain loop, and
+// deterministic.
+constexpr int RS_PC = 64 * 4 * 3;  // contribution slots (doubles): 256 pairs in FP64
+
 template <typename T, int K>
-__global__ void __launch_bounds__(256) k_realspace(RealArgs a, const double* __restrict__ ys,
-                                                   const double* __restrict__ ss, const double* __restrict__ xt,
-                                                   double* __restrict__ upart)
+__global__ void __launch_bounds__(64) k_realspace(RealArgs a, const double* __restrict__ ys,
+                                                  const double* __restrict__ ss, const double* __restrict__ xt,
+                                                  double* __restrict__ upart)
 {
     constexpr int NS = (K == STRESSLET) ? 6 : 3;
-    const int lane = threadIdx.x & 63;
-    const long long w = blockIdx.x * 4LL + (threadIdx.x >> 6);
-    if (w >= (long long)(*a.nchunks)) return;
+    constexpr int SB = sizeof(T) == 8 ? 4 : 8;  // sources per batch: 64 SB pairs of 3 T fit RS_PC
+    constexpr int SBI = 4;                      // image sources per batch (FP64 contributions)
+    constexpr int SW = 3 + NS;                  // staged values per source
+    __shared__ double pcb[RS_PC];
+    __shared__ uint16_t plist[64 * SB];
+    __shared__ double sb[SB * SW];
+    __shared__ double tpos[3 * 64];
+    const int lane = threadIdx.x;
+    const long long w = blockIdx.x;
+    if (w >= (long long)(*a.nchunks)) return;  // the whole (one-wavefront) block
     const uint32_t cell = a.chunk_cell[w];
     const uint32_t first = a.chunk_first[w];
     const int cnt = (int)min(64u, a.tgt_off[cell + 1] - first);
@@ -168,6 +192,9 @@ __global__ void __launch_bounds__(256) k_realspace(RealArgs a, const double* __r
     const long long t = first + (act ? lane : 0);
     const long long N = a.N, TT = a.T;
     const double xd0 = xt[t], xd1 = xt[TT + t], xd2 = xt[2 * TT + t];
+    tpos[lane] = xd0;
+    tpos[64 + lane] = xd1;
+    tpos[128 + lane] = xd2;
     const int n0 = a.cg.nc[0], n1 = a.cg.nc[1], n2 = a.cg.nc[2];
     const int c1 = (int)(cell % (uint32_t)n0);
     const int c2i = (int)((cell / (uint32_t)n0) % (uint32_t)n1);
@@ -178,6 +205,94 @@ __global__ void __launch_bounds__(256) k_realspace(RealArgs a, const double* __r
     T acc[3] = {0, 0, 0};
     double self[3] = {0.0, 0.0, 0.0};
     const int lo1 = c1 > 0 ? c1 - 1 : 0, hi1 = c1 < n0 - 1 ? c1 + 1 : n0 - 1;
+
+    // one batch of sources [mb, mb + nb) of the sorted arrays; IMG: their
+    // images (and harmonic corrections) instead of the direct terms
+    auto batch = [&](uint32_t mb, int nb, auto img_tag) {
+        constexpr bool IMG = decltype(img_tag)::value;
+        constexpr int B = IMG ? SBI : SB;
+        for (int f = lane; f < nb * SW; f += 64) {
+            const int jj = f / SW, c = f - jj * SW;
+            sb[f] = c < 3 ? ys[c * N + mb + jj] : ss[(c - 3) * N + mb + jj];
+        }
+        wave_sync();
+        unsigned long long mask[B];
+        int pre[B + 1];
+        pre[0] = 0;
+#pragma unroll
+        for (int j = 0; j < B; ++j) {
+            bool hit = false;
+            if (j < nb) {
+                const double* s = sb + j * SW;
+                const double dx = xd0 - s[0], dy = xd1 - s[1], dz = IMG ? xd2 + s[2] : xd2 - s[2];
+                const double r2 = dx * dx + dy * dy + dz * dz;
+                hit = act && r2 < rc2 && (IMG || r2 > 0.0);
+                if (!IMG && K == STOKESLET && act && r2 == 0.0) {
+                    // self interaction: limit of S_R - S at r = 0 is -(4 xi / sqrt(pi)) I
+                    const double cs = 4.0 * a.xi / 1.7724538509055160273;
+                    self[0] -= cs * s[3];
+                    self[1] -= cs * s[4];
+                    self[2] -= cs * s[5];
+                }
+            }
+            mask[j] = __ballot(hit);
+            const int below = (int)__builtin_amdgcn_mbcnt_hi((unsigned)(mask[j] >> 32),
+                                                             __builtin_amdgcn_mbcnt_lo((unsigned)mask[j], 0u));
+            if (hit) plist[pre[j] + below] = (uint16_t)(lane | (j << 6));
+            pre[j + 1] = pre[j] + __popcll(mask[j]);
+        }
+        wave_sync();
+        const int np = pre[B];
+        for (int q = lane; q < np; q += 64) {
+            const int pr = plist[q], tl = pr & 63, j = pr >> 6;
+            const double* s = sb + j * SW;
+            const double px = tpos[tl], py = tpos[64 + tl], pz = tpos[128 + tl];
+            if (IMG) {
+                const double y3 = s[2];
+                const double dx = px - s[0], dy = py - s[1], dz = pz + y3;
+                double sv[NS], ci[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+                for (int c = 0; c < NS; ++c) sv[c] = s[3 + c];
+                image_term<double, K>(dx, dy, dz, dx * dx + dy * dy + dz * dz, sv, y3, pz, a.xi,
+                                      2.0 * a.xi / 1.7724538509055160273, ci);
+                pcb[3 * q] = ci[0];
+                pcb[3 * q + 1] = ci[1];
+                pcb[3 * q + 2] = ci[2];
+            } else {
+                const double dx = px - s[0], dy = py - s[1], dz = pz - s[2];
+                T sv[NS], cd[3] = {0, 0, 0};
+#pragma unroll
+                for (int c = 0; c < NS; ++c) sv[c] = (T)s[3 + c];
+                direct_term<T, K>((T)dx, (T)dy, (T)dz, (T)(dx * dx + dy * dy + dz * dz), sv, xi, c2, cd);
+                T* pt = reinterpret_cast<T*>(pcb);
+                pt[3 * q] = cd[0];
+                pt[3 * q + 1] = cd[1];
+                pt[3 * q + 2] = cd[2];
+            }
+        }
+        wave_sync();
+        return [&, mask, pre](double* ai, T* ad) {
+#pragma unroll
+            for (int j = 0; j < B; ++j) {
+                if ((mask[j] >> lane) & 1ull) {
+                    const int q = pre[j] + (int)__builtin_amdgcn_mbcnt_hi((unsigned)(mask[j] >> 32),
+                                                                          __builtin_amdgcn_mbcnt_lo((unsigned)mask[j], 0u));
+                    if (IMG) {
+                        ai[0] += pcb[3 * q];
+                        ai[1] += pcb[3 * q + 1];
+                        ai[2] += pcb[3 * q + 2];
+                    } else {
+                        const T* pt = reinterpret_cast<const T*>(pcb);
+                        ad[0] += pt[3 * q];
+                        ad[1] += pt[3 * q + 1];
+                        ad[2] += pt[3 * q + 2];
+                    }
+                }
+            }
+            wave_sync();  // the next batch overwrites the lists
+        };
+    };
+
     for (int d3 = -1; d3 <= 1; ++d3) {
         int cc3 = c3 + d3;
         if (cc3 < 0 || cc3 >= n2) continue;
@@ -186,24 +301,8 @@ __global__ void __launch_bounds__(256) k_realspace(RealArgs a, const double* __r
             if (cc2 < 0 || cc2 >= n1) continue;
             long long row = ((long long)cc3 * n1 + cc2) * n0;
             uint32_t s0 = a.src_off[row + lo1], s1 = a.src_off[row + hi1 + 1];
-            for (uint32_t m = s0; m < s1; ++m) {
-                double dx = xd0 - ys[m], dy = xd1 - ys[N + m], dz = xd2 - ys[2 * N + m];
-                double r2 = dx * dx + dy * dy + dz * dz;
-                if (r2 < rc2) {
-                    if (r2 > 0.0) {
-                        T sv[NS];
-#pragma unroll
-                        for (int c = 0; c < NS; ++c) sv[c] = (T)ss[c * N + m];
-                        direct_term<T, K>((T)dx, (T)dy, (T)dz, (T)r2, sv, xi, c2, acc);
-                    } else if (K == STOKESLET) {
-                        // self interaction: limit of S_R - S at r = 0 is -(4 xi / sqrt(pi)) I
-                        double cs = 4.0 * a.xi / 1.7724538509055160273;
-                        self[0] -= cs * ss[m];
-                        self[1] -= cs * ss[N + m];
-                        self[2] -= cs * ss[2 * N + m];
-                    }
-                }
-            }
+            for (uint32_t mb = s0; mb < s1; mb += SB)
+                batch(mb, (int)min((uint32_t)SB, s1 - mb), std::false_type())(nullptr, acc);
         }
     }
     // Image and correction terms in FP64 in both precisions: for a source and
@@ -212,24 +311,13 @@ __global__ void __launch_bounds__(256) k_realspace(RealArgs a, const double* __r
     // the wall have images here, so this is a small share of the work.
     double acci[3] = {0.0, 0.0, 0.0};
     if (c3 == 0) {
-        const double x3 = xd2;
-        const double xid = a.xi, c2d = 2.0 * a.xi / 1.7724538509055160273;
         for (int d2 = -1; d2 <= 1; ++d2) {
             int cc2 = c2i + d2;
             if (cc2 < 0 || cc2 >= n1) continue;
             long long row = (long long)cc2 * n0;
             uint32_t s0 = a.src_off[row + lo1], s1 = a.src_off[row + hi1 + 1];
-            for (uint32_t m = s0; m < s1; ++m) {
-                double y3 = ys[2 * N + m];
-                double dx = xd0 - ys[m], dy = xd1 - ys[N + m], dz = xd2 + y3;
-                double r2 = dx * dx + dy * dy + dz * dz;
-                if (r2 < rc2) {
-                    double sv[NS];
-#pragma unroll
-                    for (int c = 0; c < NS; ++c) sv[c] = ss[c * N + m];
-                    image_term<double, K>(dx, dy, dz, r2, sv, y3, x3, xid, c2d, acci);
-                }
-            }
+            for (uint32_t mb = s0; mb < s1; mb += SBI)
+                batch(mb, (int)min((uint32_t)SBI, s1 - mb), std::true_type())(acci, nullptr);
         }
     }
     if (act) {
@@ -245,11 +333,11 @@ hipError_t launch_realspace(int family, const RealArgs& a, const double* ys, con
                             double* upart, long long max_chunks, hipStream_t st)
 {
     if (max_chunks <= 0) return hipSuccess;
-    dim3 grid((unsigned)((max_chunks + 3) / 4));
+    dim3 grid((unsigned)max_chunks);  // one wavefront per chunk
     switch (family) {
-        case STOKESLET: hipLaunchKernelGGL((k_realspace<T, STOKESLET>), grid, dim3(256), 0, st, a, ys, ss, xt, upart); break;
-        case STRESSLET: hipLaunchKernelGGL((k_realspace<T, STRESSLET>), grid, dim3(256), 0, st, a, ys, ss, xt, upart); break;
-        default: hipLaunchKernelGGL((k_realspace<T, ROTLET>), grid, dim3(256), 0, st, a, ys, ss, xt, upart); break;
+        case STOKESLET: hipLaunchKernelGGL((k_realspace<T, STOKESLET>), grid, dim3(64), 0, st, a, ys, ss, xt, upart); break;
+        case STRESSLET: hipLaunchKernelGGL((k_realspace<T, STRESSLET>), grid, dim3(64), 0, st, a, ys, ss, xt, upart); break;
+        default: hipLaunchKernelGGL((k_realspace<T, ROTLET>), grid, dim3(64), 0, st, a, ys, ss, xt, upart); break;
     }
     return hipGetLastError();
 }
