@@ -397,7 +397,7 @@ __device__ __forceinline__ void fft_stage(cplx<T>* buf, int ld, int nl, const Ff
         int b = tid + i * NT;
         base[i] = -1;
         if (b < total) {
-            int line = fdiv(b, nb, mnb);
+            int line = nl == 1 ? 0 : fdiv(b, nb, mnb);  // nl is a literal 1 in the single-line callers
             int j = b - line * nb;
             int jq = fdiv(j, Ns, mns);
             int k = j - jq * Ns;
