@@ -252,7 +252,8 @@ int ensure_octants(ehs_ctx* c, const Plan& p, hipStream_t st, bool* ran, Octants
 // workspace layout
 // ---------------------------------------------------------------------------
 struct Layout {
-    size_t X, Y, ZS, Zo, rec, keys, sortsc, toff, soff, tgoff, chunks, ys, ss, xs, upart, bb, ez, total;
+    size_t X, Y, ZS, Zo, rec, keys, sortsc, toff, soff, tgoff, chunks, ys, ss, xs, upart, bb, ez, gkeys, gtoff, grec,
+        gpart, total;
 };
 
 // Host-side audit: the largest extent every pass writes or reads must fit the
@@ -287,7 +288,13 @@ int check_extents(const Plan& p, const Layout& L, size_t esz)
               && fits((size_t)(2 * p.ncell + 2 * p.max_chunks + 1) * 4, L.ys - L.chunks)
               && fits((size_t)3 * p.N * 8, L.ss - L.ys) && fits((size_t)6 * p.N * 8, L.xs - L.ss)
               && fits((size_t)3 * p.T * 8, L.upart - L.xs) && fits((size_t)3 * p.T * 8, L.bb - L.upart)
-              && fits((size_t)(2 * Mt + 1) * 8, L.total - L.ez);
+              && fits((size_t)(2 * Mt + 1) * 8, L.gkeys - L.ez)
+              && (!p.gtiles || (fits((size_t)4 * p.T * 4, L.gtoff - L.gkeys)
+                                && fits((size_t)(p.ntiles_g + 1) * 4, L.grec - L.gtoff)
+                                && fits((size_t)p.T * target_record_stride(p.gg.P, esz) * esz, L.gpart - L.grec)
+                                && fits((size_t)p.T * gather_slots(p.gg) * 6 * esz, L.total - L.gpart)))
+              && p.gg.tile[0] == 8 && p.gg.tile[1] == 8 && p.gg.tile[2] == 8 && p.gg.K[0] == p.gg.K[1] &&
+              p.gg.K[0] == p.gg.K[2] && p.gg.K[0] * 8 >= p.gg.P - 1;
     // precompute scratch in X
     size_t h1 = p.nf / 2 + 1;
     ok = ok && fits((h1 * h1 * (2 * Mt + 1) + h1 * (Mt + 1) * (2 * Mt + 1)) * 8, xreg);
@@ -346,6 +353,13 @@ Layout layout(const Plan& p, size_t esz)
     L.upart = off; off += al((size_t)3 * T * sizeof(double));
     L.bb = off; off += al((size_t)(1024 * 10 + 16) * sizeof(double));
     L.ez = off; off += al((size_t)(2 * Mt + 1) * sizeof(double));
+    // quadrature: target keys / values (4 T), tile offsets, target records and
+    // the partial sums (6 per target and tile of its support box)
+    const size_t gt = p.gtiles ? 1 : 0;  // regions of the node-owner quadrature only
+    L.gkeys = off; off += al(gt * 4 * T * sizeof(uint32_t));
+    L.gtoff = off; off += al(gt * (p.ntiles_g + 1) * sizeof(uint32_t));
+    L.grec = off; off += al(gt * T * target_record_stride(p.gg.P, esz) * esz);
+    L.gpart = off; off += al(gt * T * gather_slots(p.gg) * 6 * esz);
     L.total = off;
     return L;
 }
@@ -561,8 +575,27 @@ int run(ehs_ctx* c, Plan& p, const Octants& oct, const double* y, const double* 
     HIPCHK(launch_inv_x<T>(Yc, X, pa, Out<T>::n, st));
     rec_ev(EHS_ST_GATHER);
 
-    // -- quadrature at the targets and FP64 combination with the real part
-    HIPCHK(launch_gather<T>(p.gg, X, csR, xs, tperm, TT, upart, u, st));
+    // -- quadrature at the targets and FP64 combination with the real part:
+    //    small supports one wavefront per target; large ones in node-owner
+    //    form (targets sorted by the quadrature tile of their support base,
+    //    one wavefront per tile for the partial sums, then a fixed-order sum
+    //    per target)
+    if (!p.gtiles) {
+        HIPCHK(launch_gather<T>(p.gg, X, csR, xs, tperm, TT, upart, u, st));
+    } else {
+        uint32_t* gk = reinterpret_cast<uint32_t*>(base + Lo.gkeys);
+        uint32_t *gv = gk + TT, *gk2 = gv + TT, *gv2 = gk2 + TT;
+        uint32_t* gtoff = reinterpret_cast<uint32_t*>(base + Lo.gtoff);
+        T* grec = reinterpret_cast<T*>(base + Lo.grec);
+        T* gpart = reinterpret_cast<T*>(base + Lo.gpart);
+        uint32_t *gks, *gperm;
+        HIPCHK(launch_target_keys(xs, TT, p.gg, gk, gv, st));
+        HIPCHK(radix_sort(gk, gv, gk2, gv2, TT, bits_for(p.ntiles_g), sortsc, st, &gks, &gperm));
+        HIPCHK(launch_cell_ranges(gks, TT, gtoff, nullptr, p.ntiles_g, st));
+        HIPCHK(launch_target_records<T>(xs, gperm, TT, p.gg, grec, st));
+        HIPCHK(launch_gather_tiles<T>(p.gg, X, csR, grec, gtoff, p.l3lo / 8, gpart, st));
+        HIPCHK(launch_gather_final<T>(p.gg, grec, gpart, TT, xs, tperm, upart, u, st));
+    }
     rec_ev(EHS_ST_TOTAL);
     return EHS_OK;
 }

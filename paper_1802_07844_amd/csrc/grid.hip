@@ -346,9 +346,247 @@ hipError_t launch_spread(int family, bool dgrid, GridArgs g, const T* rec, const
 // formed here as the gradient of the potential's quadrature,
 //   grad_x W(x - x_g) = 2 a (x_g - x) W,  separable like W;
 // FP32: the grids hold T1 (0..2) and T2 (3..5).
-// One wavefront per target; lanes cover P consecutive x1 nodes of
-// floor(64 / P) rows at a time.
+//
+// Node-owner form, the adjoint of the spreading: the targets are sorted by
+// the 8^3-node tile that holds the first node of their support; one
+// wavefront owns a tile (lane = one (x1, x2) column of 8 nodes along x3, held
+// in registers) and, for every target whose support reaches the tile, forms
+// the six partial sums over the tile's nodes and reduces them across the
+// wavefront.  Each grid node is read once (a target-per-wavefront gather
+// reads every node about ten times, once per target whose support holds
+// it).  The partial sums go to one slot per (target, tile); a last pass adds
+// a target's slots in a fixed order, so the result is deterministic.
 // ---------------------------------------------------------------------------
+constexpr int GT_CHUNK = 8;  // target records staged in LDS per chunk
+
+// header of 4 int32 (support base x, y, z; cell-sorted target index), then
+// the 3 Pg factors of W along x1, x2, x3 (the first carries the prefactor)
+// and, with GQ, their derivatives 2 a (x_g - x) w
+__host__ __device__ __forceinline__ size_t trec_stride(int Pg, size_t esz)
+{
+    return 16 / esz + (esz == 8 ? 6 : 3) * (size_t)Pg;
+}
+size_t target_record_stride(int Pg, size_t esz) { return trec_stride(Pg, esz); }
+
+int gather_slots(const GridArgs& gg)
+{
+    const int ks = gg.K[0] + 1;
+    return ks * ks * ks;
+}
+
+__global__ void k_target_keys(const double* __restrict__ xs, long long TT, GridArgs gg, uint32_t* __restrict__ keys,
+                              uint32_t* __restrict__ idx)
+{
+    long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (t >= TT) return;
+    const int dims[3] = {gg.Mt, gg.Mt, 2 * gg.Mt};
+    int b[3];
+    for (int a = 0; a < 3; ++a) b[a] = support_base(xs[a * TT + t], gg.o[a], gg.h, gg.P, dims[a]) / gg.tile[a];
+    keys[t] = (uint32_t)(((long long)b[2] * gg.nt[1] + b[1]) * gg.nt[0] + b[0]);
+    idx[t] = (uint32_t)t;
+}
+
+hipError_t launch_target_keys(const double* xs, long long TT, GridArgs gg, uint32_t* keys, uint32_t* idx,
+                              hipStream_t st)
+{
+    if (TT <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_target_keys, dim3((unsigned)((TT + 255) / 256)), dim3(256), 0, st, xs, TT, gg, keys, idx);
+    return hipGetLastError();
+}
+
+// one wavefront per (tile-sorted) target
+template <typename T>
+__global__ void __launch_bounds__(64) k_target_records(const double* __restrict__ xs, const uint32_t* __restrict__ perm,
+                                                       long long TT, GridArgs gg, T* __restrict__ rec)
+{
+    constexpr bool GQ = Out<T>::grad_quad;
+    const long long r = blockIdx.x;
+    const int lane = threadIdx.x;
+    const int Pg = gg.P;
+    const long long t = perm[r];
+    const double x[3] = {xs[t], xs[TT + t], xs[2 * TT + t]};
+    const int dims[3] = {gg.Mt, gg.Mt, 2 * gg.Mt};
+    int base[3];
+    for (int a = 0; a < 3; ++a) base[a] = support_base(x[a], gg.o[a], gg.h, Pg, dims[a]);
+    const long long stride = (long long)trec_stride(Pg, sizeof(T));
+    T* R = rec + r * stride;
+    if (lane == 0) {
+        int* hdr = reinterpret_cast<int*>(R);
+        hdr[0] = base[0];
+        hdr[1] = base[1];
+        hdr[2] = base[2];
+        hdr[3] = (int)t;
+    }
+    T* w = R + 16 / sizeof(T);
+    for (int f = lane; f < 3 * Pg; f += 64) {
+        const int a = f / Pg, q = f - a * Pg;
+        const double dd = gg.o[a] + (base[a] + q) * gg.h - x[a];
+        double v = exp(-gg.a2 * dd * dd);
+        if (a == 0) v *= gg.pref;
+        w[f] = (T)v;
+        if (GQ) w[3 * Pg + f] = (T)(2.0 * gg.a2 * dd * v);
+    }
+}
+
+template <typename T>
+hipError_t launch_target_records(const double* xs, const uint32_t* perm, long long TT, GridArgs gg, T* rec,
+                                 hipStream_t st)
+{
+    if (TT <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_target_records<T>, dim3((unsigned)TT), dim3(64), 0, st, xs, perm, TT, gg, rec);
+    return hipGetLastError();
+}
+
+// grid: (nt0, nt1, nt2 - tz0): tiles from x3 tile tz0 up (no target's support
+// reaches lower)
+template <typename T>
+__global__ void __launch_bounds__(64) k_gather_tiles(GridArgs gg, const T* __restrict__ grids, long long cs,
+                                                     const T* __restrict__ rec, const uint32_t* __restrict__ gtoff,
+                                                     int tz0, T* __restrict__ part)
+{
+    constexpr bool GQ = Out<T>::grad_quad;
+    constexpr int NOUT = Out<T>::n;
+    extern __shared__ unsigned char smem_raw[];
+    T* sh = reinterpret_cast<T*>(smem_raw);
+    const int Pg = gg.P, Mt = gg.Mt;
+    const int stride = (int)trec_stride(Pg, sizeof(T));
+    const int lane = threadIdx.x;
+    const int tx = blockIdx.x, ty = blockIdx.y, tz = tz0 + (int)blockIdx.z;
+    const int i = tx * 8 + (lane & 7), j = ty * 8 + (lane >> 3), l0 = tz * 8;
+    // this lane's column: NOUT grids at 8 nodes along x3 (zero outside the grid)
+    T gv[8][NOUT];
+#pragma unroll
+    for (int z = 0; z < 8; ++z) {
+        const int l = l0 + z;
+        const bool ok = i < Mt && j < Mt && l < 2 * Mt;
+        const long long node = ok ? ((long long)l * Mt + j) * Mt + i : 0;
+#pragma unroll
+        for (int c = 0; c < NOUT; ++c) gv[z][c] = ok ? grids[c * cs + node] : (T)0;
+    }
+    const int K = gg.K[0], KS = K + 1;
+    const int x_lo = tx - K < 0 ? 0 : tx - K;
+    for (int sz = tz - K; sz <= tz; ++sz) {
+        if (sz < 0) continue;
+        for (int sy = ty - K; sy <= ty; ++sy) {
+            if (sy < 0) continue;
+            const long long row = ((long long)sz * gg.nt[1] + sy) * gg.nt[0];
+            const uint32_t r0 = gtoff[row + x_lo], r1 = gtoff[row + tx + 1];
+            for (uint32_t c0 = r0; c0 < r1; c0 += GT_CHUNK) {
+                const int nr = (int)min((uint32_t)GT_CHUNK, r1 - c0);
+                const T* src = rec + (long long)c0 * stride;
+                for (int f = lane; f < nr * stride; f += 64) sh[f] = src[f];
+                __syncthreads();
+                for (int q = 0; q < nr; ++q) {
+                    const T* r = sh + q * stride;
+                    const int* hdr = reinterpret_cast<const int*>(r);
+                    const int bx = hdr[0], by = hdr[1], bz = hdr[2];
+                    // this tile beyond the support's last tile: nothing to add
+                    // (wavefront-uniform; the first tile is never beyond this one)
+                    if (tx > (bx + Pg - 1) / 8 || ty > (by + Pg - 1) / 8 || tz > (bz + Pg - 1) / 8) continue;
+                    const T* w = r + 16 / sizeof(T);
+                    const int dx = i - bx, dy = j - by;
+                    T s[6] = {0, 0, 0, 0, 0, 0};
+                    if ((unsigned)dx < (unsigned)Pg && (unsigned)dy < (unsigned)Pg) {
+                        const T wx = w[dx], wy = w[Pg + dy];
+                        const T dwx = GQ ? w[3 * Pg + dx] : (T)0, dwy = GQ ? w[4 * Pg + dy] : (T)0;
+#pragma unroll
+                        for (int z = 0; z < 8; ++z) {
+                            const int dz = l0 + z - bz;
+                            if ((unsigned)dz < (unsigned)Pg) {
+                                const T wz = w[2 * Pg + dz];
+                                const T wyz = wy * wz;
+                                const T wv = wx * wyz;
+#pragma unroll
+                                for (int c = 0; c < 3; ++c) s[c] += wv * gv[z][c];
+                                if (GQ) {
+                                    const T ph = gv[z][3];
+                                    s[3] += dwx * wyz * ph;
+                                    s[4] += wx * dwy * wz * ph;
+                                    s[5] += wx * wy * w[5 * Pg + dz] * ph;
+                                } else {
+#pragma unroll
+                                    for (int c = 3; c < 6; ++c) s[c] += wv * gv[z][c < NOUT ? c : 0];
+                                }
+                            }
+                        }
+                    }
+#pragma unroll
+                    for (int c = 0; c < 6; ++c) {
+                        T v = s[c];
+                        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+                        s[c] = v;
+                    }
+                    if (lane == 0) {
+                        const int slot = ((tz - bz / 8) * KS + (ty - by / 8)) * KS + (tx - bx / 8);
+                        T* o = part + ((long long)(c0 + q) * (KS * KS * KS) + slot) * 6;
+#pragma unroll
+                        for (int c = 0; c < 6; ++c) o[c] = s[c];
+                    }
+                }
+                __syncthreads();
+            }
+        }
+    }
+}
+
+template <typename T>
+hipError_t launch_gather_tiles(GridArgs gg, const T* grids, long long cs, const T* rec, const uint32_t* gtoff,
+                               int tz0, T* part, hipStream_t st)
+{
+    const int nz = gg.nt[2] - tz0;
+    if (nz <= 0) return hipSuccess;
+    size_t lds = (size_t)GT_CHUNK * target_record_stride(gg.P, sizeof(T)) * sizeof(T);
+    hipLaunchKernelGGL(k_gather_tiles<T>, dim3(gg.nt[0], gg.nt[1], nz), dim3(64), lds, st, gg, grids, cs, rec, gtoff,
+                       tz0, part);
+    return hipGetLastError();
+}
+
+// one thread per (tile-sorted) target: its slots, in order over the tiles of
+// its support box, then u = u_R + h^3 (T1 - x3 T2)
+template <typename T>
+__global__ void k_gather_final(GridArgs gg, const T* __restrict__ rec, const T* __restrict__ part, long long TT,
+                               const double* __restrict__ xs, const uint32_t* __restrict__ tperm,
+                               const double* __restrict__ upart, double* __restrict__ uout)
+{
+    const long long r = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (r >= TT) return;
+    const int Pg = gg.P;
+    const long long stride = (long long)trec_stride(Pg, sizeof(T));
+    const int* hdr = reinterpret_cast<const int*>(rec + r * stride);
+    const int b[3] = {hdr[0], hdr[1], hdr[2]};
+    const long long t = hdr[3];
+    const int KS = gg.K[0] + 1;
+    const T* ps = part + r * (long long)(KS * KS * KS) * 6;
+    double acc[6] = {0, 0, 0, 0, 0, 0};
+    for (int dz = 0; dz <= (b[2] + Pg - 1) / 8 - b[2] / 8; ++dz)
+        for (int dy = 0; dy <= (b[1] + Pg - 1) / 8 - b[1] / 8; ++dy)
+            for (int dx = 0; dx <= (b[0] + Pg - 1) / 8 - b[0] / 8; ++dx) {
+                const T* o = ps + ((dz * KS + dy) * KS + dx) * 6;
+#pragma unroll
+                for (int c = 0; c < 6; ++c) acc[c] += (double)o[c];
+            }
+    const long long o = tperm[t];
+    const double x3 = xs[2 * TT + t];
+    const double h3 = gg.h * gg.h * gg.h;
+    for (int a = 0; a < 3; ++a) uout[3 * o + a] = upart[3 * o + a] + h3 * (acc[a] - x3 * acc[3 + a]);
+}
+
+template <typename T>
+hipError_t launch_gather_final(GridArgs gg, const T* rec, const T* part, long long TT, const double* xs,
+                               const uint32_t* tperm, const double* upart, double* uout, hipStream_t st)
+{
+    if (TT <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_gather_final<T>, dim3((unsigned)((TT + 255) / 256)), dim3(256), 0, st, gg, rec, part, TT, xs,
+                       tperm, upart, uout);
+    return hipGetLastError();
+}
+
+// Target-per-wavefront form, for small supports (where a tile holds few of a
+// support's nodes and the per-tile reductions of the node-owner form cost
+// more than the repeated reads): lanes cover Pg consecutive x1 nodes of
+// floor(64 / Pg) rows at a time; blocks of 4 consecutive (cell-sorted, so
+// nearby) targets, spread over the XCDs in contiguous ranges so that
+// overlapping supports share an L2.
 template <typename T>
 __global__ void __launch_bounds__(256) k_gather(GridArgs g, const T* __restrict__ grids, long long cs,
                                                 const double* __restrict__ xs, const uint32_t* __restrict__ tperm,
@@ -444,5 +682,17 @@ template hipError_t launch_gather<double>(GridArgs, const double*, long long, co
                                           long long, const double*, double*, hipStream_t);
 template hipError_t launch_gather<float>(GridArgs, const float*, long long, const double*, const uint32_t*, long long,
                                          const double*, double*, hipStream_t);
+template hipError_t launch_target_records<double>(const double*, const uint32_t*, long long, GridArgs, double*,
+                                                  hipStream_t);
+template hipError_t launch_target_records<float>(const double*, const uint32_t*, long long, GridArgs, float*,
+                                                 hipStream_t);
+template hipError_t launch_gather_tiles<double>(GridArgs, const double*, long long, const double*, const uint32_t*,
+                                                int, double*, hipStream_t);
+template hipError_t launch_gather_tiles<float>(GridArgs, const float*, long long, const float*, const uint32_t*, int,
+                                               float*, hipStream_t);
+template hipError_t launch_gather_final<double>(GridArgs, const double*, const double*, long long, const double*,
+                                                const uint32_t*, const double*, double*, hipStream_t);
+template hipError_t launch_gather_final<float>(GridArgs, const float*, const float*, long long, const double*,
+                                               const uint32_t*, const double*, double*, hipStream_t);
 
 }  // namespace ehs

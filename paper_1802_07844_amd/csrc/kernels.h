@@ -163,8 +163,28 @@ hipError_t launch_records(int family, bool dgrid, const double* y, const double*
 template <typename T>
 hipError_t launch_spread(int family, bool dgrid, GridArgs g, const T* rec, const uint32_t* toff, T* grids, long long cs,
                          hipStream_t st);
+// quadrature at the targets, one wavefront per target (small supports)
 template <typename T>
 hipError_t launch_gather(GridArgs g, const T* grids, long long cs, const double* x, const uint32_t* tperm,
                          long long T_, const double* upart, double* uout, hipStream_t st);
+// quadrature at the targets, node-owner form (see grid.hip):
+//   keys: quadrature tile of each target's support base (xs: cell-sorted SoA targets)
+hipError_t launch_target_keys(const double* xs, long long T_, GridArgs gg, uint32_t* keys, uint32_t* idx,
+                              hipStream_t st);
+//   records of the tile-sorted targets: support base, cell-sorted index, 1D factors
+size_t target_record_stride(int Pg, size_t esz);
+template <typename T>
+hipError_t launch_target_records(const double* xs, const uint32_t* perm, long long T_, GridArgs gg, T* rec,
+                                 hipStream_t st);
+//   slots per target of the partial sums (one per tile of its support box)
+int gather_slots(const GridArgs& gg);
+//   one wavefront per tile: partial sums of every target whose support reaches it
+template <typename T>
+hipError_t launch_gather_tiles(GridArgs gg, const T* grids, long long cs, const T* rec, const uint32_t* gtoff,
+                               int tz0, T* part, hipStream_t st);
+//   per target: the partial sums in a fixed order, and the FP64 combination
+template <typename T>
+hipError_t launch_gather_final(GridArgs gg, const T* rec, const T* part, long long T_, const double* xs,
+                               const uint32_t* tperm, const double* upart, double* uout, hipStream_t st);
 
 }  // namespace ehs
