@@ -111,6 +111,7 @@ struct CellGeom {
     int nc[3];        // cells per axis
     double lo[3];     // origin of the cell grid (x3 origin is the wall)
     double inv[3];    // 1 / cell side
+    int nr;           // neighbour reach in cells per axis: side >= r_c / nr
 };
 
 struct RealArgs {

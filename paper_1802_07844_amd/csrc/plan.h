@@ -333,11 +333,22 @@ inline int make_plan(const PlanInput& in, Plan* out)
     p.By = p.Bx;
     if (p.Bx < 2 || p.By < 1) return -3;
 
-    // real-space cells (side >= r_c; x3 measured from the wall)
+    // real-space cells (x3 measured from the wall): side >= r_c, walked
+    // 3 x 3 x 3 around a target's cell; where cells of that side would hold
+    // many targets (256 or more on average), side >= r_c / 2 walked 5 x 5 x 5:
+    // the candidates' volume drops from 27 r_c^3 to 15.6 r_c^3 while the
+    // cells' chunks of 64 targets stay mostly full.  Measured: N = 1e6 with
+    // 2000 neighbours (480 targets per r_c cell) 38.6 -> 29.1 ms; with 600
+    // (146 per cell) 11.3 -> 14.9 ms and with 300 at N = 1e5 (75 per cell)
+    // 0.72 -> 1.0 ms, the chunks of the smaller cells being too sparse.
     double extent[3] = {ext1, ext2, ext3};
+    double cells_rc = 1.0;
+    for (int a = 0; a < 3; ++a) cells_rc *= std::max(1.0, std::floor(extent[a] / in.rc));
+    const int nr = (double)in.T >= 256.0 * cells_rc ? 2 : 1;
+    p.cg.nr = nr;
     long long ncell = 1;
     for (int a = 0; a < 3; ++a) {
-        int nc = (int)std::floor(extent[a] / in.rc);
+        int nc = (int)std::floor(extent[a] * nr / in.rc);
         nc = std::max(1, std::min(nc, 256));
         p.cg.nc[a] = nc;
         p.cg.lo[a] = a < 2 ? in.lo[a] : 0.0;

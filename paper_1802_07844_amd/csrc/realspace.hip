@@ -1,13 +1,14 @@
 // Real-space (short-range) part of the half-space Ewald sum.
 //
 // One wavefront per chunk of <= 64 targets of one cell (cells have side
-// >= r_c).  All lanes walk the same neighbour-cell source ranges (staged in
-// LDS per batch); each lane accumulates its own target.  Direct terms
+// >= r_c / nr, so the neighbours lie within nr cells).  All lanes walk the
+// same neighbour-cell source ranges (staged in LDS per batch); each lane
+// accumulates its own target.  Direct terms
 // use the Ewald real-space kernels S_R, T_R, W_R (paper Sec. 4 and Appendix);
 // image and correction terms use the same kernels at r~ = x - y^I together
 // with the real-space parts of G, grad G, grad grad G and grad grad grad G
 // (paper eq. (G_R), written with erfc instead of 1 - erf).  Only targets in
-// the bottom cell layer can be within r_c of an image.
+// the bottom nr cell layers can be within r_c of an image.
 #include <math.h>
 
 #include <type_traits>
@@ -204,7 +205,8 @@ __global__ void __launch_bounds__(64) k_realspace(RealArgs a, const double* __re
     const double rc2 = a.rc2;
     T acc[3] = {0, 0, 0};
     double self[3] = {0.0, 0.0, 0.0};
-    const int lo1 = c1 > 0 ? c1 - 1 : 0, hi1 = c1 < n0 - 1 ? c1 + 1 : n0 - 1;
+    const int nr = a.cg.nr;  // cells of side >= r_c / nr: neighbours within nr cells
+    const int lo1 = c1 - nr > 0 ? c1 - nr : 0, hi1 = c1 + nr < n0 - 1 ? c1 + nr : n0 - 1;
 
     // one batch of sources [mb, mb + nb) of the sorted arrays; IMG: their
     // images (and harmonic corrections) instead of the direct terms
@@ -293,10 +295,10 @@ __global__ void __launch_bounds__(64) k_realspace(RealArgs a, const double* __re
         };
     };
 
-    for (int d3 = -1; d3 <= 1; ++d3) {
+    for (int d3 = -nr; d3 <= nr; ++d3) {
         int cc3 = c3 + d3;
         if (cc3 < 0 || cc3 >= n2) continue;
-        for (int d2 = -1; d2 <= 1; ++d2) {
+        for (int d2 = -nr; d2 <= nr; ++d2) {
             int cc2 = c2i + d2;
             if (cc2 < 0 || cc2 >= n1) continue;
             long long row = ((long long)cc3 * n1 + cc2) * n0;
@@ -309,15 +311,19 @@ __global__ void __launch_bounds__(64) k_realspace(RealArgs a, const double* __re
     // target near the wall they are of size 1/(x3 + y3)^2 and cancel to O(1)
     // on the wall, beyond what FP32 can resolve.  Only sources within r_c of
     // the wall have images here, so this is a small share of the work.
+    // (a target and a source can both lie within r_c of the wall only in the
+    // bottom nr cell layers)
     double acci[3] = {0.0, 0.0, 0.0};
-    if (c3 == 0) {
-        for (int d2 = -1; d2 <= 1; ++d2) {
-            int cc2 = c2i + d2;
-            if (cc2 < 0 || cc2 >= n1) continue;
-            long long row = (long long)cc2 * n0;
-            uint32_t s0 = a.src_off[row + lo1], s1 = a.src_off[row + hi1 + 1];
-            for (uint32_t mb = s0; mb < s1; mb += SBI)
-                batch(mb, (int)min((uint32_t)SBI, s1 - mb), std::true_type())(acci, nullptr);
+    if (c3 < nr) {
+        for (int cc3 = 0; cc3 < nr && cc3 < n2; ++cc3) {
+            for (int d2 = -nr; d2 <= nr; ++d2) {
+                int cc2 = c2i + d2;
+                if (cc2 < 0 || cc2 >= n1) continue;
+                long long row = ((long long)cc3 * n1 + cc2) * n0;
+                uint32_t s0 = a.src_off[row + lo1], s1 = a.src_off[row + hi1 + 1];
+                for (uint32_t mb = s0; mb < s1; mb += SBI)
+                    batch(mb, (int)min((uint32_t)SBI, s1 - mb), std::true_type())(acci, nullptr);
+            }
         }
     }
     if (act) {

@@ -244,3 +244,21 @@ def test_correction_grids_end_above_the_highest_image_support(dgrid_family, z0):
     assert top < r.x3_corr_end <= 2 * r.Mt
     assert r.x3_corr_end <= top + 2 + 16
     assert r.x3_corr_end <= r.Mt + r.Ps // 2 + 18  # never above the wall's support
+
+
+@pytest.mark.parametrize("n,nb", [(100_000, 30), (1_000_000, 2000), (4_000_000, 300)])
+def test_real_space_cells_cover_the_cutoff(n, nb):
+    """Cells have side >= r_c (3^3 walk) or, where cells of side r_c would
+    hold 256 targets or more on average, side >= r_c / 2 (5^3 walk): either
+    way the walked cells hold every source within r_c."""
+    rc = (nb * 3.0 / (4.0 * math.pi * n)) ** (1.0 / 3.0)
+    r = _plan(n=n, rc=rc, xi=ehs.xi_for_cutoff("stokeslet", rc, 0.5e-10), prec=1)
+    L = [1.0, 1.0, 1.0]
+    dense = n >= 256 * np.prod([max(1.0, math.floor(x / rc)) for x in L])
+    reach = 2 if dense else 1
+    for a in range(3):
+        side = L[a] / r.ncell[a]
+        assert side * reach >= rc * (1 - 1e-12)
+        assert r.ncell[a] <= 256
+    if dense:
+        assert r.ncell[0] >= 2 * math.floor(1.0 / rc) - 1 or r.ncell[0] == 256
