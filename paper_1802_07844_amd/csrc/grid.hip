@@ -465,6 +465,14 @@ __global__ void __launch_bounds__(64) k_gather_tiles(GridArgs gg, const T* __res
     }
     const int K = gg.K[0], KS = K + 1;
     const int x_lo = tx - K < 0 ? 0 : tx - K;
+    // staged per target: its header and, for each factor array (W along x1,
+    // x2, x3 and, with GQ, their derivatives), the 8 entries that fall on
+    // this tile (zero outside the support), so lanes index them by their
+    // own position in the tile
+    constexpr int NA = GQ ? 6 : 3;
+    constexpr int HS = 16 / sizeof(T);
+    constexpr int SS = HS + 8 * NA;
+    const int org[3] = {tx * 8, ty * 8, l0};
     for (int sz = tz - K; sz <= tz; ++sz) {
         if (sz < 0) continue;
         for (int sy = ty - K; sy <= ty; ++sy) {
@@ -473,41 +481,44 @@ __global__ void __launch_bounds__(64) k_gather_tiles(GridArgs gg, const T* __res
             const uint32_t r0 = gtoff[row + x_lo], r1 = gtoff[row + tx + 1];
             for (uint32_t c0 = r0; c0 < r1; c0 += GT_CHUNK) {
                 const int nr = (int)min((uint32_t)GT_CHUNK, r1 - c0);
-                const T* src = rec + (long long)c0 * stride;
-                for (int f = lane; f < nr * stride; f += 64) sh[f] = src[f];
+                for (int f = lane; f < nr * SS; f += 64) {
+                    const int q = f / SS, e = f - q * SS;
+                    const T* R = rec + (long long)(c0 + q) * stride;
+                    if (e < HS) {
+                        sh[f] = R[e];
+                    } else {
+                        const int k = e - HS, arr = k >> 3, u = k & 7, ax = arr % 3;
+                        const int off = org[ax] + u - reinterpret_cast<const int*>(R)[ax];
+                        sh[f] = (off >= 0 && off < Pg) ? R[HS + arr * Pg + off] : (T)0;
+                    }
+                }
                 __syncthreads();
                 for (int q = 0; q < nr; ++q) {
-                    const T* r = sh + q * stride;
+                    const T* r = sh + q * SS;
                     const int* hdr = reinterpret_cast<const int*>(r);
                     const int bx = hdr[0], by = hdr[1], bz = hdr[2];
                     // this tile beyond the support's last tile: nothing to add
                     // (wavefront-uniform; the first tile is never beyond this one)
                     if (tx > (bx + Pg - 1) / 8 || ty > (by + Pg - 1) / 8 || tz > (bz + Pg - 1) / 8) continue;
-                    const T* w = r + 16 / sizeof(T);
-                    const int dx = i - bx, dy = j - by;
+                    const T* w = r + HS;  // [array][8]
+                    const T wx = w[lane & 7], wy = w[8 + (lane >> 3)];
+                    const T dwx = GQ ? w[24 + (lane & 7)] : (T)0, dwy = GQ ? w[32 + (lane >> 3)] : (T)0;
                     T s[6] = {0, 0, 0, 0, 0, 0};
-                    if ((unsigned)dx < (unsigned)Pg && (unsigned)dy < (unsigned)Pg) {
-                        const T wx = w[dx], wy = w[Pg + dy];
-                        const T dwx = GQ ? w[3 * Pg + dx] : (T)0, dwy = GQ ? w[4 * Pg + dy] : (T)0;
 #pragma unroll
-                        for (int z = 0; z < 8; ++z) {
-                            const int dz = l0 + z - bz;
-                            if ((unsigned)dz < (unsigned)Pg) {
-                                const T wz = w[2 * Pg + dz];
-                                const T wyz = wy * wz;
-                                const T wv = wx * wyz;
+                    for (int z = 0; z < 8; ++z) {
+                        const T wz = w[16 + z];
+                        const T wyz = wy * wz;
+                        const T wv = wx * wyz;
 #pragma unroll
-                                for (int c = 0; c < 3; ++c) s[c] += wv * gv[z][c];
-                                if (GQ) {
-                                    const T ph = gv[z][3];
-                                    s[3] += dwx * wyz * ph;
-                                    s[4] += wx * dwy * wz * ph;
-                                    s[5] += wx * wy * w[5 * Pg + dz] * ph;
-                                } else {
+                        for (int c = 0; c < 3; ++c) s[c] += wv * gv[z][c];
+                        if (GQ) {
+                            const T ph = gv[z][3];
+                            s[3] += dwx * wyz * ph;
+                            s[4] += wx * dwy * wz * ph;
+                            s[5] += wx * wy * w[40 + z] * ph;
+                        } else {
 #pragma unroll
-                                    for (int c = 3; c < 6; ++c) s[c] += wv * gv[z][c < NOUT ? c : 0];
-                                }
-                            }
+                            for (int c = 3; c < 6; ++c) s[c] += wv * gv[z][c < NOUT ? c : 0];
                         }
                     }
 #pragma unroll
@@ -535,7 +546,7 @@ hipError_t launch_gather_tiles(GridArgs gg, const T* grids, long long cs, const 
 {
     const int nz = gg.nt[2] - tz0;
     if (nz <= 0) return hipSuccess;
-    size_t lds = (size_t)GT_CHUNK * target_record_stride(gg.P, sizeof(T)) * sizeof(T);
+    size_t lds = (size_t)GT_CHUNK * (16 / sizeof(T) + 8 * (sizeof(T) == 8 ? 6 : 3)) * sizeof(T);
     hipLaunchKernelGGL(k_gather_tiles<T>, dim3(gg.nt[0], gg.nt[1], nz), dim3(64), lds, st, gg, grids, cs, rec, gtoff,
                        tz0, part);
     return hipGetLastError();
