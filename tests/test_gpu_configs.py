@@ -181,3 +181,34 @@ def test_error_codes(ctx):
     xi = ehs.xi_for_cutoff("stokeslet", 0.3, 0.5e-10)
     u = ctx.evaluate("stokeslet", yd, fd, yd, xi, 0.3, 1e-10)
     assert oracle.rel_rms(oracle.halfspace("stokeslet", y, f, y), u.cpu().numpy()) <= 1e-10
+
+
+@pytest.mark.parametrize("prec,tol,nb", [(1, 1e-10, 30), (2, 1e-5, 300)])
+def test_separate_targets_at_scale(ctx, prec, tol, nb):
+    """Field evaluation at targets other than the sources, at scale: N = 1e5
+    sources, T = 2e5 targets (uniform, a tenth of them on the wall x3 = 0,
+    where the half-space sum vanishes), compared on a sample with the oracle."""
+    n, t = 100_000, 200_000
+    y, f = workloads.uniform_stokeslet(n, workloads.SEED_BASE + 7)
+    g = workloads.rng(workloads.SEED_BASE + 8)
+    x = workloads.uniform_positions(g, t)
+    x[: t // 10, 2] = 0.0
+    rc = _rc(nb, n)
+    xi = ehs.xi_for_cutoff("stokeslet", rc, tol / 2)
+    ctx.set_option(ehs.OPT_PRECISION, prec)
+    yd = torch.from_numpy(y).to("cuda:0")
+    u, rep = ctx.evaluate("stokeslet", yd, torch.from_numpy(f).to("cuda:0"), torch.from_numpy(x).to("cuda:0"), xi, rc,
+                          tol, report=True)
+    torch.cuda.synchronize()
+    u = u.cpu().numpy()
+    idx = np.sort(workloads.rng(17).choice(t, 1024, replace=False))
+    ref = oracle.halfspace("stokeslet", y, f, x[idx])
+    err = oracle.rel_rms(ref, u[idx])
+    wall = u[: t // 10]
+    scale = np.sqrt(np.mean(ref ** 2))
+    print(f"separate targets: N={n} T={t} prec={rep.precision} Mt={rep.Mt} rel-RMS={err:.3e} "
+          f"max |u| on the wall / rms={np.max(np.abs(wall)) / scale:.2e}")
+    assert rep.precision == prec
+    assert np.all(np.isfinite(u))
+    assert err <= tol
+    assert np.max(np.abs(wall)) <= 10 * tol * scale
