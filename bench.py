@@ -25,6 +25,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+FP64_VALU_PEAK_TFS = 78.6
 
 
 def _stage_bytes(rep, ncin, esz):
@@ -83,6 +84,21 @@ def _measured_traffic(name):
     return None
 
 
+def _measured_valu(name):
+    """FP64 flops per launch of the fused x3 pass from a committed rocprofv3
+    counter summary (a line 'valu-json: {...}' in profiles/<name>), if it was
+    taken on the current kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", name)
+    if not os.path.exists(path):
+        return None
+    for line in open(path):
+        if line.startswith("valu-json:"):
+            d = json.loads(line.split(":", 1)[1])
+            if d.get("sources_sha") == _sources_sha():
+                return d
+    return None
+
+
 def _ncin(rep):
     """Input grids of the plan: the kernel grid and either the correction
     density (FP64 D-grid plans) or the separate correction grids."""
@@ -91,7 +107,7 @@ def _ncin(rep):
     return nca + (1 if rep.dgrid else ncb)
 
 
-def _roofline(rep, stage_ms, ncin, esz, traffic_file=None):
+def _roofline(rep, stage_ms, ncin, esz, traffic_file=None, valu_file=None):
     sb = _stage_bytes(rep, ncin, esz)
     dom = max(sb.keys(), key=lambda k: stage_ms[k])
     launches = 1
@@ -105,9 +121,17 @@ def _roofline(rep, stage_ms, ncin, esz, traffic_file=None):
         t = _measured_traffic(traffic_file)
         if t is not None:
             traffic = t["bytes_per_launch"] * (per_launch / t["algorithmic_bytes_per_launch"])
+    # the vector FP64 rate of the same launches (flops from the committed
+    # counter summary, time from this run)
+    valu = None
+    if valu_file and dom == "z_scale" and esz == 8:
+        v = _measured_valu(valu_file)
+        if v is not None:
+            tf = v["fp64_flops_per_launch"] / (ms_launch * 1e-3) / 1e12
+            valu = {"achieved": tf, "peak": FP64_VALU_PEAK_TFS, "unit": "TFLOP/s", "frac": tf / FP64_VALU_PEAK_TFS}
     return {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "bytes_per_launch": per_launch,
-            "launches_per_step": launches, "ms_per_launch": ms_launch}
+            "launches_per_step": launches, "ms_per_launch": ms_launch, "valu_fp64": valu}
 
 
 def _serve_rc(kernel, n, tol):
@@ -313,7 +337,8 @@ def main():
 
     # dominant kernel and its roofline: algorithmic bytes per launch / average
     # launch duration (HIP events on the evaluation's stream)
-    roofline = _roofline(rep, stage_ms, _ncin(rep), 8, "z_scale_stokeslet_N100k_fp64_counters.md")
+    roofline = _roofline(rep, stage_ms, _ncin(rep), 8, "z_scale_stokeslet_N100k_fp64_counters.md",
+                         "valu_stokeslet_N100k_fp64_counters.md")
 
     result = {
         "metric": "points/sec at rel-RMS 1e-10 (FP64)",
