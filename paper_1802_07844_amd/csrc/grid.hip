@@ -592,10 +592,10 @@ hipError_t launch_gather_final(GridArgs gg, const T* rec, const T* part, long lo
     return hipGetLastError();
 }
 
-// Target-per-wavefront form, for small supports (where a tile holds few of a
-// support's nodes and the per-tile reductions of the node-owner form cost
-// more than the repeated reads): lanes cover Pg consecutive x1 nodes of
-// floor(64 / Pg) rows at a time; blocks of 4 consecutive (cell-sorted, so
+// Target-per-wavefront form, for small supports and dense targets (where
+// the per-tile reductions of the node-owner form cost more than the repeated
+// reads, which then hit L2 more often): lanes cover Pg consecutive x1 nodes
+// of floor(64 / Pg) rows at a time; blocks of 4 consecutive (cell-sorted, so
 // nearby) targets, spread over the XCDs in contiguous ranges so that
 // overlapping supports share an L2.
 template <typename T>
