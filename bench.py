@@ -10,9 +10,11 @@ during warm-up (it depends only on the grid size and is excluded, as in the
 paper's timings).
 
 Prints one JSON line.  Extra fields: the FP32 path on the same workload at
-tol 1e-5, the relative RMS error of both against the FP64 oracle on a sample
-of targets, per-stage times, the roofline of the dominant kernel and the
-oracle's own throughput on the host cores (cpu_baseline).
+tol 1e-5, the same FP64 problem at the runtime-optimal (xi, r_c) that the
+tuning procedure of the paper's results section finds (`tuned`), the relative
+RMS error of all three against the FP64 oracle on a sample of targets,
+per-stage times, the roofline of the dominant kernel and the oracle's own
+throughput on the host cores (cpu_baseline).
 """
 import argparse
 import json
@@ -272,6 +274,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving stream")
+    ap.add_argument("--no-tune", action="store_true", help="skip the runtime-optimal (xi, r_c) search")
+    ap.add_argument("--tune-evals", type=int, default=12, help="candidates the (xi, r_c) search may time")
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--serve-util", type=float, default=0.7, help="arrival rate as a fraction of measured capacity")
     ap.add_argument("--serve-slots", type=int, default=4)
@@ -363,6 +367,32 @@ def main():
         "roofline": roofline,
     }
 
+    # the same problem at the runtime-optimal (xi, r_c) of the tuning procedure
+    # (both truncation errors held, xi perturbed), timed like the main line
+    ut = None
+    if not args.no_tune:
+        tres = ctx.tune("stokeslet", yd, fd, yd, xi, rc, tol, max_evals=args.tune_evals)
+        xit, rct = tres["xi"], tres["r_c"]
+        outt = torch.empty_like(out)
+        for _ in range(args.warmup):
+            rt = ctx.stokeslet(yd, fd, yd, xit, rct, tol, out=outt, report=True)[1]
+        torch.cuda.synchronize()
+        stt = np.zeros(ehs.NSTAGES)
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            rt = ctx.stokeslet(yd, fd, yd, xit, rct, tol, out=outt, report=True)[1]
+            stt += np.array(list(rt.ms_stage))
+        torch.cuda.synchronize()
+        dtt = time.perf_counter() - t0
+        ut = outt.cpu().numpy()
+        del outt
+        result["tuned"] = {"value": n * args.steps / dtt, "unit": "points/s", "ms_per_step": dtt / args.steps * 1e3,
+                           "dtype": "f64", "tol": tol, "xi": xit, "r_c": rct,
+                           "neighbours": 4.0 / 3.0 * math.pi * rct**3 * n, "M": rt.M, "P": rt.P, "Mt": rt.Mt,
+                           "stage_ms": dict(zip(ehs.STAGES, (stt / args.steps).tolist())),
+                           "search": [{"xi": a, "r_c": b, "ms": c} for a, b, c in tres["trace"]],
+                           "note": "same points and forces; xi perturbed with both truncation estimates held"}
+
     # FP32 path on the same workload at tol 1e-5
     u32 = None
     if not args.no_fp32:
@@ -418,6 +448,8 @@ def main():
         result["rel_rms_fp64"] = oracle.rel_rms(ref, u64[idx])
         if u32 is not None:
             result["fp32"]["rel_rms"] = oracle.rel_rms(ref, u32[idx])
+        if ut is not None:
+            result["tuned"]["rel_rms"] = oracle.rel_rms(ref, ut[idx])
     if not args.no_serve:
         del out
         if u32 is not None:

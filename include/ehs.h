@@ -163,6 +163,44 @@ const char* ehs_strerror(int code);
 double ehs_xi_for_cutoff(int family, double r_c, double tol, double L);
 
 /*
+ * Cutoff r_c at which the real-space truncation estimate (as above) equals
+ * `est` for the Ewald parameter xi and box size L: the inverse of
+ * ehs_xi_for_cutoff in the other variable.  Host-only arithmetic; returns
+ * -1 for bad arguments or when est is not reached for xi r_c in [1, 100].
+ */
+double ehs_cutoff_for_estimate(int family, double xi, double est, double L);
+
+/*
+ * Runtime-optimal Ewald parameter (the tuning procedure of Sec. 7): the two
+ * truncation errors are held where the starting point (xi0, r_c0) puts them
+ * while xi is perturbed, so that xi r_c and k_inf / xi stay (nearly)
+ * constant and only the division of the work between the real-space sum
+ * and the grid changes.  Candidates are xi = xi0 2^(j/4): r_c is the cutoff
+ * with the starting point's real-space estimate (ehs_cutoff_for_estimate)
+ * and the planner picks the grid from tol as always.  The search times
+ * j = 0, then j = -1 and j = +1, and walks in the faster direction while
+ * the time falls; it stops at max_evals candidates (1..64), at a cutoff
+ * above half the box, or where no grid is admissible or the workspace does
+ * not fit (EHS_ERANGE / EHS_ENOMEM of a candidate end the walk, they are not
+ * returned).  Each candidate is evaluated once untimed (workspace and
+ * multiplier precompute, which the paper's timings exclude too) and then
+ * twice, timed on the host around a synchronised `stream`; its time is the
+ * faster of the two.
+ *   arguments as for the single-call entry points of `family` (0 stokeslet,
+ *   1 stresslet, 2 rotlet; strengths N x 3, N x 6, N x 3), T >= 1;
+ *   u_out: T x 3, on return the result at the chosen parameters;
+ *   best: host array of 3, on return (xi, r_c, milliseconds) of the fastest
+ *   candidate; trace (host, nullable): 3 max_evals values, (xi, r_c, ms) of
+ *   every timed candidate in the order tried, their count in *ntrace
+ *   (nullable); rep (nullable): the report of the final evaluation.
+ * Synchronises `stream` repeatedly; returns 0 or the first error of an
+ * evaluation other than the two that end the walk.
+ */
+int ehs_tune(ehs_ctx* ctx, int family, const double* sources, const double* strengths, int64_t N,
+             const double* targets, int64_t T, double xi0, double r_c0, double tol, int max_evals,
+             double* u_out, double* best, double* trace, int* ntrace, void* stream, ehs_report* rep);
+
+/*
  * Parameter selection only (host arithmetic, no device work): the plan that
  * an evaluation would use for N sources, T targets in the bounding box
  * [lo, hi] (x3 of the box measured from the wall), strength measure Q (sum of

@@ -88,6 +88,12 @@ def lib():
             L.ehs_strerror.restype = ctypes.c_char_p
             L.ehs_xi_for_cutoff.argtypes = [ctypes.c_int, dp, dp, dp]
             L.ehs_xi_for_cutoff.restype = dp
+            L.ehs_cutoff_for_estimate.argtypes = [ctypes.c_int, dp, dp, dp]
+            L.ehs_cutoff_for_estimate.restype = dp
+            L.ehs_tune.argtypes = [vp, ctypes.c_int, vp, vp, i64, vp, i64, dp, dp, dp, ctypes.c_int, vp,
+                                   ctypes.POINTER(dp), ctypes.POINTER(dp), ctypes.POINTER(ctypes.c_int), vp,
+                                   ctypes.POINTER(Report)]
+            L.ehs_tune.restype = ctypes.c_int
             L.ehs_truncated_kernel_hat.argtypes = [ctypes.c_int, dp, dp]
             L.ehs_truncated_kernel_hat.restype = dp
             L.ehs_plan_query.argtypes = [ctypes.c_int, i64, i64, ctypes.POINTER(dp), ctypes.POINTER(dp), dp, dp, dp,
@@ -151,6 +157,12 @@ def xi_for_cutoff(family, r_c: float, tol: float, L: float = 1.0) -> float:
     """xi for which the real-space truncation estimate equals tol/2 (host arithmetic in the library)."""
     fam = FAMILIES[family] if isinstance(family, str) else int(family)
     return float(lib().ehs_xi_for_cutoff(fam, float(r_c), float(tol), float(L)))
+
+
+def cutoff_for_estimate(family, xi: float, est: float, L: float = 1.0) -> float:
+    """r_c at which the real-space truncation estimate equals est (host arithmetic in the library)."""
+    fam = FAMILIES[family] if isinstance(family, str) else int(family)
+    return float(lib().ehs_cutoff_for_estimate(fam, float(xi), float(est), float(L)))
 
 
 def plan_query(family, N, T, lo, hi, Q, xi, r_c, tol, precision=0) -> Report:
@@ -232,6 +244,35 @@ class Context:
                 _stream_handle(stream), ctypes.byref(rep))
         check(rc)
         return (out, rep) if report else out
+
+    def tune(self, family, sources, strengths, targets, xi0, r_c0, tol, max_evals=12, out=None, stream=None):
+        """Runtime-optimal (xi, r_c) from the starting point (xi0, r_c0) by ehs_tune.
+
+        Returns a dict: u (the result at the chosen parameters), xi, r_c, ms
+        (its time), trace (list of (xi, r_c, ms) per timed candidate) and report.
+        """
+        import torch
+
+        fam = FAMILIES[family] if isinstance(family, str) else int(family)
+        ncol = 6 if fam == STRESSLET else 3
+        ys = _dev_ptr(sources, "sources", 3)
+        ss = _dev_ptr(strengths, "strengths", ncol)
+        if strengths.shape[0] != sources.shape[0]:
+            raise ValueError("strengths and sources differ in length")
+        xs = _dev_ptr(targets, "targets", 3)
+        T = targets.shape[0]
+        if out is None:
+            out = torch.empty((T, 3), dtype=torch.float64, device=targets.device)
+        uo = _dev_ptr(out, "out", 3)
+        best = (ctypes.c_double * 3)()
+        trace = (ctypes.c_double * (3 * int(max_evals)))()
+        ntr = ctypes.c_int(0)
+        rep = Report()
+        check(lib().ehs_tune(self._h, fam, ys, ss, int(sources.shape[0]), xs, int(T), float(xi0), float(r_c0),
+                             float(tol), int(max_evals), uo, best, trace, ctypes.byref(ntr), _stream_handle(stream),
+                             ctypes.byref(rep)))
+        tr = [(trace[3 * i], trace[3 * i + 1], trace[3 * i + 2]) for i in range(ntr.value)]
+        return {"u": out, "xi": best[0], "r_c": best[1], "ms": best[2], "trace": tr, "report": rep}
 
     def stokeslet(self, y, f, x, xi, r_c, tol, **kw):
         return self.evaluate(STOKESLET, y, f, x, xi, r_c, tol, **kw)

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstring>
 #include <map>
@@ -909,6 +910,84 @@ const char* ehs_strerror(int code)
 }
 
 double ehs_xi_for_cutoff(int family, double r_c, double tol, double L) { return xi_for_cutoff(family, r_c, tol, L); }
+
+double ehs_cutoff_for_estimate(int family, double xi, double est, double L)
+{
+    return cutoff_for_estimate(family, xi, est, L);
+}
+
+int ehs_tune(ehs_ctx* c, int family, const double* y, const double* s, int64_t N, const double* x, int64_t T,
+             double xi0, double rc0, double tol, int max_evals, double* u, double* best, double* trace, int* ntrace,
+             void* stream, ehs_report* rep)
+{
+    if (!c || !u || !best || T < 1 || family < 0 || family > 2) return EHS_EINVAL;
+    if (max_evals < 1 || max_evals > 64 || !(xi0 > 0) || !(rc0 > 0)) return EHS_EINVAL;
+    if (ntrace) *ntrace = 0;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    // the starting point fixes the box and the real-space estimate
+    ehs_report r0;
+    int r = evaluate(c, family, y, s, N, x, T, xi0, rc0, tol, u, stream, &r0);
+    if (r) return r;
+    const double L = r0.L, est = r0.est_real;
+
+    struct Cand {
+        int j;
+        double xi, rc, ms;
+    };
+    std::vector<Cand> tried;
+    // 0: timed; 1: inadmissible (ends the walk in its direction); < 0: error
+    auto probe = [&](int j) -> int {
+        if ((int)tried.size() >= max_evals) return 1;
+        const double xi = xi0 * std::pow(2.0, 0.25 * j);
+        const double rc = j == 0 ? rc0 : cutoff_for_estimate(family, xi, est, L);
+        if (!(rc > 0) || rc > 0.5 * L) return 1;
+        int e = evaluate(c, family, y, s, N, x, T, xi, rc, tol, u, stream, nullptr);  // untimed
+        if (e == EHS_ERANGE || e == EHS_ENOMEM) return 1;
+        if (e) return e;
+        double ms = 1e300;
+        for (int k = 0; k < 2; ++k) {
+            if (hipStreamSynchronize(st) != hipSuccess) return EHS_EHIP;
+            auto t0 = std::chrono::steady_clock::now();
+            if ((e = evaluate(c, family, y, s, N, x, T, xi, rc, tol, u, stream, nullptr))) return e;
+            if (hipStreamSynchronize(st) != hipSuccess) return EHS_EHIP;
+            ms = std::min(ms, std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count());
+        }
+        tried.push_back({j, xi, rc, ms});
+        return 0;
+    };
+    if ((r = probe(0)) < 0) return r;
+    if (r > 0) return EHS_ERANGE;  // the starting point itself is not admissible
+    // first step down in xi (larger cutoff, smaller grid), else up
+    int dir = -1;
+    if ((r = probe(-1)) < 0) return r;
+    if (r > 0 || tried.back().ms >= tried[0].ms) {
+        dir = +1;
+        if ((r = probe(+1)) < 0) return r;
+        if (r > 0 || tried.back().ms >= tried[0].ms) dir = 0;
+    }
+    if (dir != 0) {
+        double last = tried.back().ms;
+        for (int j = 2 * dir;; j += dir) {
+            if ((r = probe(j)) < 0) return r;
+            if (r > 0 || tried.back().ms >= last) break;
+            last = tried.back().ms;
+        }
+    }
+    const Cand* b = &tried[0];
+    for (const Cand& t : tried)
+        if (t.ms < b->ms) b = &t;
+    best[0] = b->xi;
+    best[1] = b->rc;
+    best[2] = b->ms;
+    if (trace)
+        for (size_t i = 0; i < tried.size(); ++i) {
+            trace[3 * i] = tried[i].xi;
+            trace[3 * i + 1] = tried[i].rc;
+            trace[3 * i + 2] = tried[i].ms;
+        }
+    if (ntrace) *ntrace = (int)tried.size();
+    return evaluate(c, family, y, s, N, x, T, b->xi, b->rc, tol, u, stream, rep);
+}
 
 int ehs_plan_query(int family, int64_t N, int64_t T, const double* lo, const double* hi, double Q, double xi,
                    double r_c, double tol, int precision, ehs_report* rep)

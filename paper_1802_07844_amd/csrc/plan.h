@@ -136,6 +136,24 @@ inline double xi_for_cutoff(int family, double rc, double tol, double L)
     return hi;
 }
 
+// Cutoff r_c at which the real-space estimate for xi equals est: bisection
+// over xi r_c in [1, 100], where every family's estimate decreases in r_c.
+// Returns -1 for bad arguments or when est lies outside that range.
+inline double cutoff_for_estimate(int family, double xi, double est, double L)
+{
+    if (!(xi > 0) || !(est > 0) || !(L > 0) || family < 0 || family > 2) return -1.0;
+    double lo = 1.0 / xi, hi = 100.0 / xi;
+    if (est_real_rel(family, lo, xi, L) < est || est_real_rel(family, hi, xi, L) > est) return -1.0;
+    for (int it = 0; it < 200; ++it) {
+        double mid = 0.5 * (lo + hi);
+        if (est_real_rel(family, mid, xi, L) > est)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    return hi;
+}
+
 struct PlanInput {
     int family;
     long long N, T;

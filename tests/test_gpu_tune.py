@@ -1,0 +1,97 @@
+"""GPU checks of the runtime-optimal parameter search (ehs_tune).
+
+The tuning procedure of the paper's results section holds both truncation
+errors where the starting point puts them and perturbs xi for the smallest
+run time.  Checked here: the candidates lie on the xi0 2^(j/4) ladder with the
+starting point's real-space estimate, the walk stops at the first slower
+candidate in its direction, the returned parameters are the fastest timed
+ones, and the result at them meets the tolerance against the FP64 direct-sum
+oracle and is the same as a plain evaluation with those parameters.
+"""
+import math
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle  # noqa: E402
+import paper_1802_07844_amd as ehs  # noqa: E402
+from paper_1802_07844_amd import workloads  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = ehs.Context(0)
+    yield c
+    c.close()
+
+
+def _rc(nb, n):
+    return (nb * 3.0 / (4.0 * math.pi * n)) ** (1.0 / 3.0)
+
+
+def _check_walk(fam, res, xi0, rc0, est0, L):
+    tr = res["trace"]
+    assert len(tr) >= 2
+    assert tr[0][0] == pytest.approx(xi0, rel=1e-12) and tr[0][1] == pytest.approx(rc0, rel=1e-12)
+    js = []
+    for xi, rc, ms in tr:
+        j = 4 * math.log2(xi / xi0)
+        assert abs(j - round(j)) < 1e-9
+        js.append(int(round(j)))
+        assert ms > 0
+        if js[-1] != 0:
+            assert rc == pytest.approx(ehs.cutoff_for_estimate(fam, xi, est0, L), rel=1e-12)
+    # the fastest timed candidate is returned
+    k = int(np.argmin([t[2] for t in tr]))
+    assert (res["xi"], res["r_c"], res["ms"]) == tr[k]
+    assert res["ms"] <= tr[0][2]
+    # the walk: j = 0, -1, then (if -1 was not faster) +1, then further in the
+    # faster direction while each step is faster than the one before
+    assert js[:2] == [0, -1]
+    walk = [(j, t[2]) for j, t in zip(js, tr)]
+    if len(js) > 2 and js[2] == 1:
+        assert tr[1][2] >= tr[0][2]
+        seq = [walk[0]] + walk[2:]
+    else:
+        seq = walk[:]
+    # every step before the last was faster than the one before it
+    for i in range(1, len(seq) - 1):
+        assert seq[i][1] < seq[i - 1][1]
+    return js
+
+
+@pytest.mark.parametrize("fam,n,nb,tol,prec", [
+    ("stokeslet", 20000, 30, 1e-10, 1),
+    ("stresslet", 10000, 60, 1e-10, 1),
+    ("rotlet", 20000, 300, 1e-5, 2),
+])
+def test_tune_finds_the_fastest_admissible_parameters(ctx, fam, n, nb, tol, prec):
+    seed = workloads.SEED_BASE + 40
+    y, s = workloads.make(fam, n, seed)
+    rc0 = _rc(nb, n)
+    xi0 = ehs.xi_for_cutoff(fam, rc0, tol / 2)
+    ctx.set_option(ehs.OPT_PRECISION, prec)
+    yd = torch.from_numpy(y).to("cuda:0")
+    sd = torch.from_numpy(s).to("cuda:0")
+    _, rep0 = ctx.evaluate(fam, yd, sd, yd, xi0, rc0, tol, report=True)
+    res = ctx.tune(fam, yd, sd, yd, xi0, rc0, tol, max_evals=8)
+    torch.cuda.synchronize()
+    u = res["u"].cpu().numpy()
+    js = _check_walk(fam, res, xi0, rc0, rep0.est_real, rep0.L)
+    rep = res["report"]
+    assert rep.xi == res["xi"] and rep.r_c == res["r_c"]
+    assert rep.est_real <= max(rep0.est_real, tol / 2) * (1 + 1e-9)
+    # the same numbers as a plain evaluation with the chosen parameters
+    again = ctx.evaluate(fam, yd, sd, yd, res["xi"], res["r_c"], tol).cpu().numpy()
+    assert np.array_equal(u, again)
+    idx = np.sort(workloads.rng(seed + 1).choice(n, 256, replace=False))
+    err = oracle.rel_rms(oracle.halfspace(fam, y, s, y[idx]), u[idx])
+    print(f"tune {fam} N={n} prec={rep.precision}: start xi={xi0:.2f} r_c={rc0:.4f} "
+          f"{res['trace'][0][2]:.2f} ms; chose xi={res['xi']:.2f} r_c={res['r_c']:.4f} Mt={rep.Mt} "
+          f"{res['ms']:.2f} ms; ladder {js}; rel-RMS {err:.2e}")
+    assert err <= tol
+    del yd, sd

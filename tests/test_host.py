@@ -262,3 +262,46 @@ def test_real_space_cells_cover_the_cutoff(n, nb):
         assert r.ncell[a] <= 256
     if dense:
         assert r.ncell[0] >= 2 * math.floor(1.0 / rc) - 1 or r.ncell[0] == 256
+
+
+@pytest.mark.parametrize("family", ["stokeslet", "stresslet", "rotlet"])
+@pytest.mark.parametrize("tol", [1e-10, 1e-5])
+def test_cutoff_for_estimate_inverts_the_real_space_estimate(family, tol):
+    """The tuner's cutoff at a given xi: the estimate there equals the target
+    (checked through the planner's own estimate), and it inverts
+    xi_for_cutoff; along xi the product xi r_c moves only logarithmically, as
+    the tuning procedure of the results section assumes."""
+    L = 1.0
+    for rc in (0.03, 0.1, 0.3):
+        xi = ehs.xi_for_cutoff(family, rc, tol, L)
+        got = ehs.cutoff_for_estimate(family, xi, tol / 2, L)
+        assert got == pytest.approx(rc, rel=1e-9)
+        if rc == 0.3:  # a grid the planner admits at every tolerance
+            rep = _plan(family, tol=tol, xi=xi, rc=got, n=2000, hi=(L, L, L))
+            assert rep.est_real == pytest.approx(tol / 2, rel=1e-6)
+    xi0 = ehs.xi_for_cutoff(family, 0.05, tol, L)
+    p0 = xi0 * ehs.cutoff_for_estimate(family, xi0, tol / 2, L)
+    prev = None
+    for f in (0.5, 0.7071, 1.0, 1.4142, 2.0):
+        rc = ehs.cutoff_for_estimate(family, f * xi0, tol / 2, L)
+        assert rc > 0
+        if prev is not None:
+            assert rc < prev  # larger xi, smaller cutoff
+        prev = rc
+        assert f * xi0 * rc == pytest.approx(p0, rel=0.08)
+
+
+def test_cutoff_for_estimate_bad_arguments():
+    assert ehs.cutoff_for_estimate("stokeslet", -1.0, 1e-10) < 0
+    assert ehs.cutoff_for_estimate("stokeslet", 10.0, 0.0) < 0
+    assert ehs.cutoff_for_estimate(7, 10.0, 1e-10) < 0
+    # an estimate above its value at xi r_c = 1 is out of range
+    assert ehs.cutoff_for_estimate("stokeslet", 10.0, 10.0) < 0
+
+
+def test_tune_rejects_bad_arguments_without_a_device():
+    """Argument checks of ehs_tune come before any device work."""
+    L = ehs.lib()
+    best = (ctypes.c_double * 3)()
+    assert L.ehs_tune(None, 0, None, None, 10, None, 10, 10.0, 0.3, 1e-10, 4, None, best, None, None, None,
+                      None) == ehs.EHS_EINVAL
