@@ -369,32 +369,34 @@ def main():
 
     # the same problem at the runtime-optimal (xi, r_c) of the tuning procedure
     # (both truncation errors held, xi perturbed), timed like the main line
-    ut = None
-    if not args.no_tune:
-        tres = ctx.tune("stokeslet", yd, fd, yd, xi, rc, tol, max_evals=args.tune_evals)
+    def tuned(xi0, rc0, t, dtype):
+        tres = ctx.tune("stokeslet", yd, fd, yd, xi0, rc0, t, max_evals=args.tune_evals)
         xit, rct = tres["xi"], tres["r_c"]
         outt = torch.empty_like(out)
         for _ in range(args.warmup):
-            rt = ctx.stokeslet(yd, fd, yd, xit, rct, tol, out=outt, report=True)[1]
+            rt = ctx.stokeslet(yd, fd, yd, xit, rct, t, out=outt, report=True)[1]
         torch.cuda.synchronize()
         stt = np.zeros(ehs.NSTAGES)
         t0 = time.perf_counter()
         for _ in range(args.steps):
-            rt = ctx.stokeslet(yd, fd, yd, xit, rct, tol, out=outt, report=True)[1]
+            rt = ctx.stokeslet(yd, fd, yd, xit, rct, t, out=outt, report=True)[1]
             stt += np.array(list(rt.ms_stage))
         torch.cuda.synchronize()
         dtt = time.perf_counter() - t0
-        ut = outt.cpu().numpy()
-        del outt
-        result["tuned"] = {"value": n * args.steps / dtt, "unit": "points/s", "ms_per_step": dtt / args.steps * 1e3,
-                           "dtype": "f64", "tol": tol, "xi": xit, "r_c": rct,
-                           "neighbours": 4.0 / 3.0 * math.pi * rct**3 * n, "M": rt.M, "P": rt.P, "Mt": rt.Mt,
-                           "stage_ms": dict(zip(ehs.STAGES, (stt / args.steps).tolist())),
-                           "search": [{"xi": a, "r_c": b, "ms": c} for a, b, c in tres["trace"]],
-                           "note": "same points and forces; xi perturbed with both truncation estimates held"}
+        res = {"value": n * args.steps / dtt, "unit": "points/s", "ms_per_step": dtt / args.steps * 1e3,
+               "dtype": dtype, "tol": t, "xi": xit, "r_c": rct,
+               "neighbours": 4.0 / 3.0 * math.pi * rct**3 * n, "M": rt.M, "P": rt.P, "Mt": rt.Mt,
+               "stage_ms": dict(zip(ehs.STAGES, (stt / args.steps).tolist())),
+               "search": [{"xi": a, "r_c": b, "ms": c} for a, b, c in tres["trace"]],
+               "note": "same points and forces; xi perturbed with both truncation estimates held"}
+        return res, outt.cpu().numpy()
+
+    ut = None
+    if not args.no_tune:
+        result["tuned"], ut = tuned(xi, rc, tol, "f64")
 
     # FP32 path on the same workload at tol 1e-5
-    u32 = None
+    u32 = ut32 = None
     if not args.no_fp32:
         tol32 = 1e-5
         ctx.set_option(ehs.OPT_PRECISION, 2)
@@ -421,6 +423,8 @@ def main():
                           "dtype": "f32", "tol": tol32, "xi": xi32, "r_c": rc32, "neighbours": args.fp32_neighbours,
                           "M": r32.M, "P": r32.P, "Mt": r32.Mt, "stage_ms": sm32,
                           "roofline": _roofline(r32, sm32, _ncin(r32), 4)}
+        if not args.no_tune:
+            result["fp32"]["tuned"], ut32 = tuned(xi32, rc32, tol32, "f32")
 
     # oracle on the host cores: a bounded sample of targets against all sources
     if not args.no_cpu_baseline:
@@ -450,6 +454,8 @@ def main():
             result["fp32"]["rel_rms"] = oracle.rel_rms(ref, u32[idx])
         if ut is not None:
             result["tuned"]["rel_rms"] = oracle.rel_rms(ref, ut[idx])
+        if ut32 is not None:
+            result["fp32"]["tuned"]["rel_rms"] = oracle.rel_rms(ref, ut32[idx])
     if not args.no_serve:
         del out
         if u32 is not None:

@@ -180,9 +180,11 @@ double ehs_cutoff_for_estimate(int family, double xi, double est, double L);
  * and the planner picks the grid from tol as always.  The search times
  * j = 0, then j = -1 and j = +1, and walks in the faster direction while
  * the time falls; it stops at max_evals candidates (1..64), at a cutoff
- * above half the box, or where no grid is admissible or the workspace does
+ * above half the box, where no grid is admissible or the workspace does
  * not fit (EHS_ERANGE / EHS_ENOMEM of a candidate end the walk, they are not
- * returned).  Each candidate is evaluated once untimed (workspace and
+ * returned), or, with FP32 forced (EHS_OPT_PRECISION 2), where the FP32
+ * rounding estimate exceeds tol/2 (report warning bit 2) and the starting
+ * point's did not.  Each candidate is evaluated once untimed (workspace and
  * multiplier precompute, which the paper's timings exclude too) and then
  * twice, timed on the host around a synchronised `stream`; its time is the
  * faster of the two.

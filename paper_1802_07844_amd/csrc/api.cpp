@@ -941,9 +941,12 @@ int ehs_tune(ehs_ctx* c, int family, const double* y, const double* s, int64_t N
         const double xi = xi0 * std::pow(2.0, 0.25 * j);
         const double rc = j == 0 ? rc0 : cutoff_for_estimate(family, xi, est, L);
         if (!(rc > 0) || rc > 0.5 * L) return 1;
-        int e = evaluate(c, family, y, s, N, x, T, xi, rc, tol, u, stream, nullptr);  // untimed
+        ehs_report rw;
+        int e = evaluate(c, family, y, s, N, x, T, xi, rc, tol, u, stream, &rw);  // untimed
         if (e == EHS_ERANGE || e == EHS_ENOMEM) return 1;
         if (e) return e;
+        // forced FP32 whose rounding estimate exceeds tol/2 where the start's did not
+        if ((rw.warnings & 4) && !(r0.warnings & 4)) return 1;
         double ms = 1e300;
         for (int k = 0; k < 2; ++k) {
             if (hipStreamSynchronize(st) != hipSuccess) return EHS_EHIP;
