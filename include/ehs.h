@@ -196,7 +196,9 @@ double ehs_cutoff_for_estimate(int family, double xi, double est, double L);
  *   every timed candidate in the order tried, their count in *ntrace
  *   (nullable); rep (nullable): the report of the final evaluation.
  * Synchronises `stream` repeatedly; returns 0 or the first error of an
- * evaluation other than the two that end the walk.
+ * evaluation other than the two that end the walk.  The context keeps the
+ * multipliers of every grid size tried (as after any evaluation) and a
+ * workspace sized for the largest candidate, until it is destroyed.
  */
 int ehs_tune(ehs_ctx* ctx, int family, const double* sources, const double* strengths, int64_t N,
              const double* targets, int64_t T, double xi0, double r_c0, double tol, int max_evals,
