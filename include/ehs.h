@@ -175,11 +175,12 @@ double ehs_cutoff_for_estimate(int family, double xi, double est, double L);
  * truncation errors are held where the starting point (xi0, r_c0) puts them
  * while xi is perturbed, so that xi r_c and k_inf / xi stay (nearly)
  * constant and only the division of the work between the real-space sum
- * and the grid changes.  Candidates are xi = xi0 2^(j/4): r_c is the cutoff
+ * and the grid changes.  Candidates are xi = xi0 2^(k/8): r_c is the cutoff
  * with the starting point's real-space estimate (ehs_cutoff_for_estimate)
  * and the planner picks the grid from tol as always.  The search times
- * j = 0, then j = -1 and j = +1, and walks in the faster direction while
- * the time falls; it stops at max_evals candidates (1..64), at a cutoff
+ * k = 0, then k = -2 and k = +2, and walks in steps of 2 in the faster
+ * direction while the time falls; last it times the two neighbours k +- 1
+ * of the fastest.  A walk stops at max_evals candidates (1..64), at a cutoff
  * above half the box, where no grid is admissible or the workspace does
  * not fit (EHS_ERANGE / EHS_ENOMEM of a candidate end the walk, they are not
  * returned), or, with FP32 forced (EHS_OPT_PRECISION 2), where the FP32

@@ -931,15 +931,15 @@ int ehs_tune(ehs_ctx* c, int family, const double* y, const double* s, int64_t N
     const double L = r0.L, est = r0.est_real;
 
     struct Cand {
-        int j;
+        int k;  // xi = xi0 2^(k/8)
         double xi, rc, ms;
     };
     std::vector<Cand> tried;
     // 0: timed; 1: inadmissible (ends the walk in its direction); < 0: error
-    auto probe = [&](int j) -> int {
+    auto probe = [&](int k) -> int {
         if ((int)tried.size() >= max_evals) return 1;
-        const double xi = xi0 * std::pow(2.0, 0.25 * j);
-        const double rc = j == 0 ? rc0 : cutoff_for_estimate(family, xi, est, L);
+        const double xi = xi0 * std::pow(2.0, 0.125 * k);
+        const double rc = k == 0 ? rc0 : cutoff_for_estimate(family, xi, est, L);
         if (!(rc > 0) || rc > 0.5 * L) return 1;
         ehs_report rw;
         int e = evaluate(c, family, y, s, N, x, T, xi, rc, tol, u, stream, &rw);  // untimed
@@ -955,30 +955,39 @@ int ehs_tune(ehs_ctx* c, int family, const double* y, const double* s, int64_t N
             if (hipStreamSynchronize(st) != hipSuccess) return EHS_EHIP;
             ms = std::min(ms, std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count());
         }
-        tried.push_back({j, xi, rc, ms});
+        tried.push_back({k, xi, rc, ms});
         return 0;
+    };
+    auto fastest = [&]() {
+        size_t b = 0;
+        for (size_t i = 1; i < tried.size(); ++i)
+            if (tried[i].ms < tried[b].ms) b = i;
+        return b;
     };
     if ((r = probe(0)) < 0) return r;
     if (r > 0) return EHS_ERANGE;  // the starting point itself is not admissible
-    // first step down in xi (larger cutoff, smaller grid), else up
+    // the walk in quarter octaves: first down in xi (larger cutoff, smaller
+    // grid), else up
     int dir = -1;
-    if ((r = probe(-1)) < 0) return r;
+    if ((r = probe(-2)) < 0) return r;
     if (r > 0 || tried.back().ms >= tried[0].ms) {
         dir = +1;
-        if ((r = probe(+1)) < 0) return r;
+        if ((r = probe(+2)) < 0) return r;
         if (r > 0 || tried.back().ms >= tried[0].ms) dir = 0;
     }
     if (dir != 0) {
         double last = tried.back().ms;
         for (int j = 2 * dir;; j += dir) {
-            if ((r = probe(j)) < 0) return r;
+            if ((r = probe(2 * j)) < 0) return r;
             if (r > 0 || tried.back().ms >= last) break;
             last = tried.back().ms;
         }
     }
-    const Cand* b = &tried[0];
-    for (const Cand& t : tried)
-        if (t.ms < b->ms) b = &t;
+    // then the two eighth-octave neighbours of the fastest
+    const int kb = tried[fastest()].k;
+    for (int dk : {-1, +1})
+        if ((r = probe(kb + dk)) < 0) return r;
+    const Cand* b = &tried[fastest()];
     best[0] = b->xi;
     best[1] = b->rc;
     best[2] = b->ms;

@@ -2,7 +2,7 @@
 
 The tuning procedure of the paper's results section holds both truncation
 errors where the starting point puts them and perturbs xi for the smallest
-run time.  Checked here: the candidates lie on the xi0 2^(j/4) ladder with the
+run time.  Checked here: the candidates lie on the xi0 2^(k/8) ladder with the
 starting point's real-space estimate, the walk stops at the first slower
 candidate in its direction, the returned parameters are the fastest timed
 ones, and the result at them meets the tolerance against the FP64 direct-sum
@@ -37,23 +37,32 @@ def _check_walk(fam, res, xi0, rc0, est0, L):
     tr = res["trace"]
     assert len(tr) >= 2
     assert tr[0][0] == pytest.approx(xi0, rel=1e-12) and tr[0][1] == pytest.approx(rc0, rel=1e-12)
-    js = []
+    ks = []
     for xi, rc, ms in tr:
-        j = 4 * math.log2(xi / xi0)
-        assert abs(j - round(j)) < 1e-9
-        js.append(int(round(j)))
+        k = 8 * math.log2(xi / xi0)
+        assert abs(k - round(k)) < 1e-9
+        ks.append(int(round(k)))
         assert ms > 0
-        if js[-1] != 0:
+        if ks[-1] != 0:
             assert rc == pytest.approx(ehs.cutoff_for_estimate(fam, xi, est0, L), rel=1e-12)
+    assert len(set(ks)) == len(ks)
     # the fastest timed candidate is returned
     k = int(np.argmin([t[2] for t in tr]))
     assert (res["xi"], res["r_c"], res["ms"]) == tr[k]
     assert res["ms"] <= tr[0][2]
-    # the walk: j = 0, -1, then (if -1 was not faster) +1, then further in the
-    # faster direction while each step is faster than the one before
-    assert js[:2] == [0, -1]
-    walk = [(j, t[2]) for j, t in zip(js, tr)]
-    if len(js) > 2 and js[2] == 1:
+    # the walk in quarter octaves (even k): 0, -2, then (if -2 was not faster)
+    # +2, then further in the faster direction while each step is faster than
+    # the one before; after it at most the two eighth-octave neighbours of the
+    # fastest walk candidate (odd k)
+    nw = len(ks)
+    while nw > 0 and ks[nw - 1] % 2:
+        nw -= 1
+    assert all(kk % 2 == 0 for kk in ks[:nw]) and len(ks) - nw <= 2
+    kb = ks[int(np.argmin([t[2] for t in tr[:nw]]))]
+    assert all(abs(kk - kb) == 1 for kk in ks[nw:])
+    assert ks[:2] == [0, -2]
+    walk = [(kk, t[2]) for kk, t in zip(ks[:nw], tr[:nw])]
+    if nw > 2 and ks[2] == 2:
         assert tr[1][2] >= tr[0][2]
         seq = [walk[0]] + walk[2:]
     else:
@@ -61,7 +70,7 @@ def _check_walk(fam, res, xi0, rc0, est0, L):
     # every step before the last was faster than the one before it
     for i in range(1, len(seq) - 1):
         assert seq[i][1] < seq[i - 1][1]
-    return js
+    return ks
 
 
 @pytest.mark.parametrize("fam,n,nb,tol,prec", [
@@ -82,7 +91,7 @@ def test_tune_finds_the_fastest_admissible_parameters(ctx, fam, n, nb, tol, prec
     res = ctx.tune(fam, yd, sd, yd, xi0, rc0, tol, max_evals=8)
     torch.cuda.synchronize()
     u = res["u"].cpu().numpy()
-    js = _check_walk(fam, res, xi0, rc0, rep0.est_real, rep0.L)
+    ks = _check_walk(fam, res, xi0, rc0, rep0.est_real, rep0.L)
     rep = res["report"]
     assert rep.xi == res["xi"] and rep.r_c == res["r_c"]
     assert rep.est_real <= max(rep0.est_real, tol / 2) * (1 + 1e-9)
@@ -95,6 +104,6 @@ def test_tune_finds_the_fastest_admissible_parameters(ctx, fam, n, nb, tol, prec
     err = oracle.rel_rms(oracle.halfspace(fam, y, s, y[idx]), u[idx])
     print(f"tune {fam} N={n} prec={rep.precision}: start xi={xi0:.2f} r_c={rc0:.4f} "
           f"{res['trace'][0][2]:.2f} ms; chose xi={res['xi']:.2f} r_c={res['r_c']:.4f} Mt={rep.Mt} "
-          f"{res['ms']:.2f} ms; ladder {js}; rel-RMS {err:.2e}")
+          f"{res['ms']:.2f} ms; eighth-octave steps {ks}; rel-RMS {err:.2e}")
     assert err <= tol
     del yd, sd
