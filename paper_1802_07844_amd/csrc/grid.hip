@@ -594,8 +594,10 @@ hipError_t launch_gather_final(GridArgs gg, const T* rec, const T* part, long lo
 
 // Target-per-wavefront form, for small supports and dense targets (where
 // the per-tile reductions of the node-owner form cost more than the repeated
-// reads, which then hit L2 more often): lanes cover Pg consecutive x1 nodes
-// of floor(64 / Pg) rows at a time; blocks of 4 consecutive (cell-sorted, so
+// reads, which then hit L2 more often): one wavefront per target, its lanes
+// over whole x1 rows of the support where those fill at least 90 % of them,
+// else over the flattened Pg^3 support (Pg = 22: 44 of 64 lanes in rows,
+// quadrature 2.9 -> 2.5 ms at N = 1e5); blocks of 4 consecutive (cell-sorted, so
 // nearby) targets, spread over the XCDs in contiguous ranges so that
 // overlapping supports share an L2.
 template <typename T>
@@ -628,23 +630,58 @@ __global__ void __launch_bounds__(256) k_gather(GridArgs g, const T* __restrict_
         if (GQ) dsh[wv][f] = (T)(2.0 * g.a2 * d * v);
     }
     __syncthreads();
-    const int rows = 64 / P;
-    const int row = fdiv(lane, P, g.mP), xi = lane - row * P;
     T acc[6] = {0, 0, 0, 0, 0, 0};
-    if (row < rows) {
-        const T wx = wsh[wv][xi];
-        const T dx = GQ ? dsh[wv][xi] : (T)0;
+    const int rows = 64 / P;
+    if (10 * rows * P >= 9 * 64) {
+        // lanes cover P consecutive x1 nodes of `rows` rows at a time (at
+        // least 90 % of the lanes busy)
+        const int row = fdiv(lane, P, g.mP), xi = lane - row * P;
+        if (row < rows) {
+            const T wx = wsh[wv][xi];
+            const T dx = GQ ? dsh[wv][xi] : (T)0;
 #pragma unroll 4
-        for (int rr = row; rr < P * P; rr += rows) {
-            int dz = fdiv(rr, P, g.mP), dy = rr - dz * P;
-            const T wy = wsh[wv][P + dy], wz = wsh[wv][2 * P + dz];
+            for (int rr = row; rr < P * P; rr += rows) {
+                int dz = fdiv(rr, P, g.mP), dy = rr - dz * P;
+                const T wy = wsh[wv][P + dy], wz = wsh[wv][2 * P + dz];
+                const T wyz = wy * wz;
+                const T w = wx * wyz;
+                long long node = ((long long)(base[2] + dz) * Mt + base[1] + dy) * Mt + base[0] + xi;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) acc[c] += w * grids[c * cs + node];
+                if (GQ) {
+                    const T gx = dx * wyz, gy = wx * dsh[wv][P + dy] * wz, gz = wx * wy * dsh[wv][2 * P + dz];
+                    const T ph = grids[3 * cs + node];
+                    acc[3] += gx * ph;
+                    acc[4] += gy * ph;
+                    acc[5] += gz * ph;
+                } else {
+#pragma unroll
+                    for (int c = 3; c < 6; ++c) acc[c] += w * grids[c * cs + node];
+                }
+            }
+        }
+    } else {
+        // the P^3 support nodes, x1 fastest, flattened over the 64 lanes: lane
+        // takes node f = lane + 64 i, its (x1, x2, x3) offsets advanced by those
+        // of 64 with carries, so every lane is busy whatever P is
+        const int P2 = P * P, n3 = P2 * P;
+        const int sx = 64 - fdiv(64, P, g.mP) * P;  // 64 = (sz P + sy) P + sx
+        const int q64 = fdiv(64, P, g.mP);
+        const int sz = fdiv(q64, P, g.mP), sy = q64 - sz * P;
+        int r0 = fdiv(lane, P, g.mP);
+        int xi = lane - r0 * P;
+        int dz = fdiv(r0, P, g.mP);
+        int dy = r0 - dz * P;
+#pragma unroll 2
+        for (int f = lane; f < n3; f += 64) {
+            const T wx = wsh[wv][xi], wy = wsh[wv][P + dy], wz = wsh[wv][2 * P + dz];
             const T wyz = wy * wz;
             const T w = wx * wyz;
             long long node = ((long long)(base[2] + dz) * Mt + base[1] + dy) * Mt + base[0] + xi;
 #pragma unroll
             for (int c = 0; c < 3; ++c) acc[c] += w * grids[c * cs + node];
             if (GQ) {
-                const T gx = dx * wyz, gy = wx * dsh[wv][P + dy] * wz, gz = wx * wy * dsh[wv][2 * P + dz];
+                const T gx = dsh[wv][xi] * wyz, gy = wx * dsh[wv][P + dy] * wz, gz = wx * wy * dsh[wv][2 * P + dz];
                 const T ph = grids[3 * cs + node];
                 acc[3] += gx * ph;
                 acc[4] += gy * ph;
@@ -652,6 +689,17 @@ __global__ void __launch_bounds__(256) k_gather(GridArgs g, const T* __restrict_
             } else {
 #pragma unroll
                 for (int c = 3; c < 6; ++c) acc[c] += w * grids[c * cs + node];
+            }
+            xi += sx;
+            dy += sy;
+            dz += sz;
+            if (xi >= P) {
+                xi -= P;
+                ++dy;
+            }
+            if (dy >= P) {
+                dy -= P;
+                ++dz;
             }
         }
     }
