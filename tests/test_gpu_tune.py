@@ -107,3 +107,35 @@ def test_tune_finds_the_fastest_admissible_parameters(ctx, fam, n, nb, tol, prec
           f"{res['ms']:.2f} ms; eighth-octave steps {ks}; rel-RMS {err:.2e}")
     assert err <= tol
     del yd, sd
+
+
+def test_tune_limits_and_errors(ctx):
+    """One candidate returns the starting point; a memory cap below the
+    starting point's workspace is reported as EHS_ENOMEM; bad arguments are
+    rejected before any device work."""
+    n, tol = 5000, 1e-10
+    y, f = workloads.make("stokeslet", n, workloads.SEED_BASE + 41)
+    rc0 = _rc(30, n)
+    xi0 = ehs.xi_for_cutoff("stokeslet", rc0, tol / 2)
+    ctx.set_option(ehs.OPT_PRECISION, 1)
+    yd = torch.from_numpy(y).to("cuda:0")
+    fd = torch.from_numpy(f).to("cuda:0")
+    res = ctx.tune("stokeslet", yd, fd, yd, xi0, rc0, tol, max_evals=1)
+    assert len(res["trace"]) == 1
+    assert (res["xi"], res["r_c"]) == (xi0, rc0)
+    plain = ctx.stokeslet(yd, fd, yd, xi0, rc0, tol).cpu().numpy()
+    assert np.array_equal(res["u"].cpu().numpy(), plain)
+    with pytest.raises(ehs.EhsError) as e:
+        ctx.tune("stokeslet", yd, fd, yd, xi0, rc0, tol, max_evals=0)
+    assert e.value.code == ehs.EHS_EINVAL
+    _, rep = ctx.stokeslet(yd, fd, yd, xi0, rc0, tol, report=True)
+    fresh = ehs.Context(0)
+    try:
+        fresh.set_option(ehs.OPT_PRECISION, 1)
+        fresh.set_option(ehs.OPT_MEM_CAP, 0.5 * rep.workspace_bytes)
+        with pytest.raises(ehs.EhsError) as e:
+            fresh.tune("stokeslet", yd, fd, yd, xi0, rc0, tol, max_evals=4)
+        assert e.value.code == ehs.EHS_ENOMEM
+    finally:
+        fresh.close()
+    del yd, fd
