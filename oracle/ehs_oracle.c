@@ -169,9 +169,16 @@ void oracle_correction(int kernel, const double* y, const double* s, const doubl
 
 static int nstr(int kernel) { return kernel == ORACLE_STOKESLET ? 3 : 6; }
 
-/* One source's full half-space contribution at x (eq. (v_sum_halfspace)). */
-static void halfspace_term(int kernel, const double* y, const double* s, const double* x, double* acc)
+/*
+ * One source's full half-space contribution at x (eq. (v_sum_halfspace)),
+ * formed on its own before it is added to the running sum: for a source
+ * close to the wall its image and correction terms are each of size
+ * 1/(2 y3)^2 and cancel to O(1), so adding them to the sum one by one would
+ * round away what the other sources have contributed.
+ */
+static void halfspace_term(int kernel, const double* y, const double* s, const double* x, double* sum)
 {
+    double acc[3] = {0.0, 0.0, 0.0};
     double r[3] = {x[0] - y[0], x[1] - y[1], x[2] - y[2]};
     int self = (r[0] == 0.0 && r[1] == 0.0 && r[2] == 0.0);
     if (!self) kernel_term(kernel, r, s, 1.0, acc);
@@ -198,6 +205,9 @@ static void halfspace_term(int kernel, const double* y, const double* s, const d
     acc[0] += -x3 * gphi[0];
     acc[1] += -x3 * gphi[1];
     acc[2] += -x3 * gphi[2] + phi;
+    sum[0] += acc[0];
+    sum[1] += acc[1];
+    sum[2] += acc[2];
 }
 
 /*
