@@ -26,9 +26,10 @@
  *    pointer after the call returns;
  *  - `stream` is a hipStream_t passed as void* (NULL: the default stream).
  *    The call returns after enqueueing; results are valid once the stream has
- *    synchronised.  One blocking device-to-host read (64 bytes, the bounding
- *    box) happens inside every call; a cache miss of the truncated-kernel
- *    precompute adds one more synchronisation;
+ *    synchronised.  One blocking device-to-host read (128 bytes: the bounding
+ *    box, the validation counts and the strength measure) happens inside
+ *    every call; a cache miss of the truncated-kernel precompute adds one
+ *    more synchronisation;
  *  - outputs are overwritten, never accumulated;
  *  - a context is not thread safe and calls on one context must not overlap
  *    (they share the context's workspace);
@@ -63,13 +64,18 @@ extern "C" {
 #define EHS_OPT_FORCE_M 2   /* > 0: use this M (grid intervals over the box) instead of the estimate */
 #define EHS_OPT_FORCE_P 3   /* > 0: use this Gaussian support P (even) */
 #define EHS_OPT_FORCE_MT 4  /* > 0: use this total grid size M~ (>= M + P, 7-smooth, even) */
-#define EHS_OPT_MEM_CAP 5   /* > 0: refuse a workspace larger than this many bytes (EHS_ENOMEM) */
+#define EHS_OPT_MEM_CAP 5   /* > 0: bound on the workspace plus the cached octants, in bytes: octants of
+                               other grid sizes are released to make room, else EHS_ENOMEM */
 #define EHS_OPT_ZSLAB 6     /* > 0: k1 slabs per group of the y / x3 transform pipeline (default: sized for
                                the last-level cache); M~ + 1 keeps the whole grid in one group */
 #define EHS_OPT_GATHER_EXTRA 7 /* >= 0 (even): support nodes the quadrature adds to P; -1: default (2 for
                                   FP64, whose quadrature forms the correction gradient, 0 for FP32) */
-#define EHS_OPT_DGRID 8     /* FP64: 1 spreads the correction sources as one density with derivative
-                               weights, 0 as separate grids, -1 (default) chooses by cost */
+#define EHS_OPT_DGRID 8     /* FP64 stokeslet and rotlet: 1 spreads the correction sources as one density
+                               with derivative weights, 0 as separate grids, -1 (default) chooses by cost;
+                               1 with the stresslet is refused (EHS_EINVAL): its second-derivative
+                               density does not reach tol 1e-10 on the planned grid */
+#define EHS_OPT_FAIL_PRECOMPUTE 9 /* test hook: > 0 makes the next that many truncated-kernel
+                                     productions fail with EHS_EHIP before anything is launched */
 
 /* stage indices of ehs_report.ms_stage */
 #define EHS_ST_BBOX 0       /* bounding box + validation reduction and its readback */
@@ -115,9 +121,20 @@ typedef struct ehs_report {
                                support: the correction grids vanish there */
 } ehs_report;
 
-/* Create a context on HIP device `hip_device`.  `arena_bytes` is reserved
-   for future use and may be 0.  Returns EHS_OK or an error; *out is NULL on
-   error. */
+/* Smallest arena a context accepts (the table and bounding-box regions). */
+#define EHS_ARENA_MIN_BYTES ((size_t)32 << 20)
+
+/* Create a context on HIP device `hip_device`.
+   arena_bytes == 0: the context grows its workspace and its cache of
+   truncated-kernel octants (one set per grid size) on demand, with hipMalloc
+   inside the calls that need more (EHS_OPT_MEM_CAP bounds both together).
+   arena_bytes >= EHS_ARENA_MIN_BYTES: one device region of that size is
+   allocated now, and every later evaluation takes its tables, the octants of
+   its grid size and its workspace from it -- no allocation on the call path;
+   the octants of the last grid size are kept and recomputed when the size
+   changes; a problem that does not fit returns EHS_ENOMEM.
+   Returns EHS_OK, EHS_EINVAL (bad device or arena size), EHS_ENOMEM or
+   EHS_EHIP; *out is NULL on error. */
 int ehs_create(ehs_ctx** out, int hip_device, size_t arena_bytes);
 /* Release the context and all its device memory (NULL is allowed). */
 void ehs_destroy(ehs_ctx* ctx);
@@ -150,6 +167,10 @@ int ewald_halfspace_stresslet(ehs_ctx* ctx, const double* sources, const double*
 int ewald_halfspace_rotlet(ehs_ctx* ctx, const double* sources, const double* v, int64_t N,
                            const double* targets, int64_t T, double xi, double r_c, double tol,
                            double* u_out, void* stream, ehs_report* rep);
+
+/* Device memory a context holds: its workspace (or arena) bytes, the bytes
+   and number of grid sizes of its octant cache.  Any output may be NULL. */
+int ehs_context_memory(const ehs_ctx* ctx, double* workspace_bytes, double* cache_bytes, int* cache_entries);
 
 /* Message for an EHS_* code (static storage). */
 const char* ehs_strerror(int code);
@@ -255,7 +276,8 @@ typedef struct ehs_server ehs_server;
 
 typedef struct ehs_request {
     int32_t family;    /* EHS_STOKESLET, EHS_STRESSLET or EHS_ROTLET */
-    int32_t precision; /* 0 auto (FP32 when tol >= 1e-5), 1 FP64, 2 FP32 */
+    int32_t precision; /* 0 auto (FP32 when tol >= 1e-5 and the FP32 rounding estimate is at most
+                          tol/2, else FP64), 1 FP64, 2 FP32 */
     int64_t N, T;
     /* device pointers, layouts as in ewald_halfspace_*; inputs must be complete
        on the device before ehs_submit, and every pointer stays valid and
@@ -305,6 +327,10 @@ int ehs_submit(ehs_server* srv, const ehs_request* req, uint64_t* ticket);
 int ehs_wait(ehs_server* srv, uint64_t ticket, int timeout_ms, ehs_request_status* status);
 /* Counters and arena occupancy.  Thread safe. */
 int ehs_server_stats(ehs_server* srv, ehs_serve_stats* out);
+/* Server options: only EHS_OPT_FAIL_PRECOMPUTE (the next `value` octant
+   productions fail with EHS_EHIP, for tests of the failure path); EHS_EINVAL
+   for any other.  Thread safe. */
+int ehs_server_set_option(ehs_server* srv, int option, double value);
 
 #ifdef __cplusplus
 }

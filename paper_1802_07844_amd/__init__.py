@@ -22,7 +22,9 @@ LIB_PATH = os.path.join(HERE, "libehs.so")
 
 STOKESLET, STRESSLET, ROTLET = 0, 1, 2
 FAMILIES = {"stokeslet": STOKESLET, "stresslet": STRESSLET, "rotlet": ROTLET}
-OPT_PRECISION, OPT_TIMING, OPT_FORCE_M, OPT_FORCE_P, OPT_FORCE_MT, OPT_MEM_CAP, OPT_ZSLAB, OPT_GATHER_EXTRA, OPT_DGRID = range(9)
+(OPT_PRECISION, OPT_TIMING, OPT_FORCE_M, OPT_FORCE_P, OPT_FORCE_MT, OPT_MEM_CAP, OPT_ZSLAB, OPT_GATHER_EXTRA,
+ OPT_DGRID, OPT_FAIL_PRECOMPUTE) = range(10)
+ARENA_MIN_BYTES = 32 << 20
 STAGES = ["bbox", "precompute", "binning", "realspace", "spread", "fwd_x", "fwd_y", "z_scale", "inv_y", "inv_x",
           "gather", "total"]
 NSTAGES = len(STAGES)
@@ -84,6 +86,8 @@ def lib():
                 fn = getattr(L, name)
                 fn.argtypes = [vp, vp, vp, i64, vp, i64, dp, dp, dp, vp, vp, ctypes.POINTER(Report)]
                 fn.restype = ctypes.c_int
+            L.ehs_context_memory.argtypes = [vp, ctypes.POINTER(dp), ctypes.POINTER(dp), ctypes.POINTER(ctypes.c_int)]
+            L.ehs_context_memory.restype = ctypes.c_int
             L.ehs_strerror.argtypes = [ctypes.c_int]
             L.ehs_strerror.restype = ctypes.c_char_p
             L.ehs_xi_for_cutoff.argtypes = [ctypes.c_int, dp, dp, dp]
@@ -142,6 +146,8 @@ def _bind_serving(L):
     L.ehs_wait.restype = ctypes.c_int
     L.ehs_server_stats.argtypes = [vp, ctypes.POINTER(ServeStats)]
     L.ehs_server_stats.restype = ctypes.c_int
+    L.ehs_server_set_option.argtypes = [vp, ctypes.c_int, ctypes.c_double]
+    L.ehs_server_set_option.restype = ctypes.c_int
 
 
 def strerror(code: int) -> str:
@@ -202,11 +208,14 @@ def _dev_ptr(t, name, cols):
 
 
 class Context:
-    """An ehs_ctx on one HIP device (owns workspace and the kernel cache)."""
+    """An ehs_ctx on one HIP device (owns workspace and the kernel cache).
 
-    def __init__(self, device: int = 0):
+    arena_bytes > 0 makes the context allocate one device region now and take
+    every later evaluation's tables, octants and workspace from it."""
+
+    def __init__(self, device: int = 0, arena_bytes: int = 0):
         self._h = ctypes.c_void_p()
-        check(lib().ehs_create(ctypes.byref(self._h), int(device), 0))
+        check(lib().ehs_create(ctypes.byref(self._h), int(device), int(arena_bytes)))
         self.device = int(device)
 
     def close(self):
@@ -222,6 +231,12 @@ class Context:
 
     def set_option(self, option: int, value: float) -> None:
         check(lib().ehs_set_option(self._h, int(option), float(value)))
+
+    def memory(self) -> dict:
+        """Device memory the context holds (ehs_context_memory)."""
+        ws, cb, ne = ctypes.c_double(), ctypes.c_double(), ctypes.c_int()
+        check(lib().ehs_context_memory(self._h, ctypes.byref(ws), ctypes.byref(cb), ctypes.byref(ne)))
+        return {"workspace_bytes": ws.value, "cache_bytes": cb.value, "cache_entries": ne.value}
 
     def evaluate(self, family, sources, strengths, targets, xi, r_c, tol, out=None, stream=None, report=False):
         import torch
@@ -372,6 +387,9 @@ class Server:
         d = {k: getattr(st, k) for k, _ in st._fields_ if k != "report"}
         d["report"] = st.report.as_dict()
         return keep[3], d
+
+    def set_option(self, option: int, value: float) -> None:
+        check(lib().ehs_server_set_option(self._h, int(option), float(value)))
 
     def stats(self) -> dict:
         s = ServeStats()

@@ -31,6 +31,26 @@ inline size_t al(size_t n) { return (n + ALIGN - 1) / ALIGN * ALIGN; }
         if (e_ != hipSuccess) return EHS_EHIP; \
     } while (0)
 
+// device memory for one table: carved from the table region of a fixed
+// region, else allocated
+int table_alloc(Tables* t, size_t bytes, void** out)
+{
+    *out = nullptr;
+    if (t->arena) {
+        size_t off = al(t->used);
+        if (off + bytes > t->cap) return EHS_ENOMEM;
+        *out = t->arena + off;
+        t->used = off + bytes;
+        return EHS_OK;
+    }
+    if (hipMalloc(out, bytes) != hipSuccess) {
+        *out = nullptr;
+        hipGetLastError();
+        return EHS_ENOMEM;
+    }
+    return EHS_OK;
+}
+
 int tw_table(ehs_ctx* c, int n, int esz, void** out)
 {
     std::lock_guard<std::mutex> lk(c->tables->mu);
@@ -51,7 +71,7 @@ int tw_table(ehs_ctx* c, int n, int esz, void** out)
     }
     void* d = nullptr;
     size_t bytes = (size_t)n * 2 * esz;
-    if (hipMalloc(&d, bytes) != hipSuccess) return EHS_ENOMEM;
+    if (int rc = table_alloc(c->tables, bytes, &d)) return rc;
     if (esz == 8) {
         if (hipMemcpy(d, h.data(), bytes, hipMemcpyHostToDevice) != hipSuccess) return EHS_EHIP;
     } else {
@@ -102,7 +122,7 @@ int stage_table(ehs_ctx* c, int n, int esz, const std::vector<int>& r, FftPlanDe
     }
     void* d = nullptr;
     size_t bytes = (h.size() / 2) * 2 * esz;
-    if (hipMalloc(&d, bytes) != hipSuccess) return EHS_ENOMEM;
+    if (int rc = table_alloc(c->tables, bytes, &d)) return rc;
     if (esz == 8) {
         if (hipMemcpy(d, h.data(), bytes, hipMemcpyHostToDevice) != hipSuccess) return EHS_EHIP;
     } else {
@@ -208,44 +228,117 @@ int ehs::precompute_octant(ehs_ctx* c, const Plan& p, int kind, double* oct, hip
 
 namespace {
 
-// standalone contexts: octants by M~ in the context's own cache; the stream is
+size_t cache_bytes(const ehs_ctx* c)
+{
+    size_t b = 0;
+    for (auto& kv : c->cache) {
+        const size_t n = (size_t)octant_elems(kv.first);
+        const Octants& o = kv.second;
+        b += (o.H64 ? 8 * n : 0) + (o.B64 ? 8 * n : 0) + (o.H32 ? 4 * n : 0) + (o.B32 ? 4 * n : 0);
+    }
+    return b;
+}
+
+void free_octants(Octants& o)
+{
+    if (o.B64) hipFree(o.B64);
+    if (o.H64) hipFree(o.H64);
+    if (o.B32) hipFree(o.B32);
+    if (o.H32) hipFree(o.H32);
+    o = Octants();
+}
+
+// Drop every cached grid size except `keep` (hipFree waits for the device).
+void evict_octants_except(ehs_ctx* c, int keep)
+{
+    for (auto it = c->cache.begin(); it != c->cache.end();) {
+        if (it->first == keep) {
+            ++it;
+            continue;
+        }
+        free_octants(it->second);
+        it = c->cache.erase(it);
+    }
+}
+
+// Device memory for one more octant array: under a memory cap the workspace
+// and every cached array count against it, and other grid sizes are evicted
+// to make room.
+int octant_alloc(ehs_ctx* c, int Mt, size_t bytes, void** out)
+{
+    *out = nullptr;
+    if (c->mem_cap > 0) {
+        if ((double)(c->ws_bytes + cache_bytes(c) + bytes) > c->mem_cap) evict_octants_except(c, Mt);
+        if ((double)(c->ws_bytes + cache_bytes(c) + bytes) > c->mem_cap) return EHS_ENOMEM;
+    }
+    if (hipMalloc(out, bytes) != hipSuccess) {
+        *out = nullptr;
+        hipGetLastError();
+        return EHS_ENOMEM;
+    }
+    return EHS_OK;
+}
+
+// the test hook of EHS_OPT_FAIL_PRECOMPUTE: fail before launching anything
+int take_injected_failure(int* counter)
+{
+    if (*counter > 0) {
+        --*counter;
+        return EHS_EHIP;
+    }
+    return EHS_OK;
+}
+
+// standalone contexts: octants by M~ in the context's own cache; an array is
+// entered into the cache only once its production has been enqueued without
+// error, so a failed precompute leaves nothing behind; the stream is
 // synchronised after a precompute so that later calls on other streams see it
 int ensure_octants(ehs_ctx* c, const Plan& p, hipStream_t st, bool* ran, Octants** out)
 {
-    Octants& o = c->cache[p.Mt];
-    bool needB = p.family != EHS_ROTLET;
-    bool needH = true;
-    bool need32 = p.prec == 2;
-    const long long n = (long long)(p.Mt + 1) * (p.Mt + 1) * (2 * p.Mt + 1);
-    o.nf = p.nf;
-    o.nf3 = p.nf3;
+    const bool needB = p.family != EHS_ROTLET;
+    const bool need32 = p.prec == 2;
+    const long long n = octant_elems(p.Mt);
     *ran = false;
+    Octants cur;
+    auto it = c->cache.find(p.Mt);
+    if (it != c->cache.end()) cur = it->second;
+    cur.nf = p.nf;
+    cur.nf3 = p.nf3;
     double* scratch = static_cast<double*>(c->ws);
+    auto publish = [&]() { c->cache[p.Mt] = cur; };
     for (int kind = 0; kind < 2; ++kind) {
-        bool need = kind == 0 ? needH : needB;
-        if (!need) continue;
-        double*& d64 = kind == 0 ? o.H64 : o.B64;
-        float*& d32 = kind == 0 ? o.H32 : o.B32;
+        if (kind == 1 && !needB) continue;
+        double*& d64 = kind == 0 ? cur.H64 : cur.B64;
+        float*& d32 = kind == 0 ? cur.H32 : cur.B32;
         if (!d64) {
-            if (hipMalloc((void**)&d64, n * sizeof(double)) != hipSuccess) {
-                d64 = nullptr;
-                return EHS_ENOMEM;
-            }
-            int rc = precompute_kind(c, p.Mt, p.nf, p.nf3, kind, scratch, d64, st);
+            void* tmp = nullptr;
+            int rc = octant_alloc(c, p.Mt, n * sizeof(double), &tmp);
             if (rc) return rc;
+            if (!rc) rc = take_injected_failure(&c->fail_precompute);
+            if (!rc) rc = precompute_kind(c, p.Mt, p.nf, p.nf3, kind, scratch, static_cast<double*>(tmp), st);
+            if (rc) {
+                hipFree(tmp);
+                return rc;
+            }
+            d64 = static_cast<double*>(tmp);
+            publish();
             *ran = true;
         }
         if (need32 && !d32) {
-            if (hipMalloc((void**)&d32, n * sizeof(float)) != hipSuccess) {
-                d32 = nullptr;
-                return EHS_ENOMEM;
+            void* tmp = nullptr;
+            int rc = octant_alloc(c, p.Mt, n * sizeof(float), &tmp);
+            if (rc) return rc;
+            if (launch_oct_to_f32(d64, static_cast<float*>(tmp), n, st) != hipSuccess) {
+                hipFree(tmp);
+                return EHS_EHIP;
             }
-            HIPCHK(launch_oct_to_f32(d64, d32, n, st));
+            d32 = static_cast<float*>(tmp);
+            publish();
             *ran = true;
         }
     }
     if (*ran) HIPCHK(hipStreamSynchronize(st));
-    *out = &o;
+    *out = &c->cache[p.Mt];
     return EHS_OK;
 }
 
@@ -365,9 +458,15 @@ Layout layout(const Plan& p, size_t esz)
     return L;
 }
 
-int ensure_ws(ehs_ctx* c, size_t bytes, hipStream_t st)
+// Workspace of at least `bytes`; under a memory cap the cached octants count
+// too, and grid sizes other than keep_Mt are evicted to make room.
+int ensure_ws(ehs_ctx* c, size_t bytes, hipStream_t st, int keep_Mt)
 {
-    if (c->mem_cap > 0 && (double)bytes > c->mem_cap) return EHS_ENOMEM;
+    if (c->mem_cap > 0) {
+        if ((double)bytes > c->mem_cap) return EHS_ENOMEM;
+        if ((double)(std::max(bytes, c->ws_bytes) + cache_bytes(c)) > c->mem_cap) evict_octants_except(c, keep_Mt);
+        if ((double)(std::max(bytes, c->ws_bytes) + cache_bytes(c)) > c->mem_cap) return EHS_ENOMEM;
+    }
     if (bytes <= c->ws_bytes) return EHS_OK;
     HIPCHK(hipStreamSynchronize(st));
     if (c->ws) hipFree(c->ws);
@@ -617,7 +716,7 @@ int ehs::plan_request(ehs_ctx* c, int family, const double* y, const double* s, 
     if (c->ws_external) {
         if (c->ws_bytes < need) return EHS_ENOMEM;
     } else {
-        int rc0 = ensure_ws(c, std::max(need, c->ws_bytes), st);
+        int rc0 = ensure_ws(c, std::max(need, c->ws_bytes), st, -1);
         if (rc0) return rc0;
     }
     char* base = static_cast<char*>(c->ws);
@@ -709,19 +808,60 @@ void ehs::fill_report(const Plan& p, ehs_report* r)
 
 namespace {
 
-int evaluate(ehs_ctx* c, int family, const double* y, const double* s, int64_t N, const double* x, int64_t T,
-             double xi, double rc, double tol, double* u, void* stream, ehs_report* rep)
+// report of a finished evaluation, with the stage times when timing is on
+int finish_report(ehs_ctx* c, const Plan& p, size_t need, ehs_report* rep)
 {
-    if (!c) return EHS_EINVAL;
-    if (T > 0 && !u) return EHS_EINVAL;
-    if (hipSetDevice(c->device) != hipSuccess) return EHS_EHIP;
-    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (!rep) return EHS_OK;
+    fill_report(p, rep);
+    rep->workspace_bytes = (double)need;
+    if (!(c->opt_timing && c->ev_ok)) return EHS_OK;
+    if (hipEventSynchronize(c->ev[EHS_ST_TOTAL]) != hipSuccess) return EHS_EHIP;
+    for (int i = 0; i < EHS_ST_TOTAL; ++i) {
+        float ms = 0.f;
+        hipEventElapsedTime(&ms, c->ev[i], c->ev[i + 1]);
+        rep->ms_stage[i] = ms;
+    }
+    float tot = 0.f;
+    hipEventElapsedTime(&tot, c->ev[EHS_ST_BBOX], c->ev[EHS_ST_TOTAL]);
+    rep->ms_stage[EHS_ST_TOTAL] = tot;
+    // the y / x3 pipeline: per-kernel sums over the slab groups
+    double sy = 0, sz = 0, si = 0;
+    for (int g = 0; 3 * g + 3 < c->nsev; ++g) {
+        float m0 = 0.f, m1 = 0.f, m2 = 0.f;
+        hipEventElapsedTime(&m0, c->sev[3 * g], c->sev[3 * g + 1]);
+        hipEventElapsedTime(&m1, c->sev[3 * g + 1], c->sev[3 * g + 2]);
+        hipEventElapsedTime(&m2, c->sev[3 * g + 2], c->sev[3 * g + 3]);
+        sy += m0;
+        sz += m1;
+        si += m2;
+    }
+    if (c->nsev > 1) {
+        rep->ms_stage[EHS_ST_FWDY] = sy;
+        rep->ms_stage[EHS_ST_ZSCALE] = sz;
+        rep->ms_stage[EHS_ST_INVY] = si;
+    }
+    return EHS_OK;
+}
+
+void start_timing(ehs_ctx* c, hipStream_t st)
+{
     if (c->opt_timing && !c->ev_ok) {
         bool ok = true;
         for (int i = 0; i <= EHS_NSTAGES; ++i) ok = ok && hipEventCreate(&c->ev[i]) == hipSuccess;
         c->ev_ok = ok;
     }
     if (c->opt_timing && c->ev_ok) hipEventRecord(c->ev[EHS_ST_BBOX], st);
+}
+
+int evaluate(ehs_ctx* c, int family, const double* y, const double* s, int64_t N, const double* x, int64_t T,
+             double xi, double rc, double tol, double* u, void* stream, ehs_report* rep)
+{
+    if (!c) return EHS_EINVAL;
+    if (c->fixed) return evaluate_fixed(c, c->fixed, family, y, s, N, x, T, xi, rc, tol, u, stream, rep, EHS_ENOMEM);
+    if (T > 0 && !u) return EHS_EINVAL;
+    if (hipSetDevice(c->device) != hipSuccess) return EHS_EHIP;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    start_timing(c, st);
     Plan p;
     int r = plan_request(c, family, y, s, N, x, T, xi, rc, tol, c->opt_prec, st, &p);
     if (r) return r;
@@ -731,54 +871,153 @@ int evaluate(ehs_ctx* c, int family, const double* y, const double* s, int64_t N
     }
     size_t need = 0;
     if ((r = plan_workspace(p, &need))) return r;
-    if ((r = ensure_ws(c, need, st))) return r;
+    if ((r = ensure_ws(c, need, st, p.Mt))) return r;
     if (c->opt_timing && c->ev_ok) hipEventRecord(c->ev[EHS_ST_PRECOMP], st);
     bool ran = false;
     Octants* oct = nullptr;
     if ((r = ensure_octants(c, p, st, &ran, &oct))) return r;
     if (ran) p.warnings |= 2;
     if ((r = execute(c, p, *oct, y, s, x, u, st))) return r;
-    if (rep) {
-        fill_report(p, rep);
-        rep->workspace_bytes = (double)need;
-        if (c->opt_timing && c->ev_ok) {
-            if (hipEventSynchronize(c->ev[EHS_ST_TOTAL]) != hipSuccess) return EHS_EHIP;
-            for (int i = 0; i < EHS_ST_TOTAL; ++i) {
-                float ms = 0.f;
-                hipEventElapsedTime(&ms, c->ev[i], c->ev[i + 1]);
-                rep->ms_stage[i] = ms;
-            }
-            float tot = 0.f;
-            hipEventElapsedTime(&tot, c->ev[EHS_ST_BBOX], c->ev[EHS_ST_TOTAL]);
-            rep->ms_stage[EHS_ST_TOTAL] = tot;
-            // the y / x3 pipeline: per-kernel sums over the slab groups
-            double sy = 0, sz = 0, si = 0;
-            for (int g = 0; 3 * g + 3 < c->nsev; ++g) {
-                float m0 = 0.f, m1 = 0.f, m2 = 0.f;
-                hipEventElapsedTime(&m0, c->sev[3 * g], c->sev[3 * g + 1]);
-                hipEventElapsedTime(&m1, c->sev[3 * g + 1], c->sev[3 * g + 2]);
-                hipEventElapsedTime(&m2, c->sev[3 * g + 2], c->sev[3 * g + 3]);
-                sy += m0;
-                sz += m1;
-                si += m2;
-            }
-            if (c->nsev > 1) {
-                rep->ms_stage[EHS_ST_FWDY] = sy;
-                rep->ms_stage[EHS_ST_ZSCALE] = sz;
-                rep->ms_stage[EHS_ST_INVY] = si;
-            }
-        }
-    }
-    return EHS_OK;
+    return finish_report(c, p, need, rep);
 }
 
+// ---------------------------------------------------------------------------
+// evaluations from a fixed region (no device allocation)
+// ---------------------------------------------------------------------------
+// offsets of the octant arrays held for `mask` (bit 0 H64, 1 B64, 2 H32,
+// 3 B32), in that order; returns the bytes of the octant part
+size_t fixed_oct_layout(int Mt, unsigned mask, size_t off[4])
+{
+    const size_t n = (size_t)octant_elems(Mt);
+    size_t o = 0;
+    for (int i = 0; i < 4; ++i) {
+        off[i] = o;
+        if (mask & (1u << i)) o += al(n * (i < 2 ? 8 : 4));
+    }
+    return o;
+}
+
+unsigned octant_mask(const Plan& p)
+{
+    unsigned m = 1u;  // H64
+    if (p.family != EHS_ROTLET) m |= 2u;
+    if (p.prec == 2) m |= (p.family != EHS_ROTLET) ? 12u : 4u;
+    return m;
+}
+
+// restores the fields of a context that a fixed-region evaluation borrows
+struct Borrow {
+    ehs_ctx* c;
+    void* ws;
+    size_t ws_bytes;
+    bool ws_external;
+    Tables* tables;
+    int timing;
+    explicit Borrow(ehs_ctx* c_)
+        : c(c_), ws(c_->ws), ws_bytes(c_->ws_bytes), ws_external(c_->ws_external), tables(c_->tables),
+          timing(c_->opt_timing)
+    {
+    }
+    ~Borrow()
+    {
+        c->ws = ws;
+        c->ws_bytes = ws_bytes;
+        c->ws_external = ws_external;
+        c->tables = tables;
+        c->opt_timing = timing;
+    }
+};
+
 }  // namespace
+
+int ehs::evaluate_fixed(ehs_ctx* c, Fixed* fx, int family, const double* y, const double* s, int64_t N,
+                        const double* x, int64_t T, double xi, double rc, double tol, double* u, void* stream,
+                        ehs_report* rep, int too_big)
+{
+    if (!c || !fx || !fx->base) return EHS_EINVAL;
+    if (T > 0 && !u) return EHS_EINVAL;
+    if (hipSetDevice(c->device) != hipSuccess) return EHS_EHIP;
+    std::lock_guard<std::mutex> lk(fx->mu);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    Borrow keep(c);
+    // the scratch of the allocation-free entry point is not the context's:
+    // no timing events there (their creation is the context's business)
+    if (fx != c->fixed) c->opt_timing = 0;
+    start_timing(c, st);
+    c->tables = &fx->tables;
+    c->ws_external = true;
+    c->ws = fx->base + FIXED_TABLE_BYTES;  // the bounding-box scratch first
+    c->ws_bytes = FIXED_BB_BYTES;
+    Plan p;
+    // (the bounding-box readback synchronises the stream: every earlier call
+    // on it has finished reading the tables and octants rewritten below)
+    int r = plan_request(c, family, y, s, N, x, T, xi, rc, tol, c->opt_prec, st, &p);
+    if (r) return r;
+    if (T == 0) {
+        if (rep) fill_report(p, rep);
+        return EHS_OK;
+    }
+    const size_t head = FIXED_TABLE_BYTES + FIXED_BB_BYTES;
+    const unsigned need_mask = octant_mask(p);
+    const bool reuse = fx->oct_Mt == p.Mt && (fx->oct_mask & need_mask) == need_mask;
+    const unsigned mask = reuse ? fx->oct_mask : need_mask;
+    size_t off[4];
+    const size_t oct_bytes = fixed_oct_layout(p.Mt, mask, off);
+    if (head + oct_bytes >= fx->bytes) return too_big;
+    const size_t avail = fx->bytes - head - al(oct_bytes);
+    // the slab groups of the y / x3 pipeline shrink until the workspace fits
+    size_t need = 0;
+    for (;;) {
+        if ((r = plan_workspace(p, &need))) return r;
+        if (need <= avail) break;
+        if (p.zg == 1) return too_big;
+        p.zg = std::max(1, p.zg / 2);
+    }
+    c->ws = fx->base + head + al(oct_bytes);
+    c->ws_bytes = avail;
+    // tables: start afresh when half of the table region is used (one plan
+    // needs a few MB at most)
+    if (fx->tables.used > fx->tables.cap / 2) {
+        fx->tables.m.clear();
+        fx->tables.used = 0;
+    }
+    if (c->opt_timing && c->ev_ok) hipEventRecord(c->ev[EHS_ST_PRECOMP], st);
+    char* ob = fx->base + head;
+    Octants o;
+    o.H64 = reinterpret_cast<double*>(ob + off[0]);
+    o.B64 = (mask & 2u) ? reinterpret_cast<double*>(ob + off[1]) : nullptr;
+    o.H32 = (mask & 4u) ? reinterpret_cast<float*>(ob + off[2]) : nullptr;
+    o.B32 = (mask & 8u) ? reinterpret_cast<float*>(ob + off[3]) : nullptr;
+    if (!reuse) {
+        fx->oct_Mt = 0;  // invalid until every array is produced
+        fx->oct_mask = 0;
+        double* scratch = static_cast<double*>(c->ws);
+        for (int kind = 0; kind < 2; ++kind) {
+            double* d64 = kind == 0 ? o.H64 : o.B64;
+            if (!d64) continue;
+            if ((r = take_injected_failure(&c->fail_precompute))) return r;
+            if ((r = precompute_kind(c, p.Mt, p.nf, p.nf3, kind, scratch, d64, st))) return r;
+            float* d32 = kind == 0 ? o.H32 : o.B32;
+            if (d32) HIPCHK(launch_oct_to_f32(d64, d32, octant_elems(p.Mt), st));
+        }
+        HIPCHK(hipStreamSynchronize(st));
+        fx->oct_Mt = p.Mt;
+        fx->oct_mask = mask;
+        fx->nf = p.nf;
+        fx->nf3 = p.nf3;
+        p.warnings |= 2;
+    }
+    if ((r = execute(c, p, o, y, s, x, u, st))) return r;
+    return finish_report(c, p, need, rep);
+}
 
 void ehs::free_tables(Tables* t)
 {
     if (!t) return;
-    for (auto& kv : t->m) hipFree(kv.second);
+    if (!t->arena)
+        for (auto& kv : t->m) hipFree(kv.second);
     t->m.clear();
+    t->used = 0;
 }
 
 int ehs::ctx_init(ehs_ctx* c, int device, Tables* shared)
@@ -803,13 +1042,14 @@ void ehs::ctx_release(ehs_ctx* c)
 {
     if (c->ws && !c->ws_external) hipFree(c->ws);
     c->ws = nullptr;
-    for (auto& kv : c->cache) {
-        if (kv.second.B64) hipFree(kv.second.B64);
-        if (kv.second.H64) hipFree(kv.second.H64);
-        if (kv.second.B32) hipFree(kv.second.B32);
-        if (kv.second.H32) hipFree(kv.second.H32);
-    }
+    for (auto& kv : c->cache) free_octants(kv.second);
     c->cache.clear();
+    if (c->fixed) {
+        free_tables(&c->fixed->tables);
+        if (c->fixed->base) hipFree(c->fixed->base);
+        delete c->fixed;
+        c->fixed = nullptr;
+    }
     if (c->own_tables && c->tables) {
         free_tables(c->tables);
         delete c->tables;
@@ -828,15 +1068,30 @@ extern "C" {
 
 int ehs_create(ehs_ctx** out, int hip_device, size_t arena_bytes)
 {
-    (void)arena_bytes;
     if (!out) return EHS_EINVAL;
     *out = nullptr;
+    if (arena_bytes > 0 && arena_bytes < EHS_ARENA_MIN_BYTES) return EHS_EINVAL;
     int n = 0;
     if (hipGetDeviceCount(&n) != hipSuccess || hip_device < 0 || hip_device >= n) return EHS_EINVAL;
     if (hipSetDevice(hip_device) != hipSuccess) return EHS_EHIP;
     ehs_ctx* c = new (std::nothrow) ehs_ctx();
     if (!c) return EHS_ENOMEM;
     int rc = ctx_init(c, hip_device, nullptr);
+    if (!rc && arena_bytes > 0) {
+        // one region for tables, octants and workspace: no allocation later
+        c->fixed = new (std::nothrow) Fixed();
+        if (!c->fixed) rc = EHS_ENOMEM;
+        if (!rc && hipMalloc((void**)&c->fixed->base, arena_bytes) != hipSuccess) {
+            c->fixed->base = nullptr;
+            hipGetLastError();
+            rc = EHS_ENOMEM;
+        }
+        if (!rc) {
+            c->fixed->bytes = arena_bytes;
+            c->fixed->tables.arena = c->fixed->base;
+            c->fixed->tables.cap = FIXED_TABLE_BYTES;
+        }
+    }
     if (rc) {
         ctx_release(c);
         delete c;
@@ -871,6 +1126,7 @@ int ehs_set_option(ehs_ctx* c, int option, double value)
         case EHS_OPT_ZSLAB: c->force_zg = (int)value; return EHS_OK;
         case EHS_OPT_GATHER_EXTRA: c->gather_extra = (int)value; return EHS_OK;
         case EHS_OPT_DGRID: c->dgrid = (int)value; return EHS_OK;
+        case EHS_OPT_FAIL_PRECOMPUTE: c->fail_precompute = std::max(0, (int)value); return EHS_OK;
         default: return EHS_EINVAL;
     }
 }
@@ -924,15 +1180,27 @@ int ehs_tune(ehs_ctx* c, int family, const double* y, const double* s, int64_t N
     if (max_evals < 1 || max_evals > 64 || !(xi0 > 0) || !(rc0 > 0)) return EHS_EINVAL;
     if (ntrace) *ntrace = 0;
     hipStream_t st = static_cast<hipStream_t>(stream);
+    // grid sizes cached before the search stay; of the candidates' own, only
+    // the fastest candidate's octants are kept
+    std::vector<int> before;
+    for (auto& kv : c->cache) before.push_back(kv.first);
     // the starting point fixes the box and the real-space estimate
     ehs_report r0;
     int r = evaluate(c, family, y, s, N, x, T, xi0, rc0, tol, u, stream, &r0);
     if (r) return r;
     const double L = r0.L, est = r0.est_real;
+    auto drop_unless = [&](int Mt, int keep) {
+        if (Mt == keep || std::find(before.begin(), before.end(), Mt) != before.end()) return;
+        auto it = c->cache.find(Mt);
+        if (it == c->cache.end()) return;
+        free_octants(it->second);
+        c->cache.erase(it);
+    };
 
     struct Cand {
         int k;  // xi = xi0 2^(k/8)
         double xi, rc, ms;
+        int Mt;
     };
     std::vector<Cand> tried;
     // 0: timed; 1: inadmissible (ends the walk in its direction); < 0: error
@@ -955,7 +1223,13 @@ int ehs_tune(ehs_ctx* c, int family, const double* y, const double* s, int64_t N
             if (hipStreamSynchronize(st) != hipSuccess) return EHS_EHIP;
             ms = std::min(ms, std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count());
         }
-        tried.push_back({k, xi, rc, ms});
+        tried.push_back({k, xi, rc, ms, rw.Mt});
+        // (the octants of a slower candidate are released: under
+        // EHS_OPT_MEM_CAP they would otherwise crowd out later candidates)
+        size_t b = 0;
+        for (size_t i = 1; i < tried.size(); ++i)
+            if (tried[i].ms < tried[b].ms) b = i;
+        for (const Cand& t : tried) drop_unless(t.Mt, tried[b].Mt);
         return 0;
     };
     auto fastest = [&]() {
@@ -1032,6 +1306,18 @@ int ehs_plan_query(int family, int64_t N, int64_t T, const double* lo, const dou
     rc = check_extents(p, Lo, p.prec == 1 ? 8 : 4);
     if (rc) return rc;
     rep->workspace_bytes = (double)Lo.total;
+    return EHS_OK;
+}
+
+int ehs_context_memory(const ehs_ctx* c, double* workspace_bytes, double* cache_bytes_out, int* cache_entries)
+{
+    if (!c) return EHS_EINVAL;
+    double ws = c->fixed ? (double)c->fixed->bytes : (double)c->ws_bytes;
+    double cb = (double)cache_bytes(c);
+    int ne = (int)c->cache.size();
+    if (workspace_bytes) *workspace_bytes = ws;
+    if (cache_bytes_out) *cache_bytes_out = cb;
+    if (cache_entries) *cache_entries = ne;
     return EHS_OK;
 }
 

@@ -27,13 +27,38 @@ struct Octants {
 
 // Twiddle and Stockham stage tables by (length, element size); immutable once
 // built, the map is guarded by mu.  One per standalone context, one per server
-// (shared by its slots).
+// (shared by its slots), one per fixed region.  With `arena` set the tables
+// are carved from that device region (bump allocation, never freed one by
+// one) instead of allocated.
 struct Tables {
     std::mutex mu;
     std::map<std::pair<int, int>, void*> m;
+    char* arena = nullptr;
+    size_t cap = 0, used = 0;
 };
 
 void free_tables(Tables* t);
+
+// A fixed device region from which an evaluation takes everything it needs,
+// so that it allocates nothing: the stage tables, the octants of one grid
+// size and the workspace, laid out as
+//   [tables: FIXED_TABLE_BYTES][bounding-box scratch: FIXED_BB_BYTES]
+//   [octants of grid size oct_Mt][workspace: the rest].
+// The region of a context created with arena_bytes > 0, or the per-device
+// static scratch of the allocation-free entry point.  The octants are kept
+// between calls and recomputed when the grid size or the arrays needed change.
+constexpr size_t FIXED_TABLE_BYTES = (size_t)16 << 20;
+constexpr size_t FIXED_BB_BYTES = (size_t)128 << 10;
+
+struct Fixed {
+    char* base = nullptr;
+    size_t bytes = 0;
+    Tables tables;
+    int oct_Mt = 0;          // grid size of the octants held (0: none)
+    unsigned oct_mask = 0;   // arrays held: bit 0 H64, 1 B64, 2 H32, 3 B32
+    int nf = 0, nf3 = 0;
+    std::mutex mu;           // host-side state; calls overlapping on the device still race
+};
 
 }  // namespace ehs
 
@@ -52,6 +77,8 @@ struct ehs_ctx {
     std::vector<hipEvent_t> sev;             // per-launch events of the slab pipeline (timing)
     int nsev = 0;                            // events recorded in the last evaluation
     double mem_cap = 0.0;
+    ehs::Fixed* fixed = nullptr;             // arena_bytes > 0 at creation: everything from one region
+    int fail_precompute = 0;                 // test hook: the next octant production fails (EHS_EHIP)
 };
 
 namespace ehs {
@@ -82,5 +109,13 @@ int execute(ehs_ctx* c, Plan& p, const Octants& o, const double* y, const double
             hipStream_t st);
 
 void fill_report(const Plan& p, ehs_report* r);
+
+// One evaluation that takes its tables, octants and workspace from the fixed
+// region fx (no device allocation); `too_big` is returned when the plan does
+// not fit the region even with the smallest slab group.
+int evaluate_fixed(ehs_ctx* c, Fixed* fx, int family, const double* y, const double* s, int64_t N, const double* x,
+                   int64_t T, double xi, double rc, double tol, double* u, void* stream, ehs_report* rep,
+                   int too_big);
+
 
 }  // namespace ehs

@@ -266,6 +266,11 @@ inline int make_plan(const PlanInput& in, Plan* out)
     // weights; the choice is made below, once M~ is known
     const int Pd = P + (in.family == 1 ? 6 : 2);
     if (Pd > 30) return -1;
+    // the stresslet's second-derivative correction density stays near 1e-10
+    // at N = 1e5 whatever the support (the k^2 in its spectrum needs a finer
+    // grid than the truncation estimate gives): refused rather than run
+    // above tol
+    if (in.family == 1 && in.dgrid > 0 && p.prec == 1) return -1;
     const int Pe = std::max(std::max(P, Pg), (p.prec == 1 && in.dgrid != 0) ? Pd : P);
     // grid intervals over the box
     int M = in.force_M;
@@ -295,10 +300,8 @@ inline int make_plan(const PlanInput& in, Plan* out)
     // 10 ms per component at M~ = 480 and 4.4 ns per point and P^3 node)
     {
         bool dg = false;
-        // (the stresslet only on request: with its second-derivative weights
-        // the error stays near 1e-10 at N = 1e5 whatever the support, so
-        // the finer structure of that density needs a finer grid)
-        if (p.prec == 1 && in.dgrid != 0 && (in.family != 1 || in.dgrid > 0)) {
+        // (never for the stresslet: see the refusal above)
+        if (p.prec == 1 && in.dgrid != 0 && in.family != 1) {
             int ncB = in.family == 0 ? 4 : in.family == 1 ? 7 : 2;
             double save = 10.0 * std::pow(Mt / 480.0, 3) * (ncB - 1);
             double cost = 4.4e-9 * 2.0 * (double)in.N * ((double)Pd * Pd * Pd - (double)P * P * P) *

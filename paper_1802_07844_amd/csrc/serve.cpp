@@ -17,6 +17,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
@@ -142,6 +143,7 @@ struct ehs_server {
     bool stop = false;
     uint64_t next_ticket = 1, use_clock = 0;
     int running = 0;
+    std::atomic<int> fail_productions{0};  // test hook (EHS_OPT_FAIL_PRECOMPUTE)
     int64_t submitted = 0, completed = 0, failed = 0, rejected = 0, hits = 0, misses = 0, evictions = 0;
     size_t cache_bytes = 0;
     Clock::time_point t0;
@@ -156,7 +158,8 @@ void destroy_unit(ehs_server* s, Unit* u)
     s->arena.release(u->off, u->bytes);
     s->cache_bytes -= Arena::round(u->bytes);
     if (u->ready) hipEventDestroy(u->ready);
-    s->units.erase(unit_key(u->Mt, u->kind, u->f32));
+    auto it = s->units.find(unit_key(u->Mt, u->kind, u->f32));
+    if (it != s->units.end() && it->second == u) s->units.erase(it);
     delete u;
 }
 
@@ -298,7 +301,12 @@ void complete(ehs_server* s, Slot* sl, Req* r, int code, double gpu_ms)
     r->state = REQ_DONE;
     r->t_done = s->now_ms();
     s->arena.release(r->ws_off, r->ws_bytes);
-    for (Unit* u : r->units) u->refs--;
+    for (Unit* u : r->units) {
+        u->refs--;
+        // a unit whose production failed left the cache when the failure was
+        // recorded; its memory goes back once no admitted request holds it
+        if (u->failed && u->refs == 0) destroy_unit(s, u);
+    }
     r->units.clear();
     r->produce.clear();
     sl->job = nullptr;
@@ -324,7 +332,9 @@ int run_job(ehs_server* s, Slot* sl, Req* r)
     for (Unit* u : r->produce) {
         if (code == EHS_OK) {
             if (!u->f32) {
-                code = precompute_octant(c, p, u->kind, reinterpret_cast<double*>(s->mem + u->off), st);
+                if (s->fail_productions.load() > 0 && s->fail_productions.fetch_sub(1) > 0) code = EHS_EHIP;
+                if (code == EHS_OK)
+                    code = precompute_octant(c, p, u->kind, reinterpret_cast<double*>(s->mem + u->off), st);
             } else {
                 Unit* src = nullptr;
                 for (Unit* v : r->units)
@@ -347,6 +357,12 @@ int run_job(ehs_server* s, Slot* sl, Req* r)
         std::lock_guard<std::mutex> lk(s->mu);
         u->recorded = true;
         u->failed = code != EHS_OK;
+        if (u->failed) {
+            // out of the cache at once: the next request that needs this
+            // array allocates and produces it again
+            auto it = s->units.find(unit_key(u->Mt, u->kind, u->f32));
+            if (it != s->units.end() && it->second == u) s->units.erase(it);
+        }
         s->cv_units.notify_all();
     }
     // 2. wait (on the stream) for octants produced by other requests
@@ -567,6 +583,13 @@ int ehs_wait(ehs_server* s, uint64_t ticket, int timeout_ms, ehs_request_status*
     s->reqs.erase(it);
     delete r;
     return code;
+}
+
+int ehs_server_set_option(ehs_server* s, int option, double value)
+{
+    if (!s || option != EHS_OPT_FAIL_PRECOMPUTE) return EHS_EINVAL;
+    s->fail_productions.store(std::max(0, (int)value));
+    return EHS_OK;
 }
 
 int ehs_server_stats(ehs_server* s, ehs_serve_stats* out)

@@ -1,0 +1,187 @@
+"""GPU tests of the context's memory behaviour and failure paths.
+
+* A context created with an arena (ehs_create with arena_bytes > 0) takes
+  every evaluation's tables, octants and workspace from that one region: its
+  results equal those of a growing context, and the calls allocate nothing.
+* A failed truncated-kernel precompute (forced from the host with the
+  EHS_OPT_FAIL_PRECOMPUTE hook, before anything is launched) leaves no cache
+  entry behind, in a context and in a server: the next call succeeds.
+* The runtime-optimal search keeps only the fastest candidate's octants.
+* The correction-density option (EHS_OPT_DGRID) in both settings against the
+  oracle, and its refusal for the stresslet.
+"""
+import math
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle  # noqa: E402
+import paper_1802_07844_amd as ehs  # noqa: E402
+from paper_1802_07844_amd import workloads  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def _rc(nb, n):
+    return (nb * 3.0 / (4.0 * math.pi * n)) ** (1.0 / 3.0)
+
+
+def _problem(fam, n, seed, nb=300, tol=1e-10):
+    y, s = workloads.make(fam, n, seed)
+    rc = _rc(nb, n)
+    xi = ehs.xi_for_cutoff(fam, rc, tol / 2)
+    return y, s, torch.from_numpy(y).to(DEV), torch.from_numpy(s).to(DEV), xi, rc
+
+
+def _free():
+    torch.cuda.synchronize()
+    return torch.cuda.mem_get_info()[0]
+
+
+@pytest.mark.parametrize("prec", [1, 2])
+def test_arena_context_matches_growing_context(prec):
+    """Same plans, same arithmetic: bitwise-equal results from the arena
+    context and the growing one, over calls whose grid size changes; the arena
+    context's calls leave device memory unchanged."""
+    tol = 1e-10 if prec == 1 else 1e-5
+    grow = ehs.Context(0)
+    arena = ehs.Context(0, arena_bytes=3 << 30)
+    try:
+        for c in (grow, arena):
+            c.set_option(ehs.OPT_PRECISION, prec)
+        cases = [("stokeslet", 1000, 51), ("rotlet", 400, 52), ("stresslet", 700, 53), ("stokeslet", 300, 54)]
+        data = [_problem(f, n, sd, tol=tol) for f, n, sd in cases]
+        outs = [torch.empty((yd.shape[0], 3), dtype=torch.float64, device=DEV) for _, _, yd, _, _, _ in data]
+        ref = []
+        for (fam, n, _), (y, s, yd, sd, xi, rc) in zip(cases, data):
+            ref.append(grow.evaluate(fam, yd, sd, yd, xi, rc, tol).cpu().numpy())
+        before = _free()
+        for (fam, n, _), (y, s, yd, sd, xi, rc), o, r in zip(cases, data, outs, ref):
+            u, rep = arena.evaluate(fam, yd, sd, yd, xi, rc, tol, out=o, report=True)
+            torch.cuda.synchronize()
+            got = u.cpu().numpy()
+            print(f"arena {fam} N={n} prec={rep.precision} Mt={rep.Mt} zslab={rep.zslab} "
+                  f"max|diff|={np.max(np.abs(got - r)):.2e}")
+            assert rep.precision == prec
+            np.testing.assert_array_equal(got, r)
+        after = _free()
+        print(f"device memory change over the arena calls: {(before - after) / 2**20:.1f} MiB")
+        assert before - after < 32 * 2**20
+        # and against the oracle, for the first case
+        y, s = data[0][0], data[0][1]
+        assert oracle.rel_rms(oracle.halfspace("stokeslet", y, s, y), ref[0]) <= tol
+    finally:
+        grow.close()
+        arena.close()
+
+
+def test_arena_context_too_small():
+    arena = ehs.Context(0, arena_bytes=ehs.ARENA_MIN_BYTES)
+    try:
+        y, s, yd, sd, xi, rc = _problem("stokeslet", 1000, 55)
+        with pytest.raises(ehs.EhsError) as e:
+            arena.evaluate("stokeslet", yd, sd, yd, xi, rc, 1e-10)
+        assert e.value.code == ehs.EHS_ENOMEM
+    finally:
+        arena.close()
+    with pytest.raises(ehs.EhsError) as e:
+        ehs.Context(0, arena_bytes=1 << 20)
+    assert e.value.code == ehs.EHS_EINVAL
+
+
+@pytest.mark.parametrize("arena_bytes", [0, 2 << 30])
+def test_failed_precompute_leaves_no_cache_entry(arena_bytes):
+    c = ehs.Context(0, arena_bytes=arena_bytes)
+    try:
+        c.set_option(ehs.OPT_PRECISION, 1)
+        y, s, yd, sd, xi, rc = _problem("stokeslet", 800, 56)
+        c.set_option(ehs.OPT_FAIL_PRECOMPUTE, 1)
+        with pytest.raises(ehs.EhsError) as e:
+            c.evaluate("stokeslet", yd, sd, yd, xi, rc, 1e-10)
+        assert e.value.code == ehs.EHS_EHIP
+        if arena_bytes == 0:
+            assert c.memory()["cache_entries"] == 0
+        u, rep = c.evaluate("stokeslet", yd, sd, yd, xi, rc, 1e-10, report=True)
+        torch.cuda.synchronize()
+        assert rep.warnings & 2  # produced again in this call
+        err = oracle.rel_rms(oracle.halfspace("stokeslet", y, s, y), u.cpu().numpy())
+        print(f"after a failed precompute (arena {arena_bytes}): rel-RMS {err:.2e}")
+        assert err <= 1e-10
+    finally:
+        c.close()
+
+
+def test_server_recovers_after_failed_production():
+    """One octant production fails: that request fails, the failed octant leaves
+    the cache, and the next request with the same grid size succeeds."""
+    y, s, yd, sd, xi, rc = _problem("rotlet", 900, 57)
+    with ehs.Server(0, arena_bytes=2 << 30, nslots=1) as srv:
+        srv.set_option(ehs.OPT_FAIL_PRECOMPUTE, 1)
+        t = srv.submit("rotlet", yd, sd, yd, xi, rc, 1e-10, precision=1)
+        with pytest.raises(ehs.EhsError) as e:
+            srv.wait(t)
+        assert e.value.code == ehs.EHS_EHIP
+        st = srv.stats()
+        assert st["failed"] == 1 and st["cache_entries"] == 0 and st["arena_used"] == 0
+        t = srv.submit("rotlet", yd, sd, yd, xi, rc, 1e-10, precision=1)
+        u, status = srv.wait(t)
+        assert status["code"] == ehs.EHS_OK
+        err = oracle.rel_rms(oracle.halfspace("rotlet", y, s, y), u.cpu().numpy())
+        print(f"server after a failed production: rel-RMS {err:.2e}, stats {srv.stats()}")
+        assert err <= 1e-10
+        assert srv.stats()["cache_entries"] == 1
+
+
+def test_tune_keeps_only_the_fastest_candidates_octants():
+    n = 20_000
+    y, f, yd, fd, xi, rc = _problem("stokeslet", n, 58, nb=60)
+    c = ehs.Context(0)
+    try:
+        c.set_option(ehs.OPT_PRECISION, 1)
+        res = c.tune("stokeslet", yd, fd, yd, xi, rc, 1e-10, max_evals=12)
+        m = c.memory()
+        print(f"tune: {len(res['trace'])} candidates, best xi={res['xi']:.2f} r_c={res['r_c']:.4f}; memory {m}")
+        assert len(res["trace"]) >= 3
+        assert m["cache_entries"] == 1
+        assert m["cache_bytes"] <= 2 * 8 * (res["report"].Mt + 1) ** 2 * (2 * res["report"].Mt + 1)
+    finally:
+        c.close()
+
+
+@pytest.mark.parametrize("fam", ["stokeslet", "rotlet"])
+@pytest.mark.parametrize("dgrid", [0, 1])
+def test_correction_density_option(fam, dgrid):
+    n = 3000
+    y, s, yd, sd, xi, rc = _problem(fam, n, 59 + dgrid)
+    c = ehs.Context(0)
+    try:
+        c.set_option(ehs.OPT_PRECISION, 1)
+        c.set_option(ehs.OPT_DGRID, dgrid)
+        u, rep = c.evaluate(fam, yd, sd, yd, xi, rc, 1e-10, report=True)
+        torch.cuda.synchronize()
+        err = oracle.rel_rms(oracle.halfspace(fam, y, s, y), u.cpu().numpy())
+        print(f"{fam} dgrid={dgrid}: plan dgrid={rep.dgrid} Ps={rep.Ps} rel-RMS {err:.2e}")
+        assert rep.dgrid == dgrid
+        assert err <= 1e-10
+    finally:
+        c.close()
+
+
+def test_correction_density_refused_for_the_stresslet():
+    y, s, yd, sd, xi, rc = _problem("stresslet", 500, 61)
+    c = ehs.Context(0)
+    try:
+        c.set_option(ehs.OPT_PRECISION, 1)
+        c.set_option(ehs.OPT_DGRID, 1)
+        with pytest.raises(ehs.EhsError) as e:
+            c.evaluate("stresslet", yd, sd, yd, xi, rc, 1e-10)
+        assert e.value.code == ehs.EHS_EINVAL
+        c.set_option(ehs.OPT_DGRID, -1)
+        u = c.evaluate("stresslet", yd, sd, yd, xi, rc, 1e-10)
+        assert oracle.rel_rms(oracle.halfspace("stresslet", y, s, y), u.cpu().numpy()) <= 1e-10
+    finally:
+        c.close()
