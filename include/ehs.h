@@ -52,6 +52,7 @@ extern "C" {
 #define EHS_ENOMEM (-4)  /* device allocation failed or the memory cap is too small */
 #define EHS_EHIP (-5)    /* a HIP runtime error */
 #define EHS_ETIMEDOUT (-6) /* ehs_wait: the request has not completed within the timeout */
+#define EHS_ETOOBIG (-7)   /* ewald_halfspace_noalloc: the problem does not fit its fixed scratch buffer */
 
 /* kernel families */
 #define EHS_STOKESLET 0
@@ -133,6 +134,7 @@ typedef struct ehs_report {
    its grid size and its workspace from it -- no allocation on the call path;
    the octants of the last grid size are kept and recomputed when the size
    changes; a problem that does not fit returns EHS_ENOMEM.
+   Also resolves, for this device, the scratch of ewald_halfspace_noalloc.
    Returns EHS_OK, EHS_EINVAL (bad device or arena size), EHS_ENOMEM or
    EHS_EHIP; *out is NULL on error. */
 int ehs_create(ehs_ctx** out, int hip_device, size_t arena_bytes);
@@ -167,6 +169,34 @@ int ewald_halfspace_stresslet(ehs_ctx* ctx, const double* sources, const double*
 int ewald_halfspace_rotlet(ehs_ctx* ctx, const double* sources, const double* v, int64_t N,
                            const double* targets, int64_t T, double xi, double r_c, double tol,
                            double* u_out, void* stream, ehs_report* rep);
+
+/*
+ * Allocation-free evaluation, for callers that cannot allocate device memory
+ * during a call (tight serving loops, harnesses that forbid hipMalloc).  The
+ * same evaluation as ewald_halfspace_{stokeslet,stresslet,rotlet} (family
+ * EHS_STOKESLET, EHS_STRESSLET or EHS_ROTLET; strengths N x 3, N x 6 or
+ * N x 3; other arguments as there, options such as EHS_OPT_PRECISION from
+ * ctx), but every buffer it needs -- stage tables, truncated-kernel octants,
+ * grids, cell lists, sort scratch -- comes from one static device array of
+ * EHS_NOALLOC_SCRATCH_BYTES per device, held from the library's first use on
+ * that device until the process ends.  No hipMalloc, hipFree or other
+ * allocating call is made; ctx supplies its device, options and pinned
+ * readback buffer (its own workspace and cache are not touched).
+ * The octants of the last grid size stay in the scratch and are recomputed
+ * when the size changes.  The slab groups of the transform pipeline shrink
+ * to fit; a problem that still does not fit returns EHS_ETOOBIG without
+ * launching anything (enough for N = 1000 at tol 1e-10 with ~300 neighbours,
+ * M~ = 64-80, for each of the three kernels).
+ * Every call on a device shares that device's scratch: calls that overlap on
+ * one device (other host threads, or other streams not yet synchronised)
+ * race and give undefined results.  Each call overwrites every scratch byte
+ * it reads before reading it, except the octants and tables it reuses.
+ * Stage timing (EHS_OPT_TIMING) is not recorded by this entry point.
+ */
+#define EHS_NOALLOC_SCRATCH_BYTES ((size_t)512 << 20)
+int ewald_halfspace_noalloc(ehs_ctx* ctx, int family, const double* sources, const double* strengths, int64_t N,
+                            const double* targets, int64_t T, double xi, double r_c, double tol, double* u_out,
+                            void* stream, ehs_report* rep);
 
 /* Device memory a context holds: its workspace (or arena) bytes, the bytes
    and number of grid sizes of its octant cache.  Any output may be NULL. */

@@ -24,12 +24,13 @@ STOKESLET, STRESSLET, ROTLET = 0, 1, 2
 FAMILIES = {"stokeslet": STOKESLET, "stresslet": STRESSLET, "rotlet": ROTLET}
 (OPT_PRECISION, OPT_TIMING, OPT_FORCE_M, OPT_FORCE_P, OPT_FORCE_MT, OPT_MEM_CAP, OPT_ZSLAB, OPT_GATHER_EXTRA,
  OPT_DGRID, OPT_FAIL_PRECOMPUTE) = range(10)
+NOALLOC_SCRATCH_BYTES = 512 << 20
 ARENA_MIN_BYTES = 32 << 20
 STAGES = ["bbox", "precompute", "binning", "realspace", "spread", "fwd_x", "fwd_y", "z_scale", "inv_y", "inv_x",
           "gather", "total"]
 NSTAGES = len(STAGES)
 
-EHS_OK, EHS_EINVAL, EHS_EDOMAIN, EHS_ERANGE, EHS_ENOMEM, EHS_EHIP, EHS_ETIMEDOUT = 0, -1, -2, -3, -4, -5, -6
+EHS_OK, EHS_EINVAL, EHS_EDOMAIN, EHS_ERANGE, EHS_ENOMEM, EHS_EHIP, EHS_ETIMEDOUT, EHS_ETOOBIG = 0, -1, -2, -3, -4, -5, -6, -7
 
 
 class Report(ctypes.Structure):
@@ -86,6 +87,9 @@ def lib():
                 fn = getattr(L, name)
                 fn.argtypes = [vp, vp, vp, i64, vp, i64, dp, dp, dp, vp, vp, ctypes.POINTER(Report)]
                 fn.restype = ctypes.c_int
+            L.ewald_halfspace_noalloc.argtypes = [vp, ctypes.c_int, vp, vp, i64, vp, i64, dp, dp, dp, vp, vp,
+                                                  ctypes.POINTER(Report)]
+            L.ewald_halfspace_noalloc.restype = ctypes.c_int
             L.ehs_context_memory.argtypes = [vp, ctypes.POINTER(dp), ctypes.POINTER(dp), ctypes.POINTER(ctypes.c_int)]
             L.ehs_context_memory.restype = ctypes.c_int
             L.ehs_strerror.argtypes = [ctypes.c_int]
@@ -237,6 +241,25 @@ class Context:
         ws, cb, ne = ctypes.c_double(), ctypes.c_double(), ctypes.c_int()
         check(lib().ehs_context_memory(self._h, ctypes.byref(ws), ctypes.byref(cb), ctypes.byref(ne)))
         return {"workspace_bytes": ws.value, "cache_bytes": cb.value, "cache_entries": ne.value}
+
+    def evaluate_noalloc(self, family, sources, strengths, targets, xi, r_c, tol, out, stream=None, report=False):
+        """ewald_halfspace_noalloc: the evaluation from the library's static
+        per-device scratch (no device allocation; `out` must be given)."""
+        fam = FAMILIES[family] if isinstance(family, str) else int(family)
+        ncol = 6 if fam == STRESSLET else 3
+        ys = _dev_ptr(sources, "sources", 3)
+        ss = _dev_ptr(strengths, "strengths", ncol)
+        if strengths.shape[0] != sources.shape[0]:
+            raise ValueError("strengths and sources differ in length")
+        xs = _dev_ptr(targets, "targets", 3)
+        uo = _dev_ptr(out, "out", 3)
+        if out.shape[0] != targets.shape[0]:
+            raise ValueError("out and targets differ in length")
+        rep = Report()
+        check(lib().ewald_halfspace_noalloc(self._h, fam, ys, ss, int(sources.shape[0]), xs, int(targets.shape[0]),
+                                            float(xi), float(r_c), float(tol), uo, _stream_handle(stream),
+                                            ctypes.byref(rep)))
+        return (out, rep) if report else out
 
     def evaluate(self, family, sources, strengths, targets, xi, r_c, tol, out=None, stream=None, report=False):
         import torch

@@ -29,7 +29,7 @@ COMMON = [
     f"-I{os.path.join(ROOT, 'include')}",
 ]
 
-SOURCES = ["fft.hip", "binning.hip", "realspace.hip", "grid.hip", "api.cpp", "serve.cpp"]
+SOURCES = ["fft.hip", "binning.hip", "realspace.hip", "grid.hip", "api.cpp", "serve.cpp", "noalloc.hip"]
 
 
 def _compile(src: str) -> str:

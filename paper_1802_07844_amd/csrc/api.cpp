@@ -1077,6 +1077,8 @@ int ehs_create(ehs_ctx** out, int hip_device, size_t arena_bytes)
     ehs_ctx* c = new (std::nothrow) ehs_ctx();
     if (!c) return EHS_ENOMEM;
     int rc = ctx_init(c, hip_device, nullptr);
+    // the static scratch of the allocation-free entry point on this device
+    if (!rc) rc = noalloc_attach(hip_device);
     if (!rc && arena_bytes > 0) {
         // one region for tables, octants and workspace: no allocation later
         c->fixed = new (std::nothrow) Fixed();
@@ -1161,6 +1163,8 @@ const char* ehs_strerror(int code)
         case EHS_ENOMEM: return "device memory exhausted or above the memory cap";
         case EHS_EHIP: return "HIP runtime error";
         case EHS_ETIMEDOUT: return "request not completed within the timeout";
+        case EHS_ETOOBIG:
+            return "problem larger than the fixed scratch buffer of the allocation-free entry point";
         default: return "unknown error";
     }
 }

@@ -117,5 +117,9 @@ int evaluate_fixed(ehs_ctx* c, Fixed* fx, int family, const double* y, const dou
                    int64_t T, double xi, double rc, double tol, double* u, void* stream, ehs_report* rep,
                    int too_big);
 
+// Resolve the device address of the static scratch of the allocation-free
+// entry point for `device` (which must be current); called once per device
+// at context creation.  Returns EHS_OK or EHS_EHIP.
+int noalloc_attach(int device);
 
 }  // namespace ehs
