@@ -1,20 +1,36 @@
 """Benchmark: half-space spectral Ewald summation on one MI355X.
 
-One step = one full evaluation of the half-space stokeslet sum (binning,
-real-space sum, spreading, zero-padded 3D transforms with the fused scaling,
-inverse transforms, quadrature and FP64 combination) for N = 100,000 sources
-= targets uniform in [0,1)^2 x (0,1], forces N(0,1), FP64 at tol 1e-10, with
-xi and r_c chosen for about 30 neighbours per point.  Inputs are resident in
-device memory before the timed region; the truncated-kernel precompute is done
-during warm-up (it depends only on the grid size and is excluded, as in the
-paper's timings).
+One step = one full evaluation of the half-space sum: bounding box and plan,
+cell binning, real-space sum, spreading, zero-padded 3D transforms with the
+fused scaling, inverse transforms, quadrature and FP64 combination.  Inputs
+are resident in device memory before the timed region; the truncated-kernel
+precompute happens during warm-up (it depends on the grid size only and is
+left out, as in the paper's timings).
 
-Prints one JSON line.  Extra fields: the FP32 path on the same workload at
-tol 1e-5, the same FP64 problem at the runtime-optimal (xi, r_c) that the
-tuning procedure of the paper's results section finds (`tuned`), the relative
-RMS error of all three against the FP64 oracle on a sample of targets,
-per-stage times, the roofline of the dominant kernel and the oracle's own
-throughput on the host cores (cpu_baseline).
+Headline (`value`): the N = 4,000,000 stokeslet clustered at the wall
+(x1, x2 uniform in [0,1), x3 ~ Exp(mean 0.05) clipped to (0,1]), forces
+N(0,1), sources = targets, FP64 at tol 1e-10 -- the largest single-GPU
+workload of the benchmark set.  Beside it, each with its relative RMS error
+against the FP64 oracle on a sample of targets, its stage times and its
+roofline:
+
+  fp32      the same clustered set in FP32 at tol 1e-5;
+  c3        N = 1,000,000 uniform stresslet (unit orientations) and rotlet,
+            FP64 at tol 1e-10 and FP32 at tol 1e-5;
+  c2        N = 100,000 uniform stokeslet, FP64 at tol 1e-10 (~30
+            neighbours) and FP32 at tol 1e-5 (~300 neighbours);
+  tuned     the N = 100,000 FP64 problem at the (xi, r_c) of the runtime
+            parameter search (the tuning procedure of the paper's results);
+  serving   a Poisson stream of mixed requests through one server;
+  cpu_baseline  the FP64 oracle on the host cores, on a bounded sample of the
+            headline workload's targets against all its sources.
+
+The roofline of every leg is the per-stage model in stage_model(): closed-
+form algorithmic bytes (inputs read once, outputs written once) and flops
+(transforms counted as 5 n log2 n per complex line of length n, less one
+radix-2 stage where half the input or output is zero; spreading, quadrature
+and real-space pairs counted from their formulas), each stage bound by the
+larger of bytes / 8 TB/s and flops / vector peak.  Prints one JSON line.
 """
 import argparse
 import json
@@ -27,113 +43,248 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-FP64_VALU_PEAK_TFS = 78.6
+VALU_PEAK_TFS = {8: 78.6, 4: 157.3}  # vector FP64 / FP32, MI355X
+
+# flops per in-range pair of the real-space sum, counted from the kernels'
+# formulas (direct_term / image_term) with the transcendental parts costed as
+# their instruction sequences: exp 22, sqrt 8, division 8 (reciprocal and
+# Newton steps), erfc from the exponential 39 (division, degree-14 Horner,
+# one product); the per-pair distance 8
+PAIR_FLOPS = {
+    "direct": {0: 112, 1: 131, 2: 99},
+    "image": {0: 171, 1: 246, 2: 158},
+}
 
 
-def _stage_bytes(rep, ncin, esz):
-    """Algorithmic HBM bytes of each transform pass per evaluation (inputs read
-    once, outputs written once; the multiplier octants read once)."""
+def _fft(n, pruned=True):
+    """Flops of one complex line transform of length n (one radix-2 stage
+    fewer when half its input or output is zero)."""
+    return 5.0 * n * (math.log2(n) - (1.0 if pruned else 0.0))
+
+
+def stage_model(rep, N, T, esz):
+    """Closed-form algorithmic bytes and flops of each stage of one evaluation
+    under the plan in `rep` (an ehs.Report): {stage: (bytes, flops)}."""
     Mt = rep.Mt
-    c = 2 * esz
-    real = Mt * Mt * 2 * Mt * esz
-    a = (Mt + 1) * 2 * Mt * Mt * c
-    z = (Mt + 1) * 4 * Mt * Mt * c
-    kinds = 1 if rep.family == 2 else 2
-    nout = 4 if esz == 8 else 6  # output grids: T1 and phi (FP64) or T1 and grad phi (FP32)
-    oct_bytes = (Mt + 1) * (Mt + 1) * (2 * Mt + 1) * (8 if esz == 8 else 4) * kinds
-    # the inverse side produces only the x3 nodes from x3_first up (the ones
-    # the quadrature at the targets reads); the correction grids (components
-    # from nca on, spread at the images) are read only below x3_corr_end
-    keep = (2 * Mt - rep.x3_first) / (2 * Mt)
-    nca = 6 if rep.family == 1 else 3
-    nin = nca + (ncin - nca) * rep.x3_corr_end / (2 * Mt)
-    return {
-        "fwd_x": nin * (real + a),
-        "fwd_y": nin * (a + z),
-        "z_scale": nin * z + nout * z * keep + oct_bytes,
-        "inv_y": nout * (z + a) * keep,
-        "inv_x": nout * (a + real) * keep,
-    }
+    e = esz
+    fam = rep.family
+    nca = 6 if fam == 1 else 3                   # kernel-grid components
+    ncb = {0: 4, 1: 7, 2: 2}[fam]                # separate correction grids
+    nin = nca + (1 if rep.dgrid else ncb)        # spread / forward grids
+    nout = 4 if e == 8 else 6                    # inverse grids
+    ns = 6 if fam == 1 else 3                    # strength values per source
+    keep = (2 * Mt - rep.x3_first) / (2 * Mt)    # inverse side: rows the quadrature reads
+    czf = rep.x3_corr_end / (2 * Mt)             # correction grids: rows below the images' support top
+    nin_eff = nca + (nin - nca) * czf
+    V_R = Mt * Mt * 2 * Mt
+    V_A = (Mt + 1) * 2 * Mt * Mt
+    V_Z = (Mt + 1) * 4 * Mt * Mt
+    kinds = 1 if fam == 2 else 2
+    oct_bytes = (Mt + 1) ** 2 * (2 * Mt + 1) * (8 if e == 8 else 4) * kinds
+    n2, n4 = 2 * Mt, 4 * Mt
+    Ps3, Pg3 = rep.Ps ** 3, rep.Pg ** 3
+    m = {}
+    m["realspace"] = (N * (3 + ns) * 8 + T * 9 * 8,
+                      rep.pairs_direct * PAIR_FLOPS["direct"][fam] + rep.pairs_image * PAIR_FLOPS["image"][fam])
+    # sources carry the kernel grid, images the kernel grid and the corrections
+    m["spread"] = (nin * V_R * e + N * (3 + ns) * 8,
+                   N * Ps3 * (1 + 2 * nca) + N * Ps3 * (1 + 2 * nin))
+    # x1: real lines of padded length 2 Mt (two per complex transform)
+    m["fwd_x"] = (nin_eff * (V_R * e + V_A * 2 * e), nin_eff * Mt * n2 * 0.5 * _fft(n2))
+    # x2: A (x1 half spectrum, x2 nodes) to the x2 spectrum over the padded length
+    m["fwd_y"] = (nin_eff * (V_A + V_Z) * 2 * e, nin_eff * (Mt + 1) * n2 * _fft(n2))
+    # x3 pass: forward (input half zero) and inverse (output kept from x3_first)
+    # of length 4 Mt per (k1, k2) line, and the scaling (about 8 flops per
+    # input component and k); the k-space grid is never stored
+    m["z_scale"] = (nin_eff * V_Z * 2 * e + nout * V_Z * 2 * e * keep + oct_bytes,
+                    (Mt + 1) * n2 * ((nin + nout) * _fft(n4) + 8.0 * nin * n4))
+    m["inv_y"] = (nout * (V_Z + V_A) * keep * 2 * e, nout * (Mt + 1) * n2 * keep * _fft(n2))
+    m["inv_x"] = (nout * (V_A * 2 * e + V_R * e) * keep, nout * Mt * n2 * keep * 0.5 * _fft(n2))
+    m["gather"] = (nout * V_R * keep * e + T * 9 * 8, T * Pg3 * (1 + 2 * nout))
+    return m
 
 
-# kernels whose sources determine the fused x3 pass (a change voids the traffic counters)
-_Z_SOURCES = ["paper_1802_07844_amd/csrc/fft.hip", "paper_1802_07844_amd/csrc/common.h",
-              "paper_1802_07844_amd/csrc/kernels.h"]
-
-
-def _sources_sha():
-    import hashlib
-
-    h = hashlib.sha256()
-    for p in _Z_SOURCES:
-        with open(os.path.join(ROOT, p), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()[:16]
-
-
-def _measured_traffic(name):
-    """HBM bytes per launch from a committed rocprofv3 counter summary (a line
-    'traffic-json: {...}' in profiles/<name>), if it was taken on the current
-    kernel sources; else None."""
-    path = os.path.join(ROOT, "profiles", name)
-    if not os.path.exists(path):
-        return None
-    for line in open(path):
-        if line.startswith("traffic-json:"):
-            d = json.loads(line.split(":", 1)[1])
-            if d.get("sources_sha") == _sources_sha():
-                return d
-    return None
-
-
-def _measured_valu(name):
-    """FP64 flops per launch of the fused x3 pass from a committed rocprofv3
-    counter summary (a line 'valu-json: {...}' in profiles/<name>), if it was
-    taken on the current kernel sources; else None."""
-    path = os.path.join(ROOT, "profiles", name)
-    if not os.path.exists(path):
-        return None
-    for line in open(path):
-        if line.startswith("valu-json:"):
-            d = json.loads(line.split(":", 1)[1])
-            if d.get("sources_sha") == _sources_sha():
-                return d
-    return None
-
-
-def _ncin(rep):
-    """Input grids of the plan: the kernel grid and either the correction
-    density (FP64 D-grid plans) or the separate correction grids."""
-    nca = 6 if rep.family == 1 else 3
-    ncb = {0: 4, 1: 7, 2: 2}[rep.family]
-    return nca + (1 if rep.dgrid else ncb)
-
-
-def _roofline(rep, stage_ms, ncin, esz, traffic_file=None, valu_file=None):
-    sb = _stage_bytes(rep, ncin, esz)
-    dom = max(sb.keys(), key=lambda k: stage_ms[k])
+def roofline(rep, stage_ms, N, T, esz, ms_step):
+    """Per stage: floor = max(bytes / HBM peak, flops / vector peak) and the
+    bound it names; for the dominant stage (largest measured time) the
+    achieved rate against that bound's peak; for the whole step the sum of
+    the floors against the measured time."""
+    model = stage_model(rep, N, T, esz)
+    vpk = VALU_PEAK_TFS[esz]
+    stages = {}
+    floor_sum = 0.0
+    for k, (b, f) in model.items():
+        t_h = b / (HBM_PEAK_GBS * 1e9) * 1e3
+        t_v = f / (vpk * 1e12) * 1e3
+        fl = max(t_h, t_v)
+        floor_sum += fl
+        ms = stage_ms.get(k, 0.0)
+        stages[k] = {"ms": ms, "bytes": b, "flops": f, "floor_ms": fl, "bound": "hbm" if t_h >= t_v else "alu",
+                     "frac": fl / ms if ms > 0 else None}
+    dom = max(stages, key=lambda k: stages[k]["ms"])
+    d = stages[dom]
     launches = 1
     if dom in ("fwd_y", "z_scale", "inv_y"):
         launches = (rep.Mt + rep.zslab) // rep.zslab  # one launch per group of k1 slabs
-    per_launch = sb[dom] / launches
-    ms_launch = stage_ms[dom] / launches
-    achieved = per_launch / (ms_launch * 1e-3) / 1e9
-    traffic = None
-    if traffic_file and dom == "z_scale":
-        t = _measured_traffic(traffic_file)
-        if t is not None:
-            traffic = t["bytes_per_launch"] * (per_launch / t["algorithmic_bytes_per_launch"])
-    # the vector FP64 rate of the same launches (flops from the committed
-    # counter summary, time from this run)
-    valu = None
-    if valu_file and dom == "z_scale" and esz == 8:
-        v = _measured_valu(valu_file)
-        if v is not None:
-            tf = v["fp64_flops_per_launch"] / (ms_launch * 1e-3) / 1e12
-            valu = {"achieved": tf, "peak": FP64_VALU_PEAK_TFS, "unit": "TFLOP/s", "frac": tf / FP64_VALU_PEAK_TFS}
-    return {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "bytes_per_launch": per_launch,
-            "launches_per_step": launches, "ms_per_launch": ms_launch, "valu_fp64": valu}
+    ms_launch = d["ms"] / launches
+    gbs = d["bytes"] / launches / (ms_launch * 1e-3) / 1e9
+    tfs = d["flops"] / launches / (ms_launch * 1e-3) / 1e12
+    if d["bound"] == "hbm":
+        achieved, peak, unit = gbs, HBM_PEAK_GBS, "GB/s"
+    else:
+        achieved, peak, unit = tfs, vpk, "TFLOP/s"
+    # the method's own minimum over the whole step: the spread grids read once,
+    # the output grids written once, the octants and the point data (the
+    # transform intermediates not materialised), against all its flops
+    Mt, e = rep.Mt, esz
+    nin = (6 if rep.family == 1 else 3) + (1 if rep.dgrid else {0: 4, 1: 7, 2: 2}[rep.family])
+    nout = 4 if e == 8 else 6
+    keep = (2 * Mt - rep.x3_first) / (2 * Mt)
+    V_R = Mt * Mt * 2 * Mt
+    oct_bytes = (Mt + 1) ** 2 * (2 * Mt + 1) * (8 if e == 8 else 4) * (1 if rep.family == 2 else 2)
+    mb = (nin + nout * keep) * V_R * e + oct_bytes + model["realspace"][0]
+    mf = sum(f for _, f in model.values())
+    m_floor = max(mb / (HBM_PEAK_GBS * 1e9), mf / (vpk * 1e12)) * 1e3
+    method = {"bytes": mb, "flops": mf, "floor_ms": m_floor,
+              "bound": "hbm" if mb / (HBM_PEAK_GBS * 1e9) >= mf / (vpk * 1e12) else "alu",
+              "hbm_frac": mb / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS,
+              "valu_frac": mf / (ms_step * 1e-3) / 1e12 / vpk}
+    return {"bound": d["bound"], "kernel": dom, "achieved": achieved, "peak": peak, "unit": unit,
+            "frac": achieved / peak, "traffic": None,
+            "hbm": {"achieved_gbs": gbs, "frac": gbs / HBM_PEAK_GBS},
+            "valu": {"achieved_tfs": tfs, "frac": tfs / vpk, "precision": "fp64" if esz == 8 else "fp32"},
+            "bytes_per_launch": d["bytes"] / launches, "flops_per_launch": d["flops"] / launches,
+            "launches_per_step": launches, "ms_per_launch": ms_launch,
+            "step": {"floor_ms": floor_sum, "ms": ms_step, "frac": floor_sum / ms_step},
+            "method": method, "stages": stages}
+
+
+def _measured_traffic(name, kernel):
+    """HBM bytes per launch of `kernel` from a committed rocprofv3 counter
+    summary (a line 'traffic-json: {...}' in profiles/<name>) taken on the
+    current library sources; else None."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", name)
+    if not os.path.exists(path):
+        return None
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1802_07844_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".hip", ".h", ".cpp")):
+            with open(os.path.join(csrc, f), "rb") as fh:
+                h.update(fh.read())
+    sha = h.hexdigest()[:16]
+    for line in open(path):
+        if line.startswith("traffic-json:"):
+            d = json.loads(line.split(":", 1)[1])
+            if d.get("kernel") == kernel and d.get("sources_sha") == sha:
+                return d
+    return None
+
+
+def _rc(nb, n):
+    return (nb * 3.0 / (4.0 * math.pi * n)) ** (1.0 / 3.0)
+
+
+# the legs: (family, layout, N, precision, tol, r_c rule)
+WORKLOADS = {
+    "c4_fp64": ("stokeslet", "clustered", 4_000_000, 1, 1e-10, 0.035),
+    "c4_fp32": ("stokeslet", "clustered", 4_000_000, 2, 1e-5, 0.03),
+    "c3_stresslet_fp64": ("stresslet", "uniform", 1_000_000, 1, 1e-10, ("nb", 2000)),
+    "c3_rotlet_fp64": ("rotlet", "uniform", 1_000_000, 1, 1e-10, ("nb", 2000)),
+    "c3_stresslet_fp32": ("stresslet", "uniform", 1_000_000, 2, 1e-5, ("nb", 2000)),
+    "c3_rotlet_fp32": ("rotlet", "uniform", 1_000_000, 2, 1e-5, ("nb", 2000)),
+    "c2_fp64": ("stokeslet", "uniform", 100_000, 1, 1e-10, ("nb", 30)),
+    "c2_fp32": ("stokeslet", "uniform", 100_000, 2, 1e-5, ("nb", 300)),
+}
+SEEDS = {"c2": 1, "c3": 2, "c4": 3}
+
+
+def describe(name):
+    fam, layout, n, prec, tol, rcr = WORKLOADS[name]
+    where = ("x1, x2 uniform in [0,1), x3 ~ Exp(mean 0.05) clipped to (0,1]" if layout == "clustered"
+             else "uniform in [0,1)^2 x (0,1]")
+    strengths = {"stokeslet": "forces N(0,1)", "stresslet": "strengths N(0,1)^3, orientations uniform on S^2",
+                 "rotlet": "torques N(0,1)^3"}[fam]
+    cut = f"r_c = {rcr}" if not isinstance(rcr, tuple) else f"r_c for ~{rcr[1]} neighbours"
+    return (f"half-space {fam}, N={n} sources=targets {where}, {strengths}, "
+            f"{'FP64' if prec == 1 else 'FP32'} tol {tol:g}, {cut}")
+
+
+class Runner:
+    def __init__(self, args, ehs, workloads, torch, np):
+        self.args, self.ehs, self.wl, self.torch, self.np = args, ehs, workloads, torch, np
+        self.ctx = ehs.Context(0)
+        self.ctx.set_option(ehs.OPT_TIMING, 1)
+        self.data = {}
+
+    def inputs(self, name):
+        fam, layout, n, prec, tol, rcr = WORKLOADS[name]
+        key = (fam, layout, n)
+        if key not in self.data:
+            seed = self.wl.SEED_BASE + SEEDS[name[:2]]
+            y, s = self.wl.make(fam, n, seed, layout=layout)
+            dev = self.torch.device("cuda:0")
+            self.data = {k: v for k, v in self.data.items() if k[2] <= 1_000_000}  # keep device memory modest
+            self.data[key] = (y, s, self.torch.from_numpy(y).to(dev), self.torch.from_numpy(s).to(dev), seed)
+        return self.data[key]
+
+    def params(self, name):
+        fam, layout, n, prec, tol, rcr = WORKLOADS[name]
+        rc = _rc(rcr[1], n) if isinstance(rcr, tuple) else rcr
+        # the real-space estimate takes a quarter of the budget
+        xi = self.ehs.xi_for_cutoff(fam, rc, tol / 2)
+        return fam, n, prec, tol, rc, xi
+
+    def run(self, name, steps, warmup, xi=None, rc=None):
+        np, torch = self.np, self.torch
+        fam, n, prec, tol, rc0, xi0 = self.params(name)
+        xi = xi0 if xi is None else xi
+        rc = rc0 if rc is None else rc
+        y, s, yd, sd, seed = self.inputs(name)
+        self.ctx.set_option(self.ehs.OPT_PRECISION, prec)
+        out = torch.empty((n, 3), dtype=torch.float64, device="cuda:0")
+        for _ in range(warmup):
+            self.ctx.evaluate(fam, yd, sd, yd, xi, rc, tol, out=out, report=True)
+        torch.cuda.synchronize()
+        st = np.zeros(self.ehs.NSTAGES)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            rep = self.ctx.evaluate(fam, yd, sd, yd, xi, rc, tol, out=out, report=True)[1]
+            st += np.array(list(rep.ms_stage))
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        ms = dt / steps * 1e3
+        stage_ms = dict(zip(self.ehs.STAGES, (st / steps).tolist()))
+        esz = 8 if rep.precision == 1 else 4
+        res = {"value": n * steps / dt, "unit": "points/s", "ms_per_step": ms, "steps": steps, "warmup": warmup,
+               "dtype": "f64" if esz == 8 else "f32", "tol": tol, "xi": xi, "r_c": rc,
+               "plan": {"M": rep.M, "P": rep.P, "Mt": rep.Mt, "eta": rep.eta, "Ps": rep.Ps, "Pg": rep.Pg,
+                        "zslab": rep.zslab, "dgrid": rep.dgrid, "x3_first": rep.x3_first,
+                        "x3_corr_end": rep.x3_corr_end, "cell_reach": rep.cell_reach,
+                        "occupancy": rep.occupancy, "precision": rep.precision, "warnings": rep.warnings,
+                        "est_real": rep.est_real, "est_fourier": rep.est_fourier, "est_fp32": rep.est_fp32},
+               "pairs": {"direct": rep.pairs_direct, "image": rep.pairs_image,
+                         "per_target": (rep.pairs_direct + rep.pairs_image) / n},
+               "stage_ms": stage_ms,
+               "roofline": roofline(rep, stage_ms, n, n, esz, ms)}
+        u = out.cpu().numpy()
+        del out
+        return res, u
+
+    def check(self, name, u, nsample):
+        """rel-RMS and the worst target's error against the oracle on a seeded sample."""
+        import oracle
+
+        fam, n, prec, tol, rc, xi = self.params(name)
+        y, s, yd, sd, seed = self.inputs(name)
+        idx = self.np.sort(self.wl.rng(seed + 1000).choice(n, size=min(n, nsample), replace=False))
+        ref = oracle.halfspace(fam, y, s, y[idx])
+        err = oracle.rel_rms(ref, u[idx])
+        vrms = self.np.sqrt(self.np.mean(self.np.sum(ref * ref, axis=1)))
+        worst = float(self.np.max(self.np.linalg.norm(u[idx] - ref, axis=1)) / vrms)
+        return {"rel_rms": err, "worst_target_rel": worst, "sample": len(idx)}
 
 
 def _serve_rc(kernel, n, tol):
@@ -243,12 +394,17 @@ def serve_bench(args, ehs, workloads, torch, np):
             checked.append({"kernel": d["kernel"], "N": n, "tol": d["tol"], "precision": ran, "xi": round(xi, 3),
                             "r_c": round(rc, 5), "Mt": st["report"]["Mt"], "rel_rms": err})
     srv.close()
-    pc = lambda a, p: float(np.percentile(np.array(a), p)) if a else None
+    sizes = np.array([stream[i]["n"] for i, _, _ in rows]) if rows else np.array([])
+    pc = lambda a, p: float(np.percentile(np.array(a), p)) if len(a) else None
+    by_size = {}
+    for lo, hi, lab in ((1e3, 1e4, "N<1e4"), (1e4, 1e5, "1e4<=N<1e5"), (1e5, 1e6 + 1, "N>=1e5")):
+        sel = [lat[k] for k in range(len(lat)) if lo <= sizes[k] < hi]
+        by_size[lab] = {"requests": len(sel), "p50_ms": pc(sel, 50), "p99_ms": pc(sel, 99)}
     return {
         "requests": len(lat), "requests_planned": args.serve_requests, "lambda_per_s": lam,
         "capacity_per_s": mu, "utilization_target": args.serve_util,
         "p50_ms": pc(lat, 50), "p99_ms": pc(lat, 99), "queue_p50_ms": pc(que, 50), "queue_p99_ms": pc(que, 99),
-        "service_p50_ms": pc(svc, 50), "service_p99_ms": pc(svc, 99),
+        "service_p50_ms": pc(svc, 50), "service_p99_ms": pc(svc, 99), "by_size": by_size,
         "points_per_s": pts / max(t_end - tstart, 1e-9), "nslots": args.serve_slots, "arena_gb": arena / 2**30,
         "arena_peak_gb": stats["arena_peak"] / 2**30, "cache_hits": stats["cache_hits"],
         "cache_misses": stats["cache_misses"], "evictions": stats["evictions"], "failed": stats["failed"],
@@ -266,15 +422,14 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--n", type=int, default=100_000)
-    ap.add_argument("--neighbours", type=float, default=30.0)
-    ap.add_argument("--fp32-neighbours", type=float, default=300.0,
-                    help="neighbours per point for the FP32 variant (its rounding error grows with xi L)")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target duration of the oracle sample")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--leg-steps", type=int, default=10, help="timed steps of each leg beside the headline")
+    ap.add_argument("--workload", default="c4_fp64", choices=sorted(WORKLOADS), help="headline workload")
+    ap.add_argument("--legs", default="fp32,c3,c2,tuned",
+                    help="comma list of extra legs (fp32, c3, c2, tuned) or 'none'")
+    ap.add_argument("--oracle-sample", type=int, default=512, help="targets checked against the oracle per leg")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target duration of the oracle timing sample")
+    ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the oracle timing and every oracle check")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving stream")
-    ap.add_argument("--no-tune", action="store_true", help="skip the runtime-optimal (xi, r_c) search")
     ap.add_argument("--tune-evals", type=int, default=12, help="candidates the (xi, r_c) search may time")
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--serve-util", type=float, default=0.7, help="arrival rate as a fraction of measured capacity")
@@ -297,173 +452,88 @@ def main():
     import paper_1802_07844_amd as ehs
     from paper_1802_07844_amd import workloads
 
-    n = args.n
-    seed = workloads.SEED_BASE + 1
-    y, f = workloads.uniform_stokeslet(n, seed)
-    dev = torch.device("cuda:0")
-    yd = torch.from_numpy(y).to(dev)
-    fd = torch.from_numpy(f).to(dev)
-    out = torch.empty((n, 3), dtype=torch.float64, device=dev)
-    # r_c for ~30 neighbours in the unit box, xi from the real-space estimate
-    rc = (args.neighbours * 3.0 / (4.0 * math.pi * n)) ** (1.0 / 3.0)
-    tol = 1e-10
-    # the real-space estimate takes a quarter of the budget (xi_for_cutoff gives estimate = tol'/2)
-    xi = ehs.xi_for_cutoff("stokeslet", rc, tol / 2)
-
     if args.copy_probe:
-        src = torch.ones(2**27, dtype=torch.float64, device=dev)
+        src = torch.ones(2**27, dtype=torch.float64, device="cuda:0")
         dst = torch.empty_like(src)
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
 
-    ctx = ehs.Context(0)
-    ctx.set_option(ehs.OPT_PRECISION, 1)
-    ctx.set_option(ehs.OPT_TIMING, 1)
+    R = Runner(args, ehs, workloads, torch, np)
+    legs = [] if args.legs == "none" else [x for x in args.legs.split(",") if x]
+    head = args.workload
+    fam, layout, n, prec, tol, rcr = WORKLOADS[head]
+    res, u = R.run(head, args.steps, args.warmup)
+    rec = {"metric": "points/sec at rel-RMS 1e-10 (FP64)" if prec == 1 else "points/sec at rel-RMS 1e-5 (FP32)",
+           "value": res["value"], "unit": "points/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": res["ms_per_step"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": res["dtype"], "data": "synthetic",
+           "config": {"workload": describe(head), "N": n, "xi": res["xi"], "r_c": res["r_c"], "tol": tol,
+                      "seed": workloads.SEED_BASE + SEEDS[head[:2]], **res["plan"]},
+           "pairs": res["pairs"], "stage_ms": res["stage_ms"], "roofline": res["roofline"]}
+    tr = _measured_traffic(f"{res['roofline']['kernel']}_{head}_counters.md", res["roofline"]["kernel"])
+    if tr is not None:
+        rec["roofline"]["traffic"] = tr["bytes_per_launch"]
+    checks = []  # (record, leg name, u)
+    checks.append((rec, head, u))
+    extra = {}
 
-    def step(o, t):
-        return ctx.stokeslet(yd, fd, yd, xi, rc, t, out=o, report=True)[1]
+    def leg(name, steps=args.leg_steps):
+        r, uu = R.run(name, steps, min(args.warmup, 2))
+        r["workload"] = describe(name)
+        checks.append((r, name, uu))
+        return r
 
-    for _ in range(args.warmup):
-        step(out, tol)
-    torch.cuda.synchronize()
-    stage_sum = np.zeros(ehs.NSTAGES)
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        rep = step(out, tol)
-        stage_sum += np.array(list(rep.ms_stage))
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    ms_per_step = dt / args.steps * 1e3
-    value = n * args.steps / dt
-    stage_ms = dict(zip(ehs.STAGES, (stage_sum / args.steps).tolist()))
-    u64 = out.cpu().numpy()
+    if "fp32" in legs and head == "c4_fp64":
+        rec["fp32"] = leg("c4_fp32")
+    if "c3" in legs:
+        extra["c3"] = {k: leg(f"c3_{k}") for k in ("stresslet_fp64", "rotlet_fp64", "stresslet_fp32", "rotlet_fp32")}
+    if "c2" in legs:
+        extra["c2"] = {"fp64": leg("c2_fp64"), "fp32": leg("c2_fp32")}
+    if "tuned" in legs:
+        # the N = 1e5 FP64 problem at the runtime-optimal (xi, r_c) of the
+        # tuning procedure (both truncation errors held, xi perturbed)
+        _, nn, _, t64, rc64, xi64 = R.params("c2_fp64")
+        y, s, yd, sd, _ = R.inputs("c2_fp64")
+        R.ctx.set_option(ehs.OPT_PRECISION, 1)
+        tres = R.ctx.tune("stokeslet", yd, sd, yd, xi64, rc64, t64, max_evals=args.tune_evals)
+        r, uu = R.run("c2_fp64", args.leg_steps, min(args.warmup, 2), xi=tres["xi"], rc=tres["r_c"])
+        r["workload"] = describe("c2_fp64") + " at the (xi, r_c) of the runtime parameter search"
+        r["search"] = [{"xi": a, "r_c": b, "ms": c} for a, b, c in tres["trace"]]
+        r["neighbours"] = 4.0 / 3.0 * math.pi * tres["r_c"] ** 3 * nn
+        checks.append((r, "c2_fp64", uu))
+        extra["tuned"] = r
+    rec.update(extra)
 
-    # dominant kernel and its roofline: algorithmic bytes per launch / average
-    # launch duration (HIP events on the evaluation's stream)
-    roofline = _roofline(rep, stage_ms, _ncin(rep), 8, "z_scale_stokeslet_N100k_fp64_counters.md",
-                         "valu_stokeslet_N100k_fp64_counters.md")
-
-    result = {
-        "metric": "points/sec at rel-RMS 1e-10 (FP64)",
-        "value": value,
-        "unit": "points/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64",
-        "data": "synthetic",
-        "config": {"workload": f"half-space stokeslet, N={n} sources=targets uniform in [0,1)^2x(0,1], "
-                               f"forces N(0,1), FP64 tol 1e-10, ~{args.neighbours:g} neighbours",
-                   "N": n, "xi": xi, "r_c": rc, "tol": tol, "M": rep.M, "P": rep.P, "Mt": rep.Mt,
-                   "eta": rep.eta, "zslab": rep.zslab, "Ps": rep.Ps, "Pg": rep.Pg, "dgrid": rep.dgrid,
-                   "x3_first": rep.x3_first, "x3_corr_end": rep.x3_corr_end,
-                   "seed": seed},
-        "stage_ms": stage_ms,
-        "roofline": roofline,
-    }
-
-    # the same problem at the runtime-optimal (xi, r_c) of the tuning procedure
-    # (both truncation errors held, xi perturbed), timed like the main line
-    def tuned(xi0, rc0, t, dtype):
-        tres = ctx.tune("stokeslet", yd, fd, yd, xi0, rc0, t, max_evals=args.tune_evals)
-        xit, rct = tres["xi"], tres["r_c"]
-        outt = torch.empty_like(out)
-        for _ in range(args.warmup):
-            rt = ctx.stokeslet(yd, fd, yd, xit, rct, t, out=outt, report=True)[1]
-        torch.cuda.synchronize()
-        stt = np.zeros(ehs.NSTAGES)
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            rt = ctx.stokeslet(yd, fd, yd, xit, rct, t, out=outt, report=True)[1]
-            stt += np.array(list(rt.ms_stage))
-        torch.cuda.synchronize()
-        dtt = time.perf_counter() - t0
-        res = {"value": n * args.steps / dtt, "unit": "points/s", "ms_per_step": dtt / args.steps * 1e3,
-               "dtype": dtype, "tol": t, "xi": xit, "r_c": rct,
-               "neighbours": 4.0 / 3.0 * math.pi * rct**3 * n, "M": rt.M, "P": rt.P, "Mt": rt.Mt,
-               "stage_ms": dict(zip(ehs.STAGES, (stt / args.steps).tolist())),
-               "search": [{"xi": a, "r_c": b, "ms": c} for a, b, c in tres["trace"]],
-               "note": "same points and forces; xi perturbed with both truncation estimates held"}
-        return res, outt.cpu().numpy()
-
-    ut = None
-    if not args.no_tune:
-        result["tuned"], ut = tuned(xi, rc, tol, "f64")
-
-    # FP32 path on the same workload at tol 1e-5
-    u32 = ut32 = None
-    if not args.no_fp32:
-        tol32 = 1e-5
-        ctx.set_option(ehs.OPT_PRECISION, 2)
-        rc32 = (args.fp32_neighbours * 3.0 / (4.0 * math.pi * n)) ** (1.0 / 3.0)
-        xi32 = ehs.xi_for_cutoff("stokeslet", rc32, tol32 / 2)
-        out32 = torch.empty_like(out)
-
-        def step32():
-            return ctx.stokeslet(yd, fd, yd, xi32, rc32, tol32, out=out32, report=True)[1]
-
-        for _ in range(args.warmup):
-            step32()
-        torch.cuda.synchronize()
-        st32 = np.zeros(ehs.NSTAGES)
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            r32 = step32()
-            st32 += np.array(list(r32.ms_stage))
-        torch.cuda.synchronize()
-        dt32 = time.perf_counter() - t0
-        u32 = out32.cpu().numpy()
-        sm32 = dict(zip(ehs.STAGES, (st32 / args.steps).tolist()))
-        result["fp32"] = {"value": n * args.steps / dt32, "unit": "points/s", "ms_per_step": dt32 / args.steps * 1e3,
-                          "dtype": "f32", "tol": tol32, "xi": xi32, "r_c": rc32, "neighbours": args.fp32_neighbours,
-                          "M": r32.M, "P": r32.P, "Mt": r32.Mt, "stage_ms": sm32,
-                          "roofline": _roofline(r32, sm32, _ncin(r32), 4)}
-        if not args.no_tune:
-            result["fp32"]["tuned"], ut32 = tuned(xi32, rc32, tol32, "f32")
-
-    # oracle on the host cores: a bounded sample of targets against all sources
     if not args.no_cpu_baseline:
         import oracle
 
+        # the oracle's own throughput on the host cores: a bounded sample of
+        # the headline workload's targets against all its sources
+        y, s, yd, sd, seed = R.inputs(head)
         cores = oracle.max_threads()
-        # size the sample from two short probes (the first also absorbs thread start-up)
-        S = 64
-        for target_s in (0.5, args.cpu_seconds):
-            t0 = time.perf_counter()
-            oracle.halfspace("stokeslet", y, f, y[:S])
-            tp = time.perf_counter() - t0
-            if target_s == args.cpu_seconds:
-                break
-            S = int(max(64, min(n, S * target_s / max(tp, 1e-6))))
-        S = int(max(64, min(n, S * args.cpu_seconds / max(tp, 1e-6))))
-        g = workloads.rng(seed + 1000)
-        idx = np.sort(g.choice(n, size=S, replace=False))
+        S = 16
         t0 = time.perf_counter()
-        ref = oracle.halfspace("stokeslet", y, f, y[idx])
+        oracle.halfspace(fam, y, s, y[:S])
+        tp = time.perf_counter() - t0
+        S = int(max(16, min(n, S * args.cpu_seconds / max(tp, 1e-6))))
+        idx = np.sort(workloads.rng(seed + 2000).choice(n, size=S, replace=False))
+        t0 = time.perf_counter()
+        oracle.halfspace(fam, y, s, y[idx])
         tc = time.perf_counter() - t0
-        result["cpu_baseline"] = {"value": S / tc, "unit": "points/s", "cores": cores, "kind": "oracle",
-                                  "sample": f"{S} of {n} targets against all {n} sources, FP64 direct sum, "
-                                            f"{tc:.1f} s"}
-        result["rel_rms_fp64"] = oracle.rel_rms(ref, u64[idx])
-        if u32 is not None:
-            result["fp32"]["rel_rms"] = oracle.rel_rms(ref, u32[idx])
-        if ut is not None:
-            result["tuned"]["rel_rms"] = oracle.rel_rms(ref, ut[idx])
-        if ut32 is not None:
-            result["fp32"]["tuned"]["rel_rms"] = oracle.rel_rms(ref, ut32[idx])
+        rec["cpu_baseline"] = {"value": S / tc, "unit": "points/s", "cores": cores, "kind": "oracle",
+                               "sample": f"{S} of {n} targets against all {n} sources ({describe(head)}), "
+                                         f"FP64 direct sum, {tc:.1f} s"}
+        for r, name, uu in checks:
+            r["oracle"] = R.check(name, uu, args.oracle_sample)
+        rec["rel_rms"] = rec["oracle"]["rel_rms"]
     if not args.no_serve:
-        del out
-        if u32 is not None:
-            del out32
-        ctx.close()
+        R.ctx.close()
+        R.data.clear()
+        checks.clear()
         torch.cuda.empty_cache()
-        result["serving"] = serve_bench(args, ehs, workloads, torch, np)
-    print(json.dumps(result))
+        rec["serving"] = serve_bench(args, ehs, workloads, torch, np)
+    print(json.dumps(rec))
 
 
 if __name__ == "__main__":

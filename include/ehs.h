@@ -26,9 +26,9 @@
  *    pointer after the call returns;
  *  - `stream` is a hipStream_t passed as void* (NULL: the default stream).
  *    The call returns after enqueueing; results are valid once the stream has
- *    synchronised.  One blocking device-to-host read (128 bytes: the bounding
- *    box, the validation counts and the strength measure) happens inside
- *    every call; a cache miss of the truncated-kernel precompute adds one
+ *    synchronised.  One blocking device-to-host read (384 bytes: the bounding
+ *    box, the validation counts, the strength measure and a histogram of the
+ *    target heights) happens inside every call; a cache miss of the truncated-kernel precompute adds one
  *    more synchronisation;
  *  - outputs are overwritten, never accumulated;
  *  - a context is not thread safe and calls on one context must not overlap
@@ -77,6 +77,8 @@ extern "C" {
                                density does not reach tol 1e-10 on the planned grid */
 #define EHS_OPT_FAIL_PRECOMPUTE 9 /* test hook: > 0 makes the next that many truncated-kernel
                                      productions fail with EHS_EHIP before anything is launched */
+#define EHS_OPT_CELL_REACH 10 /* 1..3: real-space cells of side >= r_c / value; 0 (default): chosen
+                                 from the targets' density (ehs_report.occupancy) */
 
 /* stage indices of ehs_report.ms_stage */
 #define EHS_ST_BBOX 0       /* bounding box + validation reduction and its readback */
@@ -120,6 +122,12 @@ typedef struct ehs_report {
                                of the lowest target reads no node below it */
     int32_t x3_corr_end;    /* x3 grid nodes from this one up lie above every image's Gaussian
                                support: the correction grids vanish there */
+    int32_t cell_reach;     /* real-space cells have side >= r_c / cell_reach and are walked
+                               (2 cell_reach + 1)^3 around a target's cell */
+    double occupancy;       /* targets per real-space cell of side r_c, averaged over the targets
+                               (from their height histogram, x1 and x2 taken as uniform) */
+    double pairs_direct;    /* in-range (target, source) pairs of the real-space sum, direct and */
+    double pairs_image;     /* image terms (counted when EHS_OPT_TIMING is on, else 0) */
 } ehs_report;
 
 /* Smallest arena a context accepts (the table and bounding-box regions). */

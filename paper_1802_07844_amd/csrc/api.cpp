@@ -347,7 +347,7 @@ int ensure_octants(ehs_ctx* c, const Plan& p, hipStream_t st, bool* ran, Octants
 // ---------------------------------------------------------------------------
 struct Layout {
     size_t X, Y, ZS, Zo, rec, keys, sortsc, toff, soff, tgoff, chunks, ys, ss, xs, upart, bb, ez, gkeys, gtoff, grec,
-        gpart, total;
+        gpart, cnt, total;
 };
 
 // Host-side audit: the largest extent every pass writes or reads must fit the
@@ -454,6 +454,7 @@ Layout layout(const Plan& p, size_t esz)
     L.gtoff = off; off += al(gt * (p.ntiles_g + 1) * sizeof(uint32_t));
     L.grec = off; off += al(gt * T * target_record_stride(p.gg.P, esz) * esz);
     L.gpart = off; off += al(gt * T * gather_slots(p.gg) * 6 * esz);
+    L.cnt = off; off += al(2 * sizeof(unsigned long long));  // real-space pair counters (timing)
     L.total = off;
     return L;
 }
@@ -550,6 +551,13 @@ int run(ehs_ctx* c, Plan& p, const Octants& oct, const double* y, const double* 
     ra.chunk_first = ch_first;
     ra.nchunks = ch_n;
     ra.tgt_perm = tperm;
+    ra.pairs = nullptr;
+    c->pairs_dev = nullptr;
+    if (c->opt_timing && c->ev_ok) {
+        ra.pairs = reinterpret_cast<unsigned long long*>(base + Lo.cnt);
+        c->pairs_dev = ra.pairs;
+        HIPCHK(fill_u32(reinterpret_cast<uint32_t*>(ra.pairs), 0u, 4, st));
+    }
     HIPCHK(launch_realspace<T>(p.family, ra, ys, ss, xs, upart, p.max_chunks, st));
     rec_ev(EHS_ST_SPREAD);
 
@@ -711,8 +719,8 @@ int ehs::plan_request(ehs_ctx* c, int family, const double* y, const double* s, 
     if (!(xi > 0) || !(rc > 0) || !std::isfinite(xi) || !std::isfinite(rc)) return EHS_EINVAL;
     if (!(tol >= 1e-14 && tol <= 1e-2)) return EHS_EINVAL;
     if (N >= (1LL << 30) || T >= (1LL << 31)) return EHS_EINVAL;
-    // bounding box, validation and Q (one readback)
-    size_t need = al((size_t)(1024 * 10 + 16) * sizeof(double));
+    // bounding box, validation, Q and the target heights (one readback)
+    size_t need = al((size_t)(1024 * 10 + 16 + ZH_BINS / 2) * sizeof(double));
     if (c->ws_external) {
         if (c->ws_bytes < need) return EHS_ENOMEM;
     } else {
@@ -722,9 +730,12 @@ int ehs::plan_request(ehs_ctx* c, int family, const double* y, const double* s, 
     char* base = static_cast<char*>(c->ws);
     double* partial = reinterpret_cast<double*>(base);
     double* out16 = partial + 1024 * 10;
+    uint32_t* zhist = reinterpret_cast<uint32_t*>(out16 + 16);
+    const double zbin = rc / 6.0;  // layers of r_c, r_c / 2 and r_c / 3 are whole numbers of bins
     int nb = bbox_blocks(N + T);
-    HIPCHK(launch_bbox(family, y, s, N, x, T, partial, nb, out16, st));
-    HIPCHK(hipMemcpyAsync(c->host_bbox, out16, 16 * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(launch_bbox(family, y, s, N, x, T, partial, nb, out16, 1.0 / zbin, zhist, st));
+    HIPCHK(hipMemcpyAsync(c->host_bbox, out16, 16 * sizeof(double) + ZH_BINS * sizeof(uint32_t),
+                          hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     const double* b = c->host_bbox;
     if (b[8] > 0) return EHS_EDOMAIN;
@@ -751,6 +762,9 @@ int ehs::plan_request(ehs_ctx* c, int family, const double* y, const double* s, 
     in.dgrid = c->dgrid;
     in.tlo3 = T > 0 ? b[7] : 0.0;
     in.slo3 = b[6];
+    in.zhist = reinterpret_cast<const uint32_t*>(b + 16);
+    in.zbin = zbin;
+    in.force_nr = c->force_nr;
     return make_plan(in, p);
 }
 
@@ -804,6 +818,8 @@ void ehs::fill_report(const Plan& p, ehs_report* r)
     r->est_fp32 = p.est32;
     r->x3_first = p.l3lo;
     r->x3_corr_end = p.lzc;
+    r->cell_reach = p.cg.nr;
+    r->occupancy = p.occ;
 }
 
 namespace {
@@ -824,6 +840,12 @@ int finish_report(ehs_ctx* c, const Plan& p, size_t need, ehs_report* rep)
     float tot = 0.f;
     hipEventElapsedTime(&tot, c->ev[EHS_ST_BBOX], c->ev[EHS_ST_TOTAL]);
     rep->ms_stage[EHS_ST_TOTAL] = tot;
+    if (c->pairs_dev) {
+        unsigned long long h[2] = {0ull, 0ull};
+        if (hipMemcpy(h, c->pairs_dev, sizeof(h), hipMemcpyDeviceToHost) != hipSuccess) return EHS_EHIP;
+        rep->pairs_direct = (double)h[0];
+        rep->pairs_image = (double)h[1];
+    }
     // the y / x3 pipeline: per-kernel sums over the slab groups
     double sy = 0, sz = 0, si = 0;
     for (int g = 0; 3 * g + 3 < c->nsev; ++g) {
@@ -1031,7 +1053,8 @@ int ehs::ctx_init(ehs_ctx* c, int device, Tables* shared)
         c->own_tables = true;
         if (!c->tables) return EHS_ENOMEM;
     }
-    if (hipHostMalloc((void**)&c->host_bbox, 16 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+    if (hipHostMalloc((void**)&c->host_bbox, 16 * sizeof(double) + ZH_BINS * sizeof(uint32_t),
+                      hipHostMallocDefault) != hipSuccess) {
         c->host_bbox = nullptr;
         return EHS_ENOMEM;
     }
@@ -1129,6 +1152,10 @@ int ehs_set_option(ehs_ctx* c, int option, double value)
         case EHS_OPT_GATHER_EXTRA: c->gather_extra = (int)value; return EHS_OK;
         case EHS_OPT_DGRID: c->dgrid = (int)value; return EHS_OK;
         case EHS_OPT_FAIL_PRECOMPUTE: c->fail_precompute = std::max(0, (int)value); return EHS_OK;
+        case EHS_OPT_CELL_REACH:
+            if (value < 0 || value > 3) return EHS_EINVAL;
+            c->force_nr = (int)value;
+            return EHS_OK;
         default: return EHS_EINVAL;
     }
 }

@@ -66,11 +66,19 @@ int bbox_blocks(long long n)
     return (int)b;
 }
 
+// besides the box: a histogram of the target heights x3 in ZH_BINS bins of
+// width 1 / zbin_inv from the wall (the last bin holds everything above),
+// from which the planner sizes the real-space cells by the targets' actual
+// density near the wall (integer counts: the same on every run)
 __global__ void __launch_bounds__(BB_NT) k_bbox(int family, const double* __restrict__ y, const double* __restrict__ s,
                                                 long long N, const double* __restrict__ x, long long T,
-                                                double* __restrict__ partial)
+                                                double* __restrict__ partial, double zbin_inv,
+                                                uint32_t* __restrict__ zhist)
 {
     __shared__ double red[BB_NT][BB_NV];
+    __shared__ uint32_t hist[ZH_BINS];
+    if (threadIdx.x < ZH_BINS) hist[threadIdx.x] = 0u;
+    __syncthreads();
     BBox b;
     bb_init(b);
     const int ns = family == STRESSLET ? 6 : 3;
@@ -94,6 +102,8 @@ __global__ void __launch_bounds__(BB_NT) k_bbox(int family, const double* __rest
             if (fin) b.v[6] = fmin(b.v[6], p2);
         } else if (fin) {
             b.v[7] = fmin(b.v[7], p2);
+            const int bin = (int)fmin((double)(ZH_BINS - 1), fmax(0.0, p2 * zbin_inv));
+            atomicAdd(&hist[bin], 1u);
         }
         if (!fin) {
             b.v[8] += 1.0;
@@ -121,6 +131,7 @@ __global__ void __launch_bounds__(BB_NT) k_bbox(int family, const double* __rest
         __syncthreads();
     }
     if (threadIdx.x < BB_NV) partial[blockIdx.x * BB_NV + threadIdx.x] = red[0][threadIdx.x];
+    if (threadIdx.x < ZH_BINS && hist[threadIdx.x]) atomicAdd(&zhist[threadIdx.x], hist[threadIdx.x]);
 }
 
 __global__ void k_bbox_final(const double* __restrict__ partial, int nb, double* __restrict__ out16)
@@ -138,9 +149,10 @@ __global__ void k_bbox_final(const double* __restrict__ partial, int nb, double*
 }
 
 hipError_t launch_bbox(int family, const double* y, const double* s, long long N, const double* x, long long T,
-                       double* partial, int nblocks, double* out16, hipStream_t st)
+                       double* partial, int nblocks, double* out16, double zbin_inv, uint32_t* zhist, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_bbox, dim3(nblocks), dim3(BB_NT), 0, st, family, y, s, N, x, T, partial);
+    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(ZH_BINS), 0, st, zhist, 0u, (long long)ZH_BINS);
+    hipLaunchKernelGGL(k_bbox, dim3(nblocks), dim3(BB_NT), 0, st, family, y, s, N, x, T, partial, zbin_inv, zhist);
     hipLaunchKernelGGL(k_bbox_final, dim3(1), dim3(64), 0, st, partial, nblocks, out16);
     return hipGetLastError();
 }

@@ -70,7 +70,7 @@ struct ehs_ctx {
     std::map<int, ehs::Octants> cache;       // by M~ (standalone contexts only)
     ehs::Tables* tables = nullptr;
     bool own_tables = true;
-    double* host_bbox = nullptr;             // pinned, 16 doubles
+    double* host_bbox = nullptr;             // pinned: 16 doubles, then ZH_BINS uint32 counts
     hipEvent_t ev[EHS_NSTAGES + 1] = {};
     bool ev_ok = false;
     int opt_prec = 0, opt_timing = 0, force_M = 0, force_P = 0, force_Mt = 0, force_zg = 0, gather_extra = -1, dgrid = -1;
@@ -79,6 +79,8 @@ struct ehs_ctx {
     double mem_cap = 0.0;
     ehs::Fixed* fixed = nullptr;             // arena_bytes > 0 at creation: everything from one region
     int fail_precompute = 0;                 // test hook: the next octant production fails (EHS_EHIP)
+    int force_nr = 0;                        // real-space cell reach (0: by density)
+    unsigned long long* pairs_dev = nullptr; // the last timed evaluation's pair counters (workspace)
 };
 
 namespace ehs {

@@ -87,9 +87,12 @@ hipError_t launch_line_fft(const cplx<T>* in, cplx<T>* out, int nl, int per, con
 // ---------------------------------------------------------------------------
 // bbox / validation reduction over sources and targets; 16 doubles out:
 // [0..2] min over all points, [3..5] max, [6] min source x3, [7] min target x3,
-// [8] non-finite count, [9] Q (sum of squared strength norms)
+// [8] non-finite count, [9] Q (sum of squared strength norms); and zhist,
+// ZH_BINS counts of the target heights in bins of width 1 / zbin_inv
+constexpr int ZH_BINS = 64;
 hipError_t launch_bbox(int family, const double* y, const double* s, long long N, const double* x, long long T,
-                       double* partial, int nblocks, double* out16, hipStream_t st);
+                       double* partial, int nblocks, double* out16, double zbin_inv, uint32_t* zhist,
+                       hipStream_t st);
 int bbox_blocks(long long n);
 
 // stable LSD radix sort of (key, value) pairs on `bits` low key bits
@@ -124,6 +127,7 @@ struct RealArgs {
     const uint32_t* chunk_first;  // first sorted target of each chunk
     const uint32_t* nchunks;      // device count of chunks
     const uint32_t* tgt_perm;     // sorted target -> original target
+    unsigned long long* pairs;    // nullable: in-range (direct, image) pairs evaluated, added up
 };
 
 hipError_t launch_cell_keys(const double* p, long long n, CellGeom cg, uint32_t* keys, uint32_t* idx, hipStream_t st);

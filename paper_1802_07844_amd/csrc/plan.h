@@ -167,7 +167,51 @@ struct PlanInput {
     int dgrid;         // 1 / 0: force the correction density D on / off; < 0: by cost
     double tlo3;       // lowest target x3 (>= 0)
     double slo3;       // lowest source x3 (> 0): the images lie at x3 <= -slo3
+    const uint32_t* zhist;  // nullable: ZH_BINS counts of the target heights, bins of width zbin
+    double zbin;
+    int force_nr;      // 1..3: real-space cells of side >= r_c / force_nr; else chosen by density
 };
+
+// Real-space cells of side >= r_c / nr are walked (2 nr + 1)^3 around a
+// target's cell.  Smaller cells cut the candidates' volume (27 r_c^3 for
+// nr = 1, 15.6 for 2, 12.7 for 3) but leave the 64-target chunks of a cell
+// emptier and add cell ranges to walk, so nr follows the number of targets
+// a cell of side r_c holds, averaged over the targets (a cell's chunks cost
+// in proportion to its targets): below 256, nr = 1; below 1500, nr = 2
+// (60-190 targets per cell), else 3.  Measured: N = 1e6 uniform with 2000
+// neighbours (480 per r_c cell) 38.6 -> 29.1 ms with nr = 2; with 600 (146)
+// 11.3 -> 14.9 ms; 300 at N = 1e5 (75) 0.72 -> 1.0 ms.  The average over the
+// targets comes from the height histogram with x1, x2 taken as uniform
+// over the box: a set clustered at the wall has most of its targets in
+// cells far fuller than the box average.
+inline double weighted_occupancy(const double extent[3], double rc, long long T, const uint32_t* zhist,
+                                 double zbin)
+{
+    int nc[3];
+    for (int a = 0; a < 3; ++a) nc[a] = std::max(1, std::min(256, (int)std::floor(extent[a] / rc)));
+    const double plane = (double)nc[0] * nc[1];
+    if (!zhist || !(zbin > 0) || !(extent[2] > 0)) return (double)T / (plane * nc[2]);
+    const double s3 = extent[2] / nc[2];
+    std::vector<double> layer(nc[2], 0.0);
+    for (int b = 0; b < ZH_BINS; ++b) {
+        const double n = (double)zhist[b];
+        if (n == 0) continue;
+        if (b < ZH_BINS - 1) {
+            int l = (int)std::floor((b + 0.5) * zbin / s3);
+            layer[std::min(std::max(l, 0), nc[2] - 1)] += n;
+        } else {
+            // everything above: spread over the layers it can occupy
+            int l0 = std::min(nc[2] - 1, (int)std::floor((ZH_BINS - 1) * zbin / s3));
+            for (int l = l0; l < nc[2]; ++l) layer[l] += n / (nc[2] - l0);
+        }
+    }
+    double s1 = 0, s2 = 0;
+    for (double n : layer) {
+        s1 += n;
+        s2 += n * n;
+    }
+    return s1 > 0 ? s2 / (s1 * plane) : 0.0;
+}
 
 struct Plan {
     int family, prec;
@@ -191,6 +235,7 @@ struct Plan {
     int lzc;   // the correction grids (components >= ncA, spread at the images only) vanish at x3 nodes >= lzc
     long long max_chunks;
     int warnings;
+    double occ;  // targets per real-space cell of side r_c, averaged over the targets
 };
 
 constexpr int EHS_MT_MAX = 2048;
@@ -354,18 +399,12 @@ inline int make_plan(const PlanInput& in, Plan* out)
     p.By = p.Bx;
     if (p.Bx < 2 || p.By < 1) return -3;
 
-    // real-space cells (x3 measured from the wall): side >= r_c, walked
-    // 3 x 3 x 3 around a target's cell; where cells of that side would hold
-    // many targets (256 or more on average), side >= r_c / 2 walked 5 x 5 x 5:
-    // the candidates' volume drops from 27 r_c^3 to 15.6 r_c^3 while the
-    // cells' chunks of 64 targets stay mostly full.  Measured: N = 1e6 with
-    // 2000 neighbours (480 targets per r_c cell) 38.6 -> 29.1 ms; with 600
-    // (146 per cell) 11.3 -> 14.9 ms and with 300 at N = 1e5 (75 per cell)
-    // 0.72 -> 1.0 ms, the chunks of the smaller cells being too sparse.
+    // real-space cells (x3 measured from the wall): side >= r_c / nr
     double extent[3] = {ext1, ext2, ext3};
-    double cells_rc = 1.0;
-    for (int a = 0; a < 3; ++a) cells_rc *= std::max(1.0, std::floor(extent[a] / in.rc));
-    const int nr = (double)in.T >= 256.0 * cells_rc ? 2 : 1;
+    const double occ = weighted_occupancy(extent, in.rc, in.T, in.zhist, in.zbin);
+    int nr = occ < 256.0 ? 1 : occ < 1500.0 ? 2 : 3;
+    if (in.force_nr >= 1 && in.force_nr <= 3) nr = in.force_nr;
+    p.occ = occ;
     p.cg.nr = nr;
     long long ncell = 1;
     for (int a = 0; a < 3; ++a) {

@@ -14,16 +14,36 @@
 #include <type_traits>
 
 #include "common.h"
+#include "erfc_poly.h"
 #include "kernels.h"
 
 namespace ehs {
 
+// erfc(x) for x >= 0 from E = exp(-x^2), which the Gaussian terms need
+// anyway: erfc(x) = E q(t), t = 1 / (1 + x / 2), q a fitted polynomial
+// (erfc_poly.h).  One division and a Horner polynomial, the same
+// instructions on every lane, where a library erfc branches over ranges of x
+// (a wavefront's pairs span 0 <= x < xi r_c and take several branches).
 template <typename T>
-__device__ __forceinline__ T t_erfc(T x);
+__device__ __forceinline__ T erfc_e(T x, T E);
 template <>
-__device__ __forceinline__ double t_erfc<double>(double x) { return erfc(x); }
+__device__ __forceinline__ double erfc_e<double>(double x, double E)
+{
+    const double t = 1.0 / (1.0 + 0.5 * x);
+    double q = ERFC_C64[ERFC_DEG64];
+#pragma unroll
+    for (int k = ERFC_DEG64 - 1; k >= 0; --k) q = fma(q, t, ERFC_C64[k]);
+    return E * q;
+}
 template <>
-__device__ __forceinline__ float t_erfc<float>(float x) { return erfcf(x); }
+__device__ __forceinline__ float erfc_e<float>(float x, float E)
+{
+    const float t = 1.0f / (1.0f + 0.5f * x);
+    float q = ERFC_C32[ERFC_DEG32];
+#pragma unroll
+    for (int k = ERFC_DEG32 - 1; k >= 0; --k) q = fmaf(q, t, ERFC_C32[k]);
+    return E * q;
+}
 template <typename T>
 __device__ __forceinline__ T t_exp(T x);
 template <>
@@ -44,7 +64,7 @@ __device__ __forceinline__ void direct_term(T rx, T ry, T rz, T r2, const T* s, 
     T r = t_sqrt<T>(r2);
     T ir = (T)1 / r;
     T E = t_exp<T>(-xi * xi * r2);
-    T C = t_erfc<T>(xi * r);
+    T C = erfc_e<T>(xi * r, E);
     if (K == STOKESLET) {
         // S_R f = (a - 2 c2 E) f + a (r.f) r / r^2,  a = c2 E + C / r
         T a = c2 * E + C * ir;
@@ -86,7 +106,7 @@ __device__ __forceinline__ void image_term(T rx, T ry, T rz, T r2, const T* s, T
     T ir = (T)1 / r;
     T ir2 = ir * ir;
     T E = t_exp<T>(-xi * xi * r2);
-    T C = t_erfc<T>(xi * r);
+    T C = erfc_e<T>(xi * r, E);
     T xi2 = xi * xi;
     // grad G_R = -alpha r, grad grad G_R = -alpha I + beta r r,
     // grad grad grad G_R = beta (d r)_sym + gamma r r r
@@ -170,7 +190,12 @@ __device__ __forceinline__ void image_term(T rx, T ry, T rz, T r2, const T* s, T
 // deterministic.
 constexpr int RS_PC = 64 * 4 * 3;  // contribution slots (doubles): 256 pairs in FP64
 
-template <typename T, int K>
+// PASS_IMG = false: the direct terms of every chunk (and the self term),
+// written to upart; PASS_IMG = true: the image and correction terms of the chunks in the
+// bottom nr cell layers, in FP64, added to upart.  Two launches rather than
+// one kernel: the FP64 image terms need many more registers than the direct
+// ones, and in one kernel they would set the occupancy of every chunk.
+template <typename T, int K, bool PASS_IMG>
 __global__ void __launch_bounds__(64) k_realspace(RealArgs a, const double* __restrict__ ys,
                                                   const double* __restrict__ ss, const double* __restrict__ xt,
                                                   double* __restrict__ upart)
@@ -187,6 +212,9 @@ __global__ void __launch_bounds__(64) k_realspace(RealArgs a, const double* __re
     const long long w = blockIdx.x;
     if (w >= (long long)(*a.nchunks)) return;  // the whole (one-wavefront) block
     const uint32_t cell = a.chunk_cell[w];
+    // (a target and a source can both lie within r_c of the wall only in the
+    // bottom nr cell layers; the chunks run in cell order, so these come first)
+    if (PASS_IMG && cell >= (uint32_t)(a.cg.nr * a.cg.nc[0] * a.cg.nc[1])) return;
     const uint32_t first = a.chunk_first[w];
     const int cnt = (int)min(64u, a.tgt_off[cell + 1] - first);
     const bool act = lane < cnt;
@@ -205,6 +233,7 @@ __global__ void __launch_bounds__(64) k_realspace(RealArgs a, const double* __re
     const double rc2 = a.rc2;
     T acc[3] = {0, 0, 0};
     double self[3] = {0.0, 0.0, 0.0};
+    unsigned long long npair[2] = {0ull, 0ull};  // direct, image (wave-uniform)
     const int nr = a.cg.nr;  // cells of side >= r_c / nr: neighbours within nr cells
     const int lo1 = c1 - nr > 0 ? c1 - nr : 0, hi1 = c1 + nr < n0 - 1 ? c1 + nr : n0 - 1;
 
@@ -245,6 +274,7 @@ __global__ void __launch_bounds__(64) k_realspace(RealArgs a, const double* __re
         }
         wave_sync();
         const int np = pre[B];
+        npair[IMG ? 1 : 0] += (unsigned long long)np;
         for (int q = lane; q < np; q += 64) {
             const int pr = plist[q], tl = pr & 63, j = pr >> 6;
             const double* s = sb + j * SW;
@@ -295,26 +325,26 @@ __global__ void __launch_bounds__(64) k_realspace(RealArgs a, const double* __re
         };
     };
 
-    for (int d3 = -nr; d3 <= nr; ++d3) {
-        int cc3 = c3 + d3;
-        if (cc3 < 0 || cc3 >= n2) continue;
-        for (int d2 = -nr; d2 <= nr; ++d2) {
-            int cc2 = c2i + d2;
-            if (cc2 < 0 || cc2 >= n1) continue;
-            long long row = ((long long)cc3 * n1 + cc2) * n0;
-            uint32_t s0 = a.src_off[row + lo1], s1 = a.src_off[row + hi1 + 1];
-            for (uint32_t mb = s0; mb < s1; mb += SB)
-                batch(mb, (int)min((uint32_t)SB, s1 - mb), std::false_type())(nullptr, acc);
+    if (!PASS_IMG) {
+        for (int d3 = -nr; d3 <= nr; ++d3) {
+            int cc3 = c3 + d3;
+            if (cc3 < 0 || cc3 >= n2) continue;
+            for (int d2 = -nr; d2 <= nr; ++d2) {
+                int cc2 = c2i + d2;
+                if (cc2 < 0 || cc2 >= n1) continue;
+                long long row = ((long long)cc3 * n1 + cc2) * n0;
+                uint32_t s0 = a.src_off[row + lo1], s1 = a.src_off[row + hi1 + 1];
+                for (uint32_t mb = s0; mb < s1; mb += SB)
+                    batch(mb, (int)min((uint32_t)SB, s1 - mb), std::false_type())(nullptr, acc);
+            }
         }
     }
     // Image and correction terms in FP64 in both precisions: for a source and
     // target near the wall they are of size 1/(x3 + y3)^2 and cancel to O(1)
     // on the wall, beyond what FP32 can resolve.  Only sources within r_c of
-    // the wall have images here, so this is a small share of the work.
-    // (a target and a source can both lie within r_c of the wall only in the
-    // bottom nr cell layers)
+    // the wall have images here.
     double acci[3] = {0.0, 0.0, 0.0};
-    if (c3 < nr) {
+    if (PASS_IMG) {
         for (int cc3 = 0; cc3 < nr && cc3 < n2; ++cc3) {
             for (int d2 = -nr; d2 <= nr; ++d2) {
                 int cc2 = c2i + d2;
@@ -326,11 +356,19 @@ __global__ void __launch_bounds__(64) k_realspace(RealArgs a, const double* __re
             }
         }
     }
+    if (a.pairs && lane == 0) atomicAdd(a.pairs + (PASS_IMG ? 1 : 0), npair[PASS_IMG ? 1 : 0]);
     if (act) {
         long long o = a.tgt_perm[t];
-        upart[3 * o + 0] = (double)acc[0] + acci[0] + self[0];
-        upart[3 * o + 1] = (double)acc[1] + acci[1] + self[1];
-        upart[3 * o + 2] = (double)acc[2] + acci[2] + self[2];
+        if (PASS_IMG) {
+            // after the direct launch on the same stream
+            upart[3 * o + 0] += acci[0];
+            upart[3 * o + 1] += acci[1];
+            upart[3 * o + 2] += acci[2];
+        } else {
+            upart[3 * o + 0] = (double)acc[0] + self[0];
+            upart[3 * o + 1] = (double)acc[1] + self[1];
+            upart[3 * o + 2] = (double)acc[2] + self[2];
+        }
     }
 }
 
@@ -340,10 +378,20 @@ hipError_t launch_realspace(int family, const RealArgs& a, const double* ys, con
 {
     if (max_chunks <= 0) return hipSuccess;
     dim3 grid((unsigned)max_chunks);  // one wavefront per chunk
+    // direct terms of every chunk, then the images of the bottom-layer chunks
     switch (family) {
-        case STOKESLET: hipLaunchKernelGGL((k_realspace<T, STOKESLET>), grid, dim3(64), 0, st, a, ys, ss, xt, upart); break;
-        case STRESSLET: hipLaunchKernelGGL((k_realspace<T, STRESSLET>), grid, dim3(64), 0, st, a, ys, ss, xt, upart); break;
-        default: hipLaunchKernelGGL((k_realspace<T, ROTLET>), grid, dim3(64), 0, st, a, ys, ss, xt, upart); break;
+        case STOKESLET:
+            hipLaunchKernelGGL((k_realspace<T, STOKESLET, false>), grid, dim3(64), 0, st, a, ys, ss, xt, upart);
+            hipLaunchKernelGGL((k_realspace<double, STOKESLET, true>), grid, dim3(64), 0, st, a, ys, ss, xt, upart);
+            break;
+        case STRESSLET:
+            hipLaunchKernelGGL((k_realspace<T, STRESSLET, false>), grid, dim3(64), 0, st, a, ys, ss, xt, upart);
+            hipLaunchKernelGGL((k_realspace<double, STRESSLET, true>), grid, dim3(64), 0, st, a, ys, ss, xt, upart);
+            break;
+        default:
+            hipLaunchKernelGGL((k_realspace<T, ROTLET, false>), grid, dim3(64), 0, st, a, ys, ss, xt, upart);
+            hipLaunchKernelGGL((k_realspace<double, ROTLET, true>), grid, dim3(64), 0, st, a, ys, ss, xt, upart);
+            break;
     }
     return hipGetLastError();
 }

@@ -185,3 +185,30 @@ def test_correction_density_refused_for_the_stresslet():
         assert oracle.rel_rms(oracle.halfspace("stresslet", y, s, y), u.cpu().numpy()) <= 1e-10
     finally:
         c.close()
+
+
+@pytest.mark.parametrize("reach", [0, 1, 2, 3])
+def test_cell_reach(reach):
+    """Real-space cells of side r_c / reach (0: chosen from the targets'
+    height histogram) on a set clustered at the wall: the same sum."""
+    n = 20_000
+    y, f = workloads.clustered_stokeslet(n, 62)
+    rc, tol = 0.08, 1e-10
+    xi = ehs.xi_for_cutoff("stokeslet", rc, tol / 2)
+    c = ehs.Context(0)
+    try:
+        c.set_option(ehs.OPT_PRECISION, 1)
+        c.set_option(ehs.OPT_TIMING, 1)
+        c.set_option(ehs.OPT_CELL_REACH, reach)
+        yd, fd = torch.from_numpy(y).to(DEV), torch.from_numpy(f).to(DEV)
+        u, rep = c.evaluate("stokeslet", yd, fd, yd, xi, rc, tol, report=True)
+        torch.cuda.synchronize()
+        err = oracle.rel_rms(oracle.halfspace("stokeslet", y, f, y), u.cpu().numpy())
+        print(f"reach {reach}: cell_reach={rep.cell_reach} occupancy={rep.occupancy:.1f} "
+              f"pairs {rep.pairs_direct:.0f} + {rep.pairs_image:.0f} images, rel-RMS {err:.2e}")
+        if reach:
+            assert rep.cell_reach == reach
+        assert rep.pairs_direct > 0 and rep.pairs_image > 0
+        assert err <= tol
+    finally:
+        c.close()

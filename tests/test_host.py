@@ -305,3 +305,38 @@ def test_tune_rejects_bad_arguments_without_a_device():
     best = (ctypes.c_double * 3)()
     assert L.ehs_tune(None, 0, None, None, 10, None, 10, 10.0, 0.3, 1e-10, 4, None, best, None, None, None,
                       None) == ehs.EHS_EINVAL
+
+
+def _erfc_coefficients():
+    import re
+
+    text = open(os.path.join(ROOT, "paper_1802_07844_amd", "csrc", "erfc_poly.h")).read()
+    out = {}
+    for name in ("ERFC_C64", "ERFC_C32"):
+        body = text.split(name + "[] = {", 1)[1].split("};", 1)[0]
+        out[name] = [float(v.rstrip("f")) for v in re.findall(r"[-+0-9.eE]+f?", body)]
+    return out
+
+
+@pytest.mark.parametrize("name,dtype,bound", [("ERFC_C64", np.float64, 2e-15), ("ERFC_C32", np.float32, 6e-7)])
+def test_erfc_polynomial_of_the_real_space_sum(name, dtype, bound):
+    """The real-space kernels form erfc(x) = exp(-x^2) q(1 / (1 + x/2)) with
+    the coefficients of erfc_poly.h: absolute error against a 30-digit erfc
+    over every argument a cutoff can produce (0 <= x <= 6.5), evaluated in
+    the kernels' precision with the same Horner order."""
+    import mpmath as mp
+
+    mp.mp.dps = 30
+    c = [dtype(v) for v in _erfc_coefficients()[name]]
+    assert len(c) == (15 if dtype == np.float64 else 8)
+    g = np.random.default_rng(5)
+    x = np.concatenate([np.linspace(0.0, 6.5, 1500), g.random(1500) * 6.5, [0.0, 1e-12, 6.5]]).astype(dtype)
+    t = dtype(1) / (dtype(1) + dtype(0.5) * x)
+    q = np.full_like(x, c[-1])
+    for v in c[-2::-1]:
+        q = q * t + v
+    got = (np.exp(-x * x) * q).astype(np.float64)
+    ref = np.array([float(mp.erfc(mp.mpf(float(v)))) for v in x])
+    err = np.max(np.abs(got - ref))
+    print(f"{name}: max |erfc error| = {err:.2e}")
+    assert err <= bound
