@@ -6,8 +6,8 @@
 //    counted (Q -> 2Q), budget tol/4 relative to sqrt(Q)/L (tol/40 for the
 //    rotlet, whose correction terms are of the same order as the kernel and
 //    are not covered by the free-space estimate -- paper Sec. 6);
-//  * P (Gaussian support, even) from exp(-pi P c^2 / 2) <= tol/40 (tol/4 when
-//    tol >= 1e-6 except for the stresslet), c = 0.95,
+//  * P (Gaussian support, even) from exp(-pi P c^2 / 2) <= tol/40 (tol/4 for
+//    the FP32 stokeslet and rotlet when tol >= 1e-6), c = 0.95,
 //    eta = P xi^2 h^2 / (c^2 pi) (Algorithm 1 step 4), M raised until eta < 0.95;
 //  * the box is extended by max(P, m / (sqrt2 xi h)) nodes with
 //    m = sqrt(2 ln(1/tol)): the Gaussian support of Algorithm 1 step 3 plus a
@@ -294,8 +294,12 @@ inline int make_plan(const PlanInput& in, Plan* out)
     if (P <= 0) {
         P = 4;
         // the stresslet's near-field Fourier part (third derivatives)
-        // amplifies the support truncation about tenfold
-        const double pbudget = (tol < 1e-6 || in.family == 1) ? tol / 40 : tol / 4;
+        // amplifies the support truncation about tenfold; so does the FP64
+        // path's quadrature of the correction gradient with grad W, whose
+        // aliasing error on the grid is larger than W's by about the ratio of
+        // the grid's wave number to xi (measured at P = 10: about 45 times,
+        // 3.1e-5 where the Gaussian's own truncation is 6.9e-7)
+        const double pbudget = (tol < 1e-6 || in.family == 1 || p.prec == 1) ? tol / 40 : tol / 4;
         while (std::exp(-pi * P * C_SHAPE * C_SHAPE / 2) > pbudget) P += 2;
     }
     if (P < 2 || P > 30 || (P & 1)) return -1;

@@ -212,3 +212,30 @@ def test_cell_reach(reach):
         assert err <= tol
     finally:
         c.close()
+
+
+@pytest.mark.parametrize("fam", ["stokeslet", "stresslet", "rotlet"])
+@pytest.mark.parametrize("tol", [1e-5, 1e-7])
+def test_fp64_at_loose_tolerances(fam, tol):
+    """FP64 at tolerances looser than 1e-10 (auto precision picks FP64 at
+    tol >= 1e-5 where the FP32 rounding estimate is too large): the error
+    against the oracle stays within tol.  The FP64 path forms the correction
+    gradient by quadrature with grad W, whose grid aliasing error is larger
+    than W's, so its Gaussian support comes from the tighter budget."""
+    for nb in (30, 300):
+        n = 20_000
+        y, s = workloads.make(fam, n, 63)
+        rc = _rc(nb, n)
+        xi = ehs.xi_for_cutoff(fam, rc, tol / 2)
+        c = ehs.Context(0)
+        try:
+            c.set_option(ehs.OPT_PRECISION, 1)
+            yd, sd = torch.from_numpy(y).to(DEV), torch.from_numpy(s).to(DEV)
+            u, rep = c.evaluate(fam, yd, sd, yd, xi, rc, tol, report=True)
+            torch.cuda.synchronize()
+            idx = np.sort(workloads.rng(64).choice(n, 1024, replace=False))
+            err = oracle.rel_rms(oracle.halfspace(fam, y, s, y[idx]), u.cpu().numpy()[idx])
+            print(f"{fam} FP64 tol {tol:g} ~{nb} neighbours: P={rep.P} Pg={rep.Pg} Mt={rep.Mt} rel-RMS {err:.2e}")
+            assert err <= tol
+        finally:
+            c.close()
