@@ -68,18 +68,19 @@ def stage_model(rep, N, T, esz):
     Mt = rep.Mt
     e = esz
     fam = rep.family
+    free = bool(rep.free_space)                  # free space: sources only, kernel grids only
     nca = 6 if fam == 1 else 3                   # kernel-grid components
     ncb = {0: 4, 1: 7, 2: 2}[fam]                # separate correction grids
-    nin = nca + (1 if rep.dgrid else ncb)        # spread / forward grids
-    nout = 4 if e == 8 else 6                    # inverse grids
+    nin = nca + (0 if free else 1 if rep.dgrid else ncb)  # spread / forward grids
+    nout = 3 if free else 4 if e == 8 else 6     # inverse grids
     ns = 6 if fam == 1 else 3                    # strength values per source
     keep = (2 * Mt - rep.x3_first) / (2 * Mt)    # inverse side: rows the quadrature reads
     czf = rep.x3_corr_end / (2 * Mt)             # correction grids: rows below the images' support top
-    nin_eff = nca + (nin - nca) * czf
+    nin_eff = nin * czf if free else nca + (nin - nca) * czf
     V_R = Mt * Mt * 2 * Mt
     V_A = (Mt + 1) * 2 * Mt * Mt
     V_Z = (Mt + 1) * 4 * Mt * Mt
-    kinds = 1 if fam == 2 else 2
+    kinds = 1 if (fam == 2 or free) else 2
     oct_bytes = (Mt + 1) ** 2 * (2 * Mt + 1) * (8 if e == 8 else 4) * kinds
     n2, n4 = 2 * Mt, 4 * Mt
     Ps3, Pg3 = rep.Ps ** 3, rep.Pg ** 3
@@ -88,7 +89,7 @@ def stage_model(rep, N, T, esz):
                       rep.pairs_direct * PAIR_FLOPS["direct"][fam] + rep.pairs_image * PAIR_FLOPS["image"][fam])
     # sources carry the kernel grid, images the kernel grid and the corrections
     m["spread"] = (nin * V_R * e + N * (3 + ns) * 8,
-                   N * Ps3 * (1 + 2 * nca) + N * Ps3 * (1 + 2 * nin))
+                   N * Ps3 * (1 + 2 * nca) + (0 if free else N * Ps3 * (1 + 2 * nin)))
     # x1: real lines of padded length 2 Mt (two per complex transform)
     m["fwd_x"] = (nin_eff * (V_R * e + V_A * 2 * e), nin_eff * Mt * n2 * 0.5 * _fft(n2))
     # x2: A (x1 half spectrum, x2 nodes) to the x2 spectrum over the padded length
@@ -137,11 +138,12 @@ def roofline(rep, stage_ms, N, T, esz, ms_step):
     # the output grids written once, the octants and the point data (the
     # transform intermediates not materialised), against all its flops
     Mt, e = rep.Mt, esz
-    nin = (6 if rep.family == 1 else 3) + (1 if rep.dgrid else {0: 4, 1: 7, 2: 2}[rep.family])
-    nout = 4 if e == 8 else 6
+    free = bool(rep.free_space)
+    nin = (6 if rep.family == 1 else 3) + (0 if free else 1 if rep.dgrid else {0: 4, 1: 7, 2: 2}[rep.family])
+    nout = 3 if free else 4 if e == 8 else 6
     keep = (2 * Mt - rep.x3_first) / (2 * Mt)
     V_R = Mt * Mt * 2 * Mt
-    oct_bytes = (Mt + 1) ** 2 * (2 * Mt + 1) * (8 if e == 8 else 4) * (1 if rep.family == 2 else 2)
+    oct_bytes = (Mt + 1) ** 2 * (2 * Mt + 1) * (8 if e == 8 else 4) * (1 if (rep.family == 2 or free) else 2)
     mb = (nin + nout * keep) * V_R * e + oct_bytes + model["realspace"][0]
     mf = sum(f for _, f in model.values())
     m_floor = max(mb / (HBM_PEAK_GBS * 1e9), mf / (vpk * 1e12)) * 1e3
@@ -197,18 +199,28 @@ WORKLOADS = {
     "c3_rotlet_fp32": ("rotlet", "uniform", 1_000_000, 2, 1e-5, ("nb", 2000)),
     "c2_fp64": ("stokeslet", "uniform", 100_000, 1, 1e-10, ("nb", 30)),
     "c2_fp32": ("stokeslet", "uniform", 100_000, 2, 1e-5, ("nb", 300)),
+    # half space and free space side by side (the same points and parameters)
+    "c2_stresslet_fp64": ("stresslet", "uniform", 100_000, 1, 1e-10, ("nb", 300)),
+    "c2_rotlet_fp64": ("rotlet", "uniform", 100_000, 1, 1e-10, ("nb", 300)),
+    "free_stokeslet_fp64": ("stokeslet", "uniform", 100_000, 1, 1e-10, ("nb", 30), True),
+    "free_stresslet_fp64": ("stresslet", "uniform", 100_000, 1, 1e-10, ("nb", 300), True),
+    "free_rotlet_fp64": ("rotlet", "uniform", 100_000, 1, 1e-10, ("nb", 300), True),
 }
 SEEDS = {"c2": 1, "c3": 2, "c4": 3}
 
 
+def _free(name):
+    return len(WORKLOADS[name]) > 6 and WORKLOADS[name][6]
+
+
 def describe(name):
-    fam, layout, n, prec, tol, rcr = WORKLOADS[name]
+    fam, layout, n, prec, tol, rcr = WORKLOADS[name][:6]
     where = ("x1, x2 uniform in [0,1), x3 ~ Exp(mean 0.05) clipped to (0,1]" if layout == "clustered"
              else "uniform in [0,1)^2 x (0,1]")
     strengths = {"stokeslet": "forces N(0,1)", "stresslet": "strengths N(0,1)^3, orientations uniform on S^2",
                  "rotlet": "torques N(0,1)^3"}[fam]
     cut = f"r_c = {rcr}" if not isinstance(rcr, tuple) else f"r_c for ~{rcr[1]} neighbours"
-    return (f"half-space {fam}, N={n} sources=targets {where}, {strengths}, "
+    return (f"{'free-space' if _free(name) else 'half-space'} {fam}, N={n} sources=targets {where}, {strengths}, "
             f"{'FP64' if prec == 1 else 'FP32'} tol {tol:g}, {cut}")
 
 
@@ -220,7 +232,7 @@ class Runner:
         self.data = {}
 
     def inputs(self, name):
-        fam, layout, n, prec, tol, rcr = WORKLOADS[name]
+        fam, layout, n, prec, tol, rcr = WORKLOADS[name][:6]
         key = (fam, layout, n)
         if key not in self.data:
             seed = self.wl.SEED_BASE + SEEDS[name[:2]]
@@ -231,7 +243,7 @@ class Runner:
         return self.data[key]
 
     def params(self, name):
-        fam, layout, n, prec, tol, rcr = WORKLOADS[name]
+        fam, layout, n, prec, tol, rcr = WORKLOADS[name][:6]
         rc = _rc(rcr[1], n) if isinstance(rcr, tuple) else rcr
         # the real-space estimate takes a quarter of the budget
         xi = self.ehs.xi_for_cutoff(fam, rc, tol / 2)
@@ -245,20 +257,23 @@ class Runner:
         y, s, yd, sd, seed = self.inputs(name)
         self.ctx.set_option(self.ehs.OPT_PRECISION, prec)
         out = torch.empty((n, 3), dtype=torch.float64, device="cuda:0")
+        fs = _free(name)
         for _ in range(warmup):
-            self.ctx.evaluate(fam, yd, sd, yd, xi, rc, tol, out=out, report=True)
+            self.ctx.evaluate(fam, yd, sd, yd, xi, rc, tol, out=out, report=True, free_space=fs)
         torch.cuda.synchronize()
         st = np.zeros(self.ehs.NSTAGES)
         t0 = time.perf_counter()
         for _ in range(steps):
-            rep = self.ctx.evaluate(fam, yd, sd, yd, xi, rc, tol, out=out, report=True)[1]
+            rep = self.ctx.evaluate(fam, yd, sd, yd, xi, rc, tol, out=out, report=True, free_space=fs)[1]
             st += np.array(list(rep.ms_stage))
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         ms = dt / steps * 1e3
         stage_ms = dict(zip(self.ehs.STAGES, (st / steps).tolist()))
         esz = 8 if rep.precision == 1 else 4
+        nin = (6 if rep.family == 1 else 3) + (0 if fs else 1 if rep.dgrid else {0: 4, 1: 7, 2: 2}[rep.family])
         res = {"value": n * steps / dt, "unit": "points/s", "ms_per_step": ms, "steps": steps, "warmup": warmup,
+               "transforms": {"forward": nin, "inverse": 3 if fs else (4 if esz == 8 else 6)},
                "dtype": "f64" if esz == 8 else "f32", "tol": tol, "xi": xi, "r_c": rc,
                "plan": {"M": rep.M, "P": rep.P, "Mt": rep.Mt, "eta": rep.eta, "Ps": rep.Ps, "Pg": rep.Pg,
                         "zslab": rep.zslab, "dgrid": rep.dgrid, "x3_first": rep.x3_first,
@@ -280,7 +295,7 @@ class Runner:
         fam, n, prec, tol, rc, xi = self.params(name)
         y, s, yd, sd, seed = self.inputs(name)
         idx = self.np.sort(self.wl.rng(seed + 1000).choice(n, size=min(n, nsample), replace=False))
-        ref = oracle.halfspace(fam, y, s, y[idx])
+        ref = (oracle.freespace if _free(name) else oracle.halfspace)(fam, y, s, y[idx])
         err = oracle.rel_rms(ref, u[idx])
         vrms = self.np.sqrt(self.np.mean(self.np.sum(ref * ref, axis=1)))
         worst = float(self.np.max(self.np.linalg.norm(u[idx] - ref, axis=1)) / vrms)
@@ -424,8 +439,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--leg-steps", type=int, default=10, help="timed steps of each leg beside the headline")
     ap.add_argument("--workload", default="c4_fp64", choices=sorted(WORKLOADS), help="headline workload")
-    ap.add_argument("--legs", default="fp32,c3,c2,tuned",
-                    help="comma list of extra legs (fp32, c3, c2, tuned) or 'none'")
+    ap.add_argument("--legs", default="fp32,c3,c2,free,tuned",
+                    help="comma list of extra legs (fp32, c3, c2, free, tuned) or 'none'")
     ap.add_argument("--oracle-sample", type=int, default=512, help="targets checked against the oracle per leg")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target duration of the oracle timing sample")
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the oracle timing and every oracle check")
@@ -490,6 +505,17 @@ def main():
         extra["c3"] = {k: leg(f"c3_{k}") for k in ("stresslet_fp64", "rotlet_fp64", "stresslet_fp32", "rotlet_fp32")}
     if "c2" in legs:
         extra["c2"] = {"fp64": leg("c2_fp64"), "fp32": leg("c2_fp32")}
+    if "free" in legs:
+        # the free-space sum of the same kernels on the same points and
+        # parameters (no images, no corrections): the step-time ratio
+        # half space / free space and the transformed grids of each
+        half = {"stokeslet": extra["c2"]["fp64"] if "c2" in extra else leg("c2_fp64"),
+                "stresslet": leg("c2_stresslet_fp64"), "rotlet": leg("c2_rotlet_fp64")}
+        fr = {k: leg(f"free_{k}_fp64") for k in ("stokeslet", "stresslet", "rotlet")}
+        extra["free"] = {k: {"free": fr[k], "half": half[k] if k != "stokeslet" else None,
+                             "ratio_half_over_free": half[k]["ms_per_step"] / fr[k]["ms_per_step"],
+                             "transforms_half": half[k]["transforms"], "transforms_free": fr[k]["transforms"]}
+                         for k in fr}
     if "tuned" in legs:
         # the N = 1e5 FP64 problem at the runtime-optimal (xi, r_c) of the
         # tuning procedure (both truncation errors held, xi perturbed)

@@ -128,6 +128,7 @@ typedef struct ehs_report {
                                (from their height histogram, x1 and x2 taken as uniform) */
     double pairs_direct;    /* in-range (target, source) pairs of the real-space sum, direct and */
     double pairs_image;     /* image terms (counted when EHS_OPT_TIMING is on, else 0) */
+    int32_t free_space;     /* 1: an ewald_freespace_* evaluation */
 } ehs_report;
 
 /* Smallest arena a context accepts (the table and bounding-box regions). */
@@ -209,6 +210,29 @@ int ewald_halfspace_noalloc(ehs_ctx* ctx, int family, const double* sources, con
 /* Device memory a context holds: its workspace (or arena) bytes, the bytes
    and number of grid sizes of its octant cache.  Any output may be NULL. */
 int ehs_context_memory(const ehs_ctx* ctx, double* workspace_bytes, double* cache_bytes, int* cache_entries);
+
+/*
+ * Free-space sums (Sec. 2, eq. (v_sum_free_space)): u(x_t) = sum_m K(x_t - y_m) s_m,
+ * the kernels and strength layouts of the half-space entry points above, with
+ * no wall: no images, no harmonic corrections, and no restriction on x3 (any
+ * finite coordinates).  The same spectral Ewald method on the sources alone:
+ * the kernel grid only (3, 6 and 3 forward transforms, 3 inverse), the
+ * direct real-space terms only.  The grid keeps the half-space layout, with
+ * the points in the lower half of its x3 range and the upper half empty
+ * (skipped by the forward passes); the x3 transforms are therefore twice the
+ * length a cubic box would need.  Arguments, ownership, synchronisation and
+ * errors as for the half-space entry points (EHS_EDOMAIN only for non-finite
+ * input).
+ */
+int ewald_freespace_stokeslet(ehs_ctx* ctx, const double* sources, const double* f, int64_t N,
+                              const double* targets, int64_t T, double xi, double r_c, double tol,
+                              double* u_out, void* stream, ehs_report* rep);
+int ewald_freespace_stresslet(ehs_ctx* ctx, const double* sources, const double* gq, int64_t N,
+                              const double* targets, int64_t T, double xi, double r_c, double tol,
+                              double* u_out, void* stream, ehs_report* rep);
+int ewald_freespace_rotlet(ehs_ctx* ctx, const double* sources, const double* v, int64_t N, const double* targets,
+                           int64_t T, double xi, double r_c, double tol, double* u_out, void* stream,
+                           ehs_report* rep);
 
 /* Message for an EHS_* code (static storage). */
 const char* ehs_strerror(int code);

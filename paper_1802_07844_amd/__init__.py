@@ -50,6 +50,7 @@ class Report(ctypes.Structure):
         ("x3_first", ctypes.c_int32), ("x3_corr_end", ctypes.c_int32),
         ("cell_reach", ctypes.c_int32), ("occupancy", ctypes.c_double),
         ("pairs_direct", ctypes.c_double), ("pairs_image", ctypes.c_double),
+        ("free_space", ctypes.c_int32),
     ]
 
     def as_dict(self) -> dict:
@@ -85,7 +86,8 @@ def lib():
             L.ehs_destroy.restype = None
             L.ehs_set_option.argtypes = [vp, ctypes.c_int, dp]
             L.ehs_set_option.restype = ctypes.c_int
-            for name in ("ewald_halfspace_stokeslet", "ewald_halfspace_stresslet", "ewald_halfspace_rotlet"):
+            for name in ("ewald_halfspace_stokeslet", "ewald_halfspace_stresslet", "ewald_halfspace_rotlet",
+                         "ewald_freespace_stokeslet", "ewald_freespace_stresslet", "ewald_freespace_rotlet"):
                 fn = getattr(L, name)
                 fn.argtypes = [vp, vp, vp, i64, vp, i64, dp, dp, dp, vp, vp, ctypes.POINTER(Report)]
                 fn.restype = ctypes.c_int
@@ -263,7 +265,10 @@ class Context:
                                             ctypes.byref(rep)))
         return (out, rep) if report else out
 
-    def evaluate(self, family, sources, strengths, targets, xi, r_c, tol, out=None, stream=None, report=False):
+    def evaluate(self, family, sources, strengths, targets, xi, r_c, tol, out=None, stream=None, report=False,
+                 free_space=False):
+        """The half-space sum (or, with free_space, the free-space sum of the
+        same kernel: ewald_freespace_*) at the targets."""
         import torch
 
         fam = FAMILIES[family] if isinstance(family, str) else int(family)
@@ -278,8 +283,12 @@ class Context:
             out = torch.empty((T, 3), dtype=torch.float64, device=targets.device)
         uo = _dev_ptr(out, "out", 3)
         rep = Report()
-        fn = {STOKESLET: lib().ewald_halfspace_stokeslet, STRESSLET: lib().ewald_halfspace_stresslet,
-              ROTLET: lib().ewald_halfspace_rotlet}[fam]
+        if free_space:
+            fn = {STOKESLET: lib().ewald_freespace_stokeslet, STRESSLET: lib().ewald_freespace_stresslet,
+                  ROTLET: lib().ewald_freespace_rotlet}[fam]
+        else:
+            fn = {STOKESLET: lib().ewald_halfspace_stokeslet, STRESSLET: lib().ewald_halfspace_stresslet,
+                  ROTLET: lib().ewald_halfspace_rotlet}[fam]
         rc = fn(self._h, ys, ss, int(sources.shape[0]), xs, int(T), float(xi), float(r_c), float(tol), uo,
                 _stream_handle(stream), ctypes.byref(rep))
         check(rc)

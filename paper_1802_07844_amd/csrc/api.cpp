@@ -296,6 +296,7 @@ int take_injected_failure(int* counter)
 int ensure_octants(ehs_ctx* c, const Plan& p, hipStream_t st, bool* ran, Octants** out)
 {
     const bool needB = p.family != EHS_ROTLET;
+    const bool needH = !(p.free && p.family != EHS_ROTLET);  // free space: the kernel's octant only
     const bool need32 = p.prec == 2;
     const long long n = octant_elems(p.Mt);
     *ran = false;
@@ -308,6 +309,7 @@ int ensure_octants(ehs_ctx* c, const Plan& p, hipStream_t st, bool* ran, Octants
     auto publish = [&]() { c->cache[p.Mt] = cur; };
     for (int kind = 0; kind < 2; ++kind) {
         if (kind == 1 && !needB) continue;
+        if (kind == 0 && !needH) continue;
         double*& d64 = kind == 0 ? cur.H64 : cur.B64;
         float*& d32 = kind == 0 ? cur.H32 : cur.B32;
         if (!d64) {
@@ -361,7 +363,7 @@ int check_extents(const Plan& p, const Layout& L, size_t esz)
     const size_t a = (Mt + 1) * 2 * Mt * Mt * c;
     const size_t zs = (size_t)p.zg * 2 * Mt * 2 * Mt * c;  // one component of the slab buffer
     const size_t nin = (size_t)p.ncin;
-    const size_t nout = (size_t)ncout_for(p.prec);
+    const size_t nout = (size_t)ncout_for(p.prec, plan_cm(p));
     const size_t xreg = L.Y - L.X, yreg = L.ZS - L.Y, zsreg = L.Zo - L.ZS, zoreg = L.rec - L.Zo;
     auto fits = [](size_t need, size_t have) { return need <= have; };
     // in place (resident), the fused x3 pass keeps at most 16 outputs per lane
@@ -395,7 +397,7 @@ int check_extents(const Plan& p, const Layout& L, size_t esz)
     // the fused x3 pass holds lines of length 4Mt/Q for max(ncin, outputs) components,
     // each transformed by one wavefront
     int nq = 4 * p.Mt / p.Qz;
-    ok = ok && (4 * p.Mt) % p.Qz == 0 && z_lds_bytes(p.family, p.dgrid, p.Mt, p.Qz, esz) <= 160 * 1024 &&
+    ok = ok && (4 * p.Mt) % p.Qz == 0 && z_lds_bytes(p.family, plan_cm(p), p.Mt, p.Qz, esz) <= 160 * 1024 &&
          nq <= lds_fft_cap(nq, 64);
     // x / y passes: B lines of Mt in LDS and in the 16-element register budget
     ok = ok && p.Bx * p.Mt <= lds_fft_cap(p.Mt, 256) && p.By * p.Mt <= lds_fft_cap(p.Mt, 256) &&
@@ -403,7 +405,7 @@ int check_extents(const Plan& p, const Layout& L, size_t esz)
          pass_lds(p.Mt, p.By, esz) <= 160 * 1024 && pass_lds(p.Mt, p.Bx, esz) <= 160 * 1024;
     // magic-number division is exact for numerator * divisor < 2^32
     ok = ok && (long long)(p.Mt + 1) * std::max(p.Bx, 2 * p.By) * std::max(p.Mt, 2 * p.By) < (1LL << 31) &&
-         (long long)std::max(p.ncin, ncout_for(p.prec)) * 2 * p.Mt * 2 * p.Mt < (1LL << 31);
+         (long long)std::max(p.ncin, ncout_for(p.prec, plan_cm(p))) * 2 * p.Mt * 2 * p.Mt < (1LL << 31);
     // gather weights table (3P <= 96) and spread support within the grid
     // supports: the kernels read them from the grid arguments, which must agree
     // with the plan (spreading g.P = Ps >= P, quadrature gg.P = Pg >= P)
@@ -417,7 +419,7 @@ Layout layout(const Plan& p, size_t esz)
     Layout L;
     const long long Mt = p.Mt;
     const int ncin = p.ncin;
-    const int nl = std::max(ncin, ncout_for(p.prec));
+    const int nl = std::max(ncin, ncout_for(p.prec, plan_cm(p)));
     size_t czs = (size_t)p.zg * 2 * Mt * 2 * Mt * 2 * esz;  // one slab-buffer component (complex)
     size_t cy = (size_t)(Mt + 1) * 2 * Mt * Mt * 2 * esz;   // one A / D component
     size_t x_bytes = (size_t)nl * (size_t)(Mt * Mt * 2 * Mt) * esz;
@@ -429,7 +431,7 @@ Layout layout(const Plan& p, size_t esz)
     L.X = off; off += al(x_bytes);
     L.Y = off; off += al((size_t)nl * cy);  // A (ncin components), then D (outputs) in place
     L.ZS = off; off += al((size_t)nl * czs);
-    L.Zo = off; off += p.resident ? 0 : al((size_t)ncout_for(p.prec) * czs);
+    L.Zo = off; off += p.resident ? 0 : al((size_t)ncout_for(p.prec, plan_cm(p)) * czs);
     long long N = p.N, T = p.T;
     // records carry 3 g.P weights: g.P is the spreading support the kernels use
     L.rec = off; off += al((size_t)2 * N * record_stride(p.family, p.g.P, esz) * esz);
@@ -551,6 +553,7 @@ int run(ehs_ctx* c, Plan& p, const Octants& oct, const double* y, const double* 
     ra.chunk_first = ch_first;
     ra.nchunks = ch_n;
     ra.tgt_perm = tperm;
+    ra.images = p.free ? 0 : 1;
     ra.pairs = nullptr;
     c->pairs_dev = nullptr;
     if (c->opt_timing && c->ev_ok) {
@@ -566,14 +569,16 @@ int run(ehs_ctx* c, Plan& p, const Octants& oct, const double* y, const double* 
     cplx<T>* Yc = reinterpret_cast<cplx<T>*>(base + Lo.Y);
     T* rec = reinterpret_cast<T*>(base + Lo.rec);
     uint32_t *pk, *pperm;
-    HIPCHK(launch_point_keys(y, N, p.g, kp, vp, st));
-    HIPCHK(radix_sort(kp, vp, kp2, vp2, 2 * N, bits_for(p.ntiles), sortsc, st, &pk, &pperm));
-    HIPCHK(launch_cell_ranges(pk, 2 * N, toff, nullptr, p.ntiles, st));
-    HIPCHK(launch_records<T>(p.family, p.dgrid, y, s, pperm, N, p.g, rec, st));
+    const int cm = plan_cm(p);
+    const long long npts = p.free ? N : 2 * N;  // sources and (half space) their images
+    HIPCHK(launch_point_keys(y, N, npts, p.g, kp, vp, st));
+    HIPCHK(radix_sort(kp, vp, kp2, vp2, npts, bits_for(p.ntiles), sortsc, st, &pk, &pperm));
+    HIPCHK(launch_cell_ranges(pk, npts, toff, nullptr, p.ntiles, st));
+    HIPCHK(launch_records<T>(p.family, cm, y, s, pperm, N, p.g, rec, st));
     const long long Mt = p.Mt;
     const long long csR = Mt * Mt * 2 * Mt;          // real grid component
     const long long csA = (Mt + 1) * 2 * Mt * Mt;    // A / D component (complex)
-    HIPCHK(launch_spread<T>(p.family, p.dgrid, p.g, rec, toff, X, csR, st));
+    HIPCHK(launch_spread<T>(p.family, cm, p.g, rec, toff, X, csR, st));
     rec_ev(EHS_ST_FWDX);
 
     // -- forward transforms
@@ -597,7 +602,8 @@ int run(ehs_ctx* c, Plan& p, const Octants& oct, const double* y, const double* 
     pa.cs_out = csA;
     // components from ncA on (the correction grids, spread at the images)
     // vanish at x3 nodes >= lzc: the forward passes skip them there
-    pa.czero = p.family == STRESSLET ? 6 : 3;  // the kernel-grid components come first
+    // (free space: every component vanishes there)
+    pa.czero = p.free ? 0 : p.family == STRESSLET ? 6 : 3;  // the kernel-grid components come first
     pa.lzc = p.lzc;
     HIPCHK(launch_fwd_x<T>(X, Yc, pa, p.ncin, st));
     rec_ev(EHS_ST_FWDY);
@@ -663,12 +669,12 @@ int run(ehs_ctx* c, Plan& p, const Octants& oct, const double* y, const double* 
         pa.cs_out = csS;
         HIPCHK(launch_fwd_y<T>(Yc, ZS, pa, p.ncin, st));
         if (slab_ev) HIPCHK(hipEventRecord(c->sev[c->nsev++], st));
-        HIPCHK(launch_z<T>(p.family, p.dgrid, ZS, ZO, za, p.resident, st));
+        HIPCHK(launch_z<T>(p.family, cm, ZS, ZO, za, p.resident, st));
         if (slab_ev) HIPCHK(hipEventRecord(c->sev[c->nsev++], st));
         pa.cs_in = csS;
         pa.cs_out = csA;
         pa.l3lo = p.l3lo;
-        HIPCHK(launch_inv_y<T>(ZO, Yc, pa, Out<T>::n, st));
+        HIPCHK(launch_inv_y<T>(ZO, Yc, pa, ncout_for(p.prec, cm), st));
         pa.l3lo = 0;
         if (slab_ev) HIPCHK(hipEventRecord(c->sev[c->nsev++], st));
     }
@@ -680,7 +686,7 @@ int run(ehs_ctx* c, Plan& p, const Octants& oct, const double* y, const double* 
     pa.cs_in = csA;
     pa.cs_out = csR;
     pa.l3lo = p.l3lo;
-    HIPCHK(launch_inv_x<T>(Yc, X, pa, Out<T>::n, st));
+    HIPCHK(launch_inv_x<T>(Yc, X, pa, ncout_for(p.prec, cm), st));
     rec_ev(EHS_ST_GATHER);
 
     // -- quadrature at the targets and FP64 combination with the real part:
@@ -689,7 +695,7 @@ int run(ehs_ctx* c, Plan& p, const Octants& oct, const double* y, const double* 
     //    one wavefront per tile for the partial sums, then a fixed-order sum
     //    per target)
     if (!p.gtiles) {
-        HIPCHK(launch_gather<T>(p.gg, X, csR, xs, tperm, TT, upart, u, st));
+        HIPCHK(launch_gather<T>(p.gg, cm, X, csR, xs, tperm, TT, upart, u, st));
     } else {
         uint32_t* gk = reinterpret_cast<uint32_t*>(base + Lo.gkeys);
         uint32_t *gv = gk + TT, *gk2 = gv + TT, *gv2 = gk2 + TT;
@@ -711,7 +717,7 @@ int run(ehs_ctx* c, Plan& p, const Octants& oct, const double* y, const double* 
 }  // namespace
 
 int ehs::plan_request(ehs_ctx* c, int family, const double* y, const double* s, int64_t N, const double* x,
-                      int64_t T, double xi, double rc, double tol, int prec, hipStream_t st, Plan* p)
+                      int64_t T, double xi, double rc, double tol, int prec, hipStream_t st, Plan* p, bool free_space)
 {
     if (family < 0 || family > 2) return EHS_EINVAL;
     if (prec < 0 || prec > 2) return EHS_EINVAL;
@@ -739,8 +745,9 @@ int ehs::plan_request(ehs_ctx* c, int family, const double* y, const double* s, 
     HIPCHK(hipStreamSynchronize(st));
     const double* b = c->host_bbox;
     if (b[8] > 0) return EHS_EDOMAIN;
-    if (!(b[6] > 0)) return EHS_EDOMAIN;
-    if (T > 0 && !(b[7] >= 0)) return EHS_EDOMAIN;
+    // the half space: sources above the wall, targets not below it
+    if (!free_space && !(b[6] > 0)) return EHS_EDOMAIN;
+    if (!free_space && T > 0 && !(b[7] >= 0)) return EHS_EDOMAIN;
     PlanInput in;
     in.family = family;
     in.N = N;
@@ -762,9 +769,11 @@ int ehs::plan_request(ehs_ctx* c, int family, const double* y, const double* s, 
     in.dgrid = c->dgrid;
     in.tlo3 = T > 0 ? b[7] : 0.0;
     in.slo3 = b[6];
-    in.zhist = reinterpret_cast<const uint32_t*>(b + 16);
+    // (the height histogram counts from the wall: none in free space)
+    in.zhist = free_space ? nullptr : reinterpret_cast<const uint32_t*>(b + 16);
     in.zbin = zbin;
     in.force_nr = c->force_nr;
+    in.free = free_space;
     return make_plan(in, p);
 }
 
@@ -820,6 +829,7 @@ void ehs::fill_report(const Plan& p, ehs_report* r)
     r->x3_corr_end = p.lzc;
     r->cell_reach = p.cg.nr;
     r->occupancy = p.occ;
+    r->free_space = p.free ? 1 : 0;
 }
 
 namespace {
@@ -876,16 +886,18 @@ void start_timing(ehs_ctx* c, hipStream_t st)
 }
 
 int evaluate(ehs_ctx* c, int family, const double* y, const double* s, int64_t N, const double* x, int64_t T,
-             double xi, double rc, double tol, double* u, void* stream, ehs_report* rep)
+             double xi, double rc, double tol, double* u, void* stream, ehs_report* rep, bool free_space = false)
 {
     if (!c) return EHS_EINVAL;
-    if (c->fixed) return evaluate_fixed(c, c->fixed, family, y, s, N, x, T, xi, rc, tol, u, stream, rep, EHS_ENOMEM);
+    if (c->fixed)
+        return evaluate_fixed(c, c->fixed, family, y, s, N, x, T, xi, rc, tol, u, stream, rep, EHS_ENOMEM,
+                              free_space);
     if (T > 0 && !u) return EHS_EINVAL;
     if (hipSetDevice(c->device) != hipSuccess) return EHS_EHIP;
     hipStream_t st = static_cast<hipStream_t>(stream);
     start_timing(c, st);
     Plan p;
-    int r = plan_request(c, family, y, s, N, x, T, xi, rc, tol, c->opt_prec, st, &p);
+    int r = plan_request(c, family, y, s, N, x, T, xi, rc, tol, c->opt_prec, st, &p, free_space);
     if (r) return r;
     if (T == 0) {
         if (rep) fill_report(p, rep);
@@ -921,9 +933,10 @@ size_t fixed_oct_layout(int Mt, unsigned mask, size_t off[4])
 
 unsigned octant_mask(const Plan& p)
 {
-    unsigned m = 1u;  // H64
-    if (p.family != EHS_ROTLET) m |= 2u;
-    if (p.prec == 2) m |= (p.family != EHS_ROTLET) ? 12u : 4u;
+    const bool needH = !(p.free && p.family != EHS_ROTLET), needB = p.family != EHS_ROTLET;
+    unsigned m = 0u;
+    if (needH) m |= p.prec == 2 ? 5u : 1u;  // H64 (and H32)
+    if (needB) m |= p.prec == 2 ? 10u : 2u;  // B64 (and B32)
     return m;
 }
 
@@ -954,7 +967,7 @@ struct Borrow {
 
 int ehs::evaluate_fixed(ehs_ctx* c, Fixed* fx, int family, const double* y, const double* s, int64_t N,
                         const double* x, int64_t T, double xi, double rc, double tol, double* u, void* stream,
-                        ehs_report* rep, int too_big)
+                        ehs_report* rep, int too_big, bool free_space)
 {
     if (!c || !fx || !fx->base) return EHS_EINVAL;
     if (T > 0 && !u) return EHS_EINVAL;
@@ -973,7 +986,7 @@ int ehs::evaluate_fixed(ehs_ctx* c, Fixed* fx, int family, const double* y, cons
     Plan p;
     // (the bounding-box readback synchronises the stream: every earlier call
     // on it has finished reading the tables and octants rewritten below)
-    int r = plan_request(c, family, y, s, N, x, T, xi, rc, tol, c->opt_prec, st, &p);
+    int r = plan_request(c, family, y, s, N, x, T, xi, rc, tol, c->opt_prec, st, &p, free_space);
     if (r) return r;
     if (T == 0) {
         if (rep) fill_report(p, rep);
@@ -1006,7 +1019,7 @@ int ehs::evaluate_fixed(ehs_ctx* c, Fixed* fx, int family, const double* y, cons
     if (c->opt_timing && c->ev_ok) hipEventRecord(c->ev[EHS_ST_PRECOMP], st);
     char* ob = fx->base + head;
     Octants o;
-    o.H64 = reinterpret_cast<double*>(ob + off[0]);
+    o.H64 = (mask & 1u) ? reinterpret_cast<double*>(ob + off[0]) : nullptr;
     o.B64 = (mask & 2u) ? reinterpret_cast<double*>(ob + off[1]) : nullptr;
     o.H32 = (mask & 4u) ? reinterpret_cast<float*>(ob + off[2]) : nullptr;
     o.B32 = (mask & 8u) ? reinterpret_cast<float*>(ob + off[3]) : nullptr;
@@ -1178,6 +1191,26 @@ int ewald_halfspace_rotlet(ehs_ctx* c, const double* sources, const double* v, i
                            int64_t T, double xi, double r_c, double tol, double* u_out, void* stream, ehs_report* rep)
 {
     return evaluate(c, EHS_ROTLET, sources, v, N, targets, T, xi, r_c, tol, u_out, stream, rep);
+}
+
+int ewald_freespace_stokeslet(ehs_ctx* c, const double* sources, const double* f, int64_t N, const double* targets,
+                              int64_t T, double xi, double r_c, double tol, double* u_out, void* stream,
+                              ehs_report* rep)
+{
+    return evaluate(c, EHS_STOKESLET, sources, f, N, targets, T, xi, r_c, tol, u_out, stream, rep, true);
+}
+
+int ewald_freespace_stresslet(ehs_ctx* c, const double* sources, const double* gq, int64_t N, const double* targets,
+                              int64_t T, double xi, double r_c, double tol, double* u_out, void* stream,
+                              ehs_report* rep)
+{
+    return evaluate(c, EHS_STRESSLET, sources, gq, N, targets, T, xi, r_c, tol, u_out, stream, rep, true);
+}
+
+int ewald_freespace_rotlet(ehs_ctx* c, const double* sources, const double* v, int64_t N, const double* targets,
+                           int64_t T, double xi, double r_c, double tol, double* u_out, void* stream, ehs_report* rep)
+{
+    return evaluate(c, EHS_ROTLET, sources, v, N, targets, T, xi, r_c, tol, u_out, stream, rep, true);
 }
 
 const char* ehs_strerror(int code)

@@ -79,13 +79,21 @@ struct Traits<ROTLET> {
 // the gradient of the Gaussian; FP32 keeps Y1 and grad phi = IFFT(i k phi^)
 // (3), because the FP32 quantisation of the long-range potential would be
 // amplified by that gradient
+// (free space keeps Y1 only: no images and no corrections).
+//
+// Correction modes of the grid pipeline (the CM template argument):
+//   CM_GRIDS    the ncB correction grids, spread separately;
+//   CM_DENSITY  the correction sources spread as one density D (FP64, below);
+//   CM_FREE     the free-space sum of Sec. 2: sources only, no images, no
+//               corrections, the kernel grid's three outputs.
+enum CorrectionMode { CM_GRIDS = 0, CM_DENSITY = 1, CM_FREE = 2 };
 constexpr int NCOUT_MAX = 6;
-template <typename T>
+template <typename T, int CM>
 struct Out {
-    static constexpr int n = sizeof(T) == 8 ? 4 : 6;
-    static constexpr bool grad_quad = sizeof(T) == 8;  // gradient by quadrature
+    static constexpr int n = CM == CM_FREE ? 3 : sizeof(T) == 8 ? 4 : 6;
+    static constexpr bool grad_quad = CM != CM_FREE && sizeof(T) == 8;  // gradient by quadrature
 };
-inline int ncout_for(int prec) { return prec == 1 ? 4 : 6; }
+inline int ncout_for(int prec, int cm) { return cm == CM_FREE ? 3 : prec == 1 ? 4 : 6; }
 
 // input grids: the kernel grid C1 (ncA components) and the correction
 // sources.  FP64 spreads the correction sources directly as the one scalar
@@ -99,14 +107,14 @@ inline int ncout_for(int prec) { return prec == 1 ? 4 : 6; }
 // only in FP64: the FP32 quantisation would be amplified by the derivative
 // weights as in the quadrature); otherwise the ncB correction grids are
 // spread separately.
-template <int K, bool DG>
+template <int K, int CM>
 struct InGrids {
-    static constexpr int n = Traits<K>::ncA + (DG ? 1 : Traits<K>::ncB);
+    static constexpr int n = Traits<K>::ncA + (CM == CM_DENSITY ? 1 : CM == CM_FREE ? 0 : Traits<K>::ncB);
 };
-inline int ncin_for(int family, bool dgrid)
+inline int ncin_for(int family, int cm)
 {
     int ncA = family == 1 ? 6 : 3, ncB = family == 0 ? 4 : family == 1 ? 7 : 2;
-    return ncA + (dgrid ? 1 : ncB);
+    return ncA + (cm == CM_DENSITY ? 1 : cm == CM_FREE ? 0 : ncB);
 }
 
 // ---------------------------------------------------------------------------

@@ -93,7 +93,7 @@ void ctx_release(ehs_ctx* c);
 // Argument checks, bounding box / validation reduction (one readback on st)
 // and parameter selection with precision `prec` (0 auto, 1 FP64, 2 FP32).
 int plan_request(ehs_ctx* c, int family, const double* y, const double* s, int64_t N, const double* x, int64_t T,
-                 double xi, double rc, double tol, int prec, hipStream_t st, Plan* p);
+                 double xi, double rc, double tol, int prec, hipStream_t st, Plan* p, bool free_space = false);
 
 // Workspace bytes of one evaluation under plan p (after the extent audit).
 int plan_workspace(const Plan& p, size_t* bytes);
@@ -117,7 +117,7 @@ void fill_report(const Plan& p, ehs_report* r);
 // not fit the region even with the smallest slab group.
 int evaluate_fixed(ehs_ctx* c, Fixed* fx, int family, const double* y, const double* s, int64_t N, const double* x,
                    int64_t T, double xi, double rc, double tol, double* u, void* stream, ehs_report* rep,
-                   int too_big);
+                   int too_big, bool free_space = false);
 
 // Resolve the device address of the static scratch of the allocation-free
 // entry point for `device` (which must be current); called once per device

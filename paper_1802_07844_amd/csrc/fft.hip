@@ -278,23 +278,24 @@ __global__ void __launch_bounds__(XPASS_NT, 4) k_inv_x(const cplx<T>* __restrict
 //   gB = (1 + k^2/4xi^2) e^{-(1-eta) k^2/4xi^2} B^R(k) / Npad
 //   gH =                e^{-(1-eta) k^2/4xi^2} H^R(k) / Npad
 // ---------------------------------------------------------------------------
-template <typename U, bool GQ, bool DG>
+template <typename U, bool GQ, int CM>
 __device__ __forceinline__ void mult_stokeslet(const cplx<U>* X, cplx<U>* Y, U kx, U ky, U kz, U gB, U gH)
 {
     U k2 = kx * kx + ky * ky + kz * kz;
     // t1 = -(k^2 I - k k) C1 * gB   (the A^S(k) of the stokeslet)
     cplx<U> kc = cmk<U>(kx * X[0].x + ky * X[1].x + kz * X[2].x, kx * X[0].y + ky * X[1].y + kz * X[2].y);
     U kv[3] = {kx, ky, kz};
-    // phi = gH (-2 C2 - 2 i k.C3), or gH D when the density D was spread (DG)
+#pragma unroll
+    for (int q = 0; q < 3; ++q) Y[q] = cmk<U>(-gB * (k2 * X[q].x - kv[q] * kc.x), -gB * (k2 * X[q].y - kv[q] * kc.y));
+    if (CM == CM_FREE) return;
+    // phi = gH (-2 C2 - 2 i k.C3), or gH D when the density D was spread
     cplx<U> phi;
-    if (DG) {
+    if (CM == CM_DENSITY) {
         phi = cmk<U>(gH * X[3].x, gH * X[3].y);
     } else {
         cplx<U> kc3 = cmk<U>(kx * X[4].x + ky * X[5].x + kz * X[6].x, kx * X[4].y + ky * X[5].y + kz * X[6].y);
         phi = cmk<U>(gH * (-2 * X[3].x + 2 * kc3.y), gH * (-2 * X[3].y - 2 * kc3.x));
     }
-#pragma unroll
-    for (int q = 0; q < 3; ++q) Y[q] = cmk<U>(-gB * (k2 * X[q].x - kv[q] * kc.x), -gB * (k2 * X[q].y - kv[q] * kc.y));
     Y[2] = cadd(Y[2], phi);
     if (GQ) {
         Y[3] = phi;
@@ -304,7 +305,7 @@ __device__ __forceinline__ void mult_stokeslet(const cplx<U>* X, cplx<U>* Y, U k
     }
 }
 
-template <typename U, bool GQ, bool DG>
+template <typename U, bool GQ, int CM>
 __device__ __forceinline__ void mult_stresslet(const cplx<U>* X, cplx<U>* Y, U kx, U ky, U kz, U gB, U gH)
 {
     U k2 = kx * kx + ky * ky + kz * kz;
@@ -316,9 +317,17 @@ __device__ __forceinline__ void mult_stresslet(const cplx<U>* X, cplx<U>* Y, U k
     cplx<U> tr = cmk<U>(X[0].x + X[3].x + X[5].x, X[0].y + X[3].y + X[5].y);
     cplx<U> kck = cmk<U>(kx * ck[0].x + ky * ck[1].x + kz * ck[2].x, kx * ck[0].y + ky * ck[1].y + kz * ck[2].y);
     U kv[3] = {kx, ky, kz};
-    // C3 symmetric (indices 7..12), phi = gH (4 i kz C2 + 4 k.C3.k), or gH D (DG)
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        // t1 = -i gB [k^2 (2 C k + k trC) - 2 k (k.C k)]
+        cplx<U> s = cmk<U>(k2 * (2 * ck[q].x + kv[q] * tr.x) - 2 * kv[q] * kck.x,
+                           k2 * (2 * ck[q].y + kv[q] * tr.y) - 2 * kv[q] * kck.y);
+        Y[q] = cmk<U>(gB * s.y, -gB * s.x);
+    }
+    if (CM == CM_FREE) return;
+    // C3 symmetric (indices 7..12), phi = gH (4 i kz C2 + 4 k.C3.k), or gH D
     cplx<U> phi;
-    if (DG) {
+    if (CM == CM_DENSITY) {
         phi = cmk<U>(gH * X[6].x, gH * X[6].y);
     } else {
         const cplx<U>* B3 = X + 7;
@@ -328,13 +337,6 @@ __device__ __forceinline__ void mult_stresslet(const cplx<U>* X, cplx<U>* Y, U k
                   2 * (kx * ky * B3[1].y + kx * kz * B3[2].y + ky * kz * B3[4].y);
         phi = cmk<U>(gH * (-4 * kz * X[6].y + 4 * kbk_x), gH * (4 * kz * X[6].x + 4 * kbk_y));
     }
-#pragma unroll
-    for (int q = 0; q < 3; ++q) {
-        // t1 = -i gB [k^2 (2 C k + k trC) - 2 k (k.C k)]
-        cplx<U> s = cmk<U>(k2 * (2 * ck[q].x + kv[q] * tr.x) - 2 * kv[q] * kck.x,
-                           k2 * (2 * ck[q].y + kv[q] * tr.y) - 2 * kv[q] * kck.y);
-        Y[q] = cmk<U>(gB * s.y, -gB * s.x);
-    }
     Y[2] = cadd(Y[2], phi);
     if (GQ) {
         Y[3] = phi;
@@ -344,7 +346,7 @@ __device__ __forceinline__ void mult_stresslet(const cplx<U>* X, cplx<U>* Y, U k
     }
 }
 
-template <typename U, bool GQ, bool DG>
+template <typename U, bool GQ, int CM>
 __device__ __forceinline__ void mult_rotlet(const cplx<U>* X, cplx<U>* Y, U kx, U ky, U kz, U gH)
 {
     // t1 = -2 i gH (C1 x k)
@@ -352,17 +354,18 @@ __device__ __forceinline__ void mult_rotlet(const cplx<U>* X, cplx<U>* Y, U kx, 
     cx[0] = cmk<U>(X[1].x * kz - X[2].x * ky, X[1].y * kz - X[2].y * ky);
     cx[1] = cmk<U>(X[2].x * kx - X[0].x * kz, X[2].y * kx - X[0].y * kz);
     cx[2] = cmk<U>(X[0].x * ky - X[1].x * kx, X[0].y * ky - X[1].y * kx);
-    // phi = gH 2 i (kx w1 + ky w2), or gH D (DG)
+    U kv[3] = {kx, ky, kz};
+#pragma unroll
+    for (int q = 0; q < 3; ++q) Y[q] = cmk<U>(2 * gH * cx[q].y, -2 * gH * cx[q].x);
+    if (CM == CM_FREE) return;
+    // phi = gH 2 i (kx w1 + ky w2), or gH D
     cplx<U> phi;
-    if (DG) {
+    if (CM == CM_DENSITY) {
         phi = cmk<U>(gH * X[3].x, gH * X[3].y);
     } else {
         cplx<U> kw = cmk<U>(kx * X[3].x + ky * X[4].x, kx * X[3].y + ky * X[4].y);
         phi = cmk<U>(-2 * gH * kw.y, 2 * gH * kw.x);
     }
-    U kv[3] = {kx, ky, kz};
-#pragma unroll
-    for (int q = 0; q < 3; ++q) Y[q] = cmk<U>(2 * gH * cx[q].y, -2 * gH * cx[q].x);
     Y[2] = cadd(Y[2], phi);
     if (GQ) {
         Y[3] = phi;
@@ -372,15 +375,15 @@ __device__ __forceinline__ void mult_rotlet(const cplx<U>* X, cplx<U>* Y, U kx, 
     }
 }
 
-template <typename U, int K, bool GQ, bool DG>
+template <typename U, int K, bool GQ, int CM>
 __device__ __forceinline__ void apply_mult(const cplx<U>* X, cplx<U>* Y, U kx, U ky, U kz, U gB, U gH)
 {
     if (K == STOKESLET)
-        mult_stokeslet<U, GQ, DG>(X, Y, kx, ky, kz, gB, gH);
+        mult_stokeslet<U, GQ, CM>(X, Y, kx, ky, kz, gB, gH);
     else if (K == STRESSLET)
-        mult_stresslet<U, GQ, DG>(X, Y, kx, ky, kz, gB, gH);
+        mult_stresslet<U, GQ, CM>(X, Y, kx, ky, kz, gB, gH);
     else
-        mult_rotlet<U, GQ, DG>(X, Y, kx, ky, kz, gH);
+        mult_rotlet<U, GQ, CM>(X, Y, kx, ky, kz, gH);
 }
 
 // ---------------------------------------------------------------------------
@@ -405,9 +408,9 @@ __device__ __forceinline__ void apply_mult(const cplx<U>* X, cplx<U>* Y, U kx, U
 // grid: (2Mt, nk1)
 // ---------------------------------------------------------------------------
 // wavefronts per block: one per line, at most 8
-template <typename T, int K, bool DG>
+template <typename T, int K, int CM>
 struct ZWaves {
-    static constexpr int lines = InGrids<K, DG>::n > Out<T>::n ? InGrids<K, DG>::n : Out<T>::n;
+    static constexpr int lines = InGrids<K, CM>::n > Out<T, CM>::n ? InGrids<K, CM>::n : Out<T, CM>::n;
     static constexpr int n = lines < 8 ? lines : 8;
 };
 
@@ -418,33 +421,35 @@ struct ZWaves {
 // fit; their LDS allows it); FP64 blocks of more wavefronts are held to one
 // block per CU by the LDS anyway, and the FP32 stresslet's 13 input lines do
 // not fit 128 registers.
-template <typename T, int K, bool DG, int EPL>
+template <typename T, int K, int CM, int EPL>
 struct ZOcc {
-    static constexpr int n = (sizeof(T) == 4 && ZWaves<T, K, DG>::n > 4 && K != STRESSLET && EPL <= 4) ? 4 : 2;
+    static constexpr int n = (sizeof(T) == 4 && ZWaves<T, K, CM>::n > 4 && K != STRESSLET && EPL <= 4) ? 4 : 2;
 };
 
 // inputs held in registers (HOLD): 2 EPL elements per lane cover the whole
 // input line when 128 EPL >= 2Mt; only where they fit a register budget of
 // 32 per lane (more spills in the FP64 variants)
-template <typename T, int K, bool DG, int EPL>
+template <typename T, int K, int CM, int EPL>
 constexpr bool z_hold_fits()
 {
-    constexpr int zw = ZWaves<T, K, DG>::n;
-    constexpr int cpw = (InGrids<K, DG>::n + zw - 1) / zw;
-    return EPL > 0 && EPL <= 8 && cpw * 2 * EPL * (int)sizeof(cplx<T>) <= 128 && ZOcc<T, K, DG, EPL>::n == 2;
+    constexpr int zw = ZWaves<T, K, CM>::n;
+    constexpr int cpw = (InGrids<K, CM>::n + zw - 1) / zw;
+    return EPL > 0 && EPL <= 8 && cpw * 2 * EPL * (int)sizeof(cplx<T>) <= 128 && ZOcc<T, K, CM, EPL>::n == 2;
 }
 
-template <typename T, int K, int EPL, bool HOLD, bool DG>
-__global__ void __launch_bounds__((64 * ZWaves<T, K, DG>::n), (ZOcc<T, K, DG, EPL>::n))
+template <typename T, int K, int EPL, bool HOLD, int CM>
+__global__ void __launch_bounds__((64 * ZWaves<T, K, CM>::n), (ZOcc<T, K, CM, EPL>::n))
     k_z_scale(const cplx<T>* zb, cplx<T>* zout, ZArgs a)
 {
-    constexpr int ZW = ZWaves<T, K, DG>::n;
+    constexpr int ZW = ZWaves<T, K, CM>::n;
     constexpr int Z_NT = 64 * ZW;
-    constexpr int ncin = InGrids<K, DG>::n;
-    constexpr int NCOUT = Out<T>::n;
-    constexpr bool GQ = Out<T>::grad_quad;
+    constexpr int ncin = InGrids<K, CM>::n;
+    constexpr int NCOUT = Out<T, CM>::n;
+    constexpr bool GQ = Out<T, CM>::grad_quad;
+    // the harmonic kernel's octant: the corrections, and the rotlet's kernel
+    constexpr bool NEED_H = CM != CM_FREE || K == ROTLET;
     constexpr int CPW = (ncin + ZW - 1) / ZW;  // input components per wavefront
-    static_assert(!HOLD || z_hold_fits<T, K, DG, EPL>(), "held inputs exceed the register budget");
+    static_assert(!HOLD || z_hold_fits<T, K, CM, EPL>(), "held inputs exceed the register budget");
     constexpr int EPI = HOLD ? 2 * EPL : 1;  // held input elements per lane and component
     constexpr int NX = HOLD ? CPW * EPI : 1;
     constexpr int NY = EPL > 0 ? EPL : 1;
@@ -512,7 +517,7 @@ __global__ void __launch_bounds__((64 * ZWaves<T, K, DG>::n), (ZOcc<T, K, DG, EP
             const int k3s = (k3 < nz) ? k3 : k3 - n4;
             const int ak3 = k3s < 0 ? -k3s : k3s;
             pez[j] = a.ez[ak3];
-            poh[j] = octH[oct_line + ak3];
+            poh[j] = NEED_H ? octH[oct_line + ak3] : (OT)0;
             pob[j] = K != ROTLET ? octB[oct_line + ak3] : (OT)0;
         };
         if (PREF) {
@@ -620,13 +625,13 @@ __global__ void __launch_bounds__((64 * ZWaves<T, K, DG>::n), (ZOcc<T, K, DG, EP
                         // FP32 path near k = 0: FP64 multipliers
                         const long long oi = oct_line + ak3;
                         const double ep = exy * a.ez[ak3];
-                        gH = ep * a.cH * a.octH64[oi];
+                        gH = NEED_H ? ep * a.cH * a.octH64[oi] : 0.0;
                         gB = K != ROTLET ? (1.0 + a.c_has * k2v) * (ep * a.cB * a.octB64[oi]) : 0.0;
                     }
                     cplx<double> Xd[ncin], Yd[NCOUT_MAX];
 #pragma unroll
                     for (int c = 0; c < ncin; ++c) Xd[c] = cmk<double>((double)X[c].x, (double)X[c].y);
-                    apply_mult<double, K, GQ, DG>(Xd, Yd, kxd, kyd, kzd, gB, gH);
+                    apply_mult<double, K, GQ, CM>(Xd, Yd, kxd, kyd, kzd, gB, gH);
 #pragma unroll
                     for (int c = 0; c < NCOUT; ++c) Y[c] = cmk<T>((T)Yd[c].x, (T)Yd[c].y);
                 } else {
@@ -638,7 +643,7 @@ __global__ void __launch_bounds__((64 * ZWaves<T, K, DG>::n), (ZOcc<T, K, DG, EP
                     cplx<float> Xf[ncin], Yf[NCOUT_MAX];
 #pragma unroll
                     for (int c = 0; c < ncin; ++c) Xf[c] = cmk<float>((float)X[c].x, (float)X[c].y);
-                    apply_mult<float, K, GQ, DG>(Xf, Yf, kx, ky, kz, gB, gH);
+                    apply_mult<float, K, GQ, CM>(Xf, Yf, kx, ky, kz, gB, gH);
 #pragma unroll
                     for (int c = 0; c < NCOUT; ++c) Y[c] = cmk<T>((T)Yf[c].x, (T)Yf[c].y);
                 }
@@ -830,10 +835,10 @@ hipError_t launch_inv_x(const cplx<T>* in, T* out, const PassArgs& a, int ncomp,
     return hipGetLastError();
 }
 
-size_t z_lds_bytes(int family, bool dgrid, int Mt, int Q, size_t esz)
+size_t z_lds_bytes(int family, int cm, int Mt, int Q, size_t esz)
 {
-    int ncin = ncin_for(family, dgrid);
-    int nout = esz == 8 ? Out<double>::n : Out<float>::n;
+    int ncin = ncin_for(family, cm);
+    int nout = ncout_for(esz == 8 ? 1 : 2, cm);
     int nl = ncin > nout ? ncin : nout;
     int nq = 4 * Mt / Q;
     return ((size_t)nl * (nq + 1) + nq) * 2 * esz;  // lines and the nq - 1 stage twiddles
@@ -845,51 +850,59 @@ bool z_resident_ok(int family, int Mt)
     return 2 * Mt <= 3 * 512;
 }
 
-template <typename T, int K, bool DG, int EPL>
+template <typename T, int K, int CM, int EPL>
 static void launch_z_e(cplx<T>* zb, cplx<T>* zout, const ZArgs& a, hipStream_t st)
 {
     dim3 grid(2 * a.Mt, a.nk1);
-    size_t lds = z_lds_bytes(K, DG, a.Mt, a.Q, sizeof(T));
-    const dim3 blk(64 * ZWaves<T, K, DG>::n);
-    if constexpr (z_hold_fits<T, K, DG, EPL>()) {
+    size_t lds = z_lds_bytes(K, CM, a.Mt, a.Q, sizeof(T));
+    const dim3 blk(64 * ZWaves<T, K, CM>::n);
+    if constexpr (z_hold_fits<T, K, CM, EPL>()) {
         if (128 * EPL >= 2 * a.Mt) {
-            hipLaunchKernelGGL((k_z_scale<T, K, EPL, true, DG>), grid, blk, lds, st, zb, zout, a);
+            hipLaunchKernelGGL((k_z_scale<T, K, EPL, true, CM>), grid, blk, lds, st, zb, zout, a);
             return;
         }
     }
-    hipLaunchKernelGGL((k_z_scale<T, K, EPL, false, DG>), grid, blk, lds, st, zb, zout, a);
+    hipLaunchKernelGGL((k_z_scale<T, K, EPL, false, CM>), grid, blk, lds, st, zb, zout, a);
 }
 
-template <typename T, int K, bool DG>
+template <typename T, int K, int CM>
 static void launch_z_t(cplx<T>* zb, cplx<T>* zout, const ZArgs& a, bool res, hipStream_t st)
 {
     const int no = 2 * a.Mt - a.l3lo;  // outputs per line
     if (!res)
-        launch_z_e<T, K, DG, 0>(zb, zout, a, st);
+        launch_z_e<T, K, CM, 0>(zb, zout, a, st);
     else if (no <= 256)
-        launch_z_e<T, K, DG, 4>(zb, zout, a, st);
+        launch_z_e<T, K, CM, 4>(zb, zout, a, st);
     else if (no <= 512)
-        launch_z_e<T, K, DG, 8>(zb, zout, a, st);
+        launch_z_e<T, K, CM, 8>(zb, zout, a, st);
     else
-        launch_z_e<T, K, DG, 16>(zb, zout, a, st);  // no <= 1024 (the planner's audit)
+        launch_z_e<T, K, CM, 16>(zb, zout, a, st);  // no <= 1024 (the planner's audit)
+}
+
+template <typename T, int CM>
+static void launch_z_f(int family, cplx<T>* zb, cplx<T>* zout, const ZArgs& a, bool res, hipStream_t st)
+{
+    switch (family) {
+        case STOKESLET: launch_z_t<T, STOKESLET, CM>(zb, zout, a, res, st); break;
+        case STRESSLET: launch_z_t<T, STRESSLET, CM>(zb, zout, a, res, st); break;
+        default: launch_z_t<T, ROTLET, CM>(zb, zout, a, res, st); break;
+    }
 }
 
 template <typename T>
-hipError_t launch_z(int family, bool dgrid, cplx<T>* zb, cplx<T>* zout, const ZArgs& a, bool res, hipStream_t st)
+hipError_t launch_z(int family, int cm, cplx<T>* zb, cplx<T>* zout, const ZArgs& a, bool res, hipStream_t st)
 {
     // the correction density is only used in FP64
-    if (dgrid && sizeof(T) == 8) {
-        switch (family) {
-            case STOKESLET: launch_z_t<T, STOKESLET, true>(zb, zout, a, res, st); break;
-            case STRESSLET: launch_z_t<T, STRESSLET, true>(zb, zout, a, res, st); break;
-            default: launch_z_t<T, ROTLET, true>(zb, zout, a, res, st); break;
-        }
+    if (cm == CM_FREE) {
+        launch_z_f<T, CM_FREE>(family, zb, zout, a, res, st);
     } else {
-        switch (family) {
-            case STOKESLET: launch_z_t<T, STOKESLET, false>(zb, zout, a, res, st); break;
-            case STRESSLET: launch_z_t<T, STRESSLET, false>(zb, zout, a, res, st); break;
-            default: launch_z_t<T, ROTLET, false>(zb, zout, a, res, st); break;
+        if constexpr (sizeof(T) == 8) {
+            if (cm == CM_DENSITY) {
+                launch_z_f<T, CM_DENSITY>(family, zb, zout, a, res, st);
+                return hipGetLastError();
+            }
         }
+        launch_z_f<T, CM_GRIDS>(family, zb, zout, a, res, st);
     }
     return hipGetLastError();
 }
@@ -931,8 +944,8 @@ template hipError_t launch_inv_y<double>(const cplx<double>*, cplx<double>*, con
 template hipError_t launch_inv_y<float>(const cplx<float>*, cplx<float>*, const PassArgs&, int, hipStream_t);
 template hipError_t launch_inv_x<double>(const cplx<double>*, double*, const PassArgs&, int, hipStream_t);
 template hipError_t launch_inv_x<float>(const cplx<float>*, float*, const PassArgs&, int, hipStream_t);
-template hipError_t launch_z<double>(int, bool, cplx<double>*, cplx<double>*, const ZArgs&, bool, hipStream_t);
-template hipError_t launch_z<float>(int, bool, cplx<float>*, cplx<float>*, const ZArgs&, bool, hipStream_t);
+template hipError_t launch_z<double>(int, int, cplx<double>*, cplx<double>*, const ZArgs&, bool, hipStream_t);
+template hipError_t launch_z<float>(int, int, cplx<float>*, cplx<float>*, const ZArgs&, bool, hipStream_t);
 template hipError_t launch_line_fft<double>(const cplx<double>*, cplx<double>*, int, int, const FftPlanDev&, bool,
                                             hipStream_t);
 template hipError_t launch_line_fft<float>(const cplx<float>*, cplx<float>*, int, int, const FftPlanDev&, bool,

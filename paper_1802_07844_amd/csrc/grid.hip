@@ -41,11 +41,12 @@ __device__ __forceinline__ int support_base(double z, double o, double h, int P,
     return b;
 }
 
-__global__ void k_point_keys(const double* __restrict__ y, long long N, GridArgs g, uint32_t* __restrict__ keys,
-                             uint32_t* __restrict__ idx)
+// npts = 2N (sources, then their wall images) or N (free space: sources only)
+__global__ void k_point_keys(const double* __restrict__ y, long long N, long long npts, GridArgs g,
+                             uint32_t* __restrict__ keys, uint32_t* __restrict__ idx)
 {
     long long p = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-    if (p >= 2 * N) return;
+    if (p >= npts) return;
     long long m = p < N ? p : p - N;
     double z[3] = {y[3 * m], y[3 * m + 1], p < N ? y[3 * m + 2] : -y[3 * m + 2]};
     int dims[3] = {g.Mt, g.Mt, 2 * g.Mt};
@@ -55,10 +56,12 @@ __global__ void k_point_keys(const double* __restrict__ y, long long N, GridArgs
     idx[p] = (uint32_t)p;
 }
 
-hipError_t launch_point_keys(const double* y, long long N, GridArgs g, uint32_t* keys, uint32_t* idx, hipStream_t st)
+hipError_t launch_point_keys(const double* y, long long N, long long npts, GridArgs g, uint32_t* keys, uint32_t* idx,
+                             hipStream_t st)
 {
-    if (N <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_point_keys, dim3((unsigned)((2 * N + 255) / 256)), dim3(256), 0, st, y, N, g, keys, idx);
+    if (npts <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_point_keys, dim3((unsigned)((npts + 255) / 256)), dim3(256), 0, st, y, N, npts, g, keys,
+                       idx);
     return hipGetLastError();
 }
 
@@ -118,13 +121,13 @@ __device__ __forceinline__ void point_strengths(const double* s, const double* y
     }
 }
 
-template <typename T, int K, bool DG>
+template <typename T, int K, int CM>
 __global__ void k_records(const double* __restrict__ y, const double* __restrict__ s, const uint32_t* __restrict__ perm,
                           long long N, GridArgs g, T* __restrict__ rec)
 {
     constexpr int ncA = RecLayout<K>::ncA, ncB = RecLayout<K>::ncB;
     long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-    if (q >= 2 * N) return;
+    if (q >= (CM == CM_FREE ? N : 2 * N)) return;  // free space: no images
     const int P = g.P;
     const long long stride = 16 / sizeof(T) + 3 * P + 3 + ncA + ncB;
     long long p = perm[q];
@@ -153,7 +156,7 @@ __global__ void k_records(const double* __restrict__ y, const double* __restrict
     double cA[ncA], cB[ncB];
     for (int c = 0; c < ncB; ++c) cB[c] = 0.0;
     point_strengths<K>(s, y, p, N, cA, cB);
-    if (DG) {
+    if (CM == CM_DENSITY) {
         // coefficients of D (see InGrids): stokeslet (c0; cx, cy, cz) of
         // c0 W + c . grad W; stresslet (c3; Sxx, Sxy, Sxz, Syy, Syz, Szz) of
         // c3 d3 W + S : grad grad W; rotlet (cx, cy) of c . grad W
@@ -166,27 +169,29 @@ __global__ void k_records(const double* __restrict__ y, const double* __restrict
     for (int c = 0; c < ncB; ++c) cs[ncA + c] = (T)cB[c];
 }
 
-template <typename T, bool DG>
+template <typename T, int CM>
 static void launch_records_t(int family, const double* y, const double* s, const uint32_t* perm, long long N,
                              GridArgs g, T* rec, hipStream_t st)
 {
-    dim3 grid((unsigned)((2 * N + 255) / 256));
+    dim3 grid((unsigned)(((CM == CM_FREE ? N : 2 * N) + 255) / 256));
     switch (family) {
-        case STOKESLET: hipLaunchKernelGGL((k_records<T, STOKESLET, DG>), grid, dim3(256), 0, st, y, s, perm, N, g, rec); break;
-        case STRESSLET: hipLaunchKernelGGL((k_records<T, STRESSLET, DG>), grid, dim3(256), 0, st, y, s, perm, N, g, rec); break;
-        default: hipLaunchKernelGGL((k_records<T, ROTLET, DG>), grid, dim3(256), 0, st, y, s, perm, N, g, rec); break;
+        case STOKESLET: hipLaunchKernelGGL((k_records<T, STOKESLET, CM>), grid, dim3(256), 0, st, y, s, perm, N, g, rec); break;
+        case STRESSLET: hipLaunchKernelGGL((k_records<T, STRESSLET, CM>), grid, dim3(256), 0, st, y, s, perm, N, g, rec); break;
+        default: hipLaunchKernelGGL((k_records<T, ROTLET, CM>), grid, dim3(256), 0, st, y, s, perm, N, g, rec); break;
     }
 }
 
 template <typename T>
-hipError_t launch_records(int family, bool dgrid, const double* y, const double* s, const uint32_t* perm, long long N,
+hipError_t launch_records(int family, int cm, const double* y, const double* s, const uint32_t* perm, long long N,
                           GridArgs g, T* rec, hipStream_t st)
 {
     if (N <= 0) return hipSuccess;
-    if (dgrid)
-        launch_records_t<T, true>(family, y, s, perm, N, g, rec, st);
+    if (cm == CM_FREE)
+        launch_records_t<T, CM_FREE>(family, y, s, perm, N, g, rec, st);
+    else if (cm == CM_DENSITY)
+        launch_records_t<T, CM_DENSITY>(family, y, s, perm, N, g, rec, st);
     else
-        launch_records_t<T, false>(family, y, s, perm, N, g, rec, st);
+        launch_records_t<T, CM_GRIDS>(family, y, s, perm, N, g, rec, st);
     return hipGetLastError();
 }
 
@@ -201,12 +206,12 @@ hipError_t launch_records(int family, bool dgrid, const double* y, const double*
 // one-wavefront blocks per CU (32 records allowed two per SIMD; 8 allow eight)
 constexpr int SP_CHUNK = 8;
 
-template <typename T, int K, int TZ, bool DG>
+template <typename T, int K, int TZ, int CM>
 __global__ void __launch_bounds__(64) k_spread(GridArgs g, const T* __restrict__ rec,
                                                const uint32_t* __restrict__ toff, T* __restrict__ grids, long long cs)
 {
     constexpr int ncA = RecLayout<K>::ncA, ncB = RecLayout<K>::ncB;
-    constexpr int nout = InGrids<K, DG>::n;
+    constexpr int nout = InGrids<K, CM>::n;
     extern __shared__ unsigned char smem_raw[];
     T* sh = reinterpret_cast<T*>(smem_raw);
     const int P = g.P;
@@ -256,7 +261,7 @@ __global__ void __launch_bounds__(64) k_spread(GridArgs g, const T* __restrict__
                         const bool img = hdr[3] != 0;
                         // D: per-column factors of w(z), w'(z), w''(z)
                         T fa = 0, fb = 0, fc = 0;
-                        if (DG && img) {
+                        if (CM == CM_DENSITY && img) {
                             const T ex = off[0] + (T)dx * hh, ey = off[1] + (T)dy * hh;
                             const T dwx = -2 * a2 * ex * wx, dwy = -2 * a2 * ey * wy;
                             const T* c = cv + ncA;
@@ -282,15 +287,15 @@ __global__ void __launch_bounds__(64) k_spread(GridArgs g, const T* __restrict__
 #pragma unroll
                                 for (int c = 0; c < ncA; ++c) acc[z][c] += wv * cv[c];
                                 if (img) {
-                                    if (DG) {
+                                    if constexpr (CM == CM_DENSITY) {
                                         const T ez = off[2] + (T)dz * hh;
                                         T dsum = fa * wz;
                                         if (K != ROTLET) dsum += fb * (-2 * a2 * ez * wz);
                                         if (K == STRESSLET) dsum += fc * ((4 * a2 * a2 * ez * ez - 2 * a2) * wz);
                                         acc[z][ncA] += dsum;
-                                    } else {
+                                    } else if constexpr (CM == CM_GRIDS) {
 #pragma unroll
-                                        for (int c = 0; c < (DG ? 1 : ncB); ++c) acc[z][ncA + c] += wv * cv[ncA + c];
+                                        for (int c = 0; c < ncB; ++c) acc[z][ncA + c] += wv * cv[ncA + c];
                                     }
                                 }
                             }
@@ -315,27 +320,29 @@ __global__ void __launch_bounds__(64) k_spread(GridArgs g, const T* __restrict__
     }
 }
 
-template <typename T, bool DG>
+template <typename T, int CM>
 static void launch_spread_t(int family, GridArgs g, const T* rec, const uint32_t* toff, T* grids, long long cs,
                             hipStream_t st)
 {
     dim3 grid(g.nt[0], g.nt[1], g.nt[2]);
     size_t lds = (size_t)SP_CHUNK * record_stride(family, g.P, sizeof(T)) * sizeof(T);
     switch (family) {
-        case STOKESLET: hipLaunchKernelGGL((k_spread<T, STOKESLET, 8, DG>), grid, dim3(64), lds, st, g, rec, toff, grids, cs); break;
-        case STRESSLET: hipLaunchKernelGGL((k_spread<T, STRESSLET, 4, DG>), grid, dim3(64), lds, st, g, rec, toff, grids, cs); break;
-        default: hipLaunchKernelGGL((k_spread<T, ROTLET, 8, DG>), grid, dim3(64), lds, st, g, rec, toff, grids, cs); break;
+        case STOKESLET: hipLaunchKernelGGL((k_spread<T, STOKESLET, 8, CM>), grid, dim3(64), lds, st, g, rec, toff, grids, cs); break;
+        case STRESSLET: hipLaunchKernelGGL((k_spread<T, STRESSLET, 4, CM>), grid, dim3(64), lds, st, g, rec, toff, grids, cs); break;
+        default: hipLaunchKernelGGL((k_spread<T, ROTLET, 8, CM>), grid, dim3(64), lds, st, g, rec, toff, grids, cs); break;
     }
 }
 
 template <typename T>
-hipError_t launch_spread(int family, bool dgrid, GridArgs g, const T* rec, const uint32_t* toff, T* grids, long long cs,
+hipError_t launch_spread(int family, int cm, GridArgs g, const T* rec, const uint32_t* toff, T* grids, long long cs,
                          hipStream_t st)
 {
-    if (dgrid)
-        launch_spread_t<T, true>(family, g, rec, toff, grids, cs, st);
+    if (cm == CM_FREE)
+        launch_spread_t<T, CM_FREE>(family, g, rec, toff, grids, cs, st);
+    else if (cm == CM_DENSITY)
+        launch_spread_t<T, CM_DENSITY>(family, g, rec, toff, grids, cs, st);
     else
-        launch_spread_t<T, false>(family, g, rec, toff, grids, cs, st);
+        launch_spread_t<T, CM_GRIDS>(family, g, rec, toff, grids, cs, st);
     return hipGetLastError();
 }
 
@@ -399,7 +406,7 @@ template <typename T>
 __global__ void __launch_bounds__(64) k_target_records(const double* __restrict__ xs, const uint32_t* __restrict__ perm,
                                                        long long TT, GridArgs gg, T* __restrict__ rec)
 {
-    constexpr bool GQ = Out<T>::grad_quad;
+    constexpr bool GQ = Out<T, CM_GRIDS>::grad_quad;
     const long long r = blockIdx.x;
     const int lane = threadIdx.x;
     const int Pg = gg.P;
@@ -444,8 +451,8 @@ __global__ void __launch_bounds__(64) k_gather_tiles(GridArgs gg, const T* __res
                                                      const T* __restrict__ rec, const uint32_t* __restrict__ gtoff,
                                                      int tz0, T* __restrict__ part)
 {
-    constexpr bool GQ = Out<T>::grad_quad;
-    constexpr int NOUT = Out<T>::n;
+    constexpr bool GQ = Out<T, CM_GRIDS>::grad_quad;
+    constexpr int NOUT = Out<T, CM_GRIDS>::n;
     extern __shared__ unsigned char smem_raw[];
     T* sh = reinterpret_cast<T*>(smem_raw);
     const int Pg = gg.P, Mt = gg.Mt;
@@ -600,13 +607,15 @@ hipError_t launch_gather_final(GridArgs gg, const T* rec, const T* part, long lo
 // quadrature 2.9 -> 2.5 ms at N = 1e5); blocks of 4 consecutive (cell-sorted, so
 // nearby) targets, spread over the XCDs in contiguous ranges so that
 // overlapping supports share an L2.
-template <typename T>
+template <typename T, int CM>
 __global__ void __launch_bounds__(256) k_gather(GridArgs g, const T* __restrict__ grids, long long cs,
                                                 const double* __restrict__ xs, const uint32_t* __restrict__ tperm,
                                                 long long TT, const double* __restrict__ upart,
                                                 double* __restrict__ uout)
 {
-    constexpr bool GQ = Out<T>::grad_quad;
+    constexpr bool GQ = Out<T, CM>::grad_quad;
+    // free space: the kernel grid's three outputs only (no -x3 grad phi)
+    constexpr bool FREE = CM == CM_FREE;
     __shared__ T wsh[4][3 * 32];              // W factors along x1, x2, x3
     __shared__ T dsh[4][GQ ? 3 * 32 : 1];     // their derivatives with respect to the target
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -654,7 +663,7 @@ __global__ void __launch_bounds__(256) k_gather(GridArgs g, const T* __restrict_
                     acc[3] += gx * ph;
                     acc[4] += gy * ph;
                     acc[5] += gz * ph;
-                } else {
+                } else if (!FREE) {
 #pragma unroll
                     for (int c = 3; c < 6; ++c) acc[c] += w * grids[c * cs + node];
                 }
@@ -686,7 +695,7 @@ __global__ void __launch_bounds__(256) k_gather(GridArgs g, const T* __restrict_
                 acc[3] += gx * ph;
                 acc[4] += gy * ph;
                 acc[5] += gz * ph;
-            } else {
+            } else if (!FREE) {
 #pragma unroll
                 for (int c = 3; c < 6; ++c) acc[c] += w * grids[c * cs + node];
             }
@@ -713,33 +722,37 @@ __global__ void __launch_bounds__(256) k_gather(GridArgs g, const T* __restrict_
         long long o = tperm[t];
         double h3 = g.h * g.h * g.h;
         for (int a = 0; a < 3; ++a)
-            uout[3 * o + a] = upart[3 * o + a] + h3 * ((double)acc[a] - x[2] * (double)acc[3 + a]);
+            uout[3 * o + a] = upart[3 * o + a] + h3 * ((double)acc[a] - (FREE ? 0.0 : x[2] * (double)acc[3 + a]));
     }
 }
 
 template <typename T>
-hipError_t launch_gather(GridArgs g, const T* grids, long long cs, const double* xs, const uint32_t* tperm,
+hipError_t launch_gather(GridArgs g, int cm, const T* grids, long long cs, const double* xs, const uint32_t* tperm,
                          long long T_, const double* upart, double* uout, hipStream_t st)
 {
     if (T_ <= 0) return hipSuccess;
     const long long nblk = (T_ + 3) / 4;
     const long long nlaunch = (nblk + NXCD - 1) / NXCD * NXCD;  // every XCD range padded to full length
-    hipLaunchKernelGGL(k_gather<T>, dim3((unsigned)nlaunch), dim3(256), 0, st, g, grids, cs, xs, tperm, T_, upart,
-                       uout);
+    if (cm == CM_FREE)
+        hipLaunchKernelGGL((k_gather<T, CM_FREE>), dim3((unsigned)nlaunch), dim3(256), 0, st, g, grids, cs, xs, tperm,
+                           T_, upart, uout);
+    else
+        hipLaunchKernelGGL((k_gather<T, CM_GRIDS>), dim3((unsigned)nlaunch), dim3(256), 0, st, g, grids, cs, xs, tperm,
+                           T_, upart, uout);
     return hipGetLastError();
 }
 
-template hipError_t launch_records<double>(int, bool, const double*, const double*, const uint32_t*, long long,
+template hipError_t launch_records<double>(int, int, const double*, const double*, const uint32_t*, long long,
                                            GridArgs, double*, hipStream_t);
-template hipError_t launch_records<float>(int, bool, const double*, const double*, const uint32_t*, long long,
+template hipError_t launch_records<float>(int, int, const double*, const double*, const uint32_t*, long long,
                                           GridArgs, float*, hipStream_t);
-template hipError_t launch_spread<double>(int, bool, GridArgs, const double*, const uint32_t*, double*, long long,
+template hipError_t launch_spread<double>(int, int, GridArgs, const double*, const uint32_t*, double*, long long,
                                           hipStream_t);
-template hipError_t launch_spread<float>(int, bool, GridArgs, const float*, const uint32_t*, float*, long long,
+template hipError_t launch_spread<float>(int, int, GridArgs, const float*, const uint32_t*, float*, long long,
                                          hipStream_t);
-template hipError_t launch_gather<double>(GridArgs, const double*, long long, const double*, const uint32_t*,
+template hipError_t launch_gather<double>(GridArgs, int, const double*, long long, const double*, const uint32_t*,
                                           long long, const double*, double*, hipStream_t);
-template hipError_t launch_gather<float>(GridArgs, const float*, long long, const double*, const uint32_t*, long long,
+template hipError_t launch_gather<float>(GridArgs, int, const float*, long long, const double*, const uint32_t*, long long,
                                          const double*, double*, hipStream_t);
 template hipError_t launch_target_records<double>(const double*, const uint32_t*, long long, GridArgs, double*,
                                                   hipStream_t);

@@ -61,7 +61,7 @@ struct EvenArgs {
     double scale;
 };
 
-size_t z_lds_bytes(int family, bool dgrid, int Mt, int Q, size_t esz);
+size_t z_lds_bytes(int family, int cm, int Mt, int Q, size_t esz);
 size_t pass_lds(int Mt, int B, size_t esz);
 bool z_resident_ok(int family, int Mt);
 
@@ -74,7 +74,7 @@ hipError_t launch_inv_y(const cplx<T>* in, cplx<T>* out, const PassArgs& a, int 
 template <typename T>
 hipError_t launch_inv_x(const cplx<T>* in, T* out, const PassArgs& a, int ncomp, hipStream_t st);
 template <typename T>
-hipError_t launch_z(int family, bool dgrid, cplx<T>* zb, cplx<T>* zout, const ZArgs& a, bool res, hipStream_t st);
+hipError_t launch_z(int family, int cm, cplx<T>* zb, cplx<T>* zout, const ZArgs& a, bool res, hipStream_t st);
 hipError_t launch_even_line(const double* in, double* out, const EvenArgs& a, hipStream_t st);
 hipError_t launch_oct_to_f32(const double* in, float* out, long long n, hipStream_t st);
 hipError_t launch_exp_table(double* ez, int n, double c, double dk, hipStream_t st);
@@ -128,6 +128,7 @@ struct RealArgs {
     const uint32_t* nchunks;      // device count of chunks
     const uint32_t* tgt_perm;     // sorted target -> original target
     unsigned long long* pairs;    // nullable: in-range (direct, image) pairs evaluated, added up
+    int images;                   // 1: half space (image and correction terms); 0: free space
 };
 
 hipError_t launch_cell_keys(const double* p, long long n, CellGeom cg, uint32_t* keys, uint32_t* idx, hipStream_t st);
@@ -157,20 +158,20 @@ struct GridArgs {
     int K[3];           // neighbour tiles per axis: ceil((P - 1) / tile)
 };
 
-// 2N points (sources then images): support base tile keys
-hipError_t launch_point_keys(const double* y, long long N, GridArgs g, uint32_t* keys, uint32_t* idx,
+// npts points (sources, then their images when npts = 2N): support base tile keys
+hipError_t launch_point_keys(const double* y, long long N, long long npts, GridArgs g, uint32_t* keys, uint32_t* idx,
                              hipStream_t st);
 // records of the sorted points (base, 1D weights, strengths) in precision T
 size_t record_stride(int family, int P, size_t esz);
 template <typename T>
-hipError_t launch_records(int family, bool dgrid, const double* y, const double* s, const uint32_t* perm, long long N, GridArgs g,
+hipError_t launch_records(int family, int cm, const double* y, const double* s, const uint32_t* perm, long long N, GridArgs g,
                           T* rec, hipStream_t st);
 template <typename T>
-hipError_t launch_spread(int family, bool dgrid, GridArgs g, const T* rec, const uint32_t* toff, T* grids, long long cs,
+hipError_t launch_spread(int family, int cm, GridArgs g, const T* rec, const uint32_t* toff, T* grids, long long cs,
                          hipStream_t st);
 // quadrature at the targets, one wavefront per target (small supports)
 template <typename T>
-hipError_t launch_gather(GridArgs g, const T* grids, long long cs, const double* x, const uint32_t* tperm,
+hipError_t launch_gather(GridArgs g, int cm, const T* grids, long long cs, const double* x, const uint32_t* tperm,
                          long long T_, const double* upart, double* uout, hipStream_t st);
 // quadrature at the targets, node-owner form (see grid.hip):
 //   keys: quadrature tile of each target's support base (xs: cell-sorted SoA targets)

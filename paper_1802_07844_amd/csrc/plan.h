@@ -170,6 +170,7 @@ struct PlanInput {
     const uint32_t* zhist;  // nullable: ZH_BINS counts of the target heights, bins of width zbin
     double zbin;
     int force_nr;      // 1..3: real-space cells of side >= r_c / force_nr; else chosen by density
+    bool free;         // the free-space sum (Sec. 2): no wall, no images, no corrections
 };
 
 // Real-space cells of side >= r_c / nr are walked (2 nr + 1)^3 around a
@@ -236,7 +237,11 @@ struct Plan {
     long long max_chunks;
     int warnings;
     double occ;  // targets per real-space cell of side r_c, averaged over the targets
+    bool free;   // free space: sources only on the grid, kernel grids only, no image terms
 };
+
+// correction mode of the grid pipeline (CM_GRIDS, CM_DENSITY or CM_FREE)
+inline int plan_cm(const Plan& p) { return p.free ? CM_FREE : p.dgrid ? CM_DENSITY : CM_GRIDS; }
 
 constexpr int EHS_MT_MAX = 2048;
 
@@ -258,6 +263,7 @@ inline int make_plan(const PlanInput& in, Plan* out)
     Plan p;
     std::memset(&p, 0, sizeof(p));
     p.family = in.family;
+    p.free = in.free;
     p.N = in.N;
     p.T = in.T;
     p.xi = in.xi;
@@ -272,7 +278,8 @@ inline int make_plan(const PlanInput& in, Plan* out)
         // does not cancel at the source's own position; the rotlet's stays
         // near 1e-6.  Clustered sets have a larger RMS velocity, so their
         // relative rounding error is smaller.
-        double box = std::max(std::max(in.hi[0] - in.lo[0], in.hi[1] - in.lo[1]), in.hi[2]);
+        double box = std::max(std::max(in.hi[0] - in.lo[0], in.hi[1] - in.lo[1]),
+                              in.free ? in.hi[2] - in.lo[2] : in.hi[2]);
         double xl = in.xi * box;
         double e32 = in.family == 0 ? 1.7e-6 * std::pow(xl / 25.0, 1.6)
                    : in.family == 1 ? 1.1e-5 * std::pow(xl / 45.0, 2.5)
@@ -282,7 +289,8 @@ inline int make_plan(const PlanInput& in, Plan* out)
         if (p.prec == 2 && e32 > 0.5 * in.tol) p.warnings |= 4;
     }
     const double pi = 3.14159265358979323846;
-    double ext1 = in.hi[0] - in.lo[0], ext2 = in.hi[1] - in.lo[1], ext3 = in.hi[2];
+    // half space: x3 measured from the wall; free space: the points' own range
+    double ext1 = in.hi[0] - in.lo[0], ext2 = in.hi[1] - in.lo[1], ext3 = in.free ? in.hi[2] - in.lo[2] : in.hi[2];
     double L = std::max(std::max(ext1, ext2), ext3);
     if (!(L > 0)) return -3;
     L *= 1.0 + 1e-12;
@@ -308,7 +316,7 @@ inline int make_plan(const PlanInput& in, Plan* out)
     // whose truncation error is larger by about sqrt(a) times the potential's
     // length scale, so the gather truncates the same Gaussian further out
     // (FP64 only: the FP32 path transforms the gradient spectrally)
-    int Pg = P + (in.gather_extra >= 0 ? in.gather_extra : (p.prec == 1 ? 2 : 0));
+    int Pg = P + (in.gather_extra >= 0 ? in.gather_extra : (p.prec == 1 && !in.free ? 2 : 0));
     if (Pg > 30 || (Pg & 1)) return -1;
     // spreading support: P, or P + 2 (P + 6 for the stresslet's second
     // derivatives) when the correction density D is spread with derivative
@@ -319,8 +327,8 @@ inline int make_plan(const PlanInput& in, Plan* out)
     // at N = 1e5 whatever the support (the k^2 in its spectrum needs a finer
     // grid than the truncation estimate gives): refused rather than run
     // above tol
-    if (in.family == 1 && in.dgrid > 0 && p.prec == 1) return -1;
-    const int Pe = std::max(std::max(P, Pg), (p.prec == 1 && in.dgrid != 0) ? Pd : P);
+    if (in.family == 1 && in.dgrid > 0 && p.prec == 1 && !in.free) return -1;
+    const int Pe = std::max(std::max(P, Pg), (p.prec == 1 && in.dgrid != 0 && !in.free) ? Pd : P);
     // grid intervals over the box
     int M = in.force_M;
     if (M <= 0) {
@@ -350,7 +358,7 @@ inline int make_plan(const PlanInput& in, Plan* out)
     {
         bool dg = false;
         // (never for the stresslet: see the refusal above)
-        if (p.prec == 1 && in.dgrid != 0 && in.family != 1) {
+        if (p.prec == 1 && in.dgrid != 0 && in.family != 1 && !in.free) {
             int ncB = in.family == 0 ? 4 : in.family == 1 ? 7 : 2;
             double save = 10.0 * std::pow(Mt / 480.0, 3) * (ncB - 1);
             double cost = 4.4e-9 * 2.0 * (double)in.N * ((double)Pd * Pd * Pd - (double)P * P * P) *
@@ -359,7 +367,7 @@ inline int make_plan(const PlanInput& in, Plan* out)
         }
         p.dgrid = dg;
         p.Ps = dg ? Pd : P;
-        p.ncin = ncin_for(in.family, dg);
+        p.ncin = ncin_for(in.family, in.free ? CM_FREE : dg ? CM_DENSITY : CM_GRIDS);
     }
     p.Mt = Mt;
     p.h = h;
@@ -377,14 +385,15 @@ inline int make_plan(const PlanInput& in, Plan* out)
     // fused x3 pass: smallest number of phases whose lines fit one wavefront's
     // FFT and whose max(ncin, 6) lines fit the LDS
     const size_t esz = p.prec == 1 ? 8 : 4;
-    const int nl = std::max(p.ncin, ncout_for(p.prec));
+    const int cm = plan_cm(p);
+    const int nl = std::max(p.ncin, ncout_for(p.prec, cm));
     p.Qz = 0;
     for (int Q : {2, 4, 8}) {
         if ((4 * Mt) % Q) continue;
         int nq = 4 * Mt / Q;
         if (!smooth7(nq)) continue;
         if (nq > lds_fft_cap(nq, 64)) continue;  // one line per wavefront
-        if (z_lds_bytes(in.family, p.dgrid, Mt, Q, esz) > 150 * 1024) continue;
+        if (z_lds_bytes(in.family, cm, Mt, Q, esz) > 150 * 1024) continue;
         p.Qz = Q;
         break;
     }
@@ -395,7 +404,7 @@ inline int make_plan(const PlanInput& in, Plan* out)
     // ZSLAB_BUDGET bytes) instead of the whole padded spectrum
     {
         size_t slab = (size_t)nl * (2 * Mt) * (2 * Mt) * 2 * esz;
-        if (!p.resident) slab += (size_t)ncout_for(p.prec) * (2 * Mt) * (2 * Mt) * 2 * esz;
+        if (!p.resident) slab += (size_t)ncout_for(p.prec, cm) * (2 * Mt) * (2 * Mt) * 2 * esz;
         long long g = in.force_zg > 0 ? in.force_zg : (long long)(ZSLAB_BUDGET / slab);
         p.zg = (int)std::max(1LL, std::min(g, (long long)Mt + 1));
     }
@@ -415,7 +424,7 @@ inline int make_plan(const PlanInput& in, Plan* out)
         int nc = (int)std::floor(extent[a] * nr / in.rc);
         nc = std::max(1, std::min(nc, 256));
         p.cg.nc[a] = nc;
-        p.cg.lo[a] = a < 2 ? in.lo[a] : 0.0;
+        p.cg.lo[a] = (a < 2 || in.free) ? in.lo[a] : 0.0;
         double side = extent[a] > 0 ? extent[a] / nc : 1.0;
         p.cg.inv[a] = 1.0 / side;
         ncell *= nc;
@@ -429,7 +438,9 @@ inline int make_plan(const PlanInput& in, Plan* out)
     g.P = p.Ps;
     g.o[0] = in.lo[0] - Pe * h / 2;
     g.o[1] = in.lo[1] - Pe * h / 2;
-    g.o[2] = -p.Lt;
+    // half space: the wall x3 = 0 is node M~ (the images below it); free
+    // space: placed like x1 and x2, so that the upper half stays empty
+    g.o[2] = in.free ? in.lo[2] - Pe * h / 2 : -p.Lt;
     g.h = h;
     g.a2 = 2 * xi * xi / eta;
     g.mP = magic_of((unsigned)p.Ps);
@@ -458,11 +469,12 @@ inline int make_plan(const PlanInput& in, Plan* out)
     {
         // nodes from the lowest target's support up (the x3 range computed
         // as l3lo below)
-        double zt = std::max(in.tlo3, 0.0);
+        double zt = in.free ? in.tlo3 : std::max(in.tlo3, 0.0);
         long long b = (long long)std::floor((zt - g.o[2]) / h) - Pg / 2;
         b = std::max(0LL, std::min(b, (long long)(2 * Mt - Pg)));
         double nodes = (double)Mt * Mt * (double)(2 * Mt - b);
-        p.gtiles = Pg >= 16 && (double)in.T < 3e-3 * nodes;
+        // (free space: the target-per-wavefront form, which has its output layout)
+        p.gtiles = !in.free && Pg >= 16 && (double)in.T < 3e-3 * nodes;
     }
     p.ntiles_g = 1;
     for (int a = 0; a < 3; ++a) {
@@ -477,7 +489,7 @@ inline int make_plan(const PlanInput& in, Plan* out)
     // target, less one node of margin, rounded down to a multiple of 16 (one
     // 128-byte row segment of the y passes).
     {
-        double zt = std::max(in.tlo3, 0.0);
+        double zt = in.free ? in.tlo3 : std::max(in.tlo3, 0.0);
         long long b = (long long)std::floor((zt - g.o[2]) / h) - Pg / 2;
         b = std::max(0LL, std::min(b, (long long)(2 * Mt - Pg)));
         p.l3lo = (int)(b / 16) * 16;
@@ -487,7 +499,10 @@ inline int make_plan(const PlanInput& in, Plan* out)
     // the highest image's support, which the forward transforms skip.  One
     // node of margin, rounded up to a multiple of 16.
     {
-        double zi = -std::max(in.slo3, 0.0);
+        // (free space: every grid vanishes above the top of the highest
+        // point's support, and the forward passes skip those rows for all
+        // components)
+        double zi = in.free ? in.hi[2] : -std::max(in.slo3, 0.0);
         long long t = (long long)std::floor((zi - g.o[2]) / h) + p.Ps / 2 + 2;
         t = std::max(0LL, std::min(t, (long long)(2 * Mt)));
         p.lzc = (int)std::min((long long)(2 * Mt), ((t + 15) / 16) * 16);

@@ -379,6 +379,15 @@ hipError_t launch_realspace(int family, const RealArgs& a, const double* ys, con
     if (max_chunks <= 0) return hipSuccess;
     dim3 grid((unsigned)max_chunks);  // one wavefront per chunk
     // direct terms of every chunk, then the images of the bottom-layer chunks
+    // (none in free space)
+    if (!a.images) {
+        switch (family) {
+            case STOKESLET: hipLaunchKernelGGL((k_realspace<T, STOKESLET, false>), grid, dim3(64), 0, st, a, ys, ss, xt, upart); break;
+            case STRESSLET: hipLaunchKernelGGL((k_realspace<T, STRESSLET, false>), grid, dim3(64), 0, st, a, ys, ss, xt, upart); break;
+            default: hipLaunchKernelGGL((k_realspace<T, ROTLET, false>), grid, dim3(64), 0, st, a, ys, ss, xt, upart); break;
+        }
+        return hipGetLastError();
+    }
     switch (family) {
         case STOKESLET:
             hipLaunchKernelGGL((k_realspace<T, STOKESLET, false>), grid, dim3(64), 0, st, a, ys, ss, xt, upart);
