@@ -538,10 +538,13 @@ def main():
         # the headline workload's targets against all its sources
         y, s, yd, sd, seed = R.inputs(head)
         cores = oracle.max_threads()
-        S = 16
-        t0 = time.perf_counter()
-        oracle.halfspace(fam, y, s, y[:S])
-        tp = time.perf_counter() - t0
+        # size the sample from two short probes (the first also absorbs the
+        # thread pool's start-up)
+        S, tp = 16, 1.0
+        for _ in range(2):
+            t0 = time.perf_counter()
+            oracle.halfspace(fam, y, s, y[:S])
+            tp = time.perf_counter() - t0
         S = int(max(16, min(n, S * args.cpu_seconds / max(tp, 1e-6))))
         idx = np.sort(workloads.rng(seed + 2000).choice(n, size=S, replace=False))
         t0 = time.perf_counter()

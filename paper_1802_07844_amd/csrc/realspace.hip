@@ -175,20 +175,33 @@ __device__ __forceinline__ void image_term(T rx, T ry, T rz, T r2, const T* s, T
     acc[2] += phi - x3 * g2;
 }
 
+// LDS add of one contribution to a target's accumulator.  All pairs of a
+// chunk are evaluated by its one wavefront, so the adds to an accumulator
+// happen in the order of its instructions and, within one instruction, in
+// the order the LDS serves the lanes: the same for the same input.
+template <typename T>
+__device__ __forceinline__ void lds_add(T* p, T v)
+{
+    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+}
+
 // Pair compaction.  A wavefront owns <= 64 targets of one cell (one lane
 // each) and walks the sources of the neighbour cells in batches of SB.  Only
-// about a sixth of the (target, source) candidates lie within r_c, and a
-// lane-per-target loop would evaluate the kernel for every candidate with
-// most lanes idle.  Instead, per batch:
+// a fraction of the (target, source) candidates lie within r_c (a third for
+// cells of side r_c / 3, a sixth for side r_c), and a lane-per-target loop
+// would evaluate the kernel for every candidate with most lanes idle.
+// Instead, per batch:
 //   1. each lane tests its target against the SB sources (wave-uniform
-//      loads); the hits of source j form the ballot mask[j], and the hits
-//      are written, in (j, lane) order, to a pair list in LDS;
-//   2. the lanes evaluate the listed pairs, one pair per lane, and store
-//      the contributions in LDS;
-//   3. each lane adds its own target's contributions in source order.
-// The sum over sources is therefore in the same order as a plain loop, and
-// deterministic.
-constexpr int RS_PC = 64 * 4 * 3;  // contribution slots (doubles): 256 pairs in FP64
+//      loads); the hits are written, in (source, lane) order, to a pair list
+//      in LDS;
+//   2. the lanes evaluate the listed pairs, one pair per lane, and add each
+//      contribution to its target's accumulator in LDS (lds_add).
+// Batches of 16 sources keep the pair lists long (at high densities hundreds
+// of pairs per batch), so the evaluation passes run with nearly every lane
+// busy.  The accumulation by LDS adds replaced a per-target sum in source
+// order out of a contribution buffer, whose bookkeeping cost more
+// instructions per pair than the pair's own arithmetic: the clustered
+// N = 4e6 set issued about 290 instructions per lane and pair.
 
 // PASS_IMG = false: the direct terms of every chunk (and the self term),
 // written to upart; PASS_IMG = true: the image and correction terms of the chunks in the
@@ -201,13 +214,19 @@ __global__ void __launch_bounds__(64) k_realspace(RealArgs a, const double* __re
                                                   double* __restrict__ upart)
 {
     constexpr int NS = (K == STRESSLET) ? 6 : 3;
-    constexpr int SB = sizeof(T) == 8 ? 4 : 8;  // sources per batch: 64 SB pairs of 3 T fit RS_PC
-    constexpr int SBI = 4;                      // image sources per batch (FP64 contributions)
+    // sources per batch: their pairs are listed at once and evaluated in
+    // windows of the contribution slots (SB 64 entries of 16 bits: the source
+    // index in the batch is stored above the lane)
+    constexpr int SB = 16;
+    constexpr int SBI = 8;  // image sources per batch (FP64 contributions)
     constexpr int SW = 3 + NS;                  // staged values per source
-    __shared__ double pcb[RS_PC];
     __shared__ uint16_t plist[64 * SB];
     __shared__ double sb[SB * SW];
     __shared__ double tpos[3 * 64];
+    // (FP64 accumulators in both precisions: the LDS adds of FP32 values ran
+    // the FP32 kernel at less than half the speed of the FP64 adds)
+    __shared__ double acc_l[PASS_IMG ? 1 : 3 * 64];    // direct terms, per target
+    __shared__ double acci_l[PASS_IMG ? 3 * 64 : 1];   // image terms, per target (FP64)
     const int lane = threadIdx.x;
     const long long w = blockIdx.x;
     if (w >= (long long)(*a.nchunks)) return;  // the whole (one-wavefront) block
@@ -224,6 +243,13 @@ __global__ void __launch_bounds__(64) k_realspace(RealArgs a, const double* __re
     tpos[lane] = xd0;
     tpos[64 + lane] = xd1;
     tpos[128 + lane] = xd2;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        if (PASS_IMG)
+            acci_l[3 * lane + c] = 0.0;
+        else
+            acc_l[3 * lane + c] = 0.0;
+    }
     const int n0 = a.cg.nc[0], n1 = a.cg.nc[1], n2 = a.cg.nc[2];
     const int c1 = (int)(cell % (uint32_t)n0);
     const int c2i = (int)((cell / (uint32_t)n0) % (uint32_t)n1);
@@ -231,14 +257,14 @@ __global__ void __launch_bounds__(64) k_realspace(RealArgs a, const double* __re
     const T xi = (T)a.xi;
     const T c2 = (T)(2.0 * a.xi / 1.7724538509055160273);
     const double rc2 = a.rc2;
-    T acc[3] = {0, 0, 0};
     double self[3] = {0.0, 0.0, 0.0};
     unsigned long long npair[2] = {0ull, 0ull};  // direct, image (wave-uniform)
     const int nr = a.cg.nr;  // cells of side >= r_c / nr: neighbours within nr cells
     const int lo1 = c1 - nr > 0 ? c1 - nr : 0, hi1 = c1 + nr < n0 - 1 ? c1 + nr : n0 - 1;
 
     // one batch of sources [mb, mb + nb) of the sorted arrays; IMG: their
-    // images (and harmonic corrections) instead of the direct terms
+    // images (and harmonic corrections) instead of the direct terms; every
+    // pair's contribution is added to its target's accumulator in LDS
     auto batch = [&](uint32_t mb, int nb, auto img_tag) {
         constexpr bool IMG = decltype(img_tag)::value;
         constexpr int B = IMG ? SBI : SB;
@@ -247,10 +273,8 @@ __global__ void __launch_bounds__(64) k_realspace(RealArgs a, const double* __re
             sb[f] = c < 3 ? ys[c * N + mb + jj] : ss[(c - 3) * N + mb + jj];
         }
         wave_sync();
-        unsigned long long mask[B];
-        int pre[B + 1];
-        pre[0] = 0;
-#pragma unroll
+        int pre = 0;  // wavefront-uniform
+#pragma unroll 4
         for (int j = 0; j < B; ++j) {
             bool hit = false;
             if (j < nb) {
@@ -266,14 +290,14 @@ __global__ void __launch_bounds__(64) k_realspace(RealArgs a, const double* __re
                     self[2] -= cs * s[5];
                 }
             }
-            mask[j] = __ballot(hit);
-            const int below = (int)__builtin_amdgcn_mbcnt_hi((unsigned)(mask[j] >> 32),
-                                                             __builtin_amdgcn_mbcnt_lo((unsigned)mask[j], 0u));
-            if (hit) plist[pre[j] + below] = (uint16_t)(lane | (j << 6));
-            pre[j + 1] = pre[j] + __popcll(mask[j]);
+            const unsigned long long m = __ballot(hit);
+            const int below = (int)__builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32),
+                                                             __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+            if (hit) plist[pre + below] = (uint16_t)(lane | (j << 6));
+            pre += __popcll(m);
         }
         wave_sync();
-        const int np = pre[B];
+        const int np = pre;
         npair[IMG ? 1 : 0] += (unsigned long long)np;
         for (int q = lane; q < np; q += 64) {
             const int pr = plist[q], tl = pr & 63, j = pr >> 6;
@@ -287,42 +311,19 @@ __global__ void __launch_bounds__(64) k_realspace(RealArgs a, const double* __re
                 for (int c = 0; c < NS; ++c) sv[c] = s[3 + c];
                 image_term<double, K>(dx, dy, dz, dx * dx + dy * dy + dz * dz, sv, y3, pz, a.xi,
                                       2.0 * a.xi / 1.7724538509055160273, ci);
-                pcb[3 * q] = ci[0];
-                pcb[3 * q + 1] = ci[1];
-                pcb[3 * q + 2] = ci[2];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) lds_add(&acci_l[3 * tl + c], ci[c]);
             } else {
                 const double dx = px - s[0], dy = py - s[1], dz = pz - s[2];
                 T sv[NS], cd[3] = {0, 0, 0};
 #pragma unroll
                 for (int c = 0; c < NS; ++c) sv[c] = (T)s[3 + c];
                 direct_term<T, K>((T)dx, (T)dy, (T)dz, (T)(dx * dx + dy * dy + dz * dz), sv, xi, c2, cd);
-                T* pt = reinterpret_cast<T*>(pcb);
-                pt[3 * q] = cd[0];
-                pt[3 * q + 1] = cd[1];
-                pt[3 * q + 2] = cd[2];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) lds_add(&acc_l[3 * tl + c], (double)cd[c]);
             }
         }
-        wave_sync();
-        return [&, mask, pre](double* ai, T* ad) {
-#pragma unroll
-            for (int j = 0; j < B; ++j) {
-                if ((mask[j] >> lane) & 1ull) {
-                    const int q = pre[j] + (int)__builtin_amdgcn_mbcnt_hi((unsigned)(mask[j] >> 32),
-                                                                          __builtin_amdgcn_mbcnt_lo((unsigned)mask[j], 0u));
-                    if (IMG) {
-                        ai[0] += pcb[3 * q];
-                        ai[1] += pcb[3 * q + 1];
-                        ai[2] += pcb[3 * q + 2];
-                    } else {
-                        const T* pt = reinterpret_cast<const T*>(pcb);
-                        ad[0] += pt[3 * q];
-                        ad[1] += pt[3 * q + 1];
-                        ad[2] += pt[3 * q + 2];
-                    }
-                }
-            }
-            wave_sync();  // the next batch overwrites the lists
-        };
+        wave_sync();  // the next batch overwrites the lists
     };
 
     if (!PASS_IMG) {
@@ -335,7 +336,7 @@ __global__ void __launch_bounds__(64) k_realspace(RealArgs a, const double* __re
                 long long row = ((long long)cc3 * n1 + cc2) * n0;
                 uint32_t s0 = a.src_off[row + lo1], s1 = a.src_off[row + hi1 + 1];
                 for (uint32_t mb = s0; mb < s1; mb += SB)
-                    batch(mb, (int)min((uint32_t)SB, s1 - mb), std::false_type())(nullptr, acc);
+                    batch(mb, (int)min((uint32_t)SB, s1 - mb), std::false_type());
             }
         }
     }
@@ -343,7 +344,6 @@ __global__ void __launch_bounds__(64) k_realspace(RealArgs a, const double* __re
     // target near the wall they are of size 1/(x3 + y3)^2 and cancel to O(1)
     // on the wall, beyond what FP32 can resolve.  Only sources within r_c of
     // the wall have images here.
-    double acci[3] = {0.0, 0.0, 0.0};
     if (PASS_IMG) {
         for (int cc3 = 0; cc3 < nr && cc3 < n2; ++cc3) {
             for (int d2 = -nr; d2 <= nr; ++d2) {
@@ -352,9 +352,17 @@ __global__ void __launch_bounds__(64) k_realspace(RealArgs a, const double* __re
                 long long row = ((long long)cc3 * n1 + cc2) * n0;
                 uint32_t s0 = a.src_off[row + lo1], s1 = a.src_off[row + hi1 + 1];
                 for (uint32_t mb = s0; mb < s1; mb += SBI)
-                    batch(mb, (int)min((uint32_t)SBI, s1 - mb), std::true_type())(acci, nullptr);
+                    batch(mb, (int)min((uint32_t)SBI, s1 - mb), std::true_type());
             }
         }
+    }
+    wave_sync();
+    double acc[3];
+    double acci[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        acc[c] = PASS_IMG ? 0.0 : acc_l[3 * lane + c];
+        acci[c] = PASS_IMG ? acci_l[3 * lane + c] : 0.0;
     }
     if (a.pairs && lane == 0) atomicAdd(a.pairs + (PASS_IMG ? 1 : 0), npair[PASS_IMG ? 1 : 0]);
     if (act) {

@@ -239,3 +239,29 @@ def test_fp64_at_loose_tolerances(fam, tol):
             assert err <= tol
         finally:
             c.close()
+
+
+@pytest.mark.parametrize("prec", [1, 2])
+def test_repeated_evaluations_are_bitwise_equal(prec):
+    """The real-space sum adds its pair contributions to per-target LDS
+    accumulators; the order of those adds is fixed by the wavefront's
+    instructions, so two evaluations of the same input agree bit for bit
+    (dense clustered set: hundreds of pairs per target)."""
+    n = 60_000
+    y, f = workloads.clustered_stokeslet(n, 65)
+    tol = 1e-10 if prec == 1 else 1e-5
+    rc = 0.06
+    xi = ehs.xi_for_cutoff("stokeslet", rc, tol / 2)
+    c = ehs.Context(0)
+    try:
+        c.set_option(ehs.OPT_PRECISION, prec)
+        yd, fd = torch.from_numpy(y).to(DEV), torch.from_numpy(f).to(DEV)
+        u1 = c.evaluate("stokeslet", yd, fd, yd, xi, rc, tol).cpu().numpy()
+        u2 = c.evaluate("stokeslet", yd, fd, yd, xi, rc, tol).cpu().numpy()
+        np.testing.assert_array_equal(u1, u2)
+        idx = np.sort(workloads.rng(66).choice(n, 256, replace=False))
+        err = oracle.rel_rms(oracle.halfspace("stokeslet", y, f, y[idx]), u1[idx])
+        print(f"clustered N={n} prec={prec}: rel-RMS {err:.2e}, repeat bitwise equal")
+        assert err <= tol
+    finally:
+        c.close()
