@@ -309,6 +309,14 @@ inline int make_plan(const PlanInput& in, Plan* out)
         // 3.1e-5 where the Gaussian's own truncation is 6.9e-7)
         const double pbudget = (tol < 1e-6 || in.family == 1 || p.prec == 1) ? tol / 40 : tol / 4;
         while (std::exp(-pi * P * C_SHAPE * C_SHAPE / 2) > pbudget) P += 2;
+        // the stresslet's correction density carries the second derivatives
+        // of the Gaussian, a^2 d^2 W with a = 2 xi^2 / eta, whose rounding the
+        // harmonic multiplier does not damp: its error grows like a (measured
+        // at N = 1e5, tol 1e-10: 3.5e-12 and 4.7e-11 at 300 and 30
+        // neighbours, rising with M at fixed xi), and two more support nodes,
+        // which widen the Gaussian (eta grows with P), bring it to the
+        // separate grids' level (1.2e-12, 1.2e-11)
+        if (in.family == 1 && p.prec == 1 && !in.free && in.dgrid > 0) P += 2;
     }
     if (P < 2 || P > 30 || (P & 1)) return -1;
     // the quadrature forms the gradient of the correction potential with the
@@ -323,11 +331,6 @@ inline int make_plan(const PlanInput& in, Plan* out)
     // weights; the choice is made below, once M~ is known
     const int Pd = P + (in.family == 1 ? 6 : 2);
     if (Pd > 30) return -1;
-    // the stresslet's second-derivative correction density stays near 1e-10
-    // at N = 1e5 whatever the support (the k^2 in its spectrum needs a finer
-    // grid than the truncation estimate gives): refused rather than run
-    // above tol
-    if (in.family == 1 && in.dgrid > 0 && p.prec == 1 && !in.free) return -1;
     const int Pe = std::max(std::max(P, Pg), (p.prec == 1 && in.dgrid != 0 && !in.free) ? Pd : P);
     // grid intervals over the box
     int M = in.force_M;
@@ -357,8 +360,9 @@ inline int make_plan(const PlanInput& in, Plan* out)
     // 10 ms per component at M~ = 480 and 4.4 ns per point and P^3 node)
     {
         bool dg = false;
-        // (never for the stresslet: see the refusal above)
-        if (p.prec == 1 && in.dgrid != 0 && in.family != 1 && !in.free) {
+        // (the stresslet only on request: its density needs the larger
+        // support above, which the cost model does not weigh)
+        if (p.prec == 1 && in.dgrid != 0 && (in.family != 1 || in.dgrid > 0) && !in.free) {
             int ncB = in.family == 0 ? 4 : in.family == 1 ? 7 : 2;
             double save = 10.0 * std::pow(Mt / 480.0, 3) * (ncB - 1);
             double cost = 4.4e-9 * 2.0 * (double)in.N * ((double)Pd * Pd * Pd - (double)P * P * P) *

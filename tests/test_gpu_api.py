@@ -8,7 +8,7 @@
   entry behind, in a context and in a server: the next call succeeds.
 * The runtime-optimal search keeps only the fastest candidate's octants.
 * The correction-density option (EHS_OPT_DGRID) in both settings against the
-  oracle, and its refusal for the stresslet.
+  oracle, for the stresslet with its larger support.
 """
 import math
 
@@ -171,18 +171,34 @@ def test_correction_density_option(fam, dgrid):
         c.close()
 
 
-def test_correction_density_refused_for_the_stresslet():
-    y, s, yd, sd, xi, rc = _problem("stresslet", 500, 61)
+@pytest.mark.parametrize("n,nb,tol", [(100_000, 30, 1e-10), (100_000, 300, 1e-10), (1_000_000, 300, 1e-5)])
+def test_stresslet_correction_density(n, nb, tol):
+    """The stresslet's correction density (second-derivative weights), on
+    request, with the two extra support nodes it needs, in FP64 against the
+    oracle on a sample; the separate-grid plan of the same points beside it."""
+    y, s = workloads.make("stresslet", n, 61)
+    rc = _rc(nb, n)
+    xi = ehs.xi_for_cutoff("stresslet", rc, tol / 2)
+    yd, sd = torch.from_numpy(y).to(DEV), torch.from_numpy(s).to(DEV)
+    idx = np.sort(workloads.rng(67).choice(n, 256, replace=False))
+    ref = oracle.halfspace("stresslet", y, s, y[idx])
     c = ehs.Context(0)
     try:
         c.set_option(ehs.OPT_PRECISION, 1)
-        c.set_option(ehs.OPT_DGRID, 1)
-        with pytest.raises(ehs.EhsError) as e:
-            c.evaluate("stresslet", yd, sd, yd, xi, rc, 1e-10)
-        assert e.value.code == ehs.EHS_EINVAL
-        c.set_option(ehs.OPT_DGRID, -1)
-        u = c.evaluate("stresslet", yd, sd, yd, xi, rc, 1e-10)
-        assert oracle.rel_rms(oracle.halfspace("stresslet", y, s, y), u.cpu().numpy()) <= 1e-10
+        c.set_option(ehs.OPT_TIMING, 1)
+        out = {}
+        for dg in (0, 1):
+            c.set_option(ehs.OPT_DGRID, dg)
+            u, rep = c.evaluate("stresslet", yd, sd, yd, xi, rc, tol, report=True)
+            u, rep = c.evaluate("stresslet", yd, sd, yd, xi, rc, tol, report=True)  # timed without the precompute
+            torch.cuda.synchronize()
+            err = oracle.rel_rms(ref, u.cpu().numpy()[idx])
+            out[dg] = (err, rep)
+            print(f"stresslet N={n} ~{nb} neighbours tol {tol:g} dgrid={rep.dgrid}: P={rep.P} Ps={rep.Ps} "
+                  f"Mt={rep.Mt} rel-RMS {err:.2e}, {rep.ms_stage[ehs.STAGES.index('total')]:.1f} ms")
+            assert rep.dgrid == dg
+            assert err <= tol
+        assert out[1][1].P == out[0][1].P + 2
     finally:
         c.close()
 
