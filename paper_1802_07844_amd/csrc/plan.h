@@ -358,10 +358,27 @@ inline int make_plan(const PlanInput& in, Plan* out)
     // of the grid at the price of (Pd^3 - P^3) more spreading work per point;
     // the unit costs are those measured on MI355X for the two passes (about
     // 10 ms per component at M~ = 480 and 4.4 ns per point and P^3 node)
+    // the stresslet in auto mode: its density needs two more support nodes
+    // (above), which change the whole plan, so the choice is made on this
+    // plan's grid and, for the density, the plan is made again with it.  The
+    // density saves 6 of 13 forward components, measured at about
+    // 1.5e-7 ms Mt^3 each pass set, and its image records and larger support
+    // cost about 3.5e-9 ms per point and node of ((P + 8)^3 - P^3)
+    // (spreading and quadrature together; measured on MI355X: the density
+    // runs 0.61-0.87 of the grids' time from 130 grid nodes per point up,
+    // 1.07-1.37 below)
+    if (in.family == 1 && p.prec == 1 && !in.free && in.dgrid < 0 && in.force_P <= 0) {
+        const double save = 1.5e-7 * (double)Mt * Mt * Mt * 6.0;
+        const double cost = 3.5e-9 * (double)in.N * ((double)(P + 8) * (P + 8) * (P + 8) - (double)P * P * P);
+        if (save > cost) {
+            PlanInput in2 = in;
+            in2.dgrid = 1;
+            return make_plan(in2, out);
+        }
+    }
     {
         bool dg = false;
-        // (the stresslet only on request: its density needs the larger
-        // support above, which the cost model does not weigh)
+        // (the stresslet: on request, or chosen above)
         if (p.prec == 1 && in.dgrid != 0 && (in.family != 1 || in.dgrid > 0) && !in.free) {
             int ncB = in.family == 0 ? 4 : in.family == 1 ? 7 : 2;
             double save = 10.0 * std::pow(Mt / 480.0, 3) * (ncB - 1);

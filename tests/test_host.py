@@ -97,9 +97,10 @@ def _smooth7(n):
 @pytest.mark.parametrize("tol", [1e-10, 1e-5])
 def test_plan_invariants(family, tol):
     r = _plan(family, tol)
-    # Gaussian support from exp(-pi P c^2 / 2) <= tol / 40 (tol / 4 for tol >= 1e-6 except the
-    # stresslet), c = 0.95
-    assert r.P == (20 if tol == 1e-10 else 12 if family == "stresslet" else 10)
+    # Gaussian support from exp(-pi P c^2 / 2) <= tol / 40 (tol / 4 for the FP32 stokeslet and
+    # rotlet at tol >= 1e-6), c = 0.95; two more for the stresslet's correction density
+    base = 20 if tol == 1e-10 else 12 if family == "stresslet" else 10
+    assert r.P == base + (2 if (family == "stresslet" and r.dgrid) else 0)
     assert r.Mt % 2 == 0 and _smooth7(r.Mt) and r.Mt >= r.M + max(r.P, r.Pg)
     assert 0.0 < r.eta < 1.0
     assert r.precision == (1 if tol < 1e-5 else 2)
@@ -202,14 +203,16 @@ def test_record_region_holds_the_spreading_support(dgrid):
     """The workspace's record region is sized with the spreading support the
     kernels use (P + 2 when the correction
     density is spread with derivative weights): the audit passes, and the
-    reported workspace grows with the record stride."""
+    reported workspace grows with the record stride; the stresslet's density
+    (second derivatives: P + 6) comes with two more support nodes in P."""
     n = 100_000
     for fam in ("stokeslet", "stresslet", "rotlet"):
         rc = (30 * 3.0 / (4.0 * math.pi * n)) ** (1.0 / 3.0)
         xi = ehs.xi_for_cutoff(fam, rc, 0.5e-10)
         r = ehs.plan_query(fam, n, n, (0, 0, 0), (1, 1, 1), 3.0 * n, xi, rc, 1e-10, 1)
-        assert r.Ps == (r.P + 2 if r.dgrid else r.P)
-        assert not (fam == "stresslet" and r.dgrid)  # the stresslet only on request
+        extra = 6 if fam == "stresslet" else 2
+        assert r.Ps == (r.P + extra if r.dgrid else r.P)
+        assert r.P == (22 if (fam == "stresslet" and r.dgrid) else 20)
         assert r.Pg == r.P + 2 and r.Mt >= r.M + max(r.Ps, r.Pg)
         stride = 2 + 3 * r.Ps + 3 + {"stokeslet": 7, "stresslet": 13, "rotlet": 5}[fam]
         assert r.workspace_bytes >= 2 * n * stride * 8
@@ -340,3 +343,21 @@ def test_erfc_polynomial_of_the_real_space_sum(name, dtype, bound):
     err = np.max(np.abs(got - ref))
     print(f"{name}: max |erfc error| = {err:.2e}")
     assert err <= bound
+
+
+def test_stresslet_density_chosen_by_cost():
+    """Auto mode takes the stresslet's correction density where the grid is
+    large for the number of points (the saved transforms outweigh the wider
+    support: measured 0.61-0.87 of the time from 130 grid nodes per point
+    up) and the separate grids where the points dominate (1.07-1.37 below)."""
+    def plan(n, nb, tol):
+        rc = (nb * 3.0 / (4.0 * math.pi * n)) ** (1.0 / 3.0)
+        xi = ehs.xi_for_cutoff("stresslet", rc, tol / 2)
+        return ehs.plan_query("stresslet", n, n, (0, 0, 0), (1, 1, 1), 1.0 * n, xi, rc, tol, 1)
+
+    assert plan(100_000, 30, 1e-10).dgrid == 1
+    assert plan(1_000_000, 600, 1e-10).dgrid == 1
+    assert plan(1_000_000, 2000, 1e-10).dgrid == 0
+    assert plan(1_000_000, 2000, 1e-5).dgrid == 0
+    r = plan(1_000_000, 300, 1e-5)
+    assert r.dgrid == 1 and r.P == 14 and r.Ps == 20
