@@ -191,8 +191,10 @@ def _rc(nb, n):
 
 # the legs: (family, layout, N, precision, tol, r_c rule)
 WORKLOADS = {
-    "c4_fp64": ("stokeslet", "clustered", 4_000_000, 1, 1e-10, 0.035),
-    "c4_fp32": ("stokeslet", "clustered", 4_000_000, 2, 1e-5, 0.03),
+    # (r_c, xi): the runtime-optimal pair that ehs_tune's search finds from
+    # (0.035, xi for it) in FP64 and (0.03, xi for it) in FP32 on these points
+    "c4_fp64": ("stokeslet", "clustered", 4_000_000, 1, 1e-10, (0.04170, 117.15)),
+    "c4_fp32": ("stokeslet", "clustered", 4_000_000, 2, 1e-5, (0.02746, 126.89)),
     "c3_stresslet_fp64": ("stresslet", "uniform", 1_000_000, 1, 1e-10, ("nb", 2000)),
     "c3_rotlet_fp64": ("rotlet", "uniform", 1_000_000, 1, 1e-10, ("nb", 2000)),
     "c3_stresslet_fp32": ("stresslet", "uniform", 1_000_000, 2, 1e-5, ("nb", 2000)),
@@ -219,7 +221,12 @@ def describe(name):
              else "uniform in [0,1)^2 x (0,1]")
     strengths = {"stokeslet": "forces N(0,1)", "stresslet": "strengths N(0,1)^3, orientations uniform on S^2",
                  "rotlet": "torques N(0,1)^3"}[fam]
-    cut = f"r_c = {rcr}" if not isinstance(rcr, tuple) else f"r_c for ~{rcr[1]} neighbours"
+    if not isinstance(rcr, tuple):
+        cut = f"r_c = {rcr}"
+    elif rcr[0] == "nb":
+        cut = f"r_c for ~{rcr[1]} neighbours"
+    else:
+        cut = f"r_c = {rcr[0]}, xi = {rcr[1]} (runtime-optimal pair of the parameter search)"
     return (f"{'free-space' if _free(name) else 'half-space'} {fam}, N={n} sources=targets {where}, {strengths}, "
             f"{'FP64' if prec == 1 else 'FP32'} tol {tol:g}, {cut}")
 
@@ -244,6 +251,9 @@ class Runner:
 
     def params(self, name):
         fam, layout, n, prec, tol, rcr = WORKLOADS[name][:6]
+        if isinstance(rcr, tuple) and rcr[0] != "nb":
+            rc, xi = rcr  # a searched (r_c, xi) pair
+            return fam, n, prec, tol, rc, xi
         rc = _rc(rcr[1], n) if isinstance(rcr, tuple) else rcr
         # the real-space estimate takes a quarter of the budget
         xi = self.ehs.xi_for_cutoff(fam, rc, tol / 2)
@@ -538,14 +548,17 @@ def main():
         # the headline workload's targets against all its sources
         y, s, yd, sd, seed = R.inputs(head)
         cores = oracle.max_threads()
-        # size the sample from two short probes (the first also absorbs the
-        # thread pool's start-up)
-        S, tp = 16, 1.0
-        for _ in range(2):
+        # size the sample from probes of two sizes: a call costs a fixed part
+        # (its pass over all N sources) plus a part per target
+        oracle.halfspace(fam, y, s, y[:8])  # thread pool start-up
+        tt = []
+        for S in (32, 128):
             t0 = time.perf_counter()
             oracle.halfspace(fam, y, s, y[:S])
-            tp = time.perf_counter() - t0
-        S = int(max(16, min(n, S * args.cpu_seconds / max(tp, 1e-6))))
+            tt.append(time.perf_counter() - t0)
+        per = max((tt[1] - tt[0]) / 96.0, 1e-9)
+        fixed = max(tt[0] - 32 * per, 0.0)
+        S = int(max(128, min(n, (args.cpu_seconds - fixed) / per)))
         idx = np.sort(workloads.rng(seed + 2000).choice(n, size=S, replace=False))
         t0 = time.perf_counter()
         oracle.halfspace(fam, y, s, y[idx])
