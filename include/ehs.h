@@ -72,9 +72,11 @@ extern "C" {
 #define EHS_OPT_GATHER_EXTRA 7 /* >= 0 (even): support nodes the quadrature adds to P; -1: default (2 for
                                   FP64, whose quadrature forms the correction gradient, 0 for FP32) */
 #define EHS_OPT_DGRID 8     /* FP64: 1 spreads the correction sources as one density with derivative
-                               weights, 0 as separate grids, -1 (default) chooses by cost; with the
-                               density the stresslet's Gaussian support P grows by 2, which its
-                               second-derivative weights need */
+                               weights, 0 as separate grids, -1 (default) chooses by cost, and only
+                               for tol >= 1e-12 (the density's rounding floor is about 1e-13) and
+                               where its support fits 30 nodes; with the density the stresslet's
+                               Gaussian support P grows by 2, which its second-derivative weights
+                               need (1 with a support beyond 30 nodes: EHS_EINVAL) */
 #define EHS_OPT_FAIL_PRECOMPUTE 9 /* test hook: > 0 makes the next that many truncated-kernel
                                      productions fail with EHS_EHIP before anything is launched */
 #define EHS_OPT_CELL_REACH 10 /* 1..3: real-space cells of side >= r_c / value; 0 (default): chosen

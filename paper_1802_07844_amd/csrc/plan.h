@@ -330,8 +330,18 @@ inline int make_plan(const PlanInput& in, Plan* out)
     // derivatives) when the correction density D is spread with derivative
     // weights; the choice is made below, once M~ is known
     const int Pd = P + (in.family == 1 ? 6 : 2);
-    if (Pd > 30) return -1;
-    const int Pe = std::max(std::max(P, Pg), (p.prec == 1 && in.dgrid != 0 && !in.free) ? Pd : P);
+    // the density on request needs its support within the 30 nodes; by cost
+    // it is only a candidate when it fits
+    const bool dens_fits = Pd <= 30;
+    if (in.dgrid > 0 && p.prec == 1 && !in.free && !dens_fits) return -1;
+    // the density's derivative weights leave a rounding floor of about 1e-13
+    // relative (measured at N = 400, ~120 neighbours, tol 1e-13: the rotlet
+    // 1.1e-13 with the density and 5.7e-14 with the separate grids; the
+    // stokeslet 7.2e-14 with either), so auto mode takes it only from tol
+    // 1e-12 up
+    const bool dens_tol = in.dgrid > 0 || tol >= 1e-12;
+    const bool dens_cand = p.prec == 1 && in.dgrid != 0 && !in.free && dens_fits && dens_tol;
+    const int Pe = std::max(std::max(P, Pg), dens_cand ? Pd : P);
     // grid intervals over the box
     int M = in.force_M;
     if (M <= 0) {
@@ -367,19 +377,22 @@ inline int make_plan(const PlanInput& in, Plan* out)
     // (spreading and quadrature together; measured on MI355X: the density
     // runs 0.61-0.87 of the grids' time from 130 grid nodes per point up,
     // 1.07-1.37 below)
-    if (in.family == 1 && p.prec == 1 && !in.free && in.dgrid < 0 && in.force_P <= 0) {
+    if (in.family == 1 && p.prec == 1 && !in.free && in.dgrid < 0 && in.force_P <= 0 && dens_tol) {
         const double save = 1.5e-7 * (double)Mt * Mt * Mt * 6.0;
         const double cost = 3.5e-9 * (double)in.N * ((double)(P + 8) * (P + 8) * (P + 8) - (double)P * P * P);
         if (save > cost) {
+            // (at the tightest tolerances the wider density support exceeds
+            // the supported 30 nodes: the separate grids then remain)
             PlanInput in2 = in;
             in2.dgrid = 1;
-            return make_plan(in2, out);
+            const int r = make_plan(in2, out);
+            if (r == 0) return 0;
         }
     }
     {
         bool dg = false;
         // (the stresslet: on request, or chosen above)
-        if (p.prec == 1 && in.dgrid != 0 && (in.family != 1 || in.dgrid > 0) && !in.free) {
+        if (dens_cand && (in.family != 1 || in.dgrid > 0)) {
             int ncB = in.family == 0 ? 4 : in.family == 1 ? 7 : 2;
             double save = 10.0 * std::pow(Mt / 480.0, 3) * (ncB - 1);
             double cost = 4.4e-9 * 2.0 * (double)in.N * ((double)Pd * Pd * Pd - (double)P * P * P) *

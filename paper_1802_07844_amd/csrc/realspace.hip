@@ -19,61 +19,119 @@
 
 namespace ehs {
 
-// erfc(x) for x >= 0 from E = exp(-x^2), which the Gaussian terms need
-// anyway: erfc(x) = E q(t), t = 1 / (1 + x / 2), q a fitted polynomial
-// (erfc_poly.h).  One division and a Horner polynomial, the same
-// instructions on every lane, where a library erfc branches over ranges of x
-// (a wavefront's pairs span 0 <= x < xi r_c and take several branches).
-template <typename T>
-__device__ __forceinline__ T erfc_e(T x, T E);
-template <>
-__device__ __forceinline__ double erfc_e<double>(double x, double E)
-{
-    const double t = 1.0 / (1.0 + 0.5 * x);
-    double q = ERFC_C64[ERFC_DEG64];
-#pragma unroll
-    for (int k = ERFC_DEG64 - 1; k >= 0; --k) q = fma(q, t, ERFC_C64[k]);
-    return E * q;
-}
-template <>
-__device__ __forceinline__ float erfc_e<float>(float x, float E)
-{
-    const float t = 1.0f / (1.0f + 0.5f * x);
-    float q = ERFC_C32[ERFC_DEG32];
-#pragma unroll
-    for (int k = ERFC_DEG32 - 1; k >= 0; --k) q = fmaf(q, t, ERFC_C32[k]);
-    return E * q;
-}
-template <typename T>
-__device__ __forceinline__ T t_exp(T x);
-template <>
-__device__ __forceinline__ double t_exp<double>(double x) { return exp(x); }
-template <>
-__device__ __forceinline__ float t_exp<float>(float x) { return expf(x); }
-template <typename T>
-__device__ __forceinline__ T t_sqrt(T x);
-template <>
-__device__ __forceinline__ double t_sqrt<double>(double x) { return sqrt(x); }
-template <>
-__device__ __forceinline__ float t_sqrt<float>(float x) { return sqrtf(x); }
+// ---------------------------------------------------------------------------
+// Arithmetic of one pair.  The library's sqrt, division and exp cover every
+// input (denormals, overflow, infinities) in some twenty to thirty
+// instructions each.  A pair here has 0 < r < r_c and 0 <= xi r <= xi r_c,
+// so each is formed from the hardware estimate and one Newton step, or from a
+// range reduction and a series, in about a third of that.
+// ---------------------------------------------------------------------------
 
-// direct term K_R(r) s, r != 0
-template <typename T, int K>
-__device__ __forceinline__ void direct_term(T rx, T ry, T rz, T r2, const T* s, T xi, T c2, T* acc)
+// a * b + c with the constant c in scalar registers.  With the coefficients
+// of a polynomial in vector registers the compiler picks the accumulating
+// FMA form, which overwrites its addend, and copies the coefficient before
+// every use: a third more instructions for a Horner chain.
+__device__ __forceinline__ double fma_sc(double a, double b, double c)
 {
-    T r = t_sqrt<T>(r2);
-    T ir = (T)1 / r;
-    T E = t_exp<T>(-xi * xi * r2);
-    T C = erfc_e<T>(xi * r, E);
+    double d;
+    asm("v_fma_f64 %0, %1, %2, %3" : "=v"(d) : "v"(a), "v"(b), "s"(c));
+    return d;
+}
+
+template <typename T>
+struct PairMath;
+
+template <>
+struct PairMath<double> {
+    // 1/sqrt(x), x > 0 normal: the hardware estimate y (relative error
+    // about 2^-23) and one third-order Newton step y (1 + e/2 + 3e^2/8),
+    // e = 1 - x y^2, which leaves an error of order e^3, below rounding
+    static __device__ __forceinline__ double rsqrt(double x)
+    {
+        const double y = __builtin_amdgcn_rsq(x);
+        const double e = fma(-x * y, y, 1.0);
+        return fma(y * e, fma(e, 0.375, 0.5), y);
+    }
+    // 1/x, 1 <= x <= 8: the hardware estimate and the step y (1 + e + e^2),
+    // e = 1 - x y
+    static __device__ __forceinline__ double rcp(double x)
+    {
+        const double y = __builtin_amdgcn_rcp(x);
+        const double e = fma(-x, y, 1.0);
+        return fma(y * e, 1.0 + e, y);
+    }
+    // e^y, -700 < y <= 0: y = k ln2 + f, k = rint(y / ln2), |f| <= ln2 / 2,
+    // with ln2 split in two parts so that k ln2 is exact to 2^-60; e^f by its
+    // Taylor series to the f^12 term (truncation below 2.5e-16 relative);
+    // 2^k applied to the exponent
+    static __device__ __forceinline__ double exp(double y)
+    {
+        const double k = __builtin_rint(y * 1.4426950408889634074);
+        double f = fma(-k, 6.93147180369123816490e-01, y);
+        f = fma(-k, 1.90821492927058770002e-10, f);
+        double p = 1.0 / 479001600.0;  // 1/12!
+        p = fma_sc(p, f, 1.0 / 39916800.0);
+        p = fma_sc(p, f, 1.0 / 3628800.0);
+        p = fma_sc(p, f, 1.0 / 362880.0);
+        p = fma_sc(p, f, 1.0 / 40320.0);
+        p = fma_sc(p, f, 1.0 / 5040.0);
+        p = fma_sc(p, f, 1.0 / 720.0);
+        p = fma_sc(p, f, 1.0 / 120.0);
+        p = fma_sc(p, f, 1.0 / 24.0);
+        p = fma_sc(p, f, 1.0 / 6.0);
+        p = fma_sc(p, f, 0.5);
+        p = fma_sc(p, f, 1.0);
+        p = fma_sc(p, f, 1.0);
+        return __builtin_amdgcn_ldexp(p, (int)k);
+    }
+    // erfc(x), x >= 0, from E = exp(-x^2), which the Gaussian terms need
+    // anyway: erfc(x) = E q(t), t = 1 / (1 + x / 2), q a fitted polynomial
+    // (erfc_poly.h).  The library erfc branches over ranges of x, and a
+    // wavefront's pairs span 0 <= x < xi r_c and take several branches.
+    static __device__ __forceinline__ double erfc_e(double x, double E)
+    {
+        const double t = rcp(fma(0.5, x, 1.0));
+        double q = ERFC_C64[ERFC_DEG64];
+#pragma unroll
+        for (int k = ERFC_DEG64 - 1; k >= 0; --k) q = fma_sc(q, t, ERFC_C64[k]);
+        return E * q;
+    }
+};
+
+template <>
+struct PairMath<float> {
+    // the FP32 estimates are within about 1 ulp: no refinement
+    static __device__ __forceinline__ float rsqrt(float x) { return __builtin_amdgcn_rsqf(x); }
+    static __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+    static __device__ __forceinline__ float exp(float y) { return expf(y); }
+    static __device__ __forceinline__ float erfc_e(float x, float E)
+    {
+        const float t = rcp(fmaf(0.5f, x, 1.0f));
+        float q = ERFC_C32[ERFC_DEG32];
+#pragma unroll
+        for (int k = ERFC_DEG32 - 1; k >= 0; --k) q = fmaf(q, t, ERFC_C32[k]);
+        return E * q;
+    }
+};
+
+// direct term K_R(r) s, r != 0, written to out
+template <typename T, int K>
+__device__ __forceinline__ void direct_term(T rx, T ry, T rz, T r2, const T* s, T xi, T c2, T* out)
+{
+    using PM = PairMath<T>;
+    const T ir = PM::rsqrt(r2);
+    const T r = r2 * ir;
+    const T E = PM::exp(-xi * xi * r2);
+    const T C = PM::erfc_e(xi * r, E);
     if (K == STOKESLET) {
         // S_R f = (a - 2 c2 E) f + a (r.f) r / r^2,  a = c2 E + C / r
         T a = c2 * E + C * ir;
         T rf = rx * s[0] + ry * s[1] + rz * s[2];
         T b = a * rf * ir * ir;
         T d = a - (T)2 * c2 * E;
-        acc[0] += d * s[0] + b * rx;
-        acc[1] += d * s[1] + b * ry;
-        acc[2] += d * s[2] + b * rz;
+        out[0] = d * s[0] + b * rx;
+        out[1] = d * s[1] + b * ry;
+        out[2] = d * s[2] + b * rz;
     } else if (K == STRESSLET) {
         // T_R[S] = A (r.S r) r + Bc (2 S r + r tr S)
         T ir2 = ir * ir;
@@ -85,43 +143,44 @@ __device__ __forceinline__ void direct_term(T rx, T ry, T rz, T r2, const T* s, 
         T rsr = rx * sr0 + ry * sr1 + rz * sr2;
         T tr = s[0] + s[3] + s[5];
         T g = A * rsr;
-        acc[0] += g * rx + Bc * ((T)2 * sr0 + rx * tr);
-        acc[1] += g * ry + Bc * ((T)2 * sr1 + ry * tr);
-        acc[2] += g * rz + Bc * ((T)2 * sr2 + rz * tr);
+        out[0] = g * rx + Bc * ((T)2 * sr0 + rx * tr);
+        out[1] = g * ry + Bc * ((T)2 * sr1 + ry * tr);
+        out[2] = g * rz + Bc * ((T)2 * sr2 + rz * tr);
     } else {
         // W_R v = 2 alpha (v x r), alpha = C / r^3 + c2 E / r^2
         T al = (T)2 * (C * ir * ir * ir + c2 * E * ir * ir);
-        acc[0] += al * (s[1] * rz - s[2] * ry);
-        acc[1] += al * (s[2] * rx - s[0] * rz);
-        acc[2] += al * (s[0] * ry - s[1] * rx);
+        out[0] = al * (s[1] * rz - s[2] * ry);
+        out[1] = al * (s[2] * rx - s[0] * rz);
+        out[2] = al * (s[0] * ry - s[1] * rx);
     }
 }
 
 // image kernel term plus the harmonic corrections -x3 grad phi_R + e3 phi_R
-// of one source (strength s, height y3) at r~ = x - y^I
+// of one source (strength s, height y3) at r~ = x - y^I, written to out
 template <typename T, int K>
-__device__ __forceinline__ void image_term(T rx, T ry, T rz, T r2, const T* s, T y3, T x3, T xi, T c2, T* acc)
+__device__ __forceinline__ void image_term(T rx, T ry, T rz, T r2, const T* s, T y3, T x3, T xi, T c2, T* out)
 {
-    T r = t_sqrt<T>(r2);
-    T ir = (T)1 / r;
-    T ir2 = ir * ir;
-    T E = t_exp<T>(-xi * xi * r2);
-    T C = erfc_e<T>(xi * r, E);
+    using PM = PairMath<T>;
+    const T ir = PM::rsqrt(r2);
+    const T r = r2 * ir;
+    const T ir2 = ir * ir;
+    const T E = PM::exp(-xi * xi * r2);
+    const T C = PM::erfc_e(xi * r, E);
     T xi2 = xi * xi;
     // grad G_R = -alpha r, grad grad G_R = -alpha I + beta r r,
     // grad grad grad G_R = beta (d r)_sym + gamma r r r
     T al = C * ir2 * ir + c2 * E * ir2;
     T be = (T)3 * C * ir2 * ir2 * ir + c2 * E * ((T)3 * ir2 * ir2 + (T)2 * xi2 * ir2);
-    T phi, g0, g1, g2;
+    T phi, g0, g1, g2, k0, k1, k2;  // k: the image kernel term
     if (K == STOKESLET) {
         T f0 = s[0], f1 = s[1], f2 = -s[2];  // f^I
         T a = c2 * E + C * ir;
         T rf = rx * f0 + ry * f1 + rz * f2;
         T b = a * rf * ir2;
         T d = a - (T)2 * c2 * E;
-        acc[0] -= d * f0 + b * rx;
-        acc[1] -= d * f1 + b * ry;
-        acc[2] -= d * f2 + b * rz;
+        k0 = -(d * f0 + b * rx);
+        k1 = -(d * f1 + b * ry);
+        k2 = -(d * f2 + b * rz);
         // phi = -2 f3 G_R - 2 y3 f^I . grad G_R
         T f3 = s[2];
         phi = (T)-2 * f3 * C * ir + (T)2 * y3 * al * rf;
@@ -141,9 +200,9 @@ __device__ __forceinline__ void image_term(T rx, T ry, T rz, T r2, const T* s, T
         T rsr = rx * sr0 + ry * sr1 + rz * sr2;
         T tr = s0 + s3 + s5;
         T gk = A * rsr;
-        acc[0] -= gk * rx + Bc * ((T)2 * sr0 + rx * tr);
-        acc[1] -= gk * ry + Bc * ((T)2 * sr1 + ry * tr);
-        acc[2] -= gk * rz + Bc * ((T)2 * sr2 + rz * tr);
+        k0 = -(gk * rx + Bc * ((T)2 * sr0 + rx * tr));
+        k1 = -(gk * ry + Bc * ((T)2 * sr1 + ry * tr));
+        k2 = -(gk * rz + Bc * ((T)2 * sr2 + rz * tr));
         T ga = (T)-15 * C * ir2 * ir2 * ir2 * ir -
                c2 * E * ((T)15 * ir2 * ir2 * ir2 + (T)10 * xi2 * ir2 * ir2 + (T)4 * xi2 * xi2 * ir2);
         // phi = 4 tr dG_R/dx3 - 4 y3 grad grad G_R : S^I
@@ -158,9 +217,9 @@ __device__ __forceinline__ void image_term(T rx, T ry, T rz, T r2, const T* s, T
         // + W_R(r~) v^I
         T v0 = s[0], v1 = s[1], v2 = -s[2];
         T a2 = (T)2 * al;
-        acc[0] += a2 * (v1 * rz - v2 * ry);
-        acc[1] += a2 * (v2 * rx - v0 * rz);
-        acc[2] += a2 * (v0 * ry - v1 * rx);
+        k0 = a2 * (v1 * rz - v2 * ry);
+        k1 = a2 * (v2 * rx - v0 * rz);
+        k2 = a2 * (v0 * ry - v1 * rx);
         // w = 2 (-v2, v1, 0); phi = 2 w . grad G_R; grad phi = 2 grad grad G_R w
         T w0 = (T)-2 * s[1], w1 = (T)2 * s[0];
         T rw = rx * w0 + ry * w1;
@@ -170,9 +229,9 @@ __device__ __forceinline__ void image_term(T rx, T ry, T rz, T r2, const T* s, T
         g1 = u * ry - (T)2 * al * w1;
         g2 = u * rz;
     }
-    acc[0] -= x3 * g0;
-    acc[1] -= x3 * g1;
-    acc[2] += phi - x3 * g2;
+    out[0] = k0 - x3 * g0;
+    out[1] = k1 - x3 * g1;
+    out[2] = k2 + (phi - x3 * g2);
 }
 
 // LDS add of one contribution to a target's accumulator.  All pairs of a
@@ -261,28 +320,35 @@ __global__ void __launch_bounds__(64) k_realspace(RealArgs a, const double* __re
     unsigned long long npair[2] = {0ull, 0ull};  // direct, image (wave-uniform)
     const int nr = a.cg.nr;  // cells of side >= r_c / nr: neighbours within nr cells
     const int lo1 = c1 - nr > 0 ? c1 - nr : 0, hi1 = c1 + nr < n0 - 1 ? c1 + nr : n0 - 1;
+    const unsigned long long live = __builtin_amdgcn_ballot_w64(act);  // lanes with a target
 
     // one batch of sources [mb, mb + nb) of the sorted arrays; IMG: their
     // images (and harmonic corrections) instead of the direct terms; every
-    // pair's contribution is added to its target's accumulator in LDS
-    auto batch = [&](uint32_t mb, int nb, auto img_tag) {
+    // pair's contribution is added to its target's accumulator in LDS.
+    // OWN: the row of cells holds the target's own cell, the only one where
+    // a source can coincide with it (r = 0: excluded, with the self term)
+    auto batch = [&](uint32_t mb, int nb, auto img_tag, auto own_tag) {
         constexpr bool IMG = decltype(img_tag)::value;
+        constexpr bool OWN = decltype(own_tag)::value;
         constexpr int B = IMG ? SBI : SB;
         for (int f = lane; f < nb * SW; f += 64) {
             const int jj = f / SW, c = f - jj * SW;
             sb[f] = c < 3 ? ys[c * N + mb + jj] : ss[(c - 3) * N + mb + jj];
         }
         wave_sync();
+        // every lane forms r^2 for every slot of the batch (slots past nb hold
+        // the previous batch's sources, which the mask drops): no branches,
+        // and the hits are the compare's own lane mask
         int pre = 0;  // wavefront-uniform
 #pragma unroll 4
         for (int j = 0; j < B; ++j) {
-            bool hit = false;
-            if (j < nb) {
-                const double* s = sb + j * SW;
-                const double dx = xd0 - s[0], dy = xd1 - s[1], dz = IMG ? xd2 + s[2] : xd2 - s[2];
-                const double r2 = dx * dx + dy * dy + dz * dz;
-                hit = act && r2 < rc2 && (IMG || r2 > 0.0);
-                if (!IMG && K == STOKESLET && act && r2 == 0.0) {
+            const double* s = sb + j * SW;
+            const double dx = xd0 - s[0], dy = xd1 - s[1], dz = IMG ? xd2 + s[2] : xd2 - s[2];
+            const double r2 = dx * dx + dy * dy + dz * dz;
+            bool in = r2 < rc2;
+            if (!IMG && OWN) {
+                in = in & (r2 > 0.0);
+                if (K == STOKESLET && act && j < nb && r2 == 0.0) {
                     // self interaction: limit of S_R - S at r = 0 is -(4 xi / sqrt(pi)) I
                     const double cs = 4.0 * a.xi / 1.7724538509055160273;
                     self[0] -= cs * s[3];
@@ -290,7 +356,12 @@ __global__ void __launch_bounds__(64) k_realspace(RealArgs a, const double* __re
                     self[2] -= cs * s[5];
                 }
             }
-            const unsigned long long m = __ballot(hit);
+            const bool hit = in & act & (j < nb);
+            // (the lane mask of the compare itself: a ballot of the bool
+            // would form it again from a select and a compare)
+            unsigned long long m = 0ull;
+            if (j < nb) m = (IMG || !OWN ? __builtin_amdgcn_fcmp(r2, rc2, 4 /* ordered < */)
+                                         : __builtin_amdgcn_ballot_w64(in)) & live;
             const int below = (int)__builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32),
                                                              __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
             if (hit) plist[pre + below] = (uint16_t)(lane | (j << 6));
@@ -335,8 +406,13 @@ __global__ void __launch_bounds__(64) k_realspace(RealArgs a, const double* __re
                 if (cc2 < 0 || cc2 >= n1) continue;
                 long long row = ((long long)cc3 * n1 + cc2) * n0;
                 uint32_t s0 = a.src_off[row + lo1], s1 = a.src_off[row + hi1 + 1];
-                for (uint32_t mb = s0; mb < s1; mb += SB)
-                    batch(mb, (int)min((uint32_t)SB, s1 - mb), std::false_type());
+                if (d2 == 0 && d3 == 0) {
+                    for (uint32_t mb = s0; mb < s1; mb += SB)
+                        batch(mb, (int)min((uint32_t)SB, s1 - mb), std::false_type(), std::true_type());
+                } else {
+                    for (uint32_t mb = s0; mb < s1; mb += SB)
+                        batch(mb, (int)min((uint32_t)SB, s1 - mb), std::false_type(), std::false_type());
+                }
             }
         }
     }
@@ -352,7 +428,7 @@ __global__ void __launch_bounds__(64) k_realspace(RealArgs a, const double* __re
                 long long row = ((long long)cc3 * n1 + cc2) * n0;
                 uint32_t s0 = a.src_off[row + lo1], s1 = a.src_off[row + hi1 + 1];
                 for (uint32_t mb = s0; mb < s1; mb += SBI)
-                    batch(mb, (int)min((uint32_t)SBI, s1 - mb), std::true_type());
+                    batch(mb, (int)min((uint32_t)SBI, s1 - mb), std::true_type(), std::false_type());
             }
         }
     }

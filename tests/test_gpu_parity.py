@@ -79,6 +79,23 @@ def test_fp64_parity_small(ctx, family):
 
 
 @pytest.mark.parametrize("family", FAMILIES)
+@pytest.mark.parametrize("tol", [1e-12, 1e-13])
+def test_fp64_parity_tight_tolerance(ctx, family, tol):
+    """FP64 below the workloads' 1e-10: the real-space pair terms (the
+    hardware estimates of 1/sqrt and 1/x with one refinement step, the own
+    exponential) and the spreading and quadrature at supports of 24-30
+    nodes, still within tol of the oracle."""
+    n = 400
+    y, s = workloads.make(family, n, 1803)
+    xi, rc = _params(family, n, tol, nb=120)
+    u, rep = _run(ctx, family, y, s, y, xi, rc, tol, prec=1, alias=True)
+    ref = oracle.halfspace(family, y, s, y)
+    err = oracle.rel_rms(ref, u)
+    print(f"{family}: FP64 tol {tol:g} N={n} M={rep.M} P={rep.P} Mt={rep.Mt} dgrid={rep.dgrid} rel-RMS={err:.3e}")
+    assert err <= tol
+
+
+@pytest.mark.parametrize("family", FAMILIES)
 def test_fp32_parity_small(ctx, family):
     n = 400
     y, s = workloads.make(family, n, 1802)

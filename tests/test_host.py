@@ -361,3 +361,83 @@ def test_stresslet_density_chosen_by_cost():
     assert plan(1_000_000, 2000, 1e-5).dgrid == 0
     r = plan(1_000_000, 300, 1e-5)
     assert r.dgrid == 1 and r.P == 14 and r.Ps == 20
+
+
+def test_plans_over_the_whole_tolerance_range():
+    """Every family has an FP64 plan down to tol 1e-14, the bottom of the
+    documented range.  Auto mode takes the correction density only from tol
+    1e-12 up (its rounding floor is about 1e-13) and where its support fits:
+    the stresslet's needs P + 8 spreading nodes, at most 30."""
+    n = 400
+    for fam in ("stokeslet", "stresslet", "rotlet"):
+        for tol in (1e-12, 1e-13, 1e-14):
+            rc = (120 * 3.0 / (4.0 * math.pi * n)) ** (1.0 / 3.0)
+            xi = ehs.xi_for_cutoff(fam, rc, tol / 2)
+            p = ehs.plan_query(fam, n, n, (0, 0, 0), (1, 1, 1), 1.0 * n, xi, rc, tol, 1)
+            assert p.P <= 30 and p.Pg <= 30 and p.Ps <= 30
+            if tol < 1e-12 or (fam == "stresslet" and p.P + 8 > 30):
+                assert p.dgrid == 0
+
+
+def _pair_exp_steps():
+    """The constants of the FP64 real-space exponential, read from the source."""
+    text = open(os.path.join(ROOT, "paper_1802_07844_amd", "csrc", "realspace.hip")).read()
+    body = text.split("static __device__ __forceinline__ double exp(double y)", 1)[1].split("\n    }\n", 1)[0]
+    log2e = float(re.search(r"rint\(y \* ([0-9.eE+-]+)\)", body).group(1))
+    ln2 = [float(v) for v in re.findall(r"fma\(-k, ([0-9.eE+-]+),", body)]
+    first = re.search(r"double p = ([0-9.]+) / ([0-9.]+);", body)
+    coef = [float(first.group(1)) / float(first.group(2))]
+    for num in re.findall(r"p = fma_sc\(p, f, ([^)]+?)\);", body):
+        parts = num.split("/")
+        coef.append(float(parts[0]) / float(parts[1]) if len(parts) == 2 else float(parts[0]))
+    return log2e, ln2, coef
+
+
+def _fma(a, b, c):
+    # a fused multiply-add: the product and sum in 64-bit-mantissa
+    # arithmetic, rounded once to double
+    return (np.longdouble(a) * np.longdouble(b) + np.longdouble(c)).astype(np.float64)
+
+
+def test_pair_arithmetic_of_the_real_space_sum():
+    """The FP64 real-space kernels take 1/sqrt(x) and 1/x from the hardware
+    estimates and one third-order Newton step, and e^y from a reduction by
+    ln 2 and a Taylor series to f^12.  The same steps on the host, from
+    estimates perturbed by 2^-21 (four times the estimates' stated error)
+    and on every argument a pair can produce: within 4 ulp of the exact
+    values, so the kernels' pair terms are as accurate as with the library
+    functions."""
+    import mpmath as mp
+
+    mp.mp.dps = 40
+    g = np.random.default_rng(11)
+    eps = np.finfo(np.float64).eps
+    # 1/sqrt(x) over the squared distances of pairs (positions in a unit box)
+    x = np.concatenate([10.0 ** g.uniform(-12, 0.5, 4000), [1e-12, 1.0, 3.0]])
+    for d in (2.0 ** -21, -(2.0 ** -21)):
+        y = (1.0 / np.sqrt(x)) * (1.0 + d)
+        e = _fma(-x * y, y, 1.0)
+        r = _fma(y * e, _fma(e, 0.375, 0.5), y)
+        ref = np.array([float(1 / mp.sqrt(mp.mpf(float(v)))) for v in x])
+        assert np.max(np.abs(r - ref) / ref) <= 4 * eps
+    # 1/x for x = 1 + xi r / 2 in [1, 8]
+    x = np.concatenate([g.uniform(1.0, 8.0, 4000), [1.0, 8.0]])
+    for d in (2.0 ** -21, -(2.0 ** -21)):
+        y = (1.0 / x) * (1.0 + d)
+        e = _fma(-x, y, 1.0)
+        r = _fma(y * e, 1.0 + e, y)
+        assert np.max(np.abs(r - 1.0 / x) * x) <= 4 * eps
+    # e^y for y = -(xi r)^2 down to -(6.5)^2 and beyond
+    log2e, ln2, coef = _pair_exp_steps()
+    assert len(ln2) == 2 and len(coef) == 13
+    assert abs(ln2[0] + ln2[1] - math.log(2.0)) < 1e-25 + 1e-16 * math.log(2.0)
+    y = np.concatenate([-g.uniform(0.0, 60.0, 4000), [0.0, -1e-300, -42.25, -60.0]])
+    k = np.rint(y * log2e)
+    f = _fma(-k, ln2[0], y)
+    f = _fma(-k, ln2[1], f)
+    p = np.full_like(f, coef[0])
+    for c in coef[1:]:
+        p = _fma(p, f, c)
+    r = np.ldexp(p, k.astype(int))
+    ref = np.array([float(mp.exp(mp.mpf(float(v)))) for v in y])
+    assert np.max(np.abs(r - ref) / ref) <= 4 * eps
