@@ -203,7 +203,13 @@ hipError_t launch_records(int family, int cm, const double* y, const double* s, 
 //   w'(d) = -2 a d w(d),  w''(d) = (4 a^2 d^2 - 2 a) w(d),  d = x_g - z.
 // ---------------------------------------------------------------------------
 // records staged in LDS per chunk: few, so that the LDS leaves room for many
-// one-wavefront blocks per CU (32 records allowed two per SIMD; 8 allow eight)
+// one-wavefront blocks per CU (32 records allowed two per SIMD; 8 allow eight).
+// Tiles of 8 x 8 x 4 nodes for dense point sets: the accumulators of 4 nodes
+// per lane (28 FP64 values for the stokeslet's 7 grids) leave registers for 5
+// wavefronts per SIMD, where 8 nodes per lane allowed 3, and the other
+// wavefronts hide the records' latency (clustered N = 4e6 stokeslet: 120 ->
+// 88 ms, with the strengths held in registers; 2 nodes per lane visit too
+// many records).  Sparse sets keep 8 nodes per lane (the planner decides).
 constexpr int SP_CHUNK = 8;
 
 template <typename T, int K, int TZ, int CM>
@@ -257,14 +263,23 @@ __global__ void __launch_bounds__(64) k_spread(GridArgs g, const T* __restrict__
                         const T wx = w[dx], wy = w[P + dy];
                         const T wxy = wx * wy;
                         const T* off = w + 3 * P;
-                        const T* cv = off + 3;
+                        // the strengths used at every node in registers: one
+                        // LDS read each per record, not one per node (the
+                        // density's coefficients enter once per record; with
+                        // 8 nodes per lane the density keeps them in LDS, which
+                        // holds its registers at 5 wavefronts per SIMD)
+                        constexpr int NH = CM == CM_GRIDS ? ncA + ncB : (TZ == 4 ? ncA : 0);
+                        T cvh[NH > 0 ? NH : 1];
+#pragma unroll
+                        for (int c = 0; c < NH; ++c) cvh[c] = off[3 + c];
+                        auto cv = [&](int c) -> T { return c < NH ? cvh[c < NH ? c : 0] : off[3 + c]; };
                         const bool img = hdr[3] != 0;
                         // D: per-column factors of w(z), w'(z), w''(z)
                         T fa = 0, fb = 0, fc = 0;
                         if (CM == CM_DENSITY && img) {
                             const T ex = off[0] + (T)dx * hh, ey = off[1] + (T)dy * hh;
                             const T dwx = -2 * a2 * ex * wx, dwy = -2 * a2 * ey * wy;
-                            const T* c = cv + ncA;
+                            const T* c = off + 3 + ncA;
                             if (K == STOKESLET) {
                                 fa = c[0] * wxy + c[1] * dwx * wy + c[2] * wx * dwy;
                                 fb = c[3] * wxy;
@@ -285,7 +300,7 @@ __global__ void __launch_bounds__(64) k_spread(GridArgs g, const T* __restrict__
                                 const T wz = w[2 * P + dz];
                                 const T wv = wxy * wz;
 #pragma unroll
-                                for (int c = 0; c < ncA; ++c) acc[z][c] += wv * cv[c];
+                                for (int c = 0; c < ncA; ++c) acc[z][c] += wv * cv(c);
                                 if (img) {
                                     if constexpr (CM == CM_DENSITY) {
                                         const T ez = off[2] + (T)dz * hh;
@@ -295,7 +310,7 @@ __global__ void __launch_bounds__(64) k_spread(GridArgs g, const T* __restrict__
                                         acc[z][ncA] += dsum;
                                     } else if constexpr (CM == CM_GRIDS) {
 #pragma unroll
-                                        for (int c = 0; c < ncB; ++c) acc[z][ncA + c] += wv * cv[ncA + c];
+                                        for (int c = 0; c < ncB; ++c) acc[z][ncA + c] += wv * cv(ncA + c);
                                     }
                                 }
                             }
@@ -320,17 +335,28 @@ __global__ void __launch_bounds__(64) k_spread(GridArgs g, const T* __restrict__
     }
 }
 
-template <typename T, int CM>
-static void launch_spread_t(int family, GridArgs g, const T* rec, const uint32_t* toff, T* grids, long long cs,
-                            hipStream_t st)
+template <typename T, int CM, int TZ>
+static void launch_spread_tz(int family, GridArgs g, const T* rec, const uint32_t* toff, T* grids, long long cs,
+                             hipStream_t st)
 {
     dim3 grid(g.nt[0], g.nt[1], g.nt[2]);
     size_t lds = (size_t)SP_CHUNK * record_stride(family, g.P, sizeof(T)) * sizeof(T);
     switch (family) {
-        case STOKESLET: hipLaunchKernelGGL((k_spread<T, STOKESLET, 8, CM>), grid, dim3(64), lds, st, g, rec, toff, grids, cs); break;
+        case STOKESLET: hipLaunchKernelGGL((k_spread<T, STOKESLET, TZ, CM>), grid, dim3(64), lds, st, g, rec, toff, grids, cs); break;
         case STRESSLET: hipLaunchKernelGGL((k_spread<T, STRESSLET, 4, CM>), grid, dim3(64), lds, st, g, rec, toff, grids, cs); break;
-        default: hipLaunchKernelGGL((k_spread<T, ROTLET, 8, CM>), grid, dim3(64), lds, st, g, rec, toff, grids, cs); break;
+        default: hipLaunchKernelGGL((k_spread<T, ROTLET, TZ, CM>), grid, dim3(64), lds, st, g, rec, toff, grids, cs); break;
     }
+}
+
+template <typename T, int CM>
+static void launch_spread_t(int family, GridArgs g, const T* rec, const uint32_t* toff, T* grids, long long cs,
+                            hipStream_t st)
+{
+    // the tile depth is the planner's (the stresslet's is always 4)
+    if (g.tile[2] == 8)
+        launch_spread_tz<T, CM, 8>(family, g, rec, toff, grids, cs, st);
+    else
+        launch_spread_tz<T, CM, 4>(family, g, rec, toff, grids, cs, st);
 }
 
 template <typename T>

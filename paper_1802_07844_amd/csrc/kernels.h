@@ -146,6 +146,9 @@ hipError_t launch_realspace(int family, const RealArgs& a, const double* ys, con
 // ---------------------------------------------------------------------------
 // spreading and gathering
 // ---------------------------------------------------------------------------
+// spreading tiles: 8 x 8 x tile[2] nodes, one wavefront each (lane = an x3
+// column of tile[2] nodes); tile[2] is 4 or 8 (chosen by the planner)
+
 struct GridArgs {
     int Mt, P;
     double o[3];        // grid origin

@@ -479,7 +479,16 @@ inline int make_plan(const PlanInput& in, Plan* out)
     g.a2 = 2 * xi * xi / eta;
     g.mP = magic_of((unsigned)p.Ps);
     g.pref = std::pow(2 * xi * xi / (pi * eta), 1.5);
-    int tz = in.family == 1 ? 4 : 8;
+    // spreading tile depth: 4 x3 nodes per lane where the points are dense
+    // (more wavefronts per SIMD hide the records' latency), 8 where they are
+    // sparse (fewer record visits); the stresslet's 13 grids always take 4.
+    // Measured (ms, depth 8 -> 4): clustered N = 4e6 120 -> 87 (18.5 points
+    // per 8^3 tile), N = 1e6 rotlet 24.7 -> 17.9 (31), stresslet 42.6 ->
+    // 35.7; N = 1e5 at ~415 neighbours 2.62 -> 2.84 (5.1) and at ~30
+    // neighbours 3.6 -> 4.5 (0.46)
+    const double per_tile8 = (in.free ? 1.0 : 2.0) * (double)in.N /
+                             ((double)((Mt + 7) / 8) * ((Mt + 7) / 8) * ((2 * Mt + 7) / 8));
+    int tz = (in.family == 1 || per_tile8 >= 10.0) ? 4 : 8;
     int dims[3] = {Mt, Mt, 2 * Mt};
     int tl[3] = {8, 8, tz};
     p.ntiles = 1;
