@@ -325,6 +325,15 @@ def _serve_rc(kernel, n, tol):
     return min(rc, 0.45)
 
 
+_T0 = time.perf_counter()
+
+
+def progress(msg):
+    """One line per finished step of the run, on stderr (the JSON line stays
+    alone on stdout)."""
+    print(f"[bench {time.perf_counter() - _T0:7.1f} s] {msg}", file=sys.stderr, flush=True)
+
+
 def serve_bench(args, ehs, workloads, torch, np):
     """Serving stream: Poisson arrivals of mixed requests through one ehs.Server."""
     import queue
@@ -398,6 +407,8 @@ def serve_bench(args, ehs, workloads, torch, np):
         pts += stream[i]["n"]
         t_end = max(t_end, time.perf_counter())
         rows.append((i, u, st))
+        if len(rows) % 250 == 0:
+            progress(f"serving: {len(rows)} requests done")
     th.join()
     stats = srv.stats()
     # rel-RMS against the oracle on sampled targets of a few requests
@@ -489,6 +500,7 @@ def main():
     head = args.workload
     fam, layout, n, prec, tol, rcr = WORKLOADS[head]
     res, u = R.run(head, args.steps, args.warmup)
+    progress(f"{head}: {res['ms_per_step']:.1f} ms per step")
     rec = {"metric": "points/sec at rel-RMS 1e-10 (FP64)" if prec == 1 else "points/sec at rel-RMS 1e-5 (FP32)",
            "value": res["value"], "unit": "points/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
            "ms_per_step": res["ms_per_step"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
@@ -507,6 +519,7 @@ def main():
         r, uu = R.run(name, steps, min(args.warmup, 2))
         r["workload"] = describe(name)
         checks.append((r, name, uu))
+        progress(f"{name}: {r['ms_per_step']:.1f} ms per step")
         return r
 
     if "fp32" in legs and head == "c4_fp64":
@@ -536,6 +549,7 @@ def main():
         r, uu = R.run("c2_fp64", args.leg_steps, min(args.warmup, 2), xi=tres["xi"], rc=tres["r_c"])
         r["workload"] = describe("c2_fp64") + " at the (xi, r_c) of the runtime parameter search"
         r["search"] = [{"xi": a, "r_c": b, "ms": c} for a, b, c in tres["trace"]]
+        progress(f"tuned: {r['ms_per_step']:.1f} ms per step after {len(tres['trace'])} candidates")
         r["neighbours"] = 4.0 / 3.0 * math.pi * tres["r_c"] ** 3 * nn
         checks.append((r, "c2_fp64", uu))
         extra["tuned"] = r
@@ -548,33 +562,38 @@ def main():
         # the headline workload's targets against all its sources
         y, s, yd, sd, seed = R.inputs(head)
         cores = oracle.max_threads()
-        # size the sample from probes of two sizes: a call costs a fixed part
-        # (its pass over all N sources) plus a part per target
+        # double a seeded sample of targets until one call takes at least
+        # half the requested time (a call also pays a fixed pass over all N
+        # sources, so the time is not proportional to the sample at first);
+        # the last call is the measurement
         oracle.halfspace(fam, y, s, y[:8])  # thread pool start-up
-        tt = []
-        for S in (32, 128):
+        order = workloads.rng(seed + 2000).permutation(n)
+        S = 32
+        while True:
+            idx = np.sort(order[:S])
             t0 = time.perf_counter()
-            oracle.halfspace(fam, y, s, y[:S])
-            tt.append(time.perf_counter() - t0)
-        per = max((tt[1] - tt[0]) / 96.0, 1e-9)
-        fixed = max(tt[0] - 32 * per, 0.0)
-        S = int(max(128, min(n, (args.cpu_seconds - fixed) / per)))
-        idx = np.sort(workloads.rng(seed + 2000).choice(n, size=S, replace=False))
-        t0 = time.perf_counter()
-        oracle.halfspace(fam, y, s, y[idx])
-        tc = time.perf_counter() - t0
+            oracle.halfspace(fam, y, s, y[idx])
+            tc = time.perf_counter() - t0
+            progress(f"oracle timing: {S} targets in {tc:.1f} s")
+            if tc >= 0.5 * args.cpu_seconds or S >= min(n, 1 << 20):
+                break
+            S = min(n, 1 << 20, 2 * S if tc > 0.25 * args.cpu_seconds else 4 * S)
         rec["cpu_baseline"] = {"value": S / tc, "unit": "points/s", "cores": cores, "kind": "oracle",
                                "sample": f"{S} of {n} targets against all {n} sources ({describe(head)}), "
                                          f"FP64 direct sum, {tc:.1f} s"}
+        progress(f"oracle timing sample: {S} targets, {tc:.1f} s")
         for r, name, uu in checks:
             r["oracle"] = R.check(name, uu, args.oracle_sample)
+            progress(f"{name}: oracle rel-RMS {r['oracle']['rel_rms']:.2e}")
         rec["rel_rms"] = rec["oracle"]["rel_rms"]
     if not args.no_serve:
         R.ctx.close()
         R.data.clear()
         checks.clear()
         torch.cuda.empty_cache()
+        progress("serving stream")
         rec["serving"] = serve_bench(args, ehs, workloads, torch, np)
+        progress("serving done")
     print(json.dumps(rec))
 
 
