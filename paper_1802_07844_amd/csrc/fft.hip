@@ -835,21 +835,6 @@ hipError_t launch_inv_x(const cplx<T>* in, T* out, const PassArgs& a, int ncomp,
     return hipGetLastError();
 }
 
-size_t z_lds_bytes(int family, int cm, int Mt, int Q, size_t esz)
-{
-    int ncin = ncin_for(family, cm);
-    int nout = ncout_for(esz == 8 ? 1 : 2, cm);
-    int nl = ncin > nout ? ncin : nout;
-    int nq = 4 * Mt / Q;
-    return ((size_t)nl * (nq + 1) + nq) * 2 * esz;  // lines and the nq - 1 stage twiddles
-}
-
-bool z_resident_ok(int family, int Mt)
-{
-    (void)family;
-    return 2 * Mt <= 3 * 512;
-}
-
 template <typename T, int K, int CM, int EPL>
 static void launch_z_e(cplx<T>* zb, cplx<T>* zout, const ZArgs& a, hipStream_t st)
 {

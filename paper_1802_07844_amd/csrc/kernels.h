@@ -61,9 +61,23 @@ struct EvenArgs {
     double scale;
 };
 
-size_t z_lds_bytes(int family, int cm, int Mt, int Q, size_t esz);
+// LDS of one block of the fused x3 pass: its component lines of 4 Mt / Q
+// points and the nq - 1 stage twiddles (host arithmetic, also the planner's)
+inline size_t z_lds_bytes(int family, int cm, int Mt, int Q, size_t esz)
+{
+    int ncin = ncin_for(family, cm);
+    int nout = ncout_for(esz == 8 ? 1 : 2, cm);
+    int nl = ncin > nout ? ncin : nout;
+    int nq = 4 * Mt / Q;
+    return ((size_t)nl * (nq + 1) + nq) * 2 * esz;
+}
 size_t pass_lds(int Mt, int B, size_t esz);
-bool z_resident_ok(int family, int Mt);
+// the x3 pass writes its output over its input slab (lines of up to 1536 points)
+inline bool z_resident_ok(int family, int Mt)
+{
+    (void)family;
+    return 2 * Mt <= 3 * 512;
+}
 
 template <typename T>
 hipError_t launch_fwd_x(const T* in, cplx<T>* out, const PassArgs& a, int ncomp, hipStream_t st);
