@@ -26,7 +26,9 @@
  *    pointer after the call returns;
  *  - `stream` is a hipStream_t passed as void* (NULL: the default stream).
  *    The call returns after enqueueing; results are valid once the stream has
- *    synchronised.  One blocking device-to-host read (384 bytes: the bounding
+ *    synchronised.  Part of the work may run on a stream of the context's
+ *    own (EHS_OPT_OVERLAP), forked from and joined back into `stream` by
+ *    events, so that work ordered after the call on `stream` sees all of it.  One blocking device-to-host read (384 bytes: the bounding
  *    box, the validation counts, the strength measure and a histogram of the
  *    target heights) happens inside every call; a cache miss of the truncated-kernel precompute adds one
  *    more synchronisation;
@@ -81,6 +83,11 @@ extern "C" {
                                      productions fail with EHS_EHIP before anything is launched */
 #define EHS_OPT_CELL_REACH 10 /* 1..3: real-space cells of side >= r_c / value; 0 (default): chosen
                                  from the targets' density (ehs_report.occupancy) */
+#define EHS_OPT_OVERLAP 11  /* 1 (default): the real-space sum runs on a stream of the context's own,
+                               beside the grid stages on the caller's stream (joined by events before
+                               the quadrature; the results are the same bit for bit); 0: everything on
+                               the caller's stream.  With timing on, ms_stage[EHS_ST_REAL] is then the
+                               overlapped sum's own time and the stages no longer add up to the total */
 
 /* stage indices of ehs_report.ms_stage */
 #define EHS_ST_BBOX 0       /* bounding box + validation reduction and its readback */

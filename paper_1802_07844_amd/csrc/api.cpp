@@ -561,7 +561,35 @@ int run(ehs_ctx* c, Plan& p, const Octants& oct, const double* y, const double* 
         c->pairs_dev = ra.pairs;
         HIPCHK(fill_u32(reinterpret_cast<uint32_t*>(ra.pairs), 0u, 4, st));
     }
-    HIPCHK(launch_realspace<T>(p.family, ra, ys, ss, xs, upart, p.max_chunks, st));
+    // The real-space sum (bound by the vector ALU) runs on the side stream
+    // beside the spreading and the transforms (bound by memory and latency);
+    // they share only read-only inputs, and the quadrature, which adds the
+    // real-space part, waits for it.  Every return after the fork makes the
+    // caller's stream wait for the side stream (the workspace is reused).
+    const bool ovl = c->overlap && c->side;
+    c->last_overlap = ovl && c->opt_timing && c->ev_ok;
+    struct Join {
+        ehs_ctx* c;
+        hipStream_t st;
+        bool armed;
+        void now()
+        {
+            if (!armed) return;
+            armed = false;
+            hipEventRecord(c->join, c->side);
+            hipStreamWaitEvent(st, c->join, 0);
+        }
+        ~Join() { now(); }
+    } join{c, st, false};
+    hipStream_t rst = st;
+    if (ovl) {
+        HIPCHK(hipEventRecord(c->fork, st));
+        HIPCHK(hipStreamWaitEvent(c->side, c->fork, 0));
+        join.armed = true;
+        rst = c->side;
+    }
+    HIPCHK(launch_realspace<T>(p.family, ra, ys, ss, xs, upart, p.max_chunks, rst));
+    if (c->last_overlap) HIPCHK(hipEventRecord(c->ev_rs_end, rst));
     rec_ev(EHS_ST_SPREAD);
 
     // -- spreading
@@ -687,6 +715,8 @@ int run(ehs_ctx* c, Plan& p, const Octants& oct, const double* y, const double* 
     pa.cs_out = csR;
     pa.l3lo = p.l3lo;
     HIPCHK(launch_inv_x<T>(Yc, X, pa, ncout_for(p.prec, cm), st));
+    if (c->last_overlap) HIPCHK(hipEventRecord(c->ev_pre_join, st));
+    join.now();
     rec_ev(EHS_ST_GATHER);
 
     // -- quadrature at the targets and FP64 combination with the real part:
@@ -846,6 +876,15 @@ int finish_report(ehs_ctx* c, const Plan& p, size_t need, ehs_report* rep)
         float ms = 0.f;
         hipEventElapsedTime(&ms, c->ev[i], c->ev[i + 1]);
         rep->ms_stage[i] = ms;
+    }
+    if (c->last_overlap) {
+        // the real-space sum on the side stream; the inverse x1 pass ends
+        // where the caller's stream starts waiting for it
+        float mr = 0.f, mi = 0.f;
+        hipEventElapsedTime(&mr, c->ev[EHS_ST_REAL], c->ev_rs_end);
+        hipEventElapsedTime(&mi, c->ev[EHS_ST_INVX], c->ev_pre_join);
+        rep->ms_stage[EHS_ST_REAL] = mr;
+        rep->ms_stage[EHS_ST_INVX] = mi;
     }
     float tot = 0.f;
     hipEventElapsedTime(&tot, c->ev[EHS_ST_BBOX], c->ev[EHS_ST_TOTAL]);
@@ -1071,6 +1110,15 @@ int ehs::ctx_init(ehs_ctx* c, int device, Tables* shared)
         c->host_bbox = nullptr;
         return EHS_ENOMEM;
     }
+    // the real-space sum's stream (default priority) and its fork / join
+    // events; without them the sum runs on the caller's stream
+    if (hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&c->fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->join, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreate(&c->ev_rs_end) != hipSuccess || hipEventCreate(&c->ev_pre_join) != hipSuccess) {
+        hipGetLastError();
+        c->overlap = 0;
+    }
     return EHS_OK;
 }
 
@@ -1098,6 +1146,12 @@ void ehs::ctx_release(ehs_ctx* c)
     c->sev.clear();
     if (c->host_bbox) hipHostFree(c->host_bbox);
     c->host_bbox = nullptr;
+    for (hipEvent_t* e : {&c->fork, &c->join, &c->ev_rs_end, &c->ev_pre_join}) {
+        if (*e) hipEventDestroy(*e);
+        *e = nullptr;
+    }
+    if (c->side) hipStreamDestroy(c->side);
+    c->side = nullptr;
 }
 
 extern "C" {
@@ -1168,6 +1222,10 @@ int ehs_set_option(ehs_ctx* c, int option, double value)
         case EHS_OPT_CELL_REACH:
             if (value < 0 || value > 3) return EHS_EINVAL;
             c->force_nr = (int)value;
+            return EHS_OK;
+        case EHS_OPT_OVERLAP:
+            if (value != 0 && value != 1) return EHS_EINVAL;
+            c->overlap = (value == 1 && c->side) ? 1 : 0;
             return EHS_OK;
         default: return EHS_EINVAL;
     }

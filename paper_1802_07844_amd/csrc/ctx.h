@@ -81,6 +81,13 @@ struct ehs_ctx {
     int fail_precompute = 0;                 // test hook: the next octant production fails (EHS_EHIP)
     int force_nr = 0;                        // real-space cell reach (0: by density)
     unsigned long long* pairs_dev = nullptr; // the last timed evaluation's pair counters (workspace)
+    // the real-space sum runs on `side`, beside the grid stages on the
+    // caller's stream (fork and join by events); created with the context
+    int overlap = 1;
+    hipStream_t side = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
+    hipEvent_t ev_rs_end = nullptr, ev_pre_join = nullptr;  // timing of the overlapped sum
+    bool last_overlap = false;               // the last timed evaluation overlapped
 };
 
 namespace ehs {

@@ -441,3 +441,32 @@ def test_pair_arithmetic_of_the_real_space_sum():
     r = np.ldexp(p, k.astype(int))
     ref = np.array([float(mp.exp(mp.mpf(float(v)))) for v in y])
     assert np.max(np.abs(r - ref) / ref) <= 4 * eps
+
+
+def test_header_constants_match_the_binding():
+    """Every option, error code, stage index and size constant that
+    include/ehs.h defines has the same value in the Python binding."""
+    text = open(os.path.join(ROOT, "include", "ehs.h")).read()
+    defs = {}
+    for name, val in re.findall(r"#define (EHS_\w+)\s+(\(\(size_t\)\d+ << \d+\)|\(?[-0-9]+\)?)", text):
+        if "<<" in val:
+            a, b = re.findall(r"(\d+) << (\d+)", val)[0]
+            defs[name] = int(a) << int(b)
+        else:
+            defs[name] = int(val.strip("()"))
+    opts = {k: v for k, v in defs.items() if k.startswith("EHS_OPT_")}
+    assert len(opts) >= 12
+    for k, v in opts.items():
+        assert getattr(ehs, k[4:]) == v, k
+    for k in ("EHS_OK", "EHS_EINVAL", "EHS_EDOMAIN", "EHS_ERANGE", "EHS_ENOMEM", "EHS_EHIP", "EHS_ETIMEDOUT",
+              "EHS_ETOOBIG"):
+        assert getattr(ehs, k) == defs[k], k
+    stages = {k[7:].lower(): v for k, v in defs.items() if k.startswith("EHS_ST_")}
+    assert defs["EHS_NSTAGES"] == len(ehs.STAGES)
+    names = {"bbox": "bbox", "precomp": "precompute", "bin": "binning", "real": "realspace", "spread": "spread",
+             "fwdx": "fwd_x", "fwdy": "fwd_y", "zscale": "z_scale", "invy": "inv_y", "invx": "inv_x",
+             "gather": "gather", "total": "total"}
+    for k, v in stages.items():
+        assert ehs.STAGES[v] == names[k], k
+    assert ehs.ARENA_MIN_BYTES == defs["EHS_ARENA_MIN_BYTES"]
+    assert ehs.NOALLOC_SCRATCH_BYTES == defs["EHS_NOALLOC_SCRATCH_BYTES"]
