@@ -32,6 +32,10 @@
  *    box, the validation counts, the strength measure and a histogram of the
  *    target heights) happens inside every call; a cache miss of the truncated-kernel precompute adds one
  *    more synchronisation;
+ *  - sizes: 1 <= N < 2^30 sources and 0 <= T < 2^31 targets (else
+ *    EHS_EINVAL, before anything is allocated); the workspace, about
+ *    45 GB at N = T = 2^24 with ~2000 neighbours at tol 1e-6, bounds N
+ *    before that;
  *  - outputs are overwritten, never accumulated;
  *  - a context is not thread safe and calls on one context must not overlap
  *    (they share the context's workspace);

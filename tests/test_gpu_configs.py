@@ -119,6 +119,24 @@ def test_c4_clustered_n4m(ctx, prec, tol, rc):
     _check("stokeslet", y, f, u, rep, tol, 512, 13, "C4")
 
 
+def test_largest_problem_in_the_suite(ctx):
+    """N = 2^24 = 16.8e6 uniform stokeslet sources = targets (~2000
+    neighbours, FP64, tol 1e-6, a 44 GB workspace): four times the largest
+    benchmark, past
+    2^24 keys in every sort and 33.5e6 Gaussian records; checked on a
+    seeded sample of 96 targets against all sources.  (Requests with
+    N >= 2^30 or T >= 2^31 are refused with EHS_EINVAL before anything is
+    allocated; in practice the device memory bounds N first.)"""
+    n = 1 << 24
+    y, f = workloads.uniform_stokeslet(n, workloads.SEED_BASE + 90)
+    tol = 1e-6
+    rc = (2000 * 3.0 / (4.0 * np.pi * n)) ** (1.0 / 3.0)
+    xi = ehs.xi_for_cutoff("stokeslet", rc, tol / 2)
+    u, rep = _eval(ctx, "stokeslet", y, f, xi, rc, tol, 1)
+    print(f"N = 2^24: workspace {rep.workspace_bytes / 2**30:.1f} GiB")
+    _check("stokeslet", y, f, u, rep, tol, 96, 91, "N=2^24")
+
+
 # ---------------------------------------------------------------- edge cases
 
 
