@@ -50,6 +50,11 @@ def _load():
             fn.argtypes = [ctypes.c_int, dp, dp, ctypes.c_long, dp, ctypes.c_long, dp, ctypes.c_int]
         lib.oracle_correction.restype = None
         lib.oracle_correction.argtypes = [ctypes.c_int, dp, dp, dp, dp, dp]
+        lib.oracle_ewald_real.restype = ctypes.c_int
+        lib.oracle_ewald_real.argtypes = [ctypes.c_int, dp, dp, ctypes.c_long, dp, ctypes.c_long, ctypes.c_double,
+                                          ctypes.c_double, dp, ctypes.c_int]
+        lib.oracle_correction_real.restype = None
+        lib.oracle_correction_real.argtypes = [ctypes.c_int, dp, dp, dp, ctypes.c_double, dp, dp]
         lib.oracle_set_mutation.argtypes = [ctypes.c_int]
         lib.oracle_set_mutation.restype = None
         lib.oracle_max_threads.restype = ctypes.c_int
@@ -129,6 +134,32 @@ def correction(kernel: str, y, s, x):
     phi = np.zeros(1)
     g = np.zeros(3)
     lib.oracle_correction(k, _ptr(y[0]), _ptr(s[0]), _ptr(x[0]), _ptr(phi), _ptr(g))
+    return float(phi[0]), g
+
+
+def ewald_real(kernel: str, y, s, x, xi: float, rc: float, nthreads: int = 0) -> np.ndarray:
+    """The real-space part of the Ewald split of the half-space sum (Sec. 4,
+    appendix eq. (kernel_real_parts) and eq. (G_R)): direct pairs within
+    r_c, images and corrections within r_c of the image point, and the
+    stokeslet's self term; same conventions as ``halfspace``."""
+    lib = _load()
+    k, y, s, x = _prep(kernel, y, s, x)
+    u = np.zeros((x.shape[0], 3), dtype=np.float64)
+    rc_ = lib.oracle_ewald_real(k, _ptr(y), _ptr(s), y.shape[0], _ptr(x), x.shape[0], float(xi), float(rc), _ptr(u),
+                                int(nthreads))
+    if rc_ != 0:
+        raise RuntimeError("oracle_ewald_real failed")
+    return u
+
+
+def correction_real(kernel: str, y, s, x, xi: float):
+    """phi and grad phi of one source at one point with G_R = erfc(xi r)/r
+    in place of 1/r."""
+    lib = _load()
+    k, y, s, x = _prep(kernel, y, s, x)
+    phi = np.zeros(1)
+    g = np.zeros(3)
+    lib.oracle_correction_real(k, _ptr(y[0]), _ptr(s[0]), _ptr(x[0]), float(xi), _ptr(phi), _ptr(g))
     return float(phi[0]), g
 
 

@@ -292,3 +292,163 @@ def test_pins_catch_planted_mistakes():
             assert slip > 1e-3 or div > 1e-3, f"mutation {m} not caught (slip {slip}, div {div})"
     finally:
         oracle.set_mutation(0)
+
+
+# ---------------------------------------------------------------------------
+# The real-space part of the Ewald split (oracle.ewald_real): the kernels of
+# the appendix's eq. (kernel_real_parts) and the corrections with
+# G_R = erfc(xi r)/r of eq. (G_R).  Pinned by two limits that the paper fixes:
+#   * xi -> 0 with every pair inside r_c: the real part is the whole sum
+#     (erfc -> 1, the Gaussian terms vanish), so it tends to the direct sum
+#     at rate xi (stokeslet: its self and Gaussian terms) or faster;
+#   * r -> 0 at fixed xi: K_R - K and the corrections with G_R minus those
+#     with G stay finite, with limits from the Taylor series of erf
+#     (Sec. 4: the stokeslet's self term -4 xi/sqrt(pi) f is the first), so
+#     every Gaussian term's coefficient, which cancels a singular part of the
+#     erfc term, is fixed; a wrong one leaves a term of order 1/r or worse.
+# ---------------------------------------------------------------------------
+
+
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_real_part_tends_to_the_whole_sum_as_xi_vanishes(kernel):
+    g = np.random.default_rng(17)
+    y, s = _sources(60, g), _strengths(kernel, 60, g)
+    full = oracle.halfspace(kernel, y, s, y)
+    scale = np.sqrt(np.mean(full ** 2))
+    errs = []
+    for xi in (1e-6, 1e-4):
+        re = oracle.ewald_real(kernel, y, s, y, xi, 1e9)
+        errs.append(np.sqrt(np.mean((re - full) ** 2)) / scale)
+    print(kernel, errs)
+    if kernel == "stokeslet":
+        # linear in xi: the ratio of the two errors is the ratio of the xi
+        assert 50 < errs[1] / errs[0] < 200
+        assert errs[1] < 1e-3
+    else:
+        assert max(errs) < 1e-12
+
+
+def _direct_limit_err(kernel, delta, xi=7.0):
+    """|(K_R - K)(delta n) s - its r -> 0 limit|, relative, for one source
+    (r_c excludes the image) and a random direction n."""
+    c = 2.0 * xi / np.sqrt(np.pi)
+    g = np.random.default_rng(23)
+    y = np.array([[0.3, 0.4, 0.6]])
+    s = g.standard_normal((1, 3 if kernel == "stokeslet" else 6))
+    n = g.standard_normal(3)
+    n /= np.linalg.norm(n)
+    x = y + delta * n
+    d = oracle.ewald_real(kernel, y, s, x, xi, 0.5)[0] - oracle.freespace(kernel, y, s, x)[0]
+    if kernel == "stokeslet":
+        lim = -2.0 * c * s[0]  # -4 xi/sqrt(pi) f, the self term of Sec. 4
+    elif kernel == "stresslet":
+        gv, qv = s[0, :3], s[0, 3:]
+        lim = 2.0 * c * xi ** 2 * (gv * (n @ qv) + (gv @ qv) * n + qv * (n @ gv))
+    else:
+        # W_R - W = 2 (C/r^2 + c E/r - 1/r^2)(v x n); the series of erf and
+        # exp give -(4/3) c xi^2 r (v x n) + O(xi^4 r^3)
+        lim = -(4.0 / 3.0) * c * xi ** 2 * delta * np.cross(np.cross(s[0, :3], s[0, 3:]), n)
+    return np.linalg.norm(d - lim) / max(1.0, np.linalg.norm(lim))
+
+
+def _correction_limit_err(kernel, delta, xi=5.0):
+    """H = G_R - G = -erf(xi r)/r has H(0) = -c, grad H(0) = 0,
+    grad grad H(0) = (2/3) c xi^2 I and zero third derivatives (c =
+    2 xi/sqrt(pi)), so at r~ = x - y^I -> 0 the corrections with G_R and with
+    G differ by closed forms; returns the relative errors of phi and grad phi."""
+    c = 2.0 * xi / np.sqrt(np.pi)
+    h2 = 2.0 * c * xi ** 2 / 3.0
+    g = np.random.default_rng(29)
+    y = np.array([[0.2, 0.7, 0.35]])
+    s = g.standard_normal((1, 3 if kernel == "stokeslet" else 6))
+    ss, y3 = s[0], y[0, 2]
+    n = g.standard_normal(3)
+    n /= np.linalg.norm(n)
+    x = (y[0] * np.array([1.0, 1.0, -1.0]) + delta * n)[None, :]
+    p_r, g_r = oracle.correction_real(kernel, y, s, x, xi)
+    p_0, g_0 = oracle.correction(kernel, y, s, x)
+    flip = np.array([1.0, 1.0, -1.0])
+    if kernel == "stokeslet":
+        lp, lg = 2.0 * c * ss[2], -2.0 * y3 * h2 * ss * flip
+    elif kernel == "stresslet":
+        gI, qI = ss[:3] * flip, ss[3:] * flip
+        lp, lg = -4.0 * y3 * h2 * (gI @ qI), 4.0 * (gI @ qI) * h2 * np.array([0.0, 0.0, 1.0])
+    else:
+        gI, qI = ss[:3] * flip, ss[3:] * flip
+        lp, lg = 0.0, 2.0 * h2 * 2.0 * (ss[5] * gI - ss[2] * qI)
+    return (abs((p_r - p_0) - lp) / max(1.0, abs(lp)),
+            np.linalg.norm((g_r - g_0) - lg) / max(1.0, np.linalg.norm(lg)))
+
+
+def _real_correction_gradient_err(kernel, xi=5.0):
+    """grad phi_R against 4th-order differences of phi_R (both with G_R):
+    ties the first three r-derivatives of G_R to G_R = erfc(xi r)/r itself."""
+    g = np.random.default_rng(31)
+    y = _sources(1, g)
+    s = _strengths(kernel, 1, g)
+    h, worst = 1e-4, 0.0
+    for k in range(6):
+        n = g.standard_normal(3)
+        n /= np.linalg.norm(n)
+        x = y[0] * np.array([1.0, 1.0, -1.0]) + (0.05 + 0.06 * k) * n
+        _, gphi = oracle.correction_real(kernel, y, s, x[None], xi)
+        fd = np.zeros(3)
+        for j in range(3):
+            e = np.zeros(3)
+            e[j] = h
+            v = {m: oracle.correction_real(kernel, y, s, (x + m * e)[None], xi)[0] for m in (2, 1, -1, -2)}
+            fd[j] = (-v[2] + 8 * v[1] - 8 * v[-1] + v[-2]) / (12 * h)
+        worst = max(worst, np.linalg.norm(fd - gphi) / max(1.0, np.linalg.norm(gphi)))
+    return worst
+
+
+def _converges(err, d):
+    """The error against a limit taken at distance d and d/10: a wrong
+    constant or a dropped term that does not vanish as r -> 0 leaves it
+    (nearly) unchanged; the right one falls at least tenfold per decade
+    when it is first order, and to well below the size of the limit."""
+    e1, e2 = err(d), err(d / 10)
+    return e2 <= e1 / 5 and e2 < 5e-2, (e1, e2)
+
+
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_real_kernels_minus_kernels_at_zero_distance(kernel):
+    ok, e = _converges(lambda d: _direct_limit_err(kernel, d), 1e-3)
+    print(kernel, e)
+    assert ok
+
+
+@pytest.mark.parametrize("kernel", KERNELS)
+@pytest.mark.parametrize("part", [0, 1])
+def test_real_corrections_minus_corrections_at_zero_distance(kernel, part):
+    # d from 1e-2 down to 1e-3: below ~3e-4 the cancellation in the third
+    # derivatives of G_R (terms of size 1/r^4) reaches the truncation error
+    ok, e = _converges(lambda d: _correction_limit_err(kernel, d)[part], 1e-2)
+    print(kernel, part, e)
+    assert ok
+
+
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_real_correction_gradient_is_the_gradient_of_its_potential(kernel):
+    err = _real_correction_gradient_err(kernel)
+    print(kernel, err)
+    assert err < 1e-7
+
+
+def test_split_pins_catch_planted_mistakes():
+    """A wrong Gaussian coefficient in S_R (5), T_R (6) or W_R (7), or a
+    dropped term of the second (8) or third (9) r-derivative of G_R, fails
+    one of the pins above."""
+    checks = {
+        5: lambda: not _converges(lambda d: _direct_limit_err("stokeslet", d), 1e-3)[0],
+        6: lambda: not _converges(lambda d: _direct_limit_err("stresslet", d), 1e-3)[0],
+        7: lambda: not _converges(lambda d: _direct_limit_err("rotlet", d), 1e-3)[0],
+        8: lambda: not _converges(lambda d: _correction_limit_err("stokeslet", d)[1], 1e-2)[0],
+        9: lambda: _real_correction_gradient_err("stresslet") > 1e-7,
+    }
+    try:
+        for m, caught in checks.items():
+            oracle.set_mutation(m)
+            assert caught(), f"mutation {m} not caught"
+    finally:
+        oracle.set_mutation(0)
