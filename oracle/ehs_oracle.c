@@ -43,7 +43,7 @@
  * source), the sum depending on them only through g x q.
  *
  * A debug "mutation" switch plants deliberate mistakes (used only by tests
- * that check the pins are sensitive: 1-4 in the direct sum, 5-9 in the
+ * that check the pins are sensitive: 1-4 in the direct sum, 5-10 in the
  * real-space part of the split); it is 0 in normal use.
  */
 #include <math.h>
@@ -361,7 +361,11 @@ static void correction_from(int kernel, const double* y, const double* s, double
  * (the xi -> 0 limit of each is the kernel above):
  *   S_R = 2 (xi E/sqrt(pi) + C/(2r)) (I + n n) - 4 xi E/sqrt(pi) I
  *   T_R[g,q]_j = -(2/r) (3C/r + c (3 + 2 xi^2 r^2) E) n_j (n.g)(n.q)
- *                + c xi^2 2 E (g_j (n.q) + (g.q) n_j + q_j (n.g))
+ *                + 2 c xi^2 E (g_j (r.q) + (g.q) r_j + q_j (r.g))
+ * (the appendix prints unit vectors in the Gaussian term of T_R; only the
+ * vector r itself gives T_R the dimension of T, 1/length^2, and makes
+ * T_R - T = -T_F vanish at r = 0, as the smooth odd Fourier part does, with
+ * the slope -grad T_F(0) that the Fourier multiplier gives)
  *   W_R v = 2 (C/r^2 + c E/r) (v x n),   v = g x q
  * with C = erfc(xi r), E = exp(-xi^2 r^2), c = 2 xi / sqrt(pi). */
 static void kernel_real(int kernel, const double* rv, const double* s, double xi, double sign, double* out)
@@ -378,7 +382,7 @@ static void kernel_real(int kernel, const double* rv, const double* s, double xi
         const double *g = s, *q = s + 3;
         double ng = dot3(n, g), nq = dot3(n, q), gq = dot3(g, q);
         double A = -(2.0 / r) * (3.0 * C / r + c * (3.0 + 2.0 * xi * xi * r * r) * E);
-        double B = (g_mutation == 6 ? 1.0 : 2.0) * c * xi * xi * E;
+        double B = (g_mutation == 6 ? 1.0 : 2.0) * c * xi * xi * E * (g_mutation == 10 ? 1.0 : r);
         for (int i = 0; i < 3; ++i) out[i] += sign * (A * n[i] * ng * nq + B * (g[i] * nq + gq * n[i] + q[i] * ng));
     } else {
         double v[3], vn[3];

@@ -329,8 +329,19 @@ def test_real_part_tends_to_the_whole_sum_as_xi_vanishes(kernel):
 
 
 def _direct_limit_err(kernel, delta, xi=7.0):
-    """|(K_R - K)(delta n) s - its r -> 0 limit|, relative, for one source
-    (r_c excludes the image) and a random direction n."""
+    """|(K_R - K)(delta n) s - its expansion at r -> 0|, relative, for one
+    source (r_c excludes the image) and a random direction n.
+
+    K_R - K = -K_F, and K_F is smooth, so the expansion is -K_F(0) -
+    r.grad K_F(0) + O(r^2), taken from the Fourier multipliers of the
+    appendix, not from the real-space formulas.  The stokeslet's K_F(0) is
+    minus the self term of Sec. 4.  The stresslet's and the rotlet's are odd,
+    so K_F(0) = 0, and the angular averages <k_n k_m> = k^2 delta_nm / 3 and
+    <k_n k_j k_l k_m> = k^4 (sym. deltas) / 15 reduce grad K_F(0) to one
+    radial integral: with B^ = -8 pi/k^4 (biharmonic) and H^ = 4 pi/k^2
+    (harmonic), d_n T_F,jlm(0) = -(4 xi^3/sqrt(pi))(d_nm d_jl + d_nj d_lm +
+    d_nl d_mj) and d_n W_F,jl(0) = (8 xi^3/(3 sqrt(pi))) eps_jln (the rotlet
+    multiplier with the sign fixed by W = 2 eps r / r^3)."""
     c = 2.0 * xi / np.sqrt(np.pi)
     g = np.random.default_rng(23)
     y = np.array([[0.3, 0.4, 0.6]])
@@ -343,11 +354,10 @@ def _direct_limit_err(kernel, delta, xi=7.0):
         lim = -2.0 * c * s[0]  # -4 xi/sqrt(pi) f, the self term of Sec. 4
     elif kernel == "stresslet":
         gv, qv = s[0, :3], s[0, 3:]
-        lim = 2.0 * c * xi ** 2 * (gv * (n @ qv) + (gv @ qv) * n + qv * (n @ gv))
+        lim = 4.0 * xi ** 3 / np.sqrt(np.pi) * delta * (gv * (n @ qv) + (gv @ qv) * n + qv * (n @ gv))
     else:
-        # W_R - W = 2 (C/r^2 + c E/r - 1/r^2)(v x n); the series of erf and
-        # exp give -(4/3) c xi^2 r (v x n) + O(xi^4 r^3)
-        lim = -(4.0 / 3.0) * c * xi ** 2 * delta * np.cross(np.cross(s[0, :3], s[0, 3:]), n)
+        v = np.cross(s[0, :3], s[0, 3:])
+        lim = -8.0 * xi ** 3 / (3.0 * np.sqrt(np.pi)) * delta * np.cross(v, n)
     return np.linalg.norm(d - lim) / max(1.0, np.linalg.norm(lim))
 
 
@@ -435,16 +445,40 @@ def test_real_correction_gradient_is_the_gradient_of_its_potential(kernel):
     assert err < 1e-7
 
 
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_real_part_scales_with_the_kernel(kernel):
+    """K_R depends on r only through xi r and carries the dimension of K
+    (1/length for the stokeslet, 1/length^2 for the stresslet and rotlet),
+    and so do the corrections built from G_R: scaling every position and r_c
+    by lam and xi by 1/lam scales the real-space part by lam^-1 or lam^-2."""
+    print(kernel, _scaling_err(kernel))
+    assert _scaling_err(kernel) < 1e-12
+
+
+def _scaling_err(kernel):
+    g = np.random.default_rng(37)
+    y = _sources(40, g)
+    s = _strengths(kernel, 40, g)
+    x = _sources(30, g)
+    xi, rc, lam = 6.0, 0.35, 2.5
+    d = 1 if kernel == "stokeslet" else 2
+    u1 = oracle.ewald_real(kernel, y, s, x, xi, rc)
+    u2 = oracle.ewald_real(kernel, lam * y, s, lam * x, xi / lam, lam * rc)
+    return np.linalg.norm(u2 * lam ** d - u1) / np.linalg.norm(u1)
+
+
 def test_split_pins_catch_planted_mistakes():
-    """A wrong Gaussian coefficient in S_R (5), T_R (6) or W_R (7), or a
-    dropped term of the second (8) or third (9) r-derivative of G_R, fails
-    one of the pins above."""
+    """A wrong Gaussian coefficient in S_R (5), T_R (6) or W_R (7), a
+    dropped term of the second (8) or third (9) r-derivative of G_R, or unit
+    vectors in the Gaussian term of T_R (10) fail the pins above."""
     checks = {
         5: lambda: not _converges(lambda d: _direct_limit_err("stokeslet", d), 1e-3)[0],
         6: lambda: not _converges(lambda d: _direct_limit_err("stresslet", d), 1e-3)[0],
         7: lambda: not _converges(lambda d: _direct_limit_err("rotlet", d), 1e-3)[0],
         8: lambda: not _converges(lambda d: _correction_limit_err("stokeslet", d)[1], 1e-2)[0],
         9: lambda: _real_correction_gradient_err("stresslet") > 1e-7,
+        10: lambda: (_scaling_err("stresslet") > 1e-12
+                     and not _converges(lambda d: _direct_limit_err("stresslet", d), 1e-3)[0]),
     }
     try:
         for m, caught in checks.items():
