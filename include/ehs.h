@@ -92,6 +92,10 @@ extern "C" {
                                the quadrature; the results are the same bit for bit); 0: everything on
                                the caller's stream.  With timing on, ms_stage[EHS_ST_REAL] is then the
                                overlapped sum's own time and the stages no longer add up to the total */
+#define EHS_OPT_PARTS 12    /* test hook for the split of Sec. 4: 0 (default) the whole sum; 1 only the
+                               real-space part (pairs within r_c, their images and corrections, and the
+                               stokeslet's self term); 2 only the Fourier part (spreading, transforms,
+                               scaling, quadrature).  Parts 1 and 2 add up to part 0 within rounding */
 
 /* stage indices of ehs_report.ms_stage */
 #define EHS_ST_BBOX 0       /* bounding box + validation reduction and its readback */
@@ -330,6 +334,39 @@ double ehs_truncated_kernel_hat(int kind, double k, double R);
  */
 int ehs_debug_line_fft(ehs_ctx* ctx, int n, int nl, const void* in, void* out, int inverse, int fp32,
                        void* stream);
+
+/*
+ * Unit-test entry for the Gaussian spreading and quadrature (steps 5 and 10
+ * of Algorithm 1): one evaluation exactly like ewald_halfspace_<family>
+ * (free_space == 0) or ewald_freespace_<family> (free_space == 1), with
+ * the same arguments, options and report, and two taps:
+ *  - spread_out != NULL (device, spread_elems FP64 values): the grids as
+ *    spread, before any transform, converted to FP64;
+ *  - quad_in != NULL (device, quad_elems FP64 values): the grids the
+ *    quadrature reads are replaced by these (converted to the evaluation's
+ *    precision), and the real-space part is left out, so u_out holds the
+ *    quadrature of quad_in alone.
+ * Each grid is M~ x M~ x 2M~ values (report Mt), x1 fastest then x2 then
+ * x3, node (i, j, l) at origin + h (i, j, l); the grids follow one another.
+ * n_grids (may be NULL) receives the number of spread grids and of
+ * quadrature grids of the plan:
+ *  - spread grids: the kernel strengths at the sources and at their images
+ *    (free space: sources only), then the correction sources at the images,
+ *    either as separate grids or (report dgrid == 1) as one density with
+ *    derivative weights;
+ *  - quadrature grids: FP64 half space: the three velocity grids and the
+ *    correction potential phi, whose gradient the quadrature takes with
+ *    derivative weights; FP32 half space: the three velocity grids and the
+ *    three grids of grad phi; free space: the three velocity grids.
+ * A buffer below ngrids * M~^2 * 2M~ values gives EHS_EINVAL after the plan
+ * (call once with NULL buffers to learn M~ and the counts).  Contexts
+ * created with arena_bytes > 0 give EHS_EINVAL.  Not safe against other
+ * calls on the same context at the same time.
+ */
+int ehs_debug_grid_taps(ehs_ctx* ctx, int family, int free_space, const double* sources, const double* strengths,
+                        int64_t N, const double* targets, int64_t T, double xi, double r_c, double tol,
+                        double* u_out, double* spread_out, int64_t spread_elems, const double* quad_in,
+                        int64_t quad_elems, int32_t* n_grids, void* stream, ehs_report* report);
 
 /*
  * Serving: continuous batching of many summation requests on one device.

@@ -23,7 +23,7 @@ LIB_PATH = os.path.join(HERE, "libehs.so")
 STOKESLET, STRESSLET, ROTLET = 0, 1, 2
 FAMILIES = {"stokeslet": STOKESLET, "stresslet": STRESSLET, "rotlet": ROTLET}
 (OPT_PRECISION, OPT_TIMING, OPT_FORCE_M, OPT_FORCE_P, OPT_FORCE_MT, OPT_MEM_CAP, OPT_ZSLAB, OPT_GATHER_EXTRA,
- OPT_DGRID, OPT_FAIL_PRECOMPUTE, OPT_CELL_REACH, OPT_OVERLAP) = range(12)
+ OPT_DGRID, OPT_FAIL_PRECOMPUTE, OPT_CELL_REACH, OPT_OVERLAP, OPT_PARTS) = range(13)
 NOALLOC_SCRATCH_BYTES = 512 << 20
 ARENA_MIN_BYTES = 32 << 20
 STAGES = ["bbox", "precompute", "binning", "realspace", "spread", "fwd_x", "fwd_y", "z_scale", "inv_y", "inv_x",
@@ -113,6 +113,10 @@ def lib():
             L.ehs_plan_query.restype = ctypes.c_int
             L.ehs_debug_line_fft.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp, vp, ctypes.c_int, ctypes.c_int, vp]
             L.ehs_debug_line_fft.restype = ctypes.c_int
+            L.ehs_debug_grid_taps.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp, vp, i64, vp, i64, dp, dp, dp, vp,
+                                              vp, i64, vp, i64, ctypes.POINTER(ctypes.c_int32), vp,
+                                              ctypes.POINTER(Report)]
+            L.ehs_debug_grid_taps.restype = ctypes.c_int
             _bind_serving(L)
             _lib = L
     return _lib
@@ -331,6 +335,44 @@ class Context:
 
     def rotlet(self, y, v, x, xi, r_c, tol, **kw):
         return self.evaluate(ROTLET, y, v, x, xi, r_c, tol, **kw)
+
+    def debug_grid_taps(self, family, sources, strengths, targets, xi, r_c, tol, free_space=False, quad_in=None,
+                        stream=None):
+        """One evaluation with the stage taps of ehs_debug_grid_taps (unit tests).
+
+        Returns a dict: u (with quad_in: the quadrature of those grids
+        alone), spread (the grids as spread, FP64, shape (n, 2 M~, M~, M~)),
+        n_spread, n_quad (grid counts) and report.  quad_in: FP64 CUDA tensor
+        of shape (n_quad, 2 M~, M~, M~); learn the shape from a call without it.
+        """
+        import torch
+
+        fam = FAMILIES[family] if isinstance(family, str) else int(family)
+        ncol = 6 if fam == STRESSLET else 3
+        ys = _dev_ptr(sources, "sources", 3)
+        ss = _dev_ptr(strengths, "strengths", ncol)
+        if strengths.shape[0] != sources.shape[0]:
+            raise ValueError("strengths and sources differ in length")
+        xs = _dev_ptr(targets, "targets", 3)
+        T = targets.shape[0]
+        out = torch.empty((T, 3), dtype=torch.float64, device=targets.device)
+        uo = _dev_ptr(out, "out", 3)
+        counts = (ctypes.c_int32 * 2)()
+        rep = Report()
+        args = (self._h, fam, 1 if free_space else 0, ys, ss, int(sources.shape[0]), xs, int(T), float(xi),
+                float(r_c), float(tol), uo)
+        check(lib().ehs_debug_grid_taps(*args, None, 0, None, 0, counts, _stream_handle(stream), ctypes.byref(rep)))
+        Mt = rep.Mt
+        spread = torch.empty((counts[0], 2 * Mt, Mt, Mt), dtype=torch.float64, device=targets.device)
+        qp, qn = None, 0
+        if quad_in is not None:
+            if (not quad_in.is_cuda or quad_in.dtype != torch.float64 or not quad_in.is_contiguous()
+                    or tuple(quad_in.shape) != (counts[1], 2 * Mt, Mt, Mt)):
+                raise ValueError(f"quad_in: contiguous FP64 CUDA tensor of shape {(counts[1], 2 * Mt, Mt, Mt)}")
+            qp, qn = ctypes.c_void_p(quad_in.data_ptr()), quad_in.numel()
+        check(lib().ehs_debug_grid_taps(*args, ctypes.c_void_p(spread.data_ptr()), spread.numel(), qp, qn, counts,
+                                        _stream_handle(stream), ctypes.byref(rep)))
+        return {"u": out, "spread": spread, "n_spread": counts[0], "n_quad": counts[1], "report": rep}
 
     def debug_line_fft(self, x, inverse=False, stream=None):
         """Unnormalised FFT along the last axis of a complex CUDA tensor (unit tests)."""

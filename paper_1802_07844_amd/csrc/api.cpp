@@ -588,7 +588,11 @@ int run(ehs_ctx* c, Plan& p, const Octants& oct, const double* y, const double* 
         join.armed = true;
         rst = c->side;
     }
-    HIPCHK(launch_realspace<T>(p.family, ra, ys, ss, xs, upart, p.max_chunks, rst));
+    if (c->parts != 2 && !c->tap_quad) {
+        HIPCHK(launch_realspace<T>(p.family, ra, ys, ss, xs, upart, p.max_chunks, rst));
+    } else if (TT > 0) {  // Fourier part only: the quadrature adds it to zero
+        HIPCHK(fill_u32(reinterpret_cast<uint32_t*>(upart), 0u, 6 * TT, rst));
+    }
     if (c->last_overlap) HIPCHK(hipEventRecord(c->ev_rs_end, rst));
     rec_ev(EHS_ST_SPREAD);
 
@@ -607,6 +611,11 @@ int run(ehs_ctx* c, Plan& p, const Octants& oct, const double* y, const double* 
     const long long csR = Mt * Mt * 2 * Mt;          // real grid component
     const long long csA = (Mt + 1) * 2 * Mt * Mt;    // A / D component (complex)
     HIPCHK(launch_spread<T>(p.family, cm, p.g, rec, toff, X, csR, st));
+    c->tap_grids[0] = p.ncin;
+    if (c->tap_spread) {
+        if (c->tap_spread_cap < p.ncin * csR) return EHS_EINVAL;
+        HIPCHK(launch_convert(X, c->tap_spread, p.ncin * csR, st));
+    }
     rec_ev(EHS_ST_FWDX);
 
     // -- forward transforms
@@ -715,6 +724,14 @@ int run(ehs_ctx* c, Plan& p, const Octants& oct, const double* y, const double* 
     pa.cs_out = csR;
     pa.l3lo = p.l3lo;
     HIPCHK(launch_inv_x<T>(Yc, X, pa, ncout_for(p.prec, cm), st));
+    if (c->parts == 1)  // real-space part only: the quadrature reads a cleared grid
+        HIPCHK(fill_u32(reinterpret_cast<uint32_t*>(X), 0u, (long long)((Lo.Y - Lo.X) / 4), st));
+    c->tap_grids[1] = ncout_for(p.prec, cm);
+    if (c->tap_quad) {
+        const long long nq = ncout_for(p.prec, cm) * csR;
+        if (c->tap_quad_cap < nq) return EHS_EINVAL;
+        HIPCHK(launch_convert(c->tap_quad, X, nq, st));
+    }
     if (c->last_overlap) HIPCHK(hipEventRecord(c->ev_pre_join, st));
     join.now();
     rec_ev(EHS_ST_GATHER);
@@ -1227,6 +1244,10 @@ int ehs_set_option(ehs_ctx* c, int option, double value)
             if (value != 0 && value != 1) return EHS_EINVAL;
             c->overlap = (value == 1 && c->side) ? 1 : 0;
             return EHS_OK;
+        case EHS_OPT_PARTS:
+            if (value != 0 && value != 1 && value != 2) return EHS_EINVAL;
+            c->parts = (int)value;
+            return EHS_OK;
         default: return EHS_EINVAL;
     }
 }
@@ -1269,6 +1290,36 @@ int ewald_freespace_rotlet(ehs_ctx* c, const double* sources, const double* v, i
                            int64_t T, double xi, double r_c, double tol, double* u_out, void* stream, ehs_report* rep)
 {
     return evaluate(c, EHS_ROTLET, sources, v, N, targets, T, xi, r_c, tol, u_out, stream, rep, true);
+}
+
+int ehs_debug_grid_taps(ehs_ctx* c, int family, int free_space, const double* sources, const double* strengths,
+                        int64_t N, const double* targets, int64_t T, double xi, double r_c, double tol,
+                        double* u_out, double* spread_out, int64_t spread_elems, const double* quad_in,
+                        int64_t quad_elems, int32_t* n_grids, void* stream, ehs_report* rep)
+{
+    if (!c || c->fixed) return EHS_EINVAL;
+    if ((spread_out && spread_elems < 1) || (quad_in && quad_elems < 1)) return EHS_EINVAL;
+    struct Untap {
+        ehs_ctx* c;
+        ~Untap()
+        {
+            c->tap_spread = nullptr;
+            c->tap_quad = nullptr;
+            c->tap_spread_cap = c->tap_quad_cap = 0;
+        }
+    } untap{c};
+    c->tap_spread = spread_out;
+    c->tap_spread_cap = spread_out ? spread_elems : 0;
+    c->tap_quad = quad_in;
+    c->tap_quad_cap = quad_in ? quad_elems : 0;
+    c->tap_grids[0] = c->tap_grids[1] = 0;
+    int r = evaluate(c, family, sources, strengths, N, targets, T, xi, r_c, tol, u_out, stream, rep,
+                     free_space != 0);
+    if (n_grids) {
+        n_grids[0] = c->tap_grids[0];
+        n_grids[1] = c->tap_grids[1];
+    }
+    return r;
 }
 
 const char* ehs_strerror(int code)

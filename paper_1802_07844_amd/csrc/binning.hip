@@ -13,16 +13,36 @@ namespace ehs {
 // ---------------------------------------------------------------------------
 __global__ void k_fill_u32(uint32_t* p, uint32_t v, long long n)
 {
-    long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-    if (i < n) p[i] = v;
+    const long long step = (long long)gridDim.x * blockDim.x;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += step) p[i] = v;
 }
 
 hipError_t fill_u32(uint32_t* p, uint32_t v, long long n, hipStream_t st)
 {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p, v, n);
+    const long long blocks = std::min((n + 255) / 256, 1LL << 16);  // grid-stride beyond 2^24 words
+    hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)blocks), dim3(256), 0, st, p, v, n);
     return hipGetLastError();
 }
+
+template <typename A, typename B>
+__global__ void k_convert(const A* __restrict__ in, B* __restrict__ out, long long n)
+{
+    const long long step = (long long)gridDim.x * blockDim.x;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += step) out[i] = (B)in[i];
+}
+
+template <typename A, typename B>
+hipError_t launch_convert(const A* in, B* out, long long n, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    const long long blocks = std::min((n + 255) / 256, 1LL << 16);
+    hipLaunchKernelGGL((k_convert<A, B>), dim3((unsigned)blocks), dim3(256), 0, st, in, out, n);
+    return hipGetLastError();
+}
+template hipError_t launch_convert<float, double>(const float*, double*, long long, hipStream_t);
+template hipError_t launch_convert<double, float>(const double*, float*, long long, hipStream_t);
+template hipError_t launch_convert<double, double>(const double*, double*, long long, hipStream_t);
 
 // ---------------------------------------------------------------------------
 // bounding box and validation

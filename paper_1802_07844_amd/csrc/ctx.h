@@ -84,6 +84,14 @@ struct ehs_ctx {
     // the real-space sum runs on `side`, beside the grid stages on the
     // caller's stream (fork and join by events); created with the context
     int overlap = 1;
+    int parts = 0;  // EHS_OPT_PARTS: 0 the whole sum, 1 real-space part only, 2 Fourier part only
+    // stage taps of ehs_debug_grid_taps (null outside that call): the spread
+    // grids copied out, the quadrature's grids replaced, and their counts
+    double* tap_spread = nullptr;
+    long long tap_spread_cap = 0;
+    const double* tap_quad = nullptr;
+    long long tap_quad_cap = 0;
+    int tap_grids[2] = {0, 0};
     hipStream_t side = nullptr;
     hipEvent_t fork = nullptr, join = nullptr;
     hipEvent_t ev_rs_end = nullptr, ev_pre_join = nullptr;  // timing of the overlapped sum

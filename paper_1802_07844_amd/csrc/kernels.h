@@ -117,6 +117,9 @@ hipError_t radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_tmp, uint32
 size_t scan_scratch_bytes(long long n);
 hipError_t exclusive_scan(const uint32_t* in, uint32_t* out, long long n, void* scratch, hipStream_t st);
 hipError_t fill_u32(uint32_t* p, uint32_t v, long long n, hipStream_t st);
+// out[i] = (B) in[i], i < n (float <-> double, double -> double)
+template <typename A, typename B>
+hipError_t launch_convert(const A* in, B* out, long long n, hipStream_t st);
 // off[c] (c <= ncell) = first sorted position with key >= c, written to `start`
 hipError_t launch_cell_ranges(const uint32_t* skeys, long long n, uint32_t* start, uint32_t* end, long long ncell,
                               hipStream_t st);
