@@ -385,6 +385,7 @@ int check_extents(const Plan& p, const Layout& L, size_t esz)
               && fits((size_t)3 * p.N * 8, L.ss - L.ys) && fits((size_t)6 * p.N * 8, L.xs - L.ss)
               && fits((size_t)3 * p.T * 8, L.upart - L.xs) && fits((size_t)3 * p.T * 8, L.bb - L.upart)
               && fits((size_t)(2 * Mt + 1) * 8, L.gkeys - L.ez)
+              && (!p.ggroup || fits((size_t)4 * p.T * 4, L.gtoff - L.gkeys))
               && (!p.gtiles || (fits((size_t)4 * p.T * 4, L.gtoff - L.gkeys)
                                 && fits((size_t)(p.ntiles_g + 1) * 4, L.grec - L.gtoff)
                                 && fits((size_t)p.T * target_record_stride(p.gg.P, esz) * esz, L.gpart - L.grec)
@@ -452,7 +453,7 @@ Layout layout(const Plan& p, size_t esz)
     // quadrature: target keys / values (4 T), tile offsets, target records and
     // the partial sums (6 per target and tile of its support box)
     const size_t gt = p.gtiles ? 1 : 0;  // regions of the node-owner quadrature only
-    L.gkeys = off; off += al(gt * 4 * T * sizeof(uint32_t));
+    L.gkeys = off; off += al((p.gtiles || p.ggroup ? 4 : 0) * T * sizeof(uint32_t));
     L.gtoff = off; off += al(gt * (p.ntiles_g + 1) * sizeof(uint32_t));
     L.grec = off; off += al(gt * T * target_record_stride(p.gg.P, esz) * esz);
     L.gpart = off; off += al(gt * T * gather_slots(p.gg) * 6 * esz);
@@ -741,7 +742,22 @@ int run(ehs_ctx* c, Plan& p, const Octants& oct, const double* y, const double* 
     //    form (targets sorted by the quadrature tile of their support base,
     //    one wavefront per tile for the partial sums, then a fixed-order sum
     //    per target)
-    if (!p.gtiles) {
+    if (p.ggroup) {
+        // targets sorted along a Morton curve over 2^3-node bins of their
+        // support base (wider bins on grids of 1024 nodes and more, so that
+        // the three 10-bit indices fit a 32-bit key), so that consecutive
+        // targets share most of their supports
+        int sh = 1;
+        while (((2LL * p.Mt) >> sh) >= 1024) ++sh;
+        int nb = 1;
+        while ((1LL << nb) < ((2LL * p.Mt) >> sh) + 1) ++nb;  // bits of a bin index
+        uint32_t* gk = reinterpret_cast<uint32_t*>(base + Lo.gkeys);
+        uint32_t *gv = gk + TT, *gk2 = gv + TT, *gv2 = gk2 + TT;
+        uint32_t *gks, *gperm;
+        HIPCHK(launch_target_zkeys(xs, TT, p.gg, sh, gk, gv, st));
+        HIPCHK(radix_sort(gk, gv, gk2, gv2, TT, (3 * nb + 3) / 4 * 4, sortsc, st, &gks, &gperm));
+        HIPCHK(launch_gather_group<T>(p.gg, cm, X, csR, xs, gperm, tperm, TT, upart, u, st));
+    } else if (!p.gtiles) {
         HIPCHK(launch_gather<T>(p.gg, cm, X, csR, xs, tperm, TT, upart, u, st));
     } else {
         uint32_t* gk = reinterpret_cast<uint32_t*>(base + Lo.gkeys);

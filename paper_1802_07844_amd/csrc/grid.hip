@@ -11,6 +11,8 @@
 // exactly once (zeros included).
 #include <math.h>
 
+#include <type_traits>
+
 #include "common.h"
 #include "kernels.h"
 
@@ -427,6 +429,37 @@ hipError_t launch_target_keys(const double* xs, long long TT, GridArgs gg, uint3
     return hipGetLastError();
 }
 
+// Morton (Z-order) key of the bin (support base >> shift, per axis) of each
+// target: consecutive keys stay close along all three axes
+__device__ __forceinline__ uint32_t spread_bits3(uint32_t v)
+{
+    uint32_t r = 0;
+    for (int i = 0; i < 11; ++i) r |= ((v >> i) & 1u) << (3 * i);
+    return r;
+}
+
+__global__ void k_target_zkeys(const double* __restrict__ xs, long long TT, GridArgs gg, int shift,
+                               uint32_t* __restrict__ keys, uint32_t* __restrict__ idx)
+{
+    long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (t >= TT) return;
+    const int dims[3] = {gg.Mt, gg.Mt, 2 * gg.Mt};
+    uint32_t k = 0;
+    for (int a = 0; a < 3; ++a)
+        k |= spread_bits3((uint32_t)(support_base(xs[a * TT + t], gg.o[a], gg.h, gg.P, dims[a]) >> shift)) << a;
+    keys[t] = k;
+    idx[t] = (uint32_t)t;
+}
+
+hipError_t launch_target_zkeys(const double* xs, long long TT, GridArgs gg, int shift, uint32_t* keys, uint32_t* idx,
+                               hipStream_t st)
+{
+    if (TT <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_target_zkeys, dim3((unsigned)((TT + 255) / 256)), dim3(256), 0, st, xs, TT, gg, shift, keys,
+                       idx);
+    return hipGetLastError();
+}
+
 // one wavefront per (tile-sorted) target
 template <typename T>
 __global__ void __launch_bounds__(64) k_target_records(const double* __restrict__ xs, const uint32_t* __restrict__ perm,
@@ -752,6 +785,188 @@ __global__ void __launch_bounds__(256) k_gather(GridArgs g, const T* __restrict_
     }
 }
 
+// Quadrature for dense targets, several per wavefront.  The targets are
+// sorted along a Morton curve over 2^3-node bins of their support base (so
+// that consecutive ones lie close along all three axes); a wavefront takes GK
+// consecutive ones and walks the union of their supports once -- lanes own
+// (x1, x2) node pairs of it, 64 at a time, and walk the x3 column -- so each
+// grid value is read once for the group and weighted for each of its
+// targets (by zero outside the target's own support).  The 1D factors of
+// each target over the union, and their derivatives, sit in LDS.  A group
+// whose union is wider than GX nodes on some axis is taken one target at a
+// time.  Per target the sums run over the same nodes with the same factors
+// as in the one-target form, in another order.
+constexpr int GK = 4;
+constexpr int GX = GATHER_GX;
+
+template <typename T, int CM>
+__global__ void __launch_bounds__(64) k_gather_group(GridArgs g, const T* __restrict__ grids, long long cs,
+                                                     const double* __restrict__ xs, const uint32_t* __restrict__ gperm,
+                                                     const uint32_t* __restrict__ tperm, long long TT,
+                                                     const double* __restrict__ upart, double* __restrict__ uout)
+{
+    constexpr bool GQ = Out<T, CM>::grad_quad;
+    constexpr bool FREE = CM == CM_FREE;
+    constexpr int NC = FREE ? 3 : 6;                   // sums per target
+    constexpr int NG = FREE ? 3 : GQ ? 4 : 6;          // grids read per node
+    __shared__ T tab[GK][3][GX][2];                    // (factor, derivative) per target, axis, union node
+    __shared__ double sx[GK][3];
+    __shared__ int sb[GK][3];
+    __shared__ uint32_t sti[GK];
+    const int lane = threadIdx.x;
+    const long long ng = (TT + GK - 1) / GK;
+    const long long grp = xcd_block(blockIdx.x, ng);
+    if (grp >= ng) return;  // whole block
+    const long long s0 = grp * GK;
+    const int nt = (int)min((long long)GK, TT - s0);
+    const int P = g.P, Mt = g.Mt;
+    if (lane < GK * 3) {
+        const int k = lane / 3, a = lane - 3 * k;
+        const uint32_t t = gperm[s0 + (k < nt ? k : nt - 1)];
+        const double xa = xs[a * TT + t];
+        const int dims = a == 2 ? 2 * Mt : Mt;
+        sx[k][a] = xa;
+        sb[k][a] = support_base(xa, g.o[a], g.h, P, dims);
+        if (a == 0) sti[k] = t;
+    }
+    __syncthreads();
+    int lo[3], hi[3];
+    for (int a = 0; a < 3; ++a) {
+        lo[a] = sb[0][a];
+        hi[a] = sb[0][a];
+        for (int k = 1; k < nt; ++k) {
+            lo[a] = min(lo[a], sb[k][a]);
+            hi[a] = max(hi[a], sb[k][a]);
+        }
+        hi[a] += P;
+    }
+    const bool together = hi[0] - lo[0] <= GX && hi[1] - lo[1] <= GX && hi[2] - lo[2] <= GX;
+
+    // factors of targets k0 .. k0 + nk - 1 over the window L .. L + E - 1
+    auto fill = [&](int k0, int nk, const int* L, const int* E) {
+        for (int f = lane; f < GK * 3 * GX; f += 64) {
+            const int kk = f / (3 * GX), r = f - kk * (3 * GX), a = r / GX, e = r - a * GX;
+            T w = 0, dw = 0;
+            if (kk < nk && e < E[a]) {
+                const int k = k0 + kk, n = L[a] + e;
+                if (n >= sb[k][a] && n < sb[k][a] + P) {
+                    const double d = g.o[a] + n * g.h - sx[k][a];
+                    double v = exp(-g.a2 * d * d);
+                    if (a == 0) v *= g.pref;
+                    w = (T)v;
+                    if (GQ) dw = (T)(2.0 * g.a2 * d * v);
+                }
+            }
+            tab[kk][a][e][0] = w;
+            tab[kk][a][e][1] = dw;
+        }
+    };
+    auto at = [&](const T* gb, int c, unsigned ob) -> T {
+        return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(gb + c * cs) + ob);
+    };
+    // the walk over the window for NK targets, then their sums and outputs
+    auto walk = [&](auto nk_c, int k0, const int* L, const int* E) {
+        constexpr int NK = decltype(nk_c)::value;
+        T acc[NK][6];
+#pragma unroll
+        for (int k = 0; k < NK; ++k)
+#pragma unroll
+            for (int c = 0; c < 6; ++c) acc[k][c] = (T)0;
+        const T* gb = grids + ((long long)L[2] * Mt + L[1]) * Mt + L[0];
+        const unsigned zstep = (unsigned)((long long)Mt * Mt * (long long)sizeof(T));
+        const int E2 = E[0] * E[1];
+        for (int p0 = 0; p0 < E2; p0 += 64) {
+            const bool on = p0 + lane < E2;
+            const int pr = on ? p0 + lane : E2 - 1;
+            const int dy = pr / E[0], xi = pr - dy * E[0];
+            T wxy[NK], gxy[NK], gyx[NK];
+#pragma unroll
+            for (int k = 0; k < NK; ++k) {
+                const T wx = on ? tab[k][0][xi][0] : (T)0, wy = tab[k][1][dy][0];
+                wxy[k] = wx * wy;
+                gxy[k] = GQ ? (on ? tab[k][0][xi][1] : (T)0) * wy : (T)0;
+                gyx[k] = GQ ? wx * tab[k][1][dy][1] : (T)0;
+            }
+            unsigned ob = (unsigned)((dy * Mt + xi) * (int)sizeof(T));
+#pragma unroll 2
+            for (int dz = 0; dz < E[2]; ++dz) {
+                T v[NG];
+#pragma unroll
+                for (int c = 0; c < NG; ++c) v[c] = at(gb, c, ob);
+#pragma unroll
+                for (int k = 0; k < NK; ++k) {
+                    const T wz = tab[k][2][dz][0];
+                    const T w = wxy[k] * wz;
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) acc[k][c] += w * v[c];
+                    if (GQ) {
+                        acc[k][3] += (gxy[k] * wz) * v[3];
+                        acc[k][4] += (gyx[k] * wz) * v[3];
+                        acc[k][5] += (wxy[k] * tab[k][2][dz][1]) * v[3];
+                    } else if (!FREE) {
+#pragma unroll
+                        for (int c = 3; c < NC; ++c) acc[k][c] += w * v[c];
+                    }
+                }
+                ob += zstep;
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < NK; ++k)
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                T v = acc[k][c];
+                for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+                acc[k][c] = v;
+            }
+        if (lane == 0) {
+            const double h3 = g.h * g.h * g.h;
+#pragma unroll
+            for (int k = 0; k < NK; ++k) {
+                if (k0 + k >= nt) continue;
+                const long long o = tperm[sti[k0 + k]];
+                const double x3 = sx[k0 + k][2];
+                for (int a = 0; a < 3; ++a)
+                    uout[3 * o + a] =
+                        upart[3 * o + a] + h3 * ((double)acc[k][a] - (FREE ? 0.0 : x3 * (double)acc[k][3 + a]));
+            }
+        }
+    };
+    if (together) {
+        const int E[3] = {hi[0] - lo[0], hi[1] - lo[1], hi[2] - lo[2]};
+        fill(0, nt, lo, E);
+        __syncthreads();
+        walk(std::integral_constant<int, GK>{}, 0, lo, E);
+    } else {
+        const int E[3] = {P, P, P};
+        for (int k = 0; k < nt; ++k) {
+            __syncthreads();  // the previous target's factors are read
+            const int L[3] = {sb[k][0], sb[k][1], sb[k][2]};
+            fill(k, 1, L, E);
+            __syncthreads();
+            walk(std::integral_constant<int, 1>{}, k, L, E);
+        }
+    }
+}
+
+template <typename T>
+hipError_t launch_gather_group(GridArgs g, int cm, const T* grids, long long cs, const double* xs,
+                               const uint32_t* gperm, const uint32_t* tperm, long long T_, const double* upart,
+                               double* uout, hipStream_t st)
+{
+    if (T_ <= 0) return hipSuccess;
+    if (!gather_group_fits(g.P, g.Mt, sizeof(T))) return hipErrorInvalidValue;
+    const long long ng = (T_ + GK - 1) / GK;
+    const long long nlaunch = (ng + NXCD - 1) / NXCD * NXCD;  // every XCD range padded to full length
+    if (cm == CM_FREE)
+        hipLaunchKernelGGL((k_gather_group<T, CM_FREE>), dim3((unsigned)nlaunch), dim3(64), 0, st, g, grids, cs, xs,
+                           gperm, tperm, T_, upart, uout);
+    else
+        hipLaunchKernelGGL((k_gather_group<T, CM_GRIDS>), dim3((unsigned)nlaunch), dim3(64), 0, st, g, grids, cs, xs,
+                           gperm, tperm, T_, upart, uout);
+    return hipGetLastError();
+}
+
 template <typename T>
 hipError_t launch_gather(GridArgs g, int cm, const T* grids, long long cs, const double* xs, const uint32_t* tperm,
                          long long T_, const double* upart, double* uout, hipStream_t st)
@@ -776,6 +991,11 @@ template hipError_t launch_spread<double>(int, int, GridArgs, const double*, con
                                           hipStream_t);
 template hipError_t launch_spread<float>(int, int, GridArgs, const float*, const uint32_t*, float*, long long,
                                          hipStream_t);
+template hipError_t launch_gather_group<double>(GridArgs, int, const double*, long long, const double*,
+                                                const uint32_t*, const uint32_t*, long long, const double*, double*,
+                                                hipStream_t);
+template hipError_t launch_gather_group<float>(GridArgs, int, const float*, long long, const double*, const uint32_t*,
+                                               const uint32_t*, long long, const double*, double*, hipStream_t);
 template hipError_t launch_gather<double>(GridArgs, int, const double*, long long, const double*, const uint32_t*,
                                           long long, const double*, double*, hipStream_t);
 template hipError_t launch_gather<float>(GridArgs, int, const float*, long long, const double*, const uint32_t*, long long,

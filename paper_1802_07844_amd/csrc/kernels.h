@@ -193,6 +193,23 @@ hipError_t launch_spread(int family, int cm, GridArgs g, const T* rec, const uin
 template <typename T>
 hipError_t launch_gather(GridArgs g, int cm, const T* grids, long long cs, const double* x, const uint32_t* tperm,
                          long long T_, const double* upart, double* uout, hipStream_t st);
+// the grouped form takes union windows of at most GATHER_GX nodes per axis,
+// with 32-bit byte offsets within one window
+constexpr int GATHER_GX = 48;
+inline bool gather_group_fits(int Pg, long long Mt, size_t esz)
+{
+    return Pg <= GATHER_GX && (long long)GATHER_GX * Mt * Mt * (long long)esz < (1LL << 32);
+}
+// Morton keys of the targets' support bases >> shift (bins of 2^shift nodes)
+hipError_t launch_target_zkeys(const double* xs, long long TT, GridArgs gg, int shift, uint32_t* keys, uint32_t* idx,
+                               hipStream_t st);
+// quadrature at dense targets, several targets per wavefront sharing one walk
+// over their supports (gperm: targets sorted by the Morton keys above, as
+// indices into the cell-sorted xs)
+template <typename T>
+hipError_t launch_gather_group(GridArgs g, int cm, const T* grids, long long cs, const double* xs,
+                               const uint32_t* gperm, const uint32_t* tperm, long long T_, const double* upart,
+                               double* uout, hipStream_t st);
 // quadrature at the targets, node-owner form (see grid.hip):
 //   keys: quadrature tile of each target's support base (xs: cell-sorted SoA targets)
 hipError_t launch_target_keys(const double* xs, long long T_, GridArgs gg, uint32_t* keys, uint32_t* idx,

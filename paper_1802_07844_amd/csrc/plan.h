@@ -230,6 +230,7 @@ struct Plan {
     long long ntiles;
     long long ntiles_g;  // quadrature tiles (8^3 nodes)
     bool gtiles;         // quadrature in node-owner form (large supports), else one wavefront per target
+    bool ggroup = false; // one-wavefront form with groups of nearby targets sharing the walk
     int Bx, By;
     int zg;  // k1 slabs per group of the y / x3 pipeline
     int l3lo;  // first x3 node the inverse transforms produce (the quadrature reads no lower node)
@@ -519,6 +520,8 @@ inline int make_plan(const PlanInput& in, Plan* out)
         // (free space: the target-per-wavefront form, which has its output layout)
         p.gtiles = !in.free && Pg >= 16 && (double)in.T < 3e-3 * nodes;
     }
+    // dense targets: several per wavefront, sharing the walk over their supports
+    p.ggroup = !p.gtiles && gather_group_fits(Pg, Mt, p.prec == 1 ? 8 : 4);
     p.ntiles_g = 1;
     for (int a = 0; a < 3; ++a) {
         p.gg.tile[a] = 8;
