@@ -382,6 +382,7 @@ def serve_bench(args, ehs, workloads, torch, np):
     free = torch.cuda.mem_get_info()[0]
     arena = int(min(args.serve_arena_gb * 2**30, 0.8 * free))
     srv = ehs.Server(0, arena_bytes=arena, nslots=args.serve_slots)
+    srv.set_option(ehs.OPT_ADMISSION, args.serve_admission)
     # capacity from a closed-loop calibration batch of the same distribution
     cal = workloads.serving_stream(args.serve_calib, seed + 1)
     t0 = time.perf_counter()
@@ -451,14 +452,17 @@ def serve_bench(args, ehs, workloads, torch, np):
     pc = lambda a, p: float(np.percentile(np.array(a), p)) if len(a) else None
     by_size = {}
     for lo, hi, lab in ((1e3, 1e4, "N<1e4"), (1e4, 1e5, "1e4<=N<1e5"), (1e5, 1e6 + 1, "N>=1e5")):
-        sel = [lat[k] for k in range(len(lat)) if lo <= sizes[k] < hi]
-        by_size[lab] = {"requests": len(sel), "p50_ms": pc(sel, 50), "p99_ms": pc(sel, 99)}
+        ks = [k for k in range(len(lat)) if lo <= sizes[k] < hi]
+        sel, sq, ss = [lat[k] for k in ks], [que[k] for k in ks], [svc[k] for k in ks]
+        by_size[lab] = {"requests": len(sel), "p50_ms": pc(sel, 50), "p99_ms": pc(sel, 99),
+                        "queue_p99_ms": pc(sq, 99), "service_p50_ms": pc(ss, 50), "service_p99_ms": pc(ss, 99)}
     return {
         "requests": len(lat), "requests_planned": args.serve_requests, "lambda_per_s": lam,
         "capacity_per_s": mu, "utilization_target": args.serve_util,
         "p50_ms": pc(lat, 50), "p99_ms": pc(lat, 99), "queue_p50_ms": pc(que, 50), "queue_p99_ms": pc(que, 99),
         "service_p50_ms": pc(svc, 50), "service_p99_ms": pc(svc, 99), "by_size": by_size,
         "points_per_s": pts / max(t_end - tstart, 1e-9), "nslots": args.serve_slots, "arena_gb": arena / 2**30,
+        "admission": "smallest-first, one slot kept for <= 65,536 points" if args.serve_admission else "first-come",
         "arena_peak_gb": stats["arena_peak"] / 2**30, "cache_hits": stats["cache_hits"],
         "cache_misses": stats["cache_misses"], "evictions": stats["evictions"], "failed": stats["failed"],
         "rel_rms_fp64_max": max(errs[1]) if errs[1] else None, "rel_rms_fp32_max": max(errs[2]) if errs[2] else None,
@@ -487,6 +491,8 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--serve-util", type=float, default=0.7, help="arrival rate as a fraction of measured capacity")
     ap.add_argument("--serve-slots", type=int, default=4)
+    ap.add_argument("--serve-admission", type=int, default=1, choices=[0, 1],
+                    help="1: smallest request first with one slot kept for small ones; 0: first come first served")
     ap.add_argument("--serve-arena-gb", type=float, default=200.0)
     ap.add_argument("--serve-calib", type=int, default=48, help="closed-loop calibration requests")
     ap.add_argument("--serve-max-seconds", type=float, default=120.0, help="stop admitting arrivals after this")

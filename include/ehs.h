@@ -96,6 +96,11 @@ extern "C" {
                                real-space part (pairs within r_c, their images and corrections, and the
                                stokeslet's self term); 2 only the Fourier part (spreading, transforms,
                                scaling, quadrature).  Parts 1 and 2 add up to part 0 within rounding */
+#define EHS_OPT_ADMISSION 13 /* servers only (ehs_server_set_option): 1 (default) smallest request first
+                               (by workspace), one slot of two or more kept for requests of at most
+                               65,536 points (N + T), the oldest request overtaken at most 8 times;
+                               0 first come first served, younger requests overtaking a head that does
+                               not fit at most 8 times */
 
 /* stage indices of ehs_report.ms_stage */
 #define EHS_ST_BBOX 0       /* bounding box + validation reduction and its readback */
@@ -439,9 +444,10 @@ int ehs_submit(ehs_server* srv, const ehs_request* req, uint64_t* ticket);
 int ehs_wait(ehs_server* srv, uint64_t ticket, int timeout_ms, ehs_request_status* status);
 /* Counters and arena occupancy.  Thread safe. */
 int ehs_server_stats(ehs_server* srv, ehs_serve_stats* out);
-/* Server options: only EHS_OPT_FAIL_PRECOMPUTE (the next `value` octant
-   productions fail with EHS_EHIP, for tests of the failure path); EHS_EINVAL
-   for any other.  Thread safe. */
+/* Server options: EHS_OPT_ADMISSION (the admission rule, above) and
+   EHS_OPT_FAIL_PRECOMPUTE (the next `value` octant productions fail with
+   EHS_EHIP, for tests of the failure path); EHS_EINVAL for any other.
+   Thread safe. */
 int ehs_server_set_option(ehs_server* srv, int option, double value);
 
 #ifdef __cplusplus

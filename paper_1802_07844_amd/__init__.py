@@ -23,7 +23,7 @@ LIB_PATH = os.path.join(HERE, "libehs.so")
 STOKESLET, STRESSLET, ROTLET = 0, 1, 2
 FAMILIES = {"stokeslet": STOKESLET, "stresslet": STRESSLET, "rotlet": ROTLET}
 (OPT_PRECISION, OPT_TIMING, OPT_FORCE_M, OPT_FORCE_P, OPT_FORCE_MT, OPT_MEM_CAP, OPT_ZSLAB, OPT_GATHER_EXTRA,
- OPT_DGRID, OPT_FAIL_PRECOMPUTE, OPT_CELL_REACH, OPT_OVERLAP, OPT_PARTS) = range(13)
+ OPT_DGRID, OPT_FAIL_PRECOMPUTE, OPT_CELL_REACH, OPT_OVERLAP, OPT_PARTS, OPT_ADMISSION) = range(14)
 NOALLOC_SCRATCH_BYTES = 512 << 20
 ARENA_MIN_BYTES = 32 << 20
 STAGES = ["bbox", "precompute", "binning", "realspace", "spread", "fwd_x", "fwd_y", "z_scale", "inv_y", "inv_x",

@@ -5,9 +5,15 @@
 // shared between requests and kept in the arena as a cache.  Requests run on
 // `nslots` slots, each a host worker thread with its own stream and context;
 // their device work overlaps.  Admission happens whenever a request arrives
-// or one completes: the oldest queued request that fits a free slot and the
-// arena is started.  Younger requests may overtake a head that does not fit,
-// at most MAX_BYPASS times per head.
+// or one completes.  First-come (EHS_OPT_ADMISSION 0): the oldest queued
+// request that fits a free slot and the arena is started; younger requests
+// may overtake a head that does not fit, at most MAX_BYPASS times per head.
+// Smallest-first (1, the default): among the queued requests that fit, the
+// one with the smallest workspace (a measure of its grid and point work)
+// starts first, and one slot is kept for requests of at most EXPRESS_POINTS
+// points, so that small requests neither queue behind large ones nor wait
+// for a slot they hold; the oldest request may still be overtaken at most
+// MAX_BYPASS times, after which the general slots wait for it.
 //
 // Octant sharing: a request that finds an octant missing allocates it and
 // enqueues its precompute on its own stream, then records an event.  Others
@@ -39,6 +45,7 @@ namespace {
 using Clock = std::chrono::steady_clock;
 
 constexpr int MAX_BYPASS = 8;
+constexpr long long EXPRESS_POINTS = 65536;  // N + T of a request the kept slot takes
 
 // one cached octant array in the arena
 struct Unit {
@@ -96,6 +103,7 @@ struct ehs_server {
     uint64_t next_ticket = 1, use_clock = 0;
     int running = 0;
     std::atomic<int> fail_productions{0};  // test hook (EHS_OPT_FAIL_PRECOMPUTE)
+    int admission = 1;                     // EHS_OPT_ADMISSION
     int64_t submitted = 0, completed = 0, failed = 0, rejected = 0, hits = 0, misses = 0, evictions = 0;
     size_t cache_bytes = 0;
     Clock::time_point t0;
@@ -216,9 +224,73 @@ bool admit(ehs_server* s, Req* r)
     return true;
 }
 
+void start(ehs_server* s, Req* r, Slot* sl)
+{
+    r->state = REQ_RUNNING;
+    r->t_admit = s->now_ms();
+    r->slot = (int)(std::find(s->slots.begin(), s->slots.end(), sl) - s->slots.begin());
+    sl->job = r;
+    s->running++;
+    sl->cv.notify_one();
+}
+
+bool is_small(const Req* r) { return r->r.N + r->r.T <= EXPRESS_POINTS; }
+
+// Smallest-first admission (lock held): the last slot (with two or more) is
+// kept for small requests.
+void try_admit_smallest(ehs_server* s)
+{
+    const size_t ns = s->slots.size();
+    Slot* express = ns >= 2 ? s->slots.back() : nullptr;
+    for (;;) {
+        Slot *gen = nullptr, *exp = nullptr;
+        for (Slot* sl : s->slots)
+            if (!sl->job) {
+                if (sl == express)
+                    exp = sl;
+                else if (!gen)
+                    gen = sl;
+            }
+        if ((!gen && !exp) || s->pending.empty()) return;
+        Req* head = s->pending.front();
+        const bool aged = head->bypassed >= MAX_BYPASS;
+        // candidates by workspace size, oldest first among equals
+        std::vector<Req*> cand(s->pending.begin(), s->pending.end());
+        std::stable_sort(cand.begin(), cand.end(), [](const Req* a, const Req* b) { return a->ws_bytes < b->ws_bytes; });
+        // a request that does not fit the arena stops the search for its slot
+        // (larger ones would not fit either; each try may evict cached octants)
+        bool started = false;
+        for (Req* r : cand) {
+            Slot* sl = nullptr;
+            if (is_small(r) && exp)
+                sl = exp;
+            else if (gen && (!aged || r == head))
+                sl = gen;
+            if (!sl) continue;
+            if (!admit(s, r)) {
+                if (sl == exp)
+                    exp = nullptr;
+                else
+                    gen = nullptr;
+                continue;
+            }
+            if (r != head) head->bypassed++;
+            start(s, r, sl);
+            s->pending.erase(std::find(s->pending.begin(), s->pending.end(), r));
+            started = true;
+            break;
+        }
+        if (!started) return;
+    }
+}
+
 // Start queued requests while slots and memory allow (lock held).
 void try_admit(ehs_server* s)
 {
+    if (s->admission == 1) {
+        try_admit_smallest(s);
+        return;
+    }
     auto it = s->pending.begin();
     while (it != s->pending.end()) {
         Slot* free_slot = nullptr;
@@ -231,12 +303,7 @@ void try_admit(ehs_server* s)
         Req* r = *it;
         if (admit(s, r)) {
             if (it != s->pending.begin()) s->pending.front()->bypassed++;
-            r->state = REQ_RUNNING;
-            r->t_admit = s->now_ms();
-            r->slot = (int)(std::find(s->slots.begin(), s->slots.end(), free_slot) - s->slots.begin());
-            free_slot->job = r;
-            s->running++;
-            free_slot->cv.notify_one();
+            start(s, r, free_slot);
             it = s->pending.erase(it);
             continue;
         }
@@ -539,9 +606,19 @@ int ehs_wait(ehs_server* s, uint64_t ticket, int timeout_ms, ehs_request_status*
 
 int ehs_server_set_option(ehs_server* s, int option, double value)
 {
-    if (!s || option != EHS_OPT_FAIL_PRECOMPUTE) return EHS_EINVAL;
-    s->fail_productions.store(std::max(0, (int)value));
-    return EHS_OK;
+    if (!s) return EHS_EINVAL;
+    if (option == EHS_OPT_FAIL_PRECOMPUTE) {
+        s->fail_productions.store(std::max(0, (int)value));
+        return EHS_OK;
+    }
+    if (option == EHS_OPT_ADMISSION) {
+        if (value != 0 && value != 1) return EHS_EINVAL;
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->admission = (int)value;
+        try_admit(s);
+        return EHS_OK;
+    }
+    return EHS_EINVAL;
 }
 
 int ehs_server_stats(ehs_server* s, ehs_serve_stats* out)

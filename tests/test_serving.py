@@ -148,3 +148,48 @@ def test_submit_errors():
         assert e.value.code == ehs.EHS_EINVAL
         st = srv.stats()
     assert st["rejected"] == 3 and st["submitted"] == 0
+
+
+@pytest.mark.parametrize("admission", [0, 1])
+def test_admission_rules_keep_results_and_the_small_request_slot(admission):
+    """Both admission rules give every request the result of the single call;
+    with smallest-first admission the last slot only ever runs requests of at
+    most 65,536 points (N + T), and large requests submitted first do not
+    hold it."""
+    g = workloads.rng(23)
+    reqs = []
+    for i, n in enumerate([40_000, 50_000, 45_000, 60_000] + [int(x) for x in g.integers(300, 3000, 8)]):
+        fam = ["stokeslet", "rotlet"][i % 2]
+        y, s = workloads.make(fam, n, 2300 + i)
+        xi, rc = _params(fam, n, 1e-10, nb=60)
+        reqs.append(dict(family=fam, n=n, prec=1, tol=1e-10, y=y, s=s, xi=xi, rc=rc))
+    alone = _alone(reqs)
+    nslots = 4
+    with ehs.Server(0, arena_bytes=16 << 30, nslots=nslots) as srv:
+        srv.set_option(ehs.OPT_ADMISSION, admission)
+        tickets = []
+        for r in reqs:
+            yd = _dev(r["y"])
+            tickets.append(srv.submit(r["family"], yd, _dev(r["s"]), yd, r["xi"], r["rc"], r["tol"],
+                                      precision=r["prec"]))
+        results = [srv.wait(t) for t in tickets]
+        st = srv.stats()
+    assert st["completed"] == len(reqs) and st["failed"] == 0
+    for r, a, (u, status) in zip(reqs, alone, results):
+        assert status["code"] == 0
+        assert np.array_equal(u.cpu().numpy(), a), (r["family"], r["n"])
+        print(f"admission {admission}: N={r['n']:6d} slot={status['slot']} "
+              f"queue={status['t_admit_ms'] - status['t_submit_ms']:.1f} ms "
+              f"service={status['t_done_ms'] - status['t_admit_ms']:.1f} ms")
+        if admission == 1 and 2 * r["n"] > 65536:
+            assert status["slot"] != nslots - 1
+
+
+def test_admission_option_values():
+    with ehs.Server(0, arena_bytes=1 << 30, nslots=2) as srv:
+        for v in (0, 1):
+            srv.set_option(ehs.OPT_ADMISSION, v)
+        with pytest.raises(ehs.EhsError):
+            srv.set_option(ehs.OPT_ADMISSION, 2)
+        with pytest.raises(ehs.EhsError):
+            srv.set_option(ehs.OPT_CELL_REACH, 1)
