@@ -9,6 +9,9 @@
 * The runtime-optimal search keeps only the fastest candidate's octants.
 * The correction-density option (EHS_OPT_DGRID) in both settings against the
   oracle, for the stresslet with its larger support.
+* The forcing options (M, P, M~, the quadrature's extra support, the slab
+  groups of the transform pipeline): reflected in the report, within tol of
+  the oracle, and refused out of range.
 """
 import math
 
@@ -317,5 +320,82 @@ def test_overlapped_real_space_sum_is_bitwise_the_same(fam, prec, free):
         assert out[1][1]["realspace"] > 0 and out[1][1]["total"] > 0
         with pytest.raises(ehs.EhsError):
             c.set_option(ehs.OPT_OVERLAP, 2)
+    finally:
+        c.close()
+
+
+def _next_smooth_even(n):
+    def smooth(m):
+        for p in (2, 3, 5, 7):
+            while m % p == 0:
+                m //= p
+        return m == 1
+
+    while n % 2 or not smooth(n):
+        n += 1
+    return n
+
+
+@pytest.mark.parametrize("family,prec", [("stokeslet", 1), ("stresslet", 1), ("rotlet", 2)])
+def test_forced_plan_parameters(family, prec):
+    """Forcing M, P, M~ or the quadrature's extra support shows in the report
+    and, since each only adds grid or support, keeps the result within tol of
+    the oracle; the slab grouping of the y / x3 transform pipeline (one k1
+    slab at a time, or the whole grid at once) changes no bit of it."""
+    tol = 1e-10 if prec == 1 else 1e-5
+    y, s, yd, sd, xi, rc = _problem(family, 600, 77, nb=200, tol=tol)
+    ref = oracle.halfspace(family, y, s, y)
+    c = ehs.Context(0)
+    try:
+        c.set_option(ehs.OPT_PRECISION, prec)
+        u0, r0 = c.evaluate(family, yd, sd, yd, xi, rc, tol, report=True)
+        u0 = u0.cpu().numpy()
+        assert oracle.rel_rms(ref, u0) <= tol
+
+        def run(opt, val, reset):
+            c.set_option(opt, val)
+            try:
+                u, r = c.evaluate(family, yd, sd, yd, xi, rc, tol, report=True)
+                return u.cpu().numpy(), r
+            finally:
+                c.set_option(opt, reset)
+
+        for zg in (1, r0.Mt + 1):
+            u, r = run(ehs.OPT_ZSLAB, zg, 0)
+            assert r.zslab == zg
+            assert np.array_equal(u, u0), f"slab groups of {zg}"
+        dp = 4 if max(r0.P, r0.Pg) + 4 <= 30 else 2
+        mt = _next_smooth_even(r0.Mt + 20)
+        checks = [
+            (ehs.OPT_FORCE_P, r0.P + dp, 0, lambda r: r.P == r0.P + dp),
+            (ehs.OPT_FORCE_M, r0.M + 10, 0, lambda r: r.M == r0.M + 10),
+            (ehs.OPT_FORCE_MT, mt, 0, lambda r: r.Mt == mt and r.M == r0.M),
+            (ehs.OPT_GATHER_EXTRA, r0.Pg - r0.P + 2, -1, lambda r: r.Pg == r0.Pg + 2),
+        ]
+        for opt, val, reset, ok in checks:
+            u, r = run(opt, val, reset)
+            err = oracle.rel_rms(ref, u)
+            print(f"{family} prec {prec}: option {opt} = {val}: M {r.M} P {r.P} Pg {r.Pg} Mt {r.Mt} rel-RMS {err:.2e}")
+            assert ok(r)
+            assert err <= tol
+        u, r = c.evaluate(family, yd, sd, yd, xi, rc, tol, report=True)
+        assert (r.M, r.P, r.Pg, r.Mt) == (r0.M, r0.P, r0.Pg, r0.Mt)
+    finally:
+        c.close()
+
+
+def test_forced_plan_parameters_out_of_range():
+    y, s, yd, sd, xi, rc = _problem("stokeslet", 300, 78)
+    c = ehs.Context(0)
+    try:
+        c.set_option(ehs.OPT_PRECISION, 1)
+        for opt, val, reset in ((ehs.OPT_FORCE_P, 31, 0), (ehs.OPT_FORCE_P, 13, 0), (ehs.OPT_FORCE_MT, 101, 0),
+                                (ehs.OPT_GATHER_EXTRA, 3, -1)):
+            c.set_option(opt, val)
+            with pytest.raises(ehs.EhsError) as e:
+                c.evaluate("stokeslet", yd, sd, yd, xi, rc, 1e-10)
+            c.set_option(opt, reset)
+            assert e.value.code in (ehs.EHS_EINVAL, ehs.EHS_ERANGE)
+        c.evaluate("stokeslet", yd, sd, yd, xi, rc, 1e-10)
     finally:
         c.close()
