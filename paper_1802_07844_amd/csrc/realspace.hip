@@ -270,6 +270,22 @@ __device__ __forceinline__ void lds_add(T* p, T v)
 // bottom nr cell layers, in FP64, added to upart.  Two launches rather than
 // one kernel: the FP64 image terms need many more registers than the direct
 // ones, and in one kernel they would set the occupancy of every chunk.
+// Chunks go to the XCDs in runs of RS_RUN consecutive ones: block b runs on
+// XCD b % 8, and XCD k takes runs k, k + 8, k + 16, ... in order, so that
+// neighbouring chunks, which read the same source cells, share an L2, while
+// every XCD still takes its share of each region of the cell order (the
+// dense bottom layers come first; one contiguous range per XCD would leave
+// them to one or two).  The grid is padded to a multiple of 8 RS_RUN blocks;
+// chunks past the count exit.  (Clustered N = 4e6 stokeslet: HBM fetch of
+// the direct pass 71.5 -> 54.4 GB per evaluation, time unchanged: the pass
+// is bound by instruction issue.)
+constexpr int RS_RUN = 64;
+__device__ __forceinline__ long long chunk_of_block(long long b)
+{
+    const long long q = b / NXCD;  // position in the XCD's sequence
+    return ((q / RS_RUN) * NXCD + b % NXCD) * RS_RUN + q % RS_RUN;
+}
+
 template <typename T, int K, bool PASS_IMG>
 __global__ void __launch_bounds__(64) k_realspace(RealArgs a, const double* __restrict__ ys,
                                                   const double* __restrict__ ss, const double* __restrict__ xt,
@@ -290,7 +306,7 @@ __global__ void __launch_bounds__(64) k_realspace(RealArgs a, const double* __re
     __shared__ double acc_l[PASS_IMG ? 1 : 3 * 64];    // direct terms, per target
     __shared__ double acci_l[PASS_IMG ? 3 * 64 : 1];   // image terms, per target (FP64)
     const int lane = threadIdx.x;
-    const long long w = blockIdx.x;
+    const long long w = chunk_of_block(blockIdx.x);
     if (w >= (long long)(*a.nchunks)) return;  // the whole (one-wavefront) block
     const uint32_t cell = a.chunk_cell[w];
     // (a target and a source can both lie within r_c of the wall only in the
@@ -492,7 +508,8 @@ hipError_t launch_realspace(int family, const RealArgs& a, const double* ys, con
                             double* upart, long long max_chunks, hipStream_t st)
 {
     if (max_chunks <= 0) return hipSuccess;
-    dim3 grid((unsigned)max_chunks);  // one wavefront per chunk
+    const long long span = (long long)NXCD * RS_RUN;
+    dim3 grid((unsigned)((max_chunks + span - 1) / span * span));  // one wavefront per chunk
     // direct terms of every chunk, then the images of the bottom-layer chunks
     // (none in free space)
     if (!a.images) {
