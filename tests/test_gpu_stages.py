@@ -278,3 +278,39 @@ def test_spreading_and_quadrature_against_plain_gridding(family, mode, n_targets
         assert e_q <= bound
     finally:
         c.close()
+
+
+@pytest.mark.parametrize("family", ["stokeslet", "stresslet", "rotlet"])
+@pytest.mark.parametrize("prec", [1, 2])
+def test_quadrature_of_clustered_repeated_and_wall_targets(family, prec):
+    """The grouped quadrature where targets crowd: 4000 targets clustered at
+    the wall, 300 of them repeated (equal points in one group) and 50 on the
+    wall itself (x3 = 0), against the plain CPU quadrature."""
+    n = 60
+    y, s = workloads.make(family, n, workloads.SEED_BASE + 93)
+    x, _ = workloads.make(family, 4000, workloads.SEED_BASE + 94, layout="clustered")
+    g = np.random.default_rng(95)
+    x[g.choice(len(x), 50, replace=False), 2] = 0.0
+    x[1::13][:300] = x[0::13][:300]
+    tol = 1e-8 if prec == 1 else 1e-5
+    rc = 0.3
+    xi = ehs.xi_for_cutoff(family, rc, tol / 2)
+    c = ehs.Context(0)
+    try:
+        c.set_option(ehs.OPT_PRECISION, prec)
+        yd, sd, xd = (torch.from_numpy(np.ascontiguousarray(a)).to(DEV) for a in (y, s, x))
+        r = c.debug_grid_taps(family, yd, sd, xd, xi, rc, tol)
+        rep = r["report"]
+        Q = g.standard_normal((r["n_quad"], 2 * rep.Mt, rep.Mt, rep.Mt))
+        rq = c.debug_grid_taps(family, yd, sd, xd, xi, rc, tol, quad_in=torch.from_numpy(Q).to(DEV))
+        uq = rq["u"].cpu().numpy()
+        refq = _cpu_quadrature(rep, Q, x, False, prec == 1)
+        e_q = np.max(np.abs(uq - refq)) / np.max(np.abs(refq))
+        print(f"{family} prec {prec}: Mt={rep.Mt} Pg={rep.Pg} quadrature {e_q:.2e}")
+        assert e_q <= (1e-12 if prec == 1 else 2e-5)
+        # repeated targets agree to rounding (in one group bit for bit; a group
+        # boundary between them changes the order of the sums)
+        d = np.max(np.abs(uq[1::13][:300] - uq[0::13][:300])) / np.max(np.abs(refq))
+        assert d <= (1e-13 if prec == 1 else 1e-5)
+    finally:
+        c.close()
