@@ -793,8 +793,8 @@ __global__ void __launch_bounds__(256) k_gather(GridArgs g, const T* __restrict_
 // grid value is read once for the group and weighted for each of its
 // targets (by zero outside the target's own support).  The 1D factors of
 // each target over the union, and their derivatives, sit in LDS.  A group
-// whose union is wider than GX nodes on some axis is taken one target at a
-// time.  Per target the sums run over the same nodes with the same factors
+// whose union is wider than GX nodes on some axis, or holds more nodes than
+// the targets' own supports together, is taken one target at a time.  Per target the sums run over the same nodes with the same factors
 // as in the one-target form, in another order.
 constexpr int GK = 4;
 constexpr int GX = GATHER_GX;
@@ -840,7 +840,11 @@ __global__ void __launch_bounds__(64) k_gather_group(GridArgs g, const T* __rest
         }
         hi[a] += P;
     }
-    const bool together = hi[0] - lo[0] <= GX && hi[1] - lo[1] <= GX && hi[2] - lo[2] <= GX;
+    // one walk over the union only where it is no longer than the targets'
+    // own walks together (sparse groups go one target at a time)
+    const bool together = hi[0] - lo[0] <= GX && hi[1] - lo[1] <= GX && hi[2] - lo[2] <= GX &&
+                          (long long)(hi[0] - lo[0]) * (hi[1] - lo[1]) * (hi[2] - lo[2]) <=
+                              (long long)nt * P * P * P;
 
     // factors of targets k0 .. k0 + nk - 1 over the window L .. L + E - 1
     auto fill = [&](int k0, int nk, const int* L, const int* E) {
