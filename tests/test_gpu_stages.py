@@ -314,3 +314,46 @@ def test_quadrature_of_clustered_repeated_and_wall_targets(family, prec):
         assert d <= (1e-13 if prec == 1 else 1e-5)
     finally:
         c.close()
+
+
+def test_stage_hooks_refuse_bad_arguments():
+    """EHS_OPT_PARTS takes 0, 1 or 2; the grid taps refuse a buffer smaller
+    than the plan's grids (after planning, nothing written past it) and
+    contexts created with an arena."""
+    import ctypes
+
+    y, s = workloads.make("stokeslet", 200, workloads.SEED_BASE + 96)
+    xi = ehs.xi_for_cutoff("stokeslet", 0.3, 5e-9)
+    c = ehs.Context(0)
+    try:
+        with pytest.raises(ehs.EhsError) as e:
+            c.set_option(ehs.OPT_PARTS, 3)
+        assert e.value.code == ehs.EHS_EINVAL
+        yd, sd = torch.from_numpy(y).to(DEV), torch.from_numpy(s).to(DEV)
+        r = c.debug_grid_taps("stokeslet", yd, sd, yd, xi, 0.3, 1e-8)
+        need = r["spread"].numel()
+        small = torch.full((need - 1 + 16,), 7.0, dtype=torch.float64, device=DEV)
+        out = torch.empty((200, 3), dtype=torch.float64, device=DEV)
+        counts = (ctypes.c_int32 * 2)()
+        rc = ehs.lib().ehs_debug_grid_taps(c._h, ehs.STOKESLET, 0, ctypes.c_void_p(yd.data_ptr()),
+                                           ctypes.c_void_p(sd.data_ptr()), 200, ctypes.c_void_p(yd.data_ptr()), 200,
+                                           xi, 0.3, 1e-8, ctypes.c_void_p(out.data_ptr()),
+                                           ctypes.c_void_p(small.data_ptr()), need - 1, None, 0, counts, None, None)
+        torch.cuda.synchronize()
+        assert rc == ehs.EHS_EINVAL
+        assert torch.all(small[need - 1:] == 7.0)  # nothing past the stated size
+        assert counts[0] == r["n_spread"]
+        # the context still evaluates, with the taps cleared
+        u = c.evaluate("stokeslet", yd, sd, yd, xi, 0.3, 1e-8)
+        torch.cuda.synchronize()
+        assert oracle.rel_rms(oracle.halfspace("stokeslet", y, s, y), u.cpu().numpy()) <= 1e-8
+    finally:
+        c.close()
+    a = ehs.Context(0, arena_bytes=1 << 30)
+    try:
+        yd, sd = torch.from_numpy(y).to(DEV), torch.from_numpy(s).to(DEV)
+        with pytest.raises(ehs.EhsError) as e:
+            a.debug_grid_taps("stokeslet", yd, sd, yd, xi, 0.3, 1e-8)
+        assert e.value.code == ehs.EHS_EINVAL
+    finally:
+        a.close()
