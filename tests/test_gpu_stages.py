@@ -357,3 +357,34 @@ def test_stage_hooks_refuse_bad_arguments():
         assert e.value.code == ehs.EHS_EINVAL
     finally:
         a.close()
+
+
+@pytest.mark.parametrize("n_targets", [1, 2, 3, 5, 7, 4001])
+@pytest.mark.parametrize("mode", ["fp32", "free"])
+def test_quadrature_partial_groups(mode, n_targets):
+    """Target counts that leave the last group of four short (FP32 and free
+    space take the grouped quadrature whatever the density)."""
+    n = 60
+    y, s = workloads.make("rotlet", n, workloads.SEED_BASE + 97)
+    x, _ = workloads.make("rotlet", n_targets, workloads.SEED_BASE + 98, layout="clustered")
+    fp64 = mode == "free"
+    tol = 1e-8 if fp64 else 1e-5
+    xi = ehs.xi_for_cutoff("rotlet", 0.3, tol / 2)
+    c = ehs.Context(0)
+    try:
+        c.set_option(ehs.OPT_PRECISION, 1 if fp64 else 2)
+        yd, sd, xd = (torch.from_numpy(np.ascontiguousarray(a)).to(DEV) for a in (y, s, x))
+        r = c.debug_grid_taps("rotlet", yd, sd, xd, xi, 0.3, tol, free_space=mode == "free")
+        rep = r["report"]
+        g = np.random.default_rng(99)
+        Q = g.standard_normal((r["n_quad"], 2 * rep.Mt, rep.Mt, rep.Mt))
+        rq = c.debug_grid_taps("rotlet", yd, sd, xd, xi, 0.3, tol, free_space=mode == "free",
+                               quad_in=torch.from_numpy(Q).to(DEV))
+        uq = rq["u"].cpu().numpy()
+        refq = _cpu_quadrature(rep, Q, x, mode == "free", fp64)
+        e_q = np.max(np.abs(uq - refq)) / np.max(np.abs(refq))
+        print(f"{mode} T={n_targets}: quadrature {e_q:.2e}")
+        assert uq.shape == (n_targets, 3)
+        assert e_q <= (1e-12 if fp64 else 2e-5)
+    finally:
+        c.close()
