@@ -738,10 +738,12 @@ int run(ehs_ctx* c, Plan& p, const Octants& oct, const double* y, const double* 
     rec_ev(EHS_ST_GATHER);
 
     // -- quadrature at the targets and FP64 combination with the real part:
-    //    small supports one wavefront per target; large ones in node-owner
-    //    form (targets sorted by the quadrature tile of their support base,
-    //    one wavefront per tile for the partial sums, then a fixed-order sum
-    //    per target)
+    //    dense targets four per wavefront, sharing the walk over their
+    //    supports (grouped form); large supports at low target density in
+    //    node-owner form (targets sorted by the quadrature tile of their
+    //    support base, one wavefront per tile for the partial sums, then a
+    //    fixed-order sum per target); one wavefront per target only for grids
+    //    too large for the grouped form's 32-bit offsets
     if (p.ggroup) {
         // targets sorted along a Morton curve over 2^3-node bins of their
         // support base (wider bins on grids of 1024 nodes and more, so that

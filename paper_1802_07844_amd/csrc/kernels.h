@@ -189,7 +189,8 @@ hipError_t launch_records(int family, int cm, const double* y, const double* s, 
 template <typename T>
 hipError_t launch_spread(int family, int cm, GridArgs g, const T* rec, const uint32_t* toff, T* grids, long long cs,
                          hipStream_t st);
-// quadrature at the targets, one wavefront per target (small supports)
+// quadrature at the targets, one wavefront per target (for grids too large for
+// the grouped form below)
 template <typename T>
 hipError_t launch_gather(GridArgs g, int cm, const T* grids, long long cs, const double* x, const uint32_t* tperm,
                          long long T_, const double* upart, double* uout, hipStream_t st);

@@ -229,7 +229,7 @@ struct Plan {
     GridArgs gg;  // quadrature at the targets (support Pg >= P, same Gaussian)
     long long ntiles;
     long long ntiles_g;  // quadrature tiles (8^3 nodes)
-    bool gtiles;         // quadrature in node-owner form (large supports), else one wavefront per target
+    bool gtiles;         // quadrature in node-owner form (large supports at low density), else one-wavefront forms
     bool ggroup = false; // one-wavefront form with groups of nearby targets sharing the walk
     int Bx, By;
     int zg;  // k1 slabs per group of the y / x3 pipeline
@@ -505,11 +505,13 @@ inline int make_plan(const PlanInput& in, Plan* out)
     // quadrature tiles: 8 x 8 x 8 nodes, each owned by one wavefront.  The
     // node-owner form reads each grid node once but pays a reduction per
     // (target, tile), about 45 ns per target on MI355X whatever the density;
-    // the target-per-wavefront form re-reads nodes through L2, cheaper the
-    // denser the targets.  Node-owner only for large supports at low target
-    // density: FP64 N = 1e5 (Pg = 22, 0.9e-3 targets per node) 4.6 ms
-    // against 5.9; N = 1e6 (1.7e-2 per node) 44 ms against 28.5; FP32
-    // (Pg = 10) 0.8 ms against 0.34.
+    // the one-wavefront forms re-read nodes through L2, cheaper the denser
+    // the targets (the grouped form shares the reads of four nearby targets).
+    // Node-owner only for large supports at low target density: FP64
+    // N = 1e5 (Pg = 22, 0.9e-3 targets per node) 4.6 ms against 7.0 for the
+    // grouped form; N = 1e6 (1.7e-2 per node) 44 ms against 28.5 for the
+    // one-target form (grouped: about 11); FP32 (Pg = 10) 0.8 ms against
+    // 0.34 for the one-target form.
     {
         // nodes from the lowest target's support up (the x3 range computed
         // as l3lo below)
