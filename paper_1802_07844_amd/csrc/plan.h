@@ -341,7 +341,10 @@ inline int make_plan(const PlanInput& in, Plan* out)
     // stokeslet 7.2e-14 with either), so auto mode takes it only from tol
     // 1e-12 up
     const bool dens_tol = in.dgrid > 0 || tol >= 1e-12;
-    const bool dens_cand = p.prec == 1 && in.dgrid != 0 && !in.free && dens_fits && dens_tol;
+    // (the stresslet's density in auto mode is planned by the plan made again
+    // with it, below: this plan is the separate grids' and is not widened)
+    const bool dens_cand = p.prec == 1 && in.dgrid != 0 && !in.free && dens_fits && dens_tol &&
+                           !(in.family == 1 && in.dgrid < 0);
     const int Pe = std::max(std::max(P, Pg), dens_cand ? Pd : P);
     // grid intervals over the box
     int M = in.force_M;
@@ -399,6 +402,12 @@ inline int make_plan(const PlanInput& in, Plan* out)
             double cost = 4.4e-9 * 2.0 * (double)in.N * ((double)Pd * Pd * Pd - (double)P * P * P) *
                           (in.family == 1 ? 2.0 : 1.0);
             dg = in.dgrid > 0 || save > cost;
+        }
+        // the grids chosen over a candidate density: M~ without the density's
+        // wider support
+        if (dens_cand && !dg && in.force_Mt <= 0) {
+            const int extg = std::max(std::max(P, Pg), (int)std::ceil(m / (std::sqrt(2.0) * xi * h)));
+            Mt = std::min(Mt, next_smooth_even(M + extg));
         }
         p.dgrid = dg;
         p.Ps = dg ? Pd : P;
